@@ -1,0 +1,33 @@
+"""CPU FP64 oracle for the guarded SIMP state solve (test infrastructure only).
+
+This package is the plain, slow, obviously correct reference that the HIP path
+is checked against.  It is NOT part of the product: only the test-suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it.  It shares
+no code with the HIP library (no kernels, headers, tables or constant
+generators); both sides are written independently from the paper.
+
+What it computes (citations are to arXiv 2607.26382):
+
+* ``ke``         - hex8 element stiffness (Sec. 3.1, "Discretization and units").
+* ``mesh``       - structured cantilever grid, clamped x=0 face, -z edge load.
+* ``operator``   - ersatz SIMP law E = rho_min + (1-rho_min) rho^p (Eq. floor_scaling),
+                   frozen operator K = sum_e E_e K_e (Eq. frozen_operator),
+                   direct solve and the relative residual (Eq. relative_residual).
+* ``multigrid``  - 2:1 trilinear transfers, Galerkin coarse operators, damped
+                   node-block Jacobi, fixed V-cycle (Tab. solver-config and the
+                   fixed linear V-cycle of Sec. 4.6.3 "Fixed-preconditioner control").
+* ``fgmres``     - right-preconditioned flexible GMRES with the residual-history
+                   semantics of Tab. residual-semantics.
+* ``policy``     - probe features, the two-feature rule (Eq. trigger) and the
+                   guarded floor ladder (Alg. floor_policy).
+* ``features``   - density statistics used by the learned first-floor selector.
+* ``mlp``        - forward/backward of the 8-64-64-4 GELU selector network.
+* ``stats``      - Wilson score intervals (Sec. 4.3.1 held-out reference test).
+
+Every function is pinned by tests under ``tests/`` against facts the paper or
+mathematics fix (closed forms, invariants, printed values, library routines on
+special cases).  Functions without such a pin say "parity unpinned" here:
+
+* ``mlp.train`` / Adam bookkeeping - parity unpinned (no printed trajectory;
+  the gradients it consumes are pinned by finite differences).
+"""
