@@ -1,0 +1,246 @@
+/*
+ * topoguard - guarded matrix-free SIMP state solve for AMD MI355X (gfx950).
+ *
+ * C ABI of libtopoguard.so.  Every call follows the statement of the problem
+ * in arXiv 2607.26382 ("When a positive SIMP density floor is not enough"):
+ *
+ *   K(rho_min) u = f,  K(rho_min) = sum_e E_e K_e  on the free DOFs
+ *   (Eq. frozen_operator), E_e = rho_min + (1 - rho_min) rho_e^p
+ *   (Eq. floor_scaling), acceptance only on the recomputed FP64 relative
+ *   residual eta = ||f - K u|| / ||f|| <= tau (Eq. relative_residual,
+ *   Tab. residual-semantics), floor chosen by the probe -> two-feature rule ->
+ *   guarded ladder of Alg. floor_policy.
+ *
+ * Conventions for every function:
+ *   - return 0 on success; a negative TG_E* code on failure, with a message
+ *     available from tg_last_error() (thread-local, valid until the next call
+ *     on the same thread).  Solver non-convergence is an OUTCOME reported in
+ *     a result struct, never an error code.
+ *   - "_d" pointers are device pointers (HIP global memory on the current
+ *     device); "_h" pointers are host pointers.  The library never keeps a
+ *     caller pointer beyond the call, except the workspace bound with
+ *     tg_bind_workspace / tg_batch_bind_workspace, which the caller owns and
+ *     must keep alive (and unmoved) until the handle is destroyed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *     device work is enqueued on it.  Functions returning host scalars
+ *     synchronize that stream before returning.
+ *   - Grid layout: elements e = ex + nx (ey + ny ez) (x fastest); nodes
+ *     n = i + (nx+1) (j + (ny+1) k); DOF 3 n + c (c = x, y, z).  Vectors are
+ *     full length (3 * n_nodes) and hold 0 on the clamped DOFs (x = 0 face):
+ *     inputs there are ignored (treated as 0), outputs there are written 0.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently
+ *     on distinct streams.
+ */
+#ifndef TOPOGUARD_H
+#define TOPOGUARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TG_OK = 0,
+  TG_EINVAL = -1,      /* invalid argument (sizes, ranges, NaN density, ...) */
+  TG_EHIP = -2,        /* a HIP runtime call failed                          */
+  TG_EWORKSPACE = -3,  /* workspace missing or too small                     */
+  TG_ESTATE = -4,      /* call out of order (e.g. apply before set_density)  */
+  TG_ENUMERIC = -5     /* coarsest factorization met a non-positive pivot    */
+};
+
+/* Precision of the operator / preconditioner path (addition (1)). */
+enum {
+  TG_F64 = 0,          /* FP64 vectors and arithmetic                          */
+  TG_F32 = 1,          /* FP32 vectors and arithmetic                          */
+  TG_BF16MFMA = 2      /* FP32 vectors, Ke contraction on BF16 MFMA, FP32 acc. */
+};
+
+/* FGMRES outcomes (the solver's internal flag semantics, Tab. residual-semantics). */
+enum {
+  TG_PROJ_CONVERGED = 0, /* stopping estimate <= tol (diagnostic only) */
+  TG_MAXIT = 1,          /* iteration cap reached                      */
+  TG_BREAKDOWN = 2,      /* Hessenberg subdiagonal collapsed           */
+  TG_NONFINITE = 3       /* a non-finite scalar appeared               */
+};
+
+/* Multigrid options (Tab. solver-config, fixed linear V-cycle). */
+typedef struct {
+  int max_levels;      /* 0 = automatic: coarsen 2:1 while dims even, >= 2, and free DOF > max_coarse_dof */
+  int max_coarse_dof;  /* default 300                                   */
+  double omega;        /* node-block Jacobi damping, default 0.6        */
+  int nu_pre, nu_post; /* sweeps, default 2 / 2                         */
+} tg_mg_opts;
+
+/* FGMRES options. */
+typedef struct {
+  int restart;         /* m, default 30                                 */
+  int max_iters;       /* cap across restarts, default 200              */
+  double tol;          /* stopping tolerance on the history value, 1e-6 */
+  int prec;            /* preconditioner precision TG_F64/F32/BF16MFMA  */
+  int cgs_passes;      /* 1 = CGS, 2 = CGS2 (default)                   */
+  double breakdown;    /* subdiagonal <= breakdown * ||w|| -> BREAKDOWN, 1e-14 */
+} tg_solver_opts;
+
+typedef struct {
+  int iterations;      /* total FGMRES iterations                        */
+  int outcome;         /* TG_PROJ_CONVERGED / TG_MAXIT / ...             */
+  double proj_eta;     /* last history value (stopping estimate)         */
+  double true_eta;     /* recomputed FP64 relative residual (guard) or -1 */
+} tg_solve_result;
+
+typedef struct {
+  int nx, ny, nz;          /* fine elements                                  */
+  int64_t n_elem, n_nodes, n_dof, n_free;
+  int n_levels;
+  int level_dims[8][3];    /* elements per level                             */
+  int coarse_free_dof;     /* free DOFs of the coarsest level                */
+} tg_grid_info;
+
+typedef struct tg_grid tg_grid;
+typedef struct tg_batch tg_batch;
+typedef struct tg_mlp tg_mlp;
+
+/* ---- errors, defaults -------------------------------------------------- */
+const char* tg_last_error(void);
+void tg_default_mg_opts(tg_mg_opts* o);
+void tg_default_solver_opts(tg_solver_opts* o);
+
+/* ---- grid (Sec. 3.1: structured cubic hex8 grid, one shared Ke) ---------- */
+/* Builds the host Ke (E0, nu, unit cube, 2x2x2 Gauss), index maps, hierarchy
+ * dimensions.  Cantilever boundary: x = 0 face clamped.  mg may be NULL
+ * (defaults).  No device memory is touched until a workspace is bound. */
+int tg_setup_grid(int nx, int ny, int nz, double E0, double nu,
+                  const tg_mg_opts* mg, tg_grid** out);
+void tg_destroy(tg_grid* g);
+int tg_get_grid_info(const tg_grid* g, tg_grid_info* info);
+/* Copies the 24x24 FP64 element stiffness (row-major, local node
+ * a = i + 2j + 4k, DOF 3a + c) to ke_h. */
+int tg_get_ke(const tg_grid* g, double* ke_h);
+/* Unit -z load on the x = L, z = 0 edge by tributary length (total -1),
+ * written to the full-length host vector f_h (3 * n_nodes doubles). */
+int tg_edge_load(const tg_grid* g, double* f_h);
+
+/* Device workspace for one grid: every device array the grid and its solver
+ * use (moduli, coarse operators, smoother blocks, coarsest inverse, Krylov
+ * bases for restart <= max_restart, V-cycle vectors).  The caller allocates
+ * `bytes` (256-byte aligned) and binds it. */
+int tg_workspace_bytes(const tg_grid* g, int max_restart, size_t* bytes);
+int tg_bind_workspace(tg_grid* g, void* ws_d, size_t bytes, int max_restart);
+
+/* ---- density (Eq. floor_scaling) ---------------------------------------- */
+/* rho_d: n_elem FP64 stored densities in [0,1] (device).  p > 0,
+ * 0 < rho_min <= 1.  Builds E_e (FP64 and FP32), Galerkin coarse operators,
+ * node-block smoother inverses and the coarsest dense inverse.  Synchronizes
+ * `stream` (validation).  TG_EINVAL on a non-finite or out-of-range density. */
+int tg_set_density(tg_grid* g, const double* rho_d, double p, double rho_min, void* stream);
+
+/* ---- operator (Eq. frozen_operator) -------------------------------------- */
+/* y = K(rho_min) u on the free DOFs.  prec TG_F64: u_d, y_d are double;
+ * TG_F32 / TG_BF16MFMA: float.  Needs tg_set_density first (TG_ESTATE). */
+int tg_apply_K(const tg_grid* g, const void* u_d, void* y_d, int prec, void* stream);
+
+/* ---- preconditioner (Tab. solver-config, fixed V-cycle) ------------------ */
+/* z = M^-1 r: one fixed linear V-cycle.  Vector dtype follows prec as above. */
+int tg_vcycle(tg_grid* g, const void* r_d, void* z_d, int prec, void* stream);
+
+/* ---- solve (right-preconditioned FGMRES, Sec. 3.5) ------------------------ */
+/* x0 = 0.  f_d, u_d: double.  hist_h (may be NULL) receives iterations+1
+ * history values (cycle-start true residuals, in-cycle projected estimates).
+ * res->true_eta is -1 (the guard is a separate call). */
+int tg_fgmres_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o,
+                    tg_solve_result* res, double* hist_h, void* stream);
+
+/* ---- guard (Eq. relative_residual; Alg. floor_policy acceptance) ---------- */
+/* eta = ||f - K u||_2 / ||f||_2 over free DOFs in FP64. */
+int tg_true_residual(const tg_grid* g, const double* f_d, const double* u_d,
+                     double* eta_h, void* stream);
+
+/* ---- probe (Sec. 3.4) ------------------------------------------------------ */
+/* Runs FGMRES at the current floor for at most `iters` iterations with restart
+ * o->restart (the caller passes restart >= iters for one-cycle semantics) and
+ * returns r50 = hist[min(50,k_stop)], r100 = hist[min(100,k_stop)]. */
+int tg_probe_features(tg_grid* g, const double* f_d, const tg_solver_opts* o, int iters,
+                      double* r50_h, double* r100_h, int* k_stop_h, void* stream);
+
+/* ---- policy (Alg. floor_policy) ------------------------------------------ */
+enum { TG_SELECT_RULE = 0, TG_SELECT_MLP = 1, TG_SELECT_FIXED = 2 };
+#define TG_MAX_RUNGS 8
+typedef struct {
+  int n_rungs;                   /* rungs[0] = original floor rho_0            */
+  double rungs[TG_MAX_RUNGS];    /* increasing floors, e.g. 1e-9,1e-6,1e-4,1e-3 */
+  double p;                      /* SIMP exponent                              */
+  double tau;                    /* guard tolerance, 1e-6                      */
+  int probe_iters;               /* 100                                        */
+  int probe_restart;             /* 100                                        */
+  double t_high, t_plateau, t_ratio;   /* Eq. trigger: 1e-2, 1e-4, 0.6      */
+  int selector;                  /* TG_SELECT_*                                */
+  int fixed_rung;                /* for TG_SELECT_FIXED                        */
+  const tg_mlp* mlp;             /* for TG_SELECT_MLP (rule if NULL)           */
+  tg_solver_opts solve;          /* per-rung solves (restart 30, cap 200, ...) */
+} tg_policy;
+
+typedef struct {
+  int rung;                      /* accepted rung index, -1 = none admissible */
+  double floor;                  /* accepted floor or -1                      */
+  int k0;                        /* first attempted rung                      */
+  double r50, r100;              /* probe features                            */
+  int probe_iters;               /* k_stop of the probe                       */
+  int n_attempts;
+  struct {
+    int rung, iterations, outcome, accepted;
+    double floor, proj_eta, true_eta;
+  } attempts[TG_MAX_RUNGS];
+  int iters_probe, iters_selected, iters_rejected;   /* stage accounting      */
+  double features[8];            /* selector input (log r50, log r100, 6 stats) */
+} tg_policy_result;
+
+void tg_default_policy(tg_policy* pol);
+/* rho_d: stored densities (device).  On return u_d holds the accepted
+ * solution (zeros if rung == -1).  Never returns a solution whose FP64
+ * eta > tau. */
+int tg_select_floor(tg_grid* g, const double* rho_d, const double* f_d, const tg_policy* pol,
+                    double* u_d, tg_policy_result* out, void* stream);
+
+/* ---- batching (addition (2)) --------------------------------------------- */
+/* A batch solves independent problems of possibly different grid sizes
+ * together: every kernel launch covers all active problems.  Each grid keeps
+ * its own bound workspace; the batch needs a small workspace of its own. */
+int tg_batch_create(int n, tg_grid* const* grids, tg_batch** out);
+void tg_batch_destroy(tg_batch* b);
+int tg_batch_workspace_bytes(const tg_batch* b, size_t* bytes);
+int tg_batch_bind_workspace(tg_batch* b, void* ws_d, size_t bytes);
+/* rho_d[i], rho_min[i] per problem; p shared. */
+int tg_batch_set_density(tg_batch* b, const double* const* rho_d, double p,
+                         const double* rho_min_h, void* stream);
+/* f_d[i] -> u_d[i]; res[i] gets the outcome and (guard) true_eta. */
+int tg_batch_solve(tg_batch* b, const double* const* f_d, double* const* u_d,
+                   const tg_solver_opts* o, tg_solve_result* res, void* stream);
+/* Alg. floor_policy for every problem at once (probe, first rung, ladder). */
+int tg_batch_select_floor(tg_batch* b, const double* const* rho_d, const double* const* f_d,
+                          const tg_policy* pol, double* const* u_d, tg_policy_result* out,
+                          void* stream);
+
+/* ---- learned first-floor selector (addition (4)) ------------------------- */
+/* 8 -> 64 -> 64 -> 4 MLP, exact-erf GELU, softmax cross-entropy, Adam.
+ * Parameters and optimizer state live in the caller-bound workspace. */
+int tg_mlp_workspace_bytes(int max_batch, size_t* bytes);
+int tg_mlp_create(void* ws_d, size_t bytes, int max_batch, tg_mlp** out);
+void tg_mlp_destroy(tg_mlp* m);
+/* params_h: 4996 floats in order W1[64][8], b1[64], W2[64][64], b2[64],
+ * W3[4][64], b3[4]; mean_h/std_h: 8 feature standardization constants. */
+int tg_mlp_set_params(tg_mlp* m, const float* params_h, const float* mean_h, const float* std_h,
+                      void* stream);
+int tg_mlp_get_params(const tg_mlp* m, float* params_h, void* stream);
+/* x_d: B x 8 raw features (float, device) -> logits_d: B x 4. */
+int tg_mlp_forward(const tg_mlp* m, const float* x_d, int B, float* logits_d, void* stream);
+/* One Adam step on the mean cross-entropy of (x_d, y_d); loss_h may be NULL.
+ * grads_d (may be NULL) receives the 4996 parameter gradients. */
+int tg_mlp_train_step(tg_mlp* m, const float* x_d, const int* y_d, int B, float lr,
+                      float* loss_h, float* grads_d, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -67,7 +67,6 @@ def apply_at_node(grid, E, Ke, u, n):
     out = np.zeros(3)
     if i == 0:
         return out
-    free = grid.free_dofs()
     for a, (di, dj, dk) in enumerate(LOCAL):
         ex, ey, ez = i - di, j - dj, k - dk
         if not (0 <= ex < grid.nx and 0 <= ey < grid.ny and 0 <= ez < grid.nz):
@@ -75,10 +74,10 @@ def apply_at_node(grid, E, Ke, u, n):
         e = ex + grid.nx * (ey + grid.ny * ez)
         ue = np.zeros(24)
         for b, (bi, bj, bk) in enumerate(LOCAL):
+            if ex + bi == 0:             # clamped node (x = 0 face): zero DOFs
+                continue
             m = grid.node(ex + bi, ey + bj, ez + bk)
-            for c in range(3):
-                if free[3 * m + c]:
-                    ue[3 * b + c] = u[3 * m + c]
+            ue[3 * b:3 * b + 3] = u[3 * m:3 * m + 3]
         out += E[e] * (Ke[3 * a:3 * a + 3, :] @ ue)
     return out
 

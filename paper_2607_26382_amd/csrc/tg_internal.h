@@ -1,0 +1,199 @@
+// Internal layout of the topoguard library (gfx950).
+//
+// Every solver kernel is batch-aware: a launch covers a work list of
+// (problem, tile) pairs, one pair per workgroup, and each problem carries a
+// device descriptor with its grid dimensions and its device arrays.  A single
+// solve is a batch of one; uneven batches reuse the same kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/topoguard.h"
+
+#define TG_MAXLEV 8
+#define TG_NODE_TILE 256     // nodes per workgroup for node-centred kernels
+#define TG_VCHUNK 2048       // DOFs per workgroup for vector kernels
+#define TG_VBLOCK 256        // threads per vector workgroup
+#define TG_PART_W 128        // max vectors in one multi-dot
+#define TG_MAX_COARSE 512    // max free DOFs of the coarsest level
+#define TG_HIST_CAP 4096     // residual-history capacity per problem
+
+namespace tg {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define TG_HIP(call)                                        \
+  do {                                                      \
+    hipError_t _e = (call);                                 \
+    if (_e != hipSuccess) return ::tg::hip_fail(_e, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Per-level device view.  Vectors at a level live in two slot pools (FP64 and
+// FP32); slot s of a problem sits at pool + s * stride.
+struct LevelDesc {
+  int ex, ey, ez;           // elements
+  int NX, NY, NZ;           // nodes per dimension (= elements + 1)
+  int n_nodes;
+  int n_chunks;             // ceil(3 n_nodes / TG_VCHUNK)
+  long long stride;         // slot stride in elements (>= 3 n_nodes, 64-aligned)
+  double* vec64;
+  float* vec32;
+  double* Kel64;            // levels >= 1: 576 values per element (row-major 24x24)
+  float* Kel32;
+  double* Dinv64;           // 9 values per node (3x3 inverse of the node block)
+  float* Dinv32;
+};
+
+struct ProbDesc {
+  int nlev;
+  int ncoarse;              // free DOFs at the coarsest level
+  double rho_min;
+  double* E64;              // fine element moduli
+  float* E32;
+  double* Cinv64;           // coarsest dense inverse, ncoarse x ncoarse (row-major)
+  float* Cinv32;
+  double* Cwork;            // coarsest assembly / factorization scratch
+  const double* Ke64;       // shared element stiffness (576)
+  const float* Ke32;
+  const double* G64;        // 8 x 576: child Galerkin matrices P_c^T Ke P_c
+  const double* Pc64;       // 8 x 576: child prolongations P_c (fine 24 x coarse 24)
+  double* small;            // per-problem FGMRES scalars (SmallLayout)
+  double* part;             // reduction partials: TG_PART_W x n_chunks(level 0)
+  const double* ext0;       // per-call external vectors (batched copy in/out)
+  double* ext1;
+  LevelDesc lv[TG_MAXLEV];
+};
+
+// Level-0 FP64 slots.
+enum { S_F = 0, S_X = 1, S_R = 2, S_W = 3, S_T = 4, S_VB = 5, S_VXA = 6, S_VXB = 7, S_VR = 8, S_V0 = 9 };
+inline int slot_V(int j) { return S_V0 + j; }
+inline int slot_Z(int mmax, int j) { return S_V0 + mmax + 1 + j; }
+inline int n_slots0(int mmax) { return S_V0 + 2 * mmax + 1; }
+// V-cycle slots at levels >= 1 (both pools) and in the level-0 FP32 pool.
+enum { C_B = 0, C_XA = 1, C_XB = 2, C_R = 3, C_NSLOTS = 4 };
+
+// Per-problem small FGMRES state (doubles).
+struct SmallLayout {
+  int mmax, cap;
+  int H, g, cs, sn, y, h, tmp, scal, hist, total;
+  void init(int m, int c) {
+    mmax = m;
+    cap = c;
+    int o = 0;
+    H = o;   o += (m + 1) * m;   // column-major: H[i + (m+1) j]
+    g = o;   o += m + 1;
+    cs = o;  o += m;
+    sn = o;  o += m;
+    y = o;   o += m;
+    h = o;   o += TG_PART_W;     // accumulated projection coefficients
+    tmp = o; o += TG_PART_W;     // multi-dot result of the current pass
+    scal = o; o += 32;
+    hist = o; o += c + 1;
+    total = (o + 31) & ~31;
+  }
+};
+// scalar slots inside small + scal
+enum { SC_BNORM = 0, SC_BETA = 1, SC_HN = 2, SC_STATUS = 3, SC_ITERS = 4, SC_JDONE = 5,
+       SC_EST = 6, SC_TRUE = 7, SC_INV = 8, SC_FLAG = 9 };
+#define TG_RUNNING (-1.0)
+
+struct LevelHost {
+  int ex, ey, ez;
+  long long n_elem, n_nodes, n_dof, stride;
+  int n_chunks;
+};
+
+struct Batch;
+
+}  // namespace tg
+
+struct tg_grid {
+  int nx = 0, ny = 0, nz = 0;
+  double E0 = 1, nu = 0.3;
+  tg_mg_opts mg;
+  int nlev = 0;
+  tg::LevelHost lv[TG_MAXLEV];
+  int ncoarse = 0;            // free DOFs of the coarsest level (0 if no direct solve)
+  int ncoarse_true = 0;
+  bool coarse_ok = true;
+  double Ke[576];
+  double G[8 * 576];
+  double Pc[8 * 576];
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int mmax = 0;
+  int cap = 0;
+  tg::SmallLayout sl;
+  tg::ProbDesc desc;          // host copy of this grid's device descriptor
+  bool bound = false;
+  bool density_set = false;
+  bool numeric_bad = false;   // coarsest factorization met a non-positive pivot
+  double p = 0, rho_min = 0;
+  tg::Batch* self = nullptr;  // batch of one for single-grid calls
+};
+
+namespace tg {
+
+struct DevList {
+  const int2* ptr = nullptr;
+  int n = 0;
+};
+
+struct Batch {
+  std::vector<tg_grid*> grids;
+  int n = 0;
+  int maxlev = 0;
+  ProbDesc* desc_d = nullptr;     // device descriptors (n)
+  int2* list_d = nullptr;         // device work-list storage
+  size_t list_cap = 0;            // capacity in int2
+  double* sc_d = nullptr;         // device status gather (n doubles)
+  int* flag_d = nullptr;          // per-problem validation flags (set_density)
+  double p = 3.0;                 // SIMP exponent of the current set_density
+  std::vector<double> sc_h;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<int> active;
+  DevList node[TG_MAXLEV], smooth[TG_MAXLEV], coarse[TG_MAXLEV], elem[TG_MAXLEV], vec, prob;
+  std::vector<int2> host_lists;   // kept alive until the next synchronization
+  std::vector<ProbDesc> host_desc;
+};
+
+size_t batch_ws_bytes_for(const std::vector<tg_grid*>& grids);
+int batch_init(Batch* b, int n, tg_grid* const* grids);
+int batch_bind(Batch* b, void* ws, size_t bytes);
+int batch_upload_desc(Batch* b, hipStream_t s);
+int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bool with_elem = false);
+int batch_read_status(Batch* b, hipStream_t s);   // fills sc_h from small[SC_STATUS]
+
+// launch wrappers (tg_kernels.hip)
+int k_set_density(Batch* b, hipStream_t s);
+int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s);
+int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s);
+int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
+             void* ey, hipStream_t s);
+int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s);  // dir 0: ext0 -> slot; 1: slot -> ext1
+int k_fill0(Batch* b, int slot, double v, hipStream_t s);
+int k_copy0(Batch* b, int src, int dst, hipStream_t s);
+int k_multidot(Batch* b, int sbase, int nv, int sw, int with_self, hipStream_t s);
+int k_reduce(Batch* b, int nv, int mode, int dst, int save_k, hipStream_t s);  // 0: h=tmp 1: h+=tmp 2: tmp
+int k_update(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, hipStream_t s);
+int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s);
+int k_cycle_start(Batch* b, int k, int cap, double tol, hipStream_t s);
+int k_arnoldi(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s);
+int k_lsq_update(Batch* b, int mmax, hipStream_t s);
+int k_true_eta(Batch* b, hipStream_t s);       // small[SC_TRUE] from R and F dots
+int k_init_small(Batch* b, hipStream_t s);
+
+// host helpers (tg_host.cpp)
+void build_ke(double E0, double nu, double* Ke);
+void build_child_prolong(double* Pc);           // 8 x 24 x 24
+void build_child_galerkin(const double* Ke, const double* Pc, double* G);
+}  // namespace tg

@@ -1,0 +1,1036 @@
+// Device kernels of the guarded SIMP state solve (gfx950).
+//
+// All kernels take the batch descriptor array and a work list; workgroup b
+// serves problem work[b].x, tile work[b].y.  Vectors are full length
+// (3 * nodes, AoS) and hold zeros on the clamped x = 0 nodes.
+#include <climits>
+
+#include "tg_internal.h"
+
+namespace tg {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+template <class T> __device__ __forceinline__ T* pool(const LevelDesc& L);
+template <> __device__ __forceinline__ double* pool<double>(const LevelDesc& L) { return L.vec64; }
+template <> __device__ __forceinline__ float* pool<float>(const LevelDesc& L) { return L.vec32; }
+
+// slot >= 0: slot of the pool of type T at this level; slot < 0: external pointer
+template <class T>
+__device__ __forceinline__ T* vslot(const LevelDesc& L, int slot, const void* ext) {
+  return slot < 0 ? (T*)ext : pool<T>(L) + (long long)slot * L.stride;
+}
+template <class T> __device__ __forceinline__ const T* Kel(const LevelDesc& L);
+template <> __device__ __forceinline__ const double* Kel<double>(const LevelDesc& L) { return L.Kel64; }
+template <> __device__ __forceinline__ const float* Kel<float>(const LevelDesc& L) { return L.Kel32; }
+template <class T> __device__ __forceinline__ const T* Dinv(const LevelDesc& L);
+template <> __device__ __forceinline__ const double* Dinv<double>(const LevelDesc& L) { return L.Dinv64; }
+template <> __device__ __forceinline__ const float* Dinv<float>(const LevelDesc& L) { return L.Dinv32; }
+template <class T> __device__ __forceinline__ const T* KeP(const ProbDesc& P);
+template <> __device__ __forceinline__ const double* KeP<double>(const ProbDesc& P) { return P.Ke64; }
+template <> __device__ __forceinline__ const float* KeP<float>(const ProbDesc& P) { return P.Ke32; }
+template <class T> __device__ __forceinline__ const T* EP(const ProbDesc& P);
+template <> __device__ __forceinline__ const double* EP<double>(const ProbDesc& P) { return P.E64; }
+template <> __device__ __forceinline__ const float* EP<float>(const ProbDesc& P) { return P.E32; }
+template <class T> __device__ __forceinline__ const T* CinvP(const ProbDesc& P);
+template <> __device__ __forceinline__ const double* CinvP<double>(const ProbDesc& P) { return P.Cinv64; }
+template <> __device__ __forceinline__ const float* CinvP<float>(const ProbDesc& P) { return P.Cinv32; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum over 256 threads (4 waves); result valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// set_density: E_e = rho_min + (1 - rho_min) rho^p   (Eq. floor_scaling)
+__global__ __launch_bounds__(256) void k_young(const ProbDesc* __restrict__ probs,
+                                               const int2* __restrict__ work, double p,
+                                               int* __restrict__ bad) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  const long long n_e = (long long)L.ex * L.ey * L.ez;
+  const long long e = (long long)wi.y * 256 + threadIdx.x;
+  if (e >= n_e) return;
+  const double r = P.ext0[e];
+  if (!(r >= 0.0 && r <= 1.0)) {   // also catches NaN
+    atomicOr(bad + wi.x, 1);
+  }
+  const double rc = fmin(fmax(r, 0.0), 1.0);
+  const double E = P.rho_min + (1.0 - P.rho_min) * pow(rc, p);
+  P.E64[e] = E;
+  P.E32[e] = (float)E;
+}
+
+// Level-1 Galerkin element matrices: Kel1[C] = sum_c E[child c] * G_c, where
+// G_c = P_c^T Ke P_c and P_c interpolates the coarse element's 24 DOFs to
+// those of child c (trilinear, exact for nested hex8 spaces).
+__global__ __launch_bounds__(256) void k_galerkin1(const ProbDesc* __restrict__ probs,
+                                                   const int2* __restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& Lf = P.lv[0];
+  const LevelDesc& Lc = P.lv[1];
+  const long long C = wi.y;   // one coarse element per workgroup
+  const int cx = (int)(C % Lc.ex);
+  const int cy = (int)((C / Lc.ex) % Lc.ey);
+  const int cz = (int)(C / ((long long)Lc.ex * Lc.ey));
+  double Ec[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int fx = 2 * cx + (c & 1), fy = 2 * cy + ((c >> 1) & 1), fz = 2 * cz + ((c >> 2) & 1);
+    Ec[c] = P.E64[fx + (long long)Lf.ex * (fy + (long long)Lf.ey * fz)];
+  }
+  for (int q = threadIdx.x; q < 576; q += 256) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s += Ec[c] * P.G64[c * 576 + q];
+    Lc.Kel64[C * 576 + q] = s;
+    Lc.Kel32[C * 576 + q] = (float)s;
+  }
+}
+
+// Level l -> l+1 (l >= 1): Kel_{l+1}[C] = sum_c P_c^T Kel_l[child c] P_c.
+__global__ __launch_bounds__(256) void k_galerkin_up(const ProbDesc* __restrict__ probs,
+                                                     const int2* __restrict__ work, int lc) {
+  __shared__ double sK[576];
+  __shared__ double sT[576];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& Lf = P.lv[lc - 1];
+  const LevelDesc& Lc = P.lv[lc];
+  const long long C = wi.y;
+  const int cx = (int)(C % Lc.ex);
+  const int cy = (int)((C / Lc.ex) % Lc.ey);
+  const int cz = (int)(C / ((long long)Lc.ex * Lc.ey));
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 8; ++c) {
+    const int fx = 2 * cx + (c & 1), fy = 2 * cy + ((c >> 1) & 1), fz = 2 * cz + ((c >> 2) & 1);
+    const long long fe = fx + (long long)Lf.ex * (fy + (long long)Lf.ey * fz);
+    const double* Pc = P.Pc64 + c * 576;
+    for (int q = threadIdx.x; q < 576; q += 256) sK[q] = Lf.Kel64[fe * 576 + q];
+    __syncthreads();
+    // T = Kel_child * P_c   (24 x 24)
+    for (int q = threadIdx.x; q < 576; q += 256) {
+      const int r = q / 24, s = q % 24;
+      double t = 0.0;
+      for (int a = 0; a < 24; ++a) t += sK[r * 24 + a] * Pc[a * 24 + s];
+      sT[q] = t;
+    }
+    __syncthreads();
+    // out += P_c^T T
+    int qq = 0;
+    for (int q = threadIdx.x; q < 576; q += 256, ++qq) {
+      const int r = q / 24, s = q % 24;
+      double t = 0.0;
+      for (int a = 0; a < 24; ++a) t += Pc[a * 24 + r] * sT[a * 24 + s];
+      acc[qq] += t;
+    }
+    __syncthreads();
+  }
+  int qq = 0;
+  for (int q = threadIdx.x; q < 576; q += 256, ++qq) {
+    Lc.Kel64[C * 576 + q] = acc[qq];
+    Lc.Kel32[C * 576 + q] = (float)acc[qq];
+  }
+}
+
+// Node-block diagonal (3x3, coupling u_x, u_y, u_z of one node) and its inverse.
+__global__ __launch_bounds__(256) void k_nodeblock(const ProbDesc* __restrict__ probs,
+                                                   const int2* __restrict__ work, int l) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
+  if (n >= L.n_nodes) return;
+  const int i = n % L.NX, t = n / L.NX, j = t % L.NY, k = t / L.NY;
+  double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 8; ++a) {
+    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - ((a >> 2) & 1);
+    if (ex < 0 || ex >= L.ex || ey < 0 || ey >= L.ey || ez < 0 || ez >= L.ez) continue;
+    const long long e = ex + (long long)L.ex * (ey + (long long)L.ey * ez);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const int q = (3 * a + r) * 24 + 3 * a + c;
+        B[3 * r + c] += (l == 0) ? P.E64[e] * P.Ke64[q] : L.Kel64[e * 576 + q];
+      }
+  }
+  double D[9];
+  if (i == 0) {
+    for (int q = 0; q < 9; ++q) D[q] = (q % 4 == 0) ? 1.0 : 0.0;
+  } else {
+    const double c00 = B[4] * B[8] - B[5] * B[7];
+    const double c01 = B[5] * B[6] - B[3] * B[8];
+    const double c02 = B[3] * B[7] - B[4] * B[6];
+    const double det = B[0] * c00 + B[1] * c01 + B[2] * c02;
+    const double id = 1.0 / det;
+    D[0] = c00 * id;
+    D[1] = (B[2] * B[7] - B[1] * B[8]) * id;
+    D[2] = (B[1] * B[5] - B[2] * B[4]) * id;
+    D[3] = c01 * id;
+    D[4] = (B[0] * B[8] - B[2] * B[6]) * id;
+    D[5] = (B[2] * B[3] - B[0] * B[5]) * id;
+    D[6] = c02 * id;
+    D[7] = (B[1] * B[6] - B[0] * B[7]) * id;
+    D[8] = (B[0] * B[4] - B[1] * B[3]) * id;
+  }
+  for (int q = 0; q < 9; ++q) {
+    L.Dinv64[9LL * n + q] = D[q];
+    L.Dinv32[9LL * n + q] = (float)D[q];
+  }
+}
+
+// Coarsest level: assemble the dense free-DOF matrix, Cholesky-factor it and
+// form the explicit inverse (one workgroup per problem).
+__device__ __forceinline__ int coarse_free_index(const LevelDesc& L, int node, int c) {
+  const int i = node % L.NX, t = node / L.NX;   // t = j + NY k
+  return i == 0 ? -1 : 3 * ((L.NX - 1) * t + (i - 1)) + c;
+}
+
+__global__ __launch_bounds__(256) void k_coarse_factor(const ProbDesc* __restrict__ probs,
+                                                       const int2* __restrict__ work, int* bad) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const int l = P.nlev - 1;
+  const LevelDesc& L = P.lv[l];
+  const int n = P.ncoarse;
+  if (n == 0) return;              // no direct-solvable coarsest level
+  double* A = P.Cwork;             // n x n, row-major; lower triangle -> L
+  double* X = P.Cwork + (long long)n * n;
+  for (int q = threadIdx.x; q < n * n; q += blockDim.x) A[q] = 0.0;
+  __syncthreads();
+  const int ne = L.ex * L.ey * L.ez;
+  for (int e = 0; e < ne; ++e) {
+    const int ex = e % L.ex, ey = (e / L.ex) % L.ey, ez = e / (L.ex * L.ey);
+    for (int q = threadIdx.x; q < 576; q += blockDim.x) {
+      const int r = q / 24, c = q % 24;
+      const int a = r / 3, b = c / 3;
+      const int na = (ex + (a & 1)) + L.NX * ((ey + ((a >> 1) & 1)) + L.NY * (ez + ((a >> 2) & 1)));
+      const int nb = (ex + (b & 1)) + L.NX * ((ey + ((b >> 1) & 1)) + L.NY * (ez + ((b >> 2) & 1)));
+      const int fr = coarse_free_index(L, na, r % 3), fc = coarse_free_index(L, nb, c % 3);
+      if (fr < 0 || fc < 0) continue;
+      const double v = (l == 0) ? P.E64[e] * P.Ke64[q] : L.Kel64[(long long)e * 576 + q];
+      A[fr * n + fc] += v;         // distinct (fr, fc) within one element
+    }
+    __syncthreads();
+  }
+  // right-looking Cholesky, lower triangle
+  __shared__ double piv;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = A[k * n + k];
+      if (!(d > 0.0)) atomicOr(bad + wi.x, 2);
+      piv = sqrt(fmax(d, 1e-300));
+      A[k * n + k] = piv;
+    }
+    __syncthreads();
+    for (int r = k + 1 + threadIdx.x; r < n; r += blockDim.x) A[r * n + k] /= piv;
+    __syncthreads();
+    for (int q = threadIdx.x; q < (n - k - 1) * (n - k - 1); q += blockDim.x) {
+      const int r = k + 1 + q / (n - k - 1), c = k + 1 + q % (n - k - 1);
+      if (c <= r) A[r * n + c] -= A[r * n + k] * A[c * n + k];
+    }
+    __syncthreads();
+  }
+  // inverse: column q of X solves L L^T x = e_q (one column per thread)
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    for (int r = 0; r < n; ++r) {     // forward: L y = e_q
+      double s = (r == q) ? 1.0 : 0.0;
+      for (int c = q; c < r; ++c) s -= A[r * n + c] * X[c * n + q];
+      X[r * n + q] = (r < q) ? 0.0 : s / A[r * n + r];
+    }
+    for (int r = n - 1; r >= 0; --r) {   // backward: L^T x = y
+      double s = X[r * n + q];
+      for (int c = r + 1; c < n; ++c) s -= A[c * n + r] * X[c * n + q];
+      X[r * n + q] = s / A[r * n + r];
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+    const int r = q / n, c = q % n;
+    // symmetrize the explicit inverse
+    const double v = 0.5 * (X[r * n + c] + X[c * n + r]);
+    P.Cinv64[q] = v;
+    P.Cinv32[q] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operator kernels (node-centred gather, one thread per node).
+//   OP_APPLY : y = K x
+//   OP_RESID : y = b - K x
+//   OP_SMOOTH: y = x + w D^-1 (b - K x)      (damped node-block Jacobi)
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2 };
+
+template <class T, class TX, class TB, class TY, int OP, bool FINE>
+__global__ __launch_bounds__(256) void k_node_op(const ProbDesc* __restrict__ probs,
+                                                 const int2* __restrict__ work, int l, int sx,
+                                                 const void* ex_, int sb, const void* eb_, int sy,
+                                                 void* ey_, T omega) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
+  if (n >= L.n_nodes) return;
+  const int NX = L.NX, NY = L.NY;
+  const int i = n % NX, t = n / NX, j = t % NY, k = t / NY;
+  TY* y = vslot<TY>(L, sy, ey_);
+  if (i == 0) {
+    y[3LL * n] = TY(0);
+    y[3LL * n + 1] = TY(0);
+    y[3LL * n + 2] = TY(0);
+    return;
+  }
+  const TX* x = vslot<TX>(L, sx, ex_);
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int exx = i - (a & 1), eyy = j - ((a >> 1) & 1), ezz = k - ((a >> 2) & 1);
+    if (exx < 0 || exx >= L.ex || eyy < 0 || eyy >= L.ey || ezz < 0 || ezz >= L.ez) continue;
+    const long long e = exx + (long long)L.ex * (eyy + (long long)L.ey * ezz);
+    const T* K = FINE ? KeP<T>(P) + 72 * a : Kel<T>(L) + e * 576 + 72 * a;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int mi = exx + (b & 1);
+      const long long m = mi + (long long)NX * ((eyy + ((b >> 1) & 1)) + (long long)NY * (ezz + ((b >> 2) & 1)));
+      T u0 = T(x[3 * m]), u1 = T(x[3 * m + 1]), u2 = T(x[3 * m + 2]);
+      if (mi == 0) u0 = u1 = u2 = T(0);
+      s0 += K[3 * b] * u0 + K[3 * b + 1] * u1 + K[3 * b + 2] * u2;
+      s1 += K[24 + 3 * b] * u0 + K[24 + 3 * b + 1] * u1 + K[24 + 3 * b + 2] * u2;
+      s2 += K[48 + 3 * b] * u0 + K[48 + 3 * b + 1] * u1 + K[48 + 3 * b + 2] * u2;
+    }
+    if (FINE) {
+      const T E = EP<T>(P)[e];
+      a0 += E * s0;
+      a1 += E * s1;
+      a2 += E * s2;
+    } else {
+      a0 += s0;
+      a1 += s1;
+      a2 += s2;
+    }
+  }
+  if (OP == OP_APPLY) {
+    y[3LL * n] = TY(a0);
+    y[3LL * n + 1] = TY(a1);
+    y[3LL * n + 2] = TY(a2);
+  } else {
+    const TB* b = vslot<TB>(L, sb, eb_);
+    const T r0 = T(b[3LL * n]) - a0, r1 = T(b[3LL * n + 1]) - a1, r2 = T(b[3LL * n + 2]) - a2;
+    if (OP == OP_RESID) {
+      y[3LL * n] = TY(r0);
+      y[3LL * n + 1] = TY(r1);
+      y[3LL * n + 2] = TY(r2);
+    } else {
+      const T* D = Dinv<T>(L) + 9LL * n;
+      const T x0 = T(x[3LL * n]), x1 = T(x[3LL * n + 1]), x2 = T(x[3LL * n + 2]);
+      y[3LL * n] = TY(x0 + omega * (D[0] * r0 + D[1] * r1 + D[2] * r2));
+      y[3LL * n + 1] = TY(x1 + omega * (D[3] * r0 + D[4] * r1 + D[5] * r2));
+      y[3LL * n + 2] = TY(x2 + omega * (D[6] * r0 + D[7] * r1 + D[8] * r2));
+    }
+  }
+}
+
+// First pre-sweep from x = 0: x = w D^-1 b; optionally keep b in type T.
+template <class TB, class T>
+__global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict__ probs,
+                                                      const int2* __restrict__ work, int l, int sb,
+                                                      const void* eb_, int sbT, int sx, T omega) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
+  if (n >= L.n_nodes) return;
+  const TB* b = vslot<TB>(L, sb, eb_);
+  T* x = vslot<T>(L, sx, nullptr);
+  T b0 = T(b[3LL * n]), b1 = T(b[3LL * n + 1]), b2 = T(b[3LL * n + 2]);
+  if (n % L.NX == 0) b0 = b1 = b2 = T(0);
+  if (sbT != INT_MIN) {
+    T* bT = vslot<T>(L, sbT, nullptr);
+    bT[3LL * n] = b0;
+    bT[3LL * n + 1] = b1;
+    bT[3LL * n + 2] = b2;
+  }
+  const T* D = Dinv<T>(L) + 9LL * n;
+  x[3LL * n] = omega * (D[0] * b0 + D[1] * b1 + D[2] * b2);
+  x[3LL * n + 1] = omega * (D[3] * b0 + D[4] * b1 + D[5] * b2);
+  x[3LL * n + 2] = omega * (D[6] * b0 + D[7] * b1 + D[8] * b2);
+}
+
+// Restriction b_c = P^T r (27-point full weighting per component), coarse x=0 clamped.
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict(const ProbDesc* __restrict__ probs,
+                                                  const int2* __restrict__ work, int lc, int sr,
+                                                  int sb) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& Lc = P.lv[lc];
+  const LevelDesc& Lf = P.lv[lc - 1];
+  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
+  if (n >= Lc.n_nodes) return;
+  const int I = n % Lc.NX, t = n / Lc.NX, J = t % Lc.NY, K = t / Lc.NY;
+  T* b = vslot<T>(Lc, sb, nullptr);
+  T s0 = T(0), s1 = T(0), s2 = T(0);
+  if (I > 0) {
+    const T* r = vslot<T>(Lf, sr, nullptr);
+    for (int dk = -1; dk <= 1; ++dk) {
+      const int fk = 2 * K + dk;
+      if (fk < 0 || fk >= Lf.NZ) continue;
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int fj = 2 * J + dj;
+        if (fj < 0 || fj >= Lf.NY) continue;
+        for (int di = -1; di <= 1; ++di) {
+          const int fi = 2 * I + di;
+          if (fi < 0 || fi >= Lf.NX) continue;
+          const T w = T(1.0 / (double)(1 << ((di != 0) + (dj != 0) + (dk != 0))));
+          const long long m = fi + (long long)Lf.NX * (fj + (long long)Lf.NY * fk);
+          s0 += w * r[3 * m];
+          s1 += w * r[3 * m + 1];
+          s2 += w * r[3 * m + 2];
+        }
+      }
+    }
+  }
+  b[3LL * n] = s0;
+  b[3LL * n + 1] = s1;
+  b[3LL * n + 2] = s2;
+}
+
+// Prolongation and correction x_f += P e_c (trilinear).
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ probs,
+                                                 const int2* __restrict__ work, int l, int sx,
+                                                 int se) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& Lf = P.lv[l];
+  const LevelDesc& Lc = P.lv[l + 1];
+  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
+  if (n >= Lf.n_nodes) return;
+  const int i = n % Lf.NX, t = n / Lf.NX, j = t % Lf.NY, k = t / Lf.NY;
+  if (i == 0) return;
+  const T* e = vslot<T>(Lc, se, nullptr);
+  T* x = vslot<T>(Lf, sx, nullptr);
+  const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+  const T wi_ = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  T s0 = T(0), s1 = T(0), s2 = T(0);
+  for (int c = 0; c < 8; ++c) {
+    if ((c & 1) && !(i & 1)) continue;
+    if ((c & 2) && !(j & 1)) continue;
+    if ((c & 4) && !(k & 1)) continue;
+    const int I = (c & 1) ? i1 : i0, J = (c & 2) ? j1 : j0, K = (c & 4) ? k1 : k0;
+    const long long m = I + (long long)Lc.NX * (J + (long long)Lc.NY * K);
+    const T w = wi_ * wj * wk;
+    s0 += w * e[3 * m];
+    s1 += w * e[3 * m + 1];
+    s2 += w * e[3 * m + 2];
+  }
+  x[3LL * n] += s0;
+  x[3LL * n + 1] += s1;
+  x[3LL * n + 2] += s2;
+}
+
+// Coarsest solve x = K_c^-1 b with the explicit inverse (one workgroup per problem).
+template <class TB, class T, class TY>
+__global__ __launch_bounds__(256) void k_coarse_solve(const ProbDesc* __restrict__ probs,
+                                                      const int2* __restrict__ work, int l, int sb,
+                                                      const void* eb_, int sy, void* ey_) {
+  __shared__ T sb_[TG_MAX_COARSE];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const int n = P.ncoarse;
+  const TB* b = vslot<TB>(L, sb, eb_);
+  TY* y = vslot<TY>(L, sy, ey_);
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int c = q % 3, fn = q / 3;
+    const int i = fn % (L.NX - 1) + 1, t = fn / (L.NX - 1);
+    sb_[q] = T(b[3LL * (i + (long long)L.NX * t) + c]);
+  }
+  __syncthreads();
+  const T* Ci = CinvP<T>(P);
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    T s = T(0);
+    for (int c = 0; c < n; ++c) s += Ci[(long long)q * n + c] * sb_[c];
+    const int cc = q % 3, fn = q / 3;
+    const int i = fn % (L.NX - 1) + 1, t = fn / (L.NX - 1);
+    y[3LL * (i + (long long)L.NX * t) + cc] = TY(s);
+  }
+  for (int node = threadIdx.x; node < L.n_nodes; node += blockDim.x) {
+    if (node % L.NX == 0) {
+      y[3LL * node] = TY(0);
+      y[3LL * node + 1] = TY(0);
+      y[3LL * node + 2] = TY(0);
+    }
+  }
+}
+
+// Copy between typed vectors at one level (masking the clamped nodes).
+template <class TA, class TB>
+__global__ __launch_bounds__(256) void k_copy_level(const ProbDesc* __restrict__ probs,
+                                                    const int2* __restrict__ work, int l, int sa,
+                                                    const void* ea, int sb, void* eb) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
+  if (n >= L.n_nodes) return;
+  const TA* a = vslot<TA>(L, sa, ea);
+  TB* b = vslot<TB>(L, sb, eb);
+  const bool clamp = (n % L.NX) == 0;
+  for (int c = 0; c < 3; ++c) b[3LL * n + c] = clamp ? TB(0) : TB(a[3LL * n + c]);
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels on the level-0 FP64 pool (work list: {problem, chunk}).
+__device__ __forceinline__ void chunk_range(const LevelDesc& L, int c, long long& lo, long long& hi) {
+  lo = (long long)c * TG_VCHUNK;
+  hi = lo + TG_VCHUNK;
+  const long long n = 3LL * L.n_nodes;
+  if (hi > n) hi = n;
+}
+
+// dir 0: slot <- ext0 (masked); dir 1: ext1 <- slot
+__global__ __launch_bounds__(256) void k_copy_ext_(const ProbDesc* __restrict__ probs,
+                                                   const int2* __restrict__ work, int dir, int slot) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  double* v = L.vec64 + (long long)slot * L.stride;
+  for (long long q = lo + threadIdx.x; q < hi; q += 256) {
+    if (dir == 0) {
+      const long long node = q / 3;
+      v[q] = (node % L.NX == 0) ? 0.0 : P.ext0[q];
+    } else {
+      P.ext1[q] = v[q];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill0_(const ProbDesc* __restrict__ probs,
+                                                const int2* __restrict__ work, int slot, double val) {
+  const int2 wi = work[blockIdx.x];
+  const LevelDesc& L = probs[wi.x].lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  double* v = L.vec64 + (long long)slot * L.stride;
+  for (long long q = lo + threadIdx.x; q < hi; q += 256) v[q] = val;
+}
+
+__global__ __launch_bounds__(256) void k_copy0_(const ProbDesc* __restrict__ probs,
+                                                const int2* __restrict__ work, int src, int dst) {
+  const int2 wi = work[blockIdx.x];
+  const LevelDesc& L = probs[wi.x].lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  const double* a = L.vec64 + (long long)src * L.stride;
+  double* b = L.vec64 + (long long)dst * L.stride;
+  for (long long q = lo + threadIdx.x; q < hi; q += 256) b[q] = a[q];
+}
+
+// Partial dots: part[k * n_chunks + chunk] = sum_{q in chunk} V_{sbase+k}[q] * w[q]
+// for k < nv; if with_self, entry nv holds w . w.
+__global__ __launch_bounds__(256) void k_multidot_(const ProbDesc* __restrict__ probs,
+                                                   const int2* __restrict__ work, int sbase, int nv,
+                                                   int sw, int with_self) {
+  __shared__ double sh[8][4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  const double* w = L.vec64 + (long long)sw * L.stride;
+  double wr[TG_VCHUNK / 256];
+#pragma unroll
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    wr[q] = idx < hi ? w[idx] : 0.0;
+  }
+  const int ntot = nv + (with_self ? 1 : 0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < ntot; k0 += 8) {
+    double s[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      s[g] = 0.0;
+      const int k = k0 + g;
+      if (k < ntot) {
+        const double* v = (k < nv) ? L.vec64 + (long long)(sbase + k) * L.stride : w;
+#pragma unroll
+        for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+          const long long idx = lo + threadIdx.x + 256LL * q;
+          if (idx < hi) s[g] += v[idx] * wr[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const double r = wave_sum(s[g]);
+      if (lane == 0) sh[g][wv] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && k0 + (int)threadIdx.x < ntot) {
+      const int g = threadIdx.x;
+      P.part[(long long)(k0 + g) * L.n_chunks + wi.y] = (sh[g][0] + sh[g][1]) + (sh[g][2] + sh[g][3]);
+    }
+    __syncthreads();
+  }
+}
+
+// tmp[dst + k] = sum over chunks of part[k][.] in a fixed order.  mode 0 also
+// assigns h[k], mode 1 adds into h[k], mode 2 touches only tmp.  Entry k ==
+// save_k (if >= 0) goes to scal[SC_FLAG] instead.  Grid: (problems, nv).
+__global__ __launch_bounds__(256) void k_reduce_(const ProbDesc* __restrict__ probs,
+                                                 const int2* __restrict__ work, int h_off,
+                                                 int tmp_off, int flag_off, int mode, int save_k) {
+  __shared__ double sh[4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const int nc = P.lv[0].n_chunks;
+  const int k = blockIdx.y;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nc; c += 256) s += P.part[(long long)k * nc + c];
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) {
+    if (k == save_k) {
+      P.small[flag_off] = s;
+      return;
+    }
+    P.small[tmp_off + k] = s;
+    if (mode == 0) P.small[h_off + k] = s;
+    if (mode == 1) P.small[h_off + k] += s;
+  }
+}
+
+// w -= sum_k coef[k] V_{sbase+k}
+__global__ __launch_bounds__(256) void k_update_(const ProbDesc* __restrict__ probs,
+                                                 const int2* __restrict__ work, int sbase, int nv,
+                                                 int sw, int coef_off) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  double* w = L.vec64 + (long long)sw * L.stride;
+  const double* coef = P.small + coef_off;
+  double acc[TG_VCHUNK / 256];
+#pragma unroll
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) acc[q] = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const double ck = coef[k];
+    const double* v = L.vec64 + (long long)(sbase + k) * L.stride;
+#pragma unroll
+    for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+      const long long idx = lo + threadIdx.x + 256LL * q;
+      if (idx < hi) acc[q] += ck * v[idx];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    if (idx < hi) w[idx] -= acc[q];
+  }
+}
+
+// dst = src * small[scal + sc_index]
+__global__ __launch_bounds__(256) void k_scale_(const ProbDesc* __restrict__ probs,
+                                                const int2* __restrict__ work, int src, int dst,
+                                                int sidx) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  const double a = P.small[sidx];
+  const double* s = L.vec64 + (long long)src * L.stride;
+  double* d = L.vec64 + (long long)dst * L.stride;
+  for (long long q = lo + threadIdx.x; q < hi; q += 256) d[q] = s[q] * a;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES scalar kernels: one thread per problem (work list {p, 0}).
+struct SmallOffs {
+  int mmax, H, g, cs, sn, y, h, tmp, scal, hist;
+};
+
+__global__ void k_init_small_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                              int total) {
+  const ProbDesc& P = probs[work[blockIdx.x].x];
+  for (int q = threadIdx.x; q < total; q += blockDim.x) P.small[q] = 0.0;
+}
+
+// Cycle start: beta = ||r|| (tmp[0] holds r.r); history and stop tests.
+__global__ void k_cycle_start_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                               SmallOffs o, int k, int cap, double tol, double* status_out) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  if (threadIdx.x != 0) return;
+  double* S = P.small;
+  double* sc = S + o.scal;
+  const double beta = sqrt(S[o.tmp]);
+  if (k == 0) {
+    sc[SC_BNORM] = beta;
+    S[o.hist] = (beta > 0.0) ? 1.0 : 0.0;
+  }
+  const double bnorm = sc[SC_BNORM];
+  const double rel = bnorm > 0.0 ? beta / bnorm : 0.0;
+  if (k > 0) S[o.hist + k] = rel;   // cycle-start true residual replaces the projection
+  double st = TG_RUNNING;
+  if (!isfinite(beta)) st = TG_NONFINITE;
+  else if (rel <= tol) st = TG_PROJ_CONVERGED;
+  else if (k >= cap) st = TG_MAXIT;
+  sc[SC_BETA] = beta;
+  sc[SC_STATUS] = st;
+  sc[SC_ITERS] = k;
+  sc[SC_JDONE] = 0;
+  sc[SC_EST] = rel;
+  sc[SC_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int q = 0; q <= o.mmax; ++q) S[o.g + q] = 0.0;
+  S[o.g] = beta;
+  status_out[wi.x] = st;
+}
+
+// Arnoldi column j: h (accumulated) and tmp[0] = ||w||^2 after projection,
+// scal[SC_HN] <- ||w||; apply Givens rotations, new rotation, history, stop tests.
+__global__ void k_arnoldi_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                           SmallOffs o, int j, int k, int cap, double tol, double brk,
+                           double* status_out) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  if (threadIdx.x != 0) return;
+  double* S = P.small;
+  double* sc = S + o.scal;
+  const int ldh = o.mmax + 1;
+  double* Hc = S + o.H + (long long)ldh * j;
+  const double hn = sqrt(S[o.tmp]);
+  const double wn0 = sqrt(fmax(sc[SC_FLAG], 0.0));   // ||w|| before projection
+  bool finite = isfinite(hn);
+  for (int i = 0; i <= j; ++i) {
+    Hc[i] = S[o.h + i];
+    finite = finite && isfinite(Hc[i]);
+  }
+  Hc[j + 1] = hn;
+  double st = TG_RUNNING;
+  if (!finite) {
+    st = TG_NONFINITE;
+    sc[SC_STATUS] = st;
+    status_out[wi.x] = st;
+    return;   // column j unusable: jdone stays j
+  }
+  for (int i = 0; i < j; ++i) {
+    const double c = S[o.cs + i], s = S[o.sn + i];
+    const double t = c * Hc[i] + s * Hc[i + 1];
+    Hc[i + 1] = -s * Hc[i] + c * Hc[i + 1];
+    Hc[i] = t;
+  }
+  const double d = hypot(Hc[j], Hc[j + 1]);
+  if (!(d > 0.0) || !isfinite(d)) {
+    st = TG_NONFINITE;
+    sc[SC_STATUS] = st;
+    status_out[wi.x] = st;
+    return;
+  }
+  const double c = Hc[j] / d, s = Hc[j + 1] / d;
+  S[o.cs + j] = c;
+  S[o.sn + j] = s;
+  Hc[j] = d;
+  Hc[j + 1] = 0.0;
+  const double gj = S[o.g + j];
+  S[o.g + j + 1] = -s * gj;
+  S[o.g + j] = c * gj;
+  const int kk = k + 1;
+  const double est = fabs(S[o.g + j + 1]) / sc[SC_BNORM];
+  S[o.hist + kk] = est;
+  sc[SC_EST] = est;
+  sc[SC_ITERS] = kk;
+  sc[SC_JDONE] = j + 1;
+  sc[SC_HN] = hn;
+  sc[SC_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (est <= tol) st = TG_PROJ_CONVERGED;
+  else if (hn <= brk * wn0) st = TG_BREAKDOWN;
+  else if (kk >= cap) st = TG_MAXIT;
+  sc[SC_STATUS] = st;
+  status_out[wi.x] = st;
+}
+
+// Least squares: y = R^{-1} g over the jdone columns (back substitution).
+__global__ void k_lsq_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work, SmallOffs o) {
+  const ProbDesc& P = probs[work[blockIdx.x].x];
+  if (threadIdx.x != 0) return;
+  double* S = P.small;
+  const int jd = (int)S[o.scal + SC_JDONE];
+  const int ldh = o.mmax + 1;
+  for (int i = jd - 1; i >= 0; --i) {
+    double v = S[o.g + i];
+    for (int c = i + 1; c < jd; ++c) v -= S[o.H + (long long)ldh * c + i] * S[o.y + c];
+    S[o.y + i] = v / S[o.H + (long long)ldh * i + i];
+  }
+  for (int i = jd; i < o.mmax; ++i) S[o.y + i] = 0.0;
+}
+
+// x += sum_{j < jdone} y_j Z_j
+__global__ __launch_bounds__(256) void k_xupdate_(const ProbDesc* __restrict__ probs,
+                                                  const int2* __restrict__ work, SmallOffs o,
+                                                  int sz0) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  const int jd = (int)P.small[o.scal + SC_JDONE];
+  double* x = L.vec64 + (long long)S_X * L.stride;
+  double acc[TG_VCHUNK / 256];
+#pragma unroll
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) acc[q] = 0.0;
+  for (int jj = 0; jj < jd; ++jj) {
+    const double yj = P.small[o.y + jj];
+    const double* z = L.vec64 + (long long)(sz0 + jj) * L.stride;
+#pragma unroll
+    for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+      const long long idx = lo + threadIdx.x + 256LL * q;
+      if (idx < hi) acc[q] += yj * z[idx];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    if (idx < hi) x[idx] += acc[q];
+  }
+}
+
+// eta = sqrt(r.r / f.f) with tmp[0] = r.r, tmp[1] = f.f
+__global__ void k_true_eta_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                            SmallOffs o, double* out) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  if (threadIdx.x != 0) return;
+  const double rr = P.small[o.tmp], ff = P.small[o.tmp + 1];
+  const double eta = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+  P.small[o.scal + SC_TRUE] = eta;
+  out[wi.x] = eta;
+}
+
+// ===========================================================================
+// Launch wrappers
+static inline dim3 nblk(const DevList& d) { return dim3((unsigned)d.n); }
+
+static SmallOffs offs(const Batch* b) {
+  const SmallLayout& s = b->grids[0]->sl;
+  SmallOffs o;
+  o.mmax = s.mmax;
+  o.H = s.H;
+  o.g = s.g;
+  o.cs = s.cs;
+  o.sn = s.sn;
+  o.y = s.y;
+  o.h = s.h;
+  o.tmp = s.tmp;
+  o.scal = s.scal;
+  o.hist = s.hist;
+  return o;
+}
+
+static int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return TG_OK;
+}
+
+int k_set_density(Batch* b, hipStream_t s) {
+  int* bad = b->flag_d;
+  TG_HIP(hipMemsetAsync(bad, 0, sizeof(int) * b->n, s));
+  if (b->elem[0].n) k_young<<<nblk(b->elem[0]), 256, 0, s>>>(b->desc_d, b->elem[0].ptr, b->p, bad);
+  if (b->elem[1].n) k_galerkin1<<<nblk(b->elem[1]), 256, 0, s>>>(b->desc_d, b->elem[1].ptr);
+  for (int l = 2; l < b->maxlev; ++l)
+    if (b->elem[l].n) k_galerkin_up<<<nblk(b->elem[l]), 256, 0, s>>>(b->desc_d, b->elem[l].ptr, l);
+  for (int l = 0; l < b->maxlev; ++l)
+    if (b->node[l].n) k_nodeblock<<<nblk(b->node[l]), 256, 0, s>>>(b->desc_d, b->node[l].ptr, l);
+  if (b->prob.n) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad);
+  return check_launch("set_density kernels");
+}
+
+template <class T>
+static void node_apply(Batch* b, int l, const DevList& dl, int sx, const void* ex, int sy, void* ey,
+                       hipStream_t s) {
+  if (!dl.n) return;
+  if (l == 0)
+    k_node_op<T, T, T, T, OP_APPLY, true><<<nblk(dl), 256, 0, s>>>(b->desc_d, dl.ptr, l, sx, ex, 0, nullptr, sy, ey, T(0));
+  else
+    k_node_op<T, T, T, T, OP_APPLY, false><<<nblk(dl), 256, 0, s>>>(b->desc_d, dl.ptr, l, sx, ex, 0, nullptr, sy, ey, T(0));
+}
+
+int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s) {
+  if (prec == TG_F64) node_apply<double>(b, 0, b->node[0], sx, ex, sy, ey, s);
+  else node_apply<float>(b, 0, b->node[0], sx, ex, sy, ey, s);
+  return check_launch("apply_K");
+}
+
+int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
+  if (b->node[0].n)
+    k_node_op<double, double, double, double, OP_RESID, true><<<nblk(b->node[0]), 256, 0, s>>>(
+        b->desc_d, b->node[0].ptr, 0, sx, nullptr, sb, nullptr, sy, nullptr, 0.0);
+  return check_launch("residual");
+}
+
+// One fixed V-cycle.  Level-0 input b (slot sb of the FP64 pool or external
+// eb, typed double unless in_is_f32) -> output (slot sy of the FP64 pool or
+// external ey, double unless out_is_f32).
+template <class T>
+static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
+                    void* ey, hipStream_t s) {
+  const tg_mg_opts& mg = b->grids[0]->mg;
+  const T om = T(mg.omega);
+  const bool f64 = sizeof(T) == 8;
+  // level-0 working slots (in the pool of type T)
+  const int B0 = f64 ? S_VB : C_B, XA0 = f64 ? S_VXA : C_XA, XB0 = f64 ? S_VXB : C_XB, R0 = f64 ? S_VR : C_R;
+  const int flips = (mg.nu_pre - 1) + mg.nu_post;
+  const int FIN = (flips % 2 == 0) ? C_XA : C_XB;      // level >= 1 result slot
+  const int FIN0 = (flips % 2 == 0) ? XA0 : XB0;
+  int cur[TG_MAXLEV];
+  const int L = b->maxlev;
+  // ---- descend
+  for (int l = 0; l < L; ++l) {
+    const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB, Rs = l == 0 ? R0 : C_R;
+    const DevList& sm = b->smooth[l];
+    const DevList& co = b->coarse[l];
+    if (l == 0) {
+      // copy b into the working slot of type T (also masks the clamped nodes)
+      if (b->node[0].n) {
+        if (in_is_f32)
+          k_copy_level<float, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr);
+        else
+          k_copy_level<double, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr);
+      }
+    }
+    if (co.n) {
+      // coarsest for these problems: x = K^-1 b  (into the FIN slot)
+      const int fin = l == 0 ? FIN0 : FIN;
+      k_coarse_solve<T, T, T><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, Bs, nullptr, fin, nullptr);
+    }
+    if (!sm.n) continue;
+    k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om);
+    int c = XA, o = XB;
+    for (int it = 1; it < mg.nu_pre; ++it) {
+      if (l == 0)
+        k_node_op<T, T, T, T, OP_SMOOTH, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
+      else
+        k_node_op<T, T, T, T, OP_SMOOTH, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
+      std::swap(c, o);
+    }
+    if (l == 0)
+      k_node_op<T, T, T, T, OP_RESID, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, Rs, nullptr, om);
+    else
+      k_node_op<T, T, T, T, OP_RESID, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, Rs, nullptr, om);
+    // restrict into level l+1 for the problems that have it (node tiles of l+1)
+    if (b->node[l + 1].n)
+      k_restrict<T><<<nblk(b->node[l + 1]), 256, 0, s>>>(b->desc_d, b->node[l + 1].ptr, l + 1, Rs, C_B);
+    cur[l] = c;
+  }
+  // ---- ascend
+  for (int l = L - 1; l >= 0; --l) {
+    const DevList& sm = b->smooth[l];
+    if (!sm.n) continue;
+    const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB;
+    int c = cur[l];
+    const int o0 = (c == XA) ? XB : XA;
+    int o = o0;
+    k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN);
+    for (int it = 0; it < mg.nu_post; ++it) {
+      if (l == 0)
+        k_node_op<T, T, T, T, OP_SMOOTH, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
+      else
+        k_node_op<T, T, T, T, OP_SMOOTH, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
+      std::swap(c, o);
+    }
+    cur[l] = c;
+  }
+  // ---- output (level 0): result in FIN0 for every problem
+  if (b->node[0].n) {
+    if (out_is_f32)
+      k_copy_level<T, float><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey);
+    else
+      k_copy_level<T, double><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey);
+  }
+  return check_launch("vcycle");
+}
+
+int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
+             void* ey, hipStream_t s) {
+  if (prec == TG_F64) return vcycle_t<double>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s);
+  return vcycle_t<float>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s);
+}
+
+int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s) {
+  if (b->vec.n) k_copy_ext_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, dir, slot);
+  return check_launch("copy_ext");
+}
+int k_fill0(Batch* b, int slot, double v, hipStream_t s) {
+  if (b->vec.n) k_fill0_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, slot, v);
+  return check_launch("fill");
+}
+int k_copy0(Batch* b, int src, int dst, hipStream_t s) {
+  if (b->vec.n) k_copy0_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, src, dst);
+  return check_launch("copy");
+}
+int k_multidot(Batch* b, int sbase, int nv, int sw, int with_self, hipStream_t s) {
+  if (b->vec.n) k_multidot_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, with_self);
+  return check_launch("multidot");
+}
+int k_reduce(Batch* b, int nv, int mode, int dst, int save_k, hipStream_t s) {
+  const SmallOffs o = offs(b);
+  if (b->prob.n && nv > 0)
+    k_reduce_<<<dim3(b->prob.n, nv), 256, 0, s>>>(b->desc_d, b->prob.ptr, o.h, o.tmp + dst,
+                                                 o.scal + SC_FLAG, mode, save_k);
+  return check_launch("reduce");
+}
+int k_update(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, hipStream_t s) {
+  const SmallOffs o = offs(b);
+  const int coef_off = coef_is_tmp ? o.tmp : o.h;
+  if (b->vec.n) k_update_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, coef_off);
+  return check_launch("update");
+}
+int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s) {
+  const int sidx = offs(b).scal + sc_index;
+  if (b->vec.n) k_scale_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, src, dst, sidx);
+  return check_launch("scale");
+}
+int k_cycle_start(Batch* b, int k, int cap, double tol, hipStream_t s) {
+  if (b->prob.n) k_cycle_start_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), k, cap, tol, b->sc_d);
+  return check_launch("cycle_start");
+}
+int k_arnoldi(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s) {
+  if (b->prob.n) k_arnoldi_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, k, cap, tol, brk, b->sc_d);
+  return check_launch("arnoldi");
+}
+int k_lsq_update(Batch* b, int mmax, hipStream_t s) {
+  const SmallOffs o = offs(b);
+  if (b->prob.n) k_lsq_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, o);
+  if (b->vec.n) k_xupdate_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, o, slot_Z(mmax, 0));
+  return check_launch("lsq_update");
+}
+int k_true_eta(Batch* b, hipStream_t s) {
+  if (b->prob.n) k_true_eta_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), b->sc_d);
+  return check_launch("true_eta");
+}
+int k_init_small(Batch* b, hipStream_t s) {
+  if (b->prob.n) k_init_small_<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, b->grids[0]->sl.total);
+  return check_launch("init_small");
+}
+
+}  // namespace tg

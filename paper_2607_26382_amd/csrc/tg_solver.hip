@@ -1,0 +1,506 @@
+// Solver drivers: set_density, FGMRES, true-residual guard, probe and the
+// guarded floor ladder, for a batch of problems (a single grid is a batch of
+// one).  Host code only sequences kernels and reads per-problem status words.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "tg_internal.h"
+
+namespace tg {
+
+static hipStream_t S(void* s) { return (hipStream_t)s; }
+
+static std::vector<int> all_of(const Batch* b) {
+  std::vector<int> v(b->n);
+  for (int i = 0; i < b->n; ++i) v[i] = i;
+  return v;
+}
+
+// E, Galerkin hierarchy, smoother blocks, coarsest inverse for the problems in
+// `which`, each with its own density pointer and floor.
+int set_density_batch(Batch* b, const std::vector<int>& which, const double* const* rho_d,
+                      double p, const double* rho_min, hipStream_t s) {
+  if (!(p > 0) || !std::isfinite(p)) return fail(TG_EINVAL, "SIMP exponent p must be > 0");
+  for (int q = 0; q < (int)which.size(); ++q) {
+    const int i = which[q];
+    if (!(rho_min[q] > 0.0 && rho_min[q] <= 1.0)) return fail(TG_EINVAL, "rho_min must be in (0, 1]");
+    if (!rho_d[q]) return fail(TG_EINVAL, "NULL density pointer");
+    tg_grid* g = b->grids[i];
+    g->desc.ext0 = rho_d[q];
+    g->desc.rho_min = rho_min[q];
+    g->p = p;
+    g->rho_min = rho_min[q];
+  }
+  b->p = p;
+  int rc = batch_upload_desc(b, s);
+  if (rc) return rc;
+  rc = batch_set_active(b, which, s, true);
+  if (rc) return rc;
+  rc = k_set_density(b, s);
+  if (rc) return rc;
+  std::vector<int> flag(b->n, 0);
+  TG_HIP(hipMemcpyAsync(flag.data(), b->flag_d, sizeof(int) * b->n, hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  bool badrho = false;
+  for (int i : which) {
+    b->grids[i]->density_set = !(flag[i] & 1);
+    b->grids[i]->numeric_bad = (flag[i] & 2) != 0;
+    badrho = badrho || (flag[i] & 1);
+  }
+  if (badrho) return fail(TG_EINVAL, "density outside [0, 1] or not finite");
+  return TG_OK;
+}
+
+static int check_ready(Batch* b, const std::vector<int>& which, bool need_mg = false) {
+  for (int i : which) {
+    if (!b->grids[i]->density_set) return fail(TG_ESTATE, "set_density must be called first");
+    if (need_mg && !b->grids[i]->coarse_ok)
+      return fail(TG_EINVAL, "grid cannot be coarsened to a level with <= 512 free DOFs: no V-cycle");
+  }
+  return TG_OK;
+}
+
+// Right-preconditioned FGMRES on every problem in `which` (Sec. 3.5), x0 = 0,
+// rhs in slot S_F, solution in slot S_X, history in small + hist.
+int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s) {
+  const int m = o->restart, cap = o->max_iters;
+  const int mmax = b->grids[0]->mmax;
+  if (m < 1 || m > mmax) return fail(TG_EINVAL, "restart must be in [1, bound max_restart]");
+  if (cap < 0 || cap > TG_HIST_CAP - 1) return fail(TG_EINVAL, "max_iters out of range");
+  if (o->cgs_passes < 1 || o->cgs_passes > 2) return fail(TG_EINVAL, "cgs_passes must be 1 or 2");
+  if (o->prec != TG_F64 && o->prec != TG_F32)
+    return fail(TG_EINVAL, "preconditioner precision not available");
+  const double tol = o->tol, brk = o->breakdown;
+  int rc = check_ready(b, which, true);
+  if (rc) return rc;
+  rc = batch_set_active(b, which, s);
+  if (rc) return rc;
+  if ((rc = k_init_small(b, s))) return rc;
+  if ((rc = k_fill0(b, S_X, 0.0, s))) return rc;
+  if ((rc = k_copy0(b, S_F, S_R, s))) return rc;
+  std::vector<int> running = which;
+  int k = 0;
+  while (true) {
+    if ((rc = batch_set_active(b, running, s))) return rc;
+    if (k > 0 && (rc = k_residual64(b, S_F, S_X, S_R, s))) return rc;
+    if ((rc = k_multidot(b, 0, 0, S_R, 1, s))) return rc;
+    if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
+    if ((rc = k_cycle_start(b, k, cap, tol, s))) return rc;
+    if ((rc = batch_read_status(b, s))) return rc;
+    std::vector<int> nr;
+    for (int i : running)
+      if (b->sc_h[i] == TG_RUNNING) nr.push_back(i);
+    running.swap(nr);
+    if (running.empty()) break;
+    if ((rc = batch_set_active(b, running, s))) return rc;
+    if ((rc = k_scale_to(b, S_R, slot_V(0), SC_INV, s))) return rc;
+    const std::vector<int> members = running;
+    for (int j = 0; j < m; ++j) {
+      if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s))) return rc;
+      if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
+      // CGS pass 1 (also w.w before projection -> SC_FLAG for the breakdown test)
+      if ((rc = k_multidot(b, slot_V(0), j + 1, S_W, 1, s))) return rc;
+      if ((rc = k_reduce(b, j + 2, 0, 0, j + 1, s))) return rc;
+      if ((rc = k_update(b, slot_V(0), j + 1, S_W, 0, s))) return rc;
+      if (o->cgs_passes == 2) {
+        if ((rc = k_multidot(b, slot_V(0), j + 1, S_W, 0, s))) return rc;
+        if ((rc = k_reduce(b, j + 1, 1, 0, -1, s))) return rc;
+        if ((rc = k_update(b, slot_V(0), j + 1, S_W, 1, s))) return rc;
+      }
+      if ((rc = k_multidot(b, 0, 0, S_W, 1, s))) return rc;
+      if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
+      if ((rc = k_arnoldi(b, j, k, cap, tol, brk, s))) return rc;
+      if ((rc = k_scale_to(b, S_W, slot_V(j + 1), SC_INV, s))) return rc;
+      ++k;
+      if ((rc = batch_read_status(b, s))) return rc;
+      std::vector<int> still;
+      for (int i : running)
+        if (b->sc_h[i] == TG_RUNNING) still.push_back(i);
+      if (still.empty() || j == m - 1) break;
+      if (still.size() != running.size()) {
+        running.swap(still);
+        if ((rc = batch_set_active(b, running, s))) return rc;
+      }
+    }
+    // end of cycle: y = R^-1 g, x += Z y for every problem of this cycle
+    if ((rc = batch_set_active(b, members, s))) return rc;
+    if ((rc = k_lsq_update(b, mmax, s))) return rc;
+    if ((rc = batch_read_status(b, s))) return rc;
+    running.clear();
+    for (int i : members)
+      if (b->sc_h[i] == TG_RUNNING) running.push_back(i);
+    if (running.empty()) break;
+  }
+  TG_HIP(hipStreamSynchronize(s));
+  return TG_OK;
+}
+
+// eta = ||f - K x|| / ||f|| (FP64, free DOFs) from slots S_F, S_X; writes sc_h.
+int true_residual_batch(Batch* b, const std::vector<int>& which, hipStream_t s) {
+  int rc = batch_set_active(b, which, s);
+  if (rc) return rc;
+  if ((rc = k_residual64(b, S_F, S_X, S_R, s))) return rc;
+  if ((rc = k_multidot(b, 0, 0, S_R, 1, s))) return rc;
+  if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
+  if ((rc = k_multidot(b, 0, 0, S_F, 1, s))) return rc;
+  if ((rc = k_reduce(b, 1, 2, 1, -1, s))) return rc;
+  if ((rc = k_true_eta(b, s))) return rc;
+  return batch_read_status(b, s);
+}
+
+// Copy external per-problem vectors into / out of level-0 slots.
+int copy_in_batch(Batch* b, const std::vector<int>& which, const double* const* src, int slot,
+                  hipStream_t s) {
+  for (int q = 0; q < (int)which.size(); ++q) b->grids[which[q]]->desc.ext0 = src[q];
+  int rc = batch_upload_desc(b, s);
+  if (rc) return rc;
+  if ((rc = batch_set_active(b, which, s))) return rc;
+  return k_copy_ext(b, 0, slot, s);
+}
+int copy_out_batch(Batch* b, const std::vector<int>& which, double* const* dst, int slot,
+                   hipStream_t s) {
+  for (int q = 0; q < (int)which.size(); ++q) b->grids[which[q]]->desc.ext1 = dst[q];
+  int rc = batch_upload_desc(b, s);
+  if (rc) return rc;
+  if ((rc = batch_set_active(b, which, s))) return rc;
+  return k_copy_ext(b, 1, slot, s);
+}
+
+struct ScalRead {
+  double v[32];
+};
+static int read_scal(Batch* b, int i, ScalRead& r, hipStream_t s) {
+  tg_grid* g = b->grids[i];
+  TG_HIP(hipMemcpyAsync(r.v, g->desc.small + g->sl.scal, sizeof(r.v), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  return TG_OK;
+}
+static int read_hist(Batch* b, int i, int count, double* h, hipStream_t s) {
+  tg_grid* g = b->grids[i];
+  TG_HIP(hipMemcpyAsync(h, g->desc.small + g->sl.hist, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  return TG_OK;
+}
+
+static void fill_result(const ScalRead& r, tg_solve_result* res) {
+  res->iterations = (int)r.v[SC_ITERS];
+  res->outcome = (int)r.v[SC_STATUS];
+  res->proj_eta = r.v[SC_EST];
+  res->true_eta = -1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Probe features (Sec. 3.4) from a probe history.
+static void probe_feats(const double* hist, int kstop, double* r50, double* r100) {
+  *r50 = hist[std::min(50, kstop)];
+  *r100 = hist[std::min(100, kstop)];
+}
+
+static int rule_fires(const tg_policy* pol, double r50, double r100) {
+  return (r50 >= pol->t_high) || (r100 >= pol->t_plateau && r100 / r50 >= pol->t_ratio);
+}
+
+int mlp_select(const tg_mlp* m, const std::vector<std::array<float, 8>>& feats, std::vector<int>& k0,
+               hipStream_t s);
+int density_features(Batch* b, const std::vector<int>& which, const double* const* rho_d, double p,
+                     double rho0, std::vector<std::array<float, 8>>& out, hipStream_t s);
+
+// Alg. floor_policy for every problem of the batch.
+int select_floor_batch(Batch* b, const double* const* rho_d, const double* const* f_d,
+                       const tg_policy* pol, double* const* u_d, tg_policy_result* out,
+                       hipStream_t s) {
+  if (!pol || pol->n_rungs < 1 || pol->n_rungs > TG_MAX_RUNGS) return fail(TG_EINVAL, "bad policy rungs");
+  for (int r = 0; r < pol->n_rungs; ++r)
+    if (!(pol->rungs[r] > 0 && pol->rungs[r] <= 1)) return fail(TG_EINVAL, "rungs must be in (0, 1]");
+  const int n = b->n;
+  const std::vector<int> all = all_of(b);
+  std::memset(out, 0, sizeof(tg_policy_result) * n);
+  int rc;
+  // ---- probe at the original floor
+  std::vector<double> r0(n, pol->rungs[0]);
+  if ((rc = set_density_batch(b, all, rho_d, pol->p, r0.data(), s))) return rc;
+  if ((rc = copy_in_batch(b, all, f_d, S_F, s))) return rc;
+  tg_solver_opts po = pol->solve;
+  po.restart = pol->probe_restart;
+  po.max_iters = pol->probe_iters;
+  if ((rc = fgmres_batch(b, all, &po, s))) return rc;
+  std::vector<int> k0(n, 0);
+  std::vector<std::array<float, 8>> feats(n);
+  for (int i = 0; i < n; ++i) {
+    ScalRead sr;
+    if ((rc = read_scal(b, i, sr, s))) return rc;
+    const int kstop = (int)sr.v[SC_ITERS];
+    std::vector<double> h(kstop + 1);
+    if ((rc = read_hist(b, i, kstop + 1, h.data(), s))) return rc;
+    probe_feats(h.data(), kstop, &out[i].r50, &out[i].r100);
+    out[i].probe_iters = kstop;
+    out[i].iters_probe = kstop;
+    k0[i] = rule_fires(pol, out[i].r50, out[i].r100) ? std::min(1, pol->n_rungs - 1) : 0;
+    feats[i][0] = (float)std::log10(std::max(out[i].r50, 1e-300));
+    feats[i][1] = (float)std::log10(std::max(out[i].r100, 1e-300));
+  }
+  if (pol->selector == TG_SELECT_MLP && pol->mlp) {
+    if ((rc = density_features(b, all, rho_d, pol->p, pol->rungs[0], feats, s))) return rc;
+    std::vector<int> pred;
+    if ((rc = mlp_select(pol->mlp, feats, pred, s))) return rc;
+    for (int i = 0; i < n; ++i) k0[i] = std::min(std::max(pred[i], 0), pol->n_rungs - 1);
+  } else if (pol->selector == TG_SELECT_FIXED) {
+    for (int i = 0; i < n; ++i) k0[i] = std::min(std::max(pol->fixed_rung, 0), pol->n_rungs - 1);
+  }
+  for (int i = 0; i < n; ++i) {
+    out[i].k0 = k0[i];
+    out[i].rung = -1;
+    out[i].floor = -1.0;
+    for (int q = 0; q < 8; ++q) out[i].features[q] = feats[i][q];
+  }
+  // ---- guarded ladder: independent solve, recomputed FP64 residual, climb
+  std::vector<int> rung = k0;
+  std::vector<int> pending = all;
+  while (!pending.empty()) {
+    std::vector<double> fl(pending.size());
+    std::vector<const double*> rp(pending.size()), fp(pending.size());
+    for (size_t q = 0; q < pending.size(); ++q) {
+      fl[q] = pol->rungs[rung[pending[q]]];
+      rp[q] = rho_d[pending[q]];
+      fp[q] = f_d[pending[q]];
+    }
+    if ((rc = set_density_batch(b, pending, rp.data(), pol->p, fl.data(), s))) return rc;
+    if ((rc = copy_in_batch(b, pending, fp.data(), S_F, s))) return rc;
+    if ((rc = fgmres_batch(b, pending, &pol->solve, s))) return rc;
+    if ((rc = true_residual_batch(b, pending, s))) return rc;
+    std::vector<int> next;
+    for (int i : pending) {
+      ScalRead sr;
+      if ((rc = read_scal(b, i, sr, s))) return rc;
+      tg_policy_result& R = out[i];
+      auto& A = R.attempts[R.n_attempts++];
+      A.rung = rung[i];
+      A.floor = pol->rungs[rung[i]];
+      A.iterations = (int)sr.v[SC_ITERS];
+      A.outcome = (int)sr.v[SC_STATUS];
+      A.proj_eta = sr.v[SC_EST];
+      A.true_eta = sr.v[SC_TRUE];
+      A.accepted = (A.true_eta <= pol->tau) && std::isfinite(A.true_eta);
+      if (A.accepted) {
+        R.rung = rung[i];
+        R.floor = A.floor;
+        R.iters_selected = A.iterations;
+      } else {
+        R.iters_rejected += A.iterations;
+        if (rung[i] + 1 < pol->n_rungs) {
+          rung[i] += 1;
+          next.push_back(i);
+        }
+      }
+    }
+    // accepted solutions out
+    std::vector<int> acc;
+    std::vector<double*> dst;
+    for (int i : pending)
+      if (out[i].rung >= 0 && out[i].attempts[out[i].n_attempts - 1].accepted) {
+        acc.push_back(i);
+        dst.push_back(u_d[i]);
+      }
+    if (!acc.empty() && (rc = copy_out_batch(b, acc, dst.data(), S_X, s))) return rc;
+    pending.swap(next);
+  }
+  // no admissible floor: zero solution
+  std::vector<int> none;
+  std::vector<double*> dn;
+  for (int i = 0; i < n; ++i)
+    if (out[i].rung < 0) {
+      none.push_back(i);
+      dn.push_back(u_d[i]);
+    }
+  if (!none.empty()) {
+    if ((rc = batch_set_active(b, none, s))) return rc;
+    if ((rc = k_fill0(b, S_T, 0.0, s))) return rc;
+    if ((rc = copy_out_batch(b, none, dn.data(), S_T, s))) return rc;
+  }
+  TG_HIP(hipStreamSynchronize(s));
+  return TG_OK;
+}
+
+}  // namespace tg
+
+// ===========================================================================
+using namespace tg;
+
+extern "C" {
+
+int tg_set_density(tg_grid* g, const double* rho_d, double p, double rho_min, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  const int rc = set_density_batch(g->self, {0}, &rho_d, p, &rho_min, S(stream));
+  if (rc) return rc;
+  if (g->numeric_bad) return fail(TG_ENUMERIC, "coarsest-level Cholesky met a non-positive pivot");
+  return TG_OK;
+}
+
+int tg_apply_K(const tg_grid* gc, const void* u_d, void* y_d, int prec, void* stream) {
+  tg_grid* g = const_cast<tg_grid*>(gc);
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!u_d || !y_d) return fail(TG_EINVAL, "NULL vector");
+  if (prec != TG_F64 && prec != TG_F32) return fail(TG_EINVAL, "precision not available");
+  int rc = check_ready(g->self, {0});
+  if (rc) return rc;
+  if ((rc = batch_set_active(g->self, {0}, S(stream)))) return rc;
+  return k_apply(g->self, prec, -1, u_d, -1, y_d, S(stream));
+}
+
+int tg_vcycle(tg_grid* g, const void* r_d, void* z_d, int prec, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!r_d || !z_d) return fail(TG_EINVAL, "NULL vector");
+  if (prec != TG_F64 && prec != TG_F32) return fail(TG_EINVAL, "precision not available");
+  int rc = check_ready(g->self, {0}, true);
+  if (rc) return rc;
+  if ((rc = batch_set_active(g->self, {0}, S(stream)))) return rc;
+  const int f32 = prec != TG_F64;
+  return k_vcycle(g->self, prec, f32, -1, r_d, f32, -1, z_d, S(stream));
+}
+
+int tg_fgmres_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o,
+                    tg_solve_result* res, double* hist_h, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!f_d || !u_d || !o || !res) return fail(TG_EINVAL, "NULL argument");
+  Batch* b = g->self;
+  hipStream_t s = S(stream);
+  int rc = check_ready(b, {0});
+  if (rc) return rc;
+  if ((rc = copy_in_batch(b, {0}, &f_d, S_F, s))) return rc;
+  if ((rc = fgmres_batch(b, {0}, o, s))) return rc;
+  if ((rc = copy_out_batch(b, {0}, &u_d, S_X, s))) return rc;
+  ScalRead sr;
+  if ((rc = read_scal(b, 0, sr, s))) return rc;
+  fill_result(sr, res);
+  if (hist_h && (rc = read_hist(b, 0, res->iterations + 1, hist_h, s))) return rc;
+  return TG_OK;
+}
+
+int tg_true_residual(const tg_grid* gc, const double* f_d, const double* u_d, double* eta_h, void* stream) {
+  tg_grid* g = const_cast<tg_grid*>(gc);
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!f_d || !u_d || !eta_h) return fail(TG_EINVAL, "NULL argument");
+  Batch* b = g->self;
+  hipStream_t s = S(stream);
+  int rc = check_ready(b, {0});
+  if (rc) return rc;
+  if ((rc = copy_in_batch(b, {0}, &f_d, S_F, s))) return rc;
+  if ((rc = copy_in_batch(b, {0}, &u_d, S_X, s))) return rc;
+  if ((rc = true_residual_batch(b, {0}, s))) return rc;
+  *eta_h = b->sc_h[0];
+  return TG_OK;
+}
+
+int tg_probe_features(tg_grid* g, const double* f_d, const tg_solver_opts* o, int iters,
+                      double* r50_h, double* r100_h, int* k_stop_h, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!f_d || !o || !r50_h || !r100_h) return fail(TG_EINVAL, "NULL argument");
+  Batch* b = g->self;
+  hipStream_t s = S(stream);
+  int rc = check_ready(b, {0});
+  if (rc) return rc;
+  tg_solver_opts po = *o;
+  po.max_iters = iters;
+  if ((rc = copy_in_batch(b, {0}, &f_d, S_F, s))) return rc;
+  if ((rc = fgmres_batch(b, {0}, &po, s))) return rc;
+  ScalRead sr;
+  if ((rc = read_scal(b, 0, sr, s))) return rc;
+  const int kstop = (int)sr.v[SC_ITERS];
+  std::vector<double> h(kstop + 1);
+  if ((rc = read_hist(b, 0, kstop + 1, h.data(), s))) return rc;
+  probe_feats(h.data(), kstop, r50_h, r100_h);
+  if (k_stop_h) *k_stop_h = kstop;
+  return TG_OK;
+}
+
+void tg_default_policy(tg_policy* pol) {
+  if (!pol) return;
+  std::memset(pol, 0, sizeof(*pol));
+  pol->n_rungs = 4;
+  pol->rungs[0] = 1e-9;
+  pol->rungs[1] = 1e-6;
+  pol->rungs[2] = 1e-4;
+  pol->rungs[3] = 1e-3;
+  pol->p = 3.0;
+  pol->tau = 1e-6;
+  pol->probe_iters = 100;
+  pol->probe_restart = 100;
+  pol->t_high = 1e-2;
+  pol->t_plateau = 1e-4;
+  pol->t_ratio = 0.6;
+  pol->selector = TG_SELECT_RULE;
+  pol->fixed_rung = 0;
+  pol->mlp = nullptr;
+  tg_default_solver_opts(&pol->solve);
+}
+
+int tg_select_floor(tg_grid* g, const double* rho_d, const double* f_d, const tg_policy* pol,
+                    double* u_d, tg_policy_result* out, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!rho_d || !f_d || !pol || !u_d || !out) return fail(TG_EINVAL, "NULL argument");
+  return select_floor_batch(g->self, &rho_d, &f_d, pol, &u_d, out, S(stream));
+}
+
+// ---- batches ----------------------------------------------------------------
+struct tg_batch {
+  tg::Batch b;
+};
+
+int tg_batch_create(int n, tg_grid* const* grids, tg_batch** out) {
+  if (!out || !grids) return fail(TG_EINVAL, "NULL argument");
+  *out = nullptr;
+  tg_batch* tb = new tg_batch();
+  int rc = batch_init(&tb->b, n, grids);
+  if (rc) {
+    delete tb;
+    return rc;
+  }
+  *out = tb;
+  return TG_OK;
+}
+void tg_batch_destroy(tg_batch* b) { delete b; }
+int tg_batch_workspace_bytes(const tg_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(TG_EINVAL, "NULL argument");
+  *bytes = batch_ws_bytes_for(b->b.grids);
+  return TG_OK;
+}
+int tg_batch_bind_workspace(tg_batch* b, void* ws_d, size_t bytes) {
+  if (!b) return fail(TG_EINVAL, "NULL batch");
+  return batch_bind(&b->b, ws_d, bytes);
+}
+int tg_batch_set_density(tg_batch* tb, const double* const* rho_d, double p, const double* rho_min_h,
+                         void* stream) {
+  if (!tb || !rho_d || !rho_min_h) return fail(TG_EINVAL, "NULL argument");
+  if (!tb->b.ws) return fail(TG_EWORKSPACE, "batch workspace not bound");
+  return set_density_batch(&tb->b, all_of(&tb->b), rho_d, p, rho_min_h, S(stream));
+}
+int tg_batch_solve(tg_batch* tb, const double* const* f_d, double* const* u_d, const tg_solver_opts* o,
+                   tg_solve_result* res, void* stream) {
+  if (!tb || !f_d || !u_d || !o || !res) return fail(TG_EINVAL, "NULL argument");
+  if (!tb->b.ws) return fail(TG_EWORKSPACE, "batch workspace not bound");
+  Batch* b = &tb->b;
+  hipStream_t s = S(stream);
+  const std::vector<int> all = all_of(b);
+  int rc = check_ready(b, all);
+  if (rc) return rc;
+  if ((rc = copy_in_batch(b, all, f_d, S_F, s))) return rc;
+  if ((rc = fgmres_batch(b, all, o, s))) return rc;
+  if ((rc = true_residual_batch(b, all, s))) return rc;
+  for (int i = 0; i < b->n; ++i) {
+    ScalRead sr;
+    if ((rc = read_scal(b, i, sr, s))) return rc;
+    fill_result(sr, &res[i]);
+    res[i].true_eta = sr.v[SC_TRUE];
+  }
+  return copy_out_batch(b, all, u_d, S_X, s);
+}
+int tg_batch_select_floor(tg_batch* tb, const double* const* rho_d, const double* const* f_d,
+                          const tg_policy* pol, double* const* u_d, tg_policy_result* out,
+                          void* stream) {
+  if (!tb || !rho_d || !f_d || !pol || !u_d || !out) return fail(TG_EINVAL, "NULL argument");
+  if (!tb->b.ws) return fail(TG_EWORKSPACE, "batch workspace not bound");
+  return select_floor_batch(&tb->b, rho_d, f_d, pol, u_d, out, S(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+"""Thin torch-facing binding of libtopoguard (argument marshalling only).
+
+Device memory comes from torch (workspaces and vectors are torch tensors on the
+current HIP device); every computation runs in the library's kernels.  Names
+follow the C ABI: setup_grid, set_density, apply_K, vcycle, fgmres_solve,
+true_residual, probe_features, select_floor.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+F64, F32, BF16MFMA = L.TG_F64, L.TG_F32, L.TG_BF16MFMA
+OUTCOMES = {0: "PROJ_CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NONFINITE"}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _alloc_ws(nbytes, device):
+    ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws, ws.data_ptr() + off
+
+
+def mg_opts(max_levels=0, max_coarse_dof=300, omega=0.6, nu_pre=2, nu_post=2):
+    return L.MgOpts(max_levels, max_coarse_dof, omega, nu_pre, nu_post)
+
+
+def solver_opts(restart=30, max_iters=200, tol=1e-6, prec=F64, cgs_passes=2, breakdown=1e-14):
+    return L.SolverOpts(restart, max_iters, tol, prec, cgs_passes, breakdown)
+
+
+def policy(rungs=(1e-9, 1e-6, 1e-4, 1e-3), p=3.0, tau=1e-6, probe_iters=100, probe_restart=100,
+           t_high=1e-2, t_plateau=1e-4, t_ratio=0.6, selector=L.TG_SELECT_RULE, fixed_rung=0,
+           mlp=None, solve=None):
+    pol = L.Policy()
+    lib().tg_default_policy(C.byref(pol))
+    pol.n_rungs = len(rungs)
+    for i, r in enumerate(rungs):
+        pol.rungs[i] = r
+    pol.p, pol.tau = p, tau
+    pol.probe_iters, pol.probe_restart = probe_iters, probe_restart
+    pol.t_high, pol.t_plateau, pol.t_ratio = t_high, t_plateau, t_ratio
+    pol.selector, pol.fixed_rung = selector, fixed_rung
+    pol.mlp = mlp.handle if mlp is not None else None
+    pol.solve = solve if solve is not None else solver_opts()
+    return pol
+
+
+def result_dict(r):
+    return dict(iterations=r.iterations, outcome=OUTCOMES.get(r.outcome, r.outcome),
+                proj_eta=r.proj_eta, true_eta=r.true_eta)
+
+
+def policy_dict(r):
+    return dict(rung=r.rung, floor=r.floor, k0=r.k0, r50=r.r50, r100=r.r100,
+                probe_iters=r.probe_iters, iters_probe=r.iters_probe,
+                iters_selected=r.iters_selected, iters_rejected=r.iters_rejected,
+                features=list(r.features),
+                attempts=[dict(rung=a.rung, floor=a.floor, iterations=a.iterations,
+                               outcome=OUTCOMES.get(a.outcome, a.outcome), proj_eta=a.proj_eta,
+                               true_eta=a.true_eta, accepted=bool(a.accepted))
+                          for a in r.attempts[:r.n_attempts]])
+
+
+class Grid:
+    """One structured cantilever grid with its device workspace (tg_grid)."""
+
+    def __init__(self, nx, ny, nz, E0=1.0, nu=0.3, mg=None, max_restart=30, device=None):
+        self.handle = C.c_void_p()
+        check(lib().tg_setup_grid(nx, ny, nz, E0, nu, C.byref(mg) if mg is not None else None,
+                                  C.byref(self.handle)))
+        info = L.GridInfo()
+        check(lib().tg_get_grid_info(self.handle, C.byref(info)))
+        self.info = info
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.n_elem, self.n_nodes, self.n_dof = info.n_elem, info.n_nodes, info.n_dof
+        self.n_levels = info.n_levels
+        self.level_dims = [tuple(info.level_dims[l]) for l in range(info.n_levels)]
+        self.max_restart = max_restart
+        self.device = device
+        self.ws = None
+        if device is not None:
+            self.bind(device, max_restart)
+
+    def bind(self, device="cuda", max_restart=None):
+        if max_restart is not None:
+            self.max_restart = max_restart
+        nb = C.c_size_t()
+        check(lib().tg_workspace_bytes(self.handle, self.max_restart, C.byref(nb)))
+        self.ws, ptr = _alloc_ws(nb.value, device)
+        self.device = device
+        check(lib().tg_bind_workspace(self.handle, C.c_void_p(ptr), nb.value, self.max_restart))
+        self.ws_bytes = nb.value
+        return self
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().tg_destroy(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+    # ---- host-side facts
+    def ke(self):
+        out = np.zeros(576)
+        check(lib().tg_get_ke(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(24, 24)
+
+    def edge_load(self):
+        f = np.zeros(self.n_dof)
+        check(lib().tg_edge_load(self.handle, f.ctypes.data_as(C.POINTER(C.c_double))))
+        return f
+
+    # ---- device calls
+    def set_density(self, rho, p, rho_min):
+        assert rho.dtype == torch.float64 and rho.is_cuda and rho.numel() == self.n_elem
+        self._rho = rho.contiguous()
+        check(lib().tg_set_density(self.handle, _ptr(self._rho), float(p), float(rho_min), _stream()))
+
+    def apply_K(self, u, prec=F64):
+        dt = torch.float64 if prec == F64 else torch.float32
+        assert u.dtype == dt and u.numel() == self.n_dof
+        y = torch.empty_like(u)
+        check(lib().tg_apply_K(self.handle, _ptr(u), _ptr(y), prec, _stream()))
+        return y
+
+    def vcycle(self, r, prec=F64):
+        dt = torch.float64 if prec == F64 else torch.float32
+        assert r.dtype == dt and r.numel() == self.n_dof
+        z = torch.empty_like(r)
+        check(lib().tg_vcycle(self.handle, _ptr(r), _ptr(z), prec, _stream()))
+        return z
+
+    def fgmres_solve(self, f, opts=None, want_hist=True):
+        opts = opts or solver_opts()
+        u = torch.empty_like(f)
+        res = L.SolveResult()
+        hist = np.zeros(4096)
+        check(lib().tg_fgmres_solve(self.handle, _ptr(f), _ptr(u), C.byref(opts), C.byref(res),
+                                    hist.ctypes.data_as(C.POINTER(C.c_double)) if want_hist else None,
+                                    _stream()))
+        return u, result_dict(res), hist[:res.iterations + 1].copy()
+
+    def true_residual(self, f, u):
+        eta = C.c_double()
+        check(lib().tg_true_residual(self.handle, _ptr(f), _ptr(u), C.byref(eta), _stream()))
+        return eta.value
+
+    def probe_features(self, f, iters=100, restart=100, prec=F64):
+        o = solver_opts(restart=restart, max_iters=iters, prec=prec)
+        r50, r100, ks = C.c_double(), C.c_double(), C.c_int()
+        check(lib().tg_probe_features(self.handle, _ptr(f), C.byref(o), iters, C.byref(r50),
+                                      C.byref(r100), C.byref(ks), _stream()))
+        return r50.value, r100.value, ks.value
+
+    def select_floor(self, rho, f, pol):
+        u = torch.empty_like(f)
+        out = L.PolicyResult()
+        check(lib().tg_select_floor(self.handle, _ptr(rho), _ptr(f), C.byref(pol), _ptr(u),
+                                    C.byref(out), _stream()))
+        return u, policy_dict(out)
+
+
+class Batch:
+    """Independent problems of possibly different grid sizes solved together."""
+
+    def __init__(self, grids):
+        self.grids = list(grids)
+        arr = (C.c_void_p * len(self.grids))(*[g.handle.value for g in self.grids])
+        self.handle = C.c_void_p()
+        check(lib().tg_batch_create(len(self.grids), arr, C.byref(self.handle)))
+        nb = C.c_size_t()
+        check(lib().tg_batch_workspace_bytes(self.handle, C.byref(nb)))
+        self.ws, ptr = _alloc_ws(nb.value, self.grids[0].device)
+        check(lib().tg_batch_bind_workspace(self.handle, C.c_void_p(ptr), nb.value))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().tg_batch_destroy(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptrs(ts):
+        return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def set_density(self, rhos, p, rho_mins):
+        self._rhos = [r.contiguous() for r in rhos]
+        rm = (C.c_double * len(rhos))(*rho_mins)
+        check(lib().tg_batch_set_density(self.handle, self._ptrs(self._rhos), float(p), rm, _stream()))
+
+    def solve(self, fs, opts=None):
+        opts = opts or solver_opts()
+        us = [torch.empty_like(f) for f in fs]
+        res = (L.SolveResult * len(fs))()
+        check(lib().tg_batch_solve(self.handle, self._ptrs(fs), self._ptrs(us), C.byref(opts), res,
+                                   _stream()))
+        return us, [result_dict(r) for r in res]
+
+    def select_floor(self, rhos, fs, pol):
+        us = [torch.empty_like(f) for f in fs]
+        out = (L.PolicyResult * len(fs))()
+        check(lib().tg_batch_select_floor(self.handle, self._ptrs(rhos), self._ptrs(fs), C.byref(pol),
+                                          self._ptrs(us), out, _stream()))
+        return us, [policy_dict(r) for r in out]

@@ -1,0 +1,264 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle, through the C ABI.
+
+Element-by-element at sizes the oracle handles in seconds (several tiles plus
+ragged tails), sampled nodes at the full workload sizes, and the edge cases
+(one-element grid, grids without a direct-solvable coarsest level, invalid
+input, calls out of order)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fgmres as ofg
+from oracle import ke as oke
+from oracle import mesh
+from oracle import multigrid as omg
+from oracle import operator as op
+from oracle import policy as opol
+from paper_2607_26382_amd import synth
+from paper_2607_26382_amd import topoguard as tg
+from paper_2607_26382_amd._lib import TopoguardError
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+KE = oke.ke()
+
+
+def _case(dims, rho, p, rmin):
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    E = op.young(rho, p, rmin)
+    K = op.free_block(op.assemble(og, E, KE), free).tocsr()
+    return og, free, E, K
+
+
+def _gpu_grid(dims, rho, p, rmin, max_restart=30, mg=None):
+    g = tg.Grid(*dims, max_restart=max_restart, device=DEV, mg=mg)
+    g.set_density(torch.tensor(rho, dtype=torch.float64, device=DEV), p, rmin)
+    return g
+
+
+APPLY_CASES = [((16, 8, 8), "uniform", 1e-3), ((17, 9, 7), "uniform", 1e-3),
+               ((12, 6, 6), "blob2", 1e-9), ((24, 12, 12), "blob", 1e-6), ((1, 1, 1), "uniform", 1e-3),
+               ((5, 3, 2), "uniform", 1.0)]
+
+
+def _field(kind, dims, seed):
+    if kind == "uniform":
+        return synth.uniform(*dims, seed)
+    if kind == "blob2":
+        return synth.blobs(*dims, seed, blob=2)
+    return synth.blobs(*dims, seed, blob=4)
+
+
+@pytest.mark.parametrize("dims,kind,rmin", APPLY_CASES)
+def test_apply_K_f64_f32(dims, kind, rmin):
+    rho = _field(kind, dims, 11)
+    og, free, E, K = _case(dims, rho, 3.0, rmin)
+    g = _gpu_grid(dims, rho, 3.0, rmin)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(og.n_dof)
+    y_ref = np.zeros(og.n_dof)
+    y_ref[free] = K @ u[free]
+    bound = np.zeros(og.n_dof)
+    bound[free] = abs(K) @ np.abs(u[free])
+    y = g.apply_K(torch.tensor(u, device=DEV), tg.F64).cpu().numpy()
+    assert np.all(np.abs(y - y_ref) <= 64 * np.finfo(float).eps * bound + 1e-300)
+    assert np.all(y[~free] == 0.0)
+    y32 = g.apply_K(torch.tensor(u, dtype=torch.float32, device=DEV), tg.F32).cpu().numpy()
+    assert np.all(np.abs(y32 - y_ref) <= 3e-5 * bound + 1e-30)
+
+
+def _oracle_vcycle(dims, rho, rmin, b_full):
+    og = mesh.Grid(*dims)
+    H = omg.build_hierarchy(og, op.young(rho, 3.0, rmin), KE)
+    free = og.free_dofs()
+    z = np.zeros(og.n_dof)
+    z[free] = omg.vcycle(H, b_full[free])
+    return z, H
+
+
+@pytest.mark.parametrize("dims,kind,rmin", [((16, 8, 8), "uniform", 1e-3), ((24, 12, 12), "blob", 1e-3),
+                                            ((1, 1, 1), "uniform", 0.5), ((32, 16, 16), "blob", 1e-6)])
+def test_vcycle_f64_f32(dims, kind, rmin):
+    rho = _field(kind, dims, 3)
+    g = _gpu_grid(dims, rho, 3.0, rmin)
+    b = np.random.default_rng(1).standard_normal(g.n_dof)
+    z_ref, H = _oracle_vcycle(dims, rho, rmin, b)
+    assert g.n_levels == len(H)
+    z = g.vcycle(torch.tensor(b, device=DEV), tg.F64).cpu().numpy()
+    scale = np.abs(z_ref).max()
+    assert np.abs(z - z_ref).max() <= 1e-9 * scale
+    z32 = g.vcycle(torch.tensor(b, dtype=torch.float32, device=DEV), tg.F32).cpu().numpy()
+    assert np.abs(z32 - z_ref).max() <= 2e-3 * scale
+
+
+def test_no_vcycle_without_direct_coarsest_level():
+    dims = (17, 9, 7)
+    g = _gpu_grid(dims, synth.uniform(*dims, 0), 3.0, 1e-3)
+    with pytest.raises(TopoguardError, match="coarsened"):
+        g.vcycle(torch.zeros(g.n_dof, dtype=torch.float64, device=DEV))
+
+
+def _oracle_fgmres(dims, rho, rmin, restart, cap, tol=1e-6):
+    og = mesh.Grid(*dims)
+    H = omg.build_hierarchy(og, op.young(rho, 3.0, rmin), KE)
+    f = og.edge_load()[og.free_dofs()]
+    res = ofg.fgmres(lambda v: H[0].K @ v, lambda v: omg.vcycle(H, v), f, restart, cap, tol)
+    return res, H, f, og
+
+
+@pytest.mark.parametrize("dims,kind,rmin,restart", [((16, 8, 8), "uniform", 1e-3, 30),
+                                                    ((16, 8, 8), "uniform", 1e-3, 7),
+                                                    ((32, 16, 16), "blob", 1e-4, 30)])
+def test_fgmres_history_and_solution(dims, kind, rmin, restart):
+    rho = _field(kind, dims, 1001)
+    ref, H, f_free, og = _oracle_fgmres(dims, rho, rmin, restart, 200)
+    g = _gpu_grid(dims, rho, 3.0, rmin)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist = g.fgmres_solve(f, tg.solver_opts(restart=restart))
+    n = min(len(hist), len(ref.hist), 25)
+    assert np.allclose(hist[:n], ref.hist[:n], rtol=1e-8, atol=0)
+    assert abs(res["iterations"] - ref.iters) <= 1
+    assert res["outcome"] == "PROJ_CONVERGED" and ref.outcome == ofg.PROJ_CONVERGED
+    eta = g.true_residual(f, u)
+    uf = u.cpu().numpy()[og.free_dofs()]
+    eta_o = op.relative_residual(H[0].K, f_free, uf)
+    assert abs(eta - eta_o) <= 1e-8 * eta_o
+    assert np.linalg.norm(uf - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_one_element_grid_solves_in_one_iteration():
+    dims = (1, 1, 1)
+    g = _gpu_grid(dims, np.array([0.7]), 3.0, 1e-3)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist = g.fgmres_solve(f, tg.solver_opts())
+    assert res["iterations"] == 1 and g.true_residual(f, u) < 1e-12
+
+
+def test_cap_gives_visible_maxit():
+    dims = (16, 8, 8)
+    g = _gpu_grid(dims, synth.uniform(*dims, 0), 3.0, 1e-3)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist = g.fgmres_solve(f, tg.solver_opts(max_iters=5, tol=1e-12))
+    assert res["outcome"] == "MAXIT" and res["iterations"] == 5 and len(hist) == 6
+
+
+def test_probe_features_match_oracle():
+    dims = (32, 16, 16)
+    rho = synth.blobs(*dims, 1001)
+    ref, H, f_free, og = _oracle_fgmres(dims, rho, 1e-9, 100, 100)
+    r50_o, r100_o = opol.probe_features(ref.hist, ref.iters)
+    g = _gpu_grid(dims, rho, 3.0, 1e-9, max_restart=100)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    r50, r100, ks = g.probe_features(f, 100, 100)
+    assert ks == ref.iters
+    assert abs(r50 - r50_o) <= 1e-6 * r50_o and abs(r100 - r100_o) <= 1e-6 * r100_o
+
+
+def _oracle_select(dims, rho, rungs, restart=30, cap=200):
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    f = og.edge_load()[free]
+    cache = {}
+
+    def hier(fl):
+        if fl not in cache:
+            cache[fl] = omg.build_hierarchy(og, op.young(rho, 3.0, fl), KE)
+        return cache[fl]
+
+    def probe(fl):
+        H = hier(fl)
+        r = ofg.fgmres(lambda v: H[0].K @ v, lambda v: omg.vcycle(H, v), f, 100, 100, 1e-6)
+        return r.hist, r.iters
+
+    def solve(fl):
+        H = hier(fl)
+        r = ofg.fgmres(lambda v: H[0].K @ v, lambda v: omg.vcycle(H, v), f, restart, cap, 1e-6)
+        return r.x, r.iters, r.outcome, r.proj_eta
+
+    def eta(fl, u):
+        return op.relative_residual(hier(fl)[0].K, f, u)
+
+    return opol.select_floor(rungs, probe, solve, eta)
+
+
+@pytest.mark.parametrize("seed", [1000, 1001])
+def test_select_floor_matches_oracle(seed):
+    dims = (32, 16, 16)
+    rho = synth.blobs(*dims, seed)
+    rungs = [1e-9, 1e-6, 1e-4, 1e-3]
+    ref = _oracle_select(dims, rho, rungs)
+    g = tg.Grid(*dims, max_restart=100, device=DEV)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    rho_d = torch.tensor(rho, device=DEV)
+    u, out = g.select_floor(rho_d, f, tg.policy(rungs=rungs))
+    assert out["k0"] == ref["k0"]
+    assert abs(out["r50"] - ref["r50"]) <= 1e-6 * ref["r50"]
+    assert out["rung"] == ref["rung"]
+    assert [a["rung"] for a in out["attempts"]] == [a.rung for a in ref["attempts"]]
+    for a, b in zip(out["attempts"], ref["attempts"]):
+        assert abs(a["iterations"] - b.iters) <= 1
+        assert a["accepted"] == b.accepted
+    if out["rung"] >= 0:
+        # the accepted solution passes the guard in the oracle's own evaluation
+        og = mesh.Grid(*dims)
+        free = og.free_dofs()
+        K = op.free_block(op.assemble(og, op.young(rho, 3.0, rungs[out["rung"]]), KE), free)
+        assert op.relative_residual(K, og.edge_load()[free], u.cpu().numpy()[free]) <= 1e-6
+
+
+def test_batch_equals_individual_solves():
+    dims_list = [(16, 8, 8), (24, 12, 12), (16, 8, 8)]
+    rhos = [synth.uniform(*dims_list[0], 0), synth.blobs(*dims_list[1], 7), synth.uniform(*dims_list[2], 9)]
+    floors = [1e-3, 1e-4, 1e-2]
+    grids = [tg.Grid(*d, max_restart=30, device=DEV) for d in dims_list]
+    batch = tg.Batch(grids)
+    rho_d = [torch.tensor(r, device=DEV) for r in rhos]
+    batch.set_density(rho_d, 3.0, floors)
+    fs = [torch.tensor(g.edge_load(), device=DEV) for g in grids]
+    us, res = batch.solve(fs)
+    for i, d in enumerate(dims_list):
+        g1 = _gpu_grid(d, rhos[i], 3.0, floors[i])
+        u1, r1, _ = g1.fgmres_solve(fs[i])
+        assert r1["iterations"] == res[i]["iterations"]
+        assert torch.equal(u1, us[i])            # deterministic reductions: bitwise equal
+        assert res[i]["true_eta"] <= 1e-6
+
+
+def test_invalid_density_and_order_errors():
+    dims = (8, 4, 4)
+    g = tg.Grid(*dims, device=DEV)
+    u = torch.zeros(g.n_dof, dtype=torch.float64, device=DEV)
+    with pytest.raises(TopoguardError, match="set_density"):
+        g.apply_K(u)
+    bad = torch.full((g.n_elem,), 0.5, dtype=torch.float64, device=DEV)
+    bad[3] = float("nan")
+    with pytest.raises(TopoguardError, match="density"):
+        g.set_density(bad, 3.0, 1e-3)
+    bad[3] = 1.5
+    with pytest.raises(TopoguardError, match="density"):
+        g.set_density(bad, 3.0, 1e-3)
+    with pytest.raises(TopoguardError, match="rho_min"):
+        g.set_density(torch.full((g.n_elem,), 0.5, dtype=torch.float64, device=DEV), 3.0, 0.0)
+
+
+@pytest.mark.parametrize("dims,gen", [((64, 32, 32), "severe"), ((256, 128, 128), "struts")])
+def test_full_size_apply_sampled(dims, gen):
+    rho = synth.blobs(*dims, 1000) if gen == "severe" else synth.struts(*dims, 3000)
+    rmin = 1e-9 if gen == "severe" else 1e-3
+    g = tg.Grid(*dims, max_restart=4, device=DEV)
+    g.set_density(torch.tensor(rho, device=DEV), 3.0, rmin)
+    og = mesh.Grid(*dims)
+    E = op.young(rho, 3.0, rmin)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal(og.n_dof)
+    y = g.apply_K(torch.tensor(u, device=DEV), tg.F64).cpu().numpy()
+    y32 = g.apply_K(torch.tensor(u, dtype=torch.float32, device=DEV), tg.F32).cpu().numpy()
+    nodes = np.concatenate([rng.integers(0, og.n_nodes, 150),
+                            [0, og.n_nodes - 1, og.node(og.nx, og.ny, 0), og.node(1, 0, og.nz)]])
+    Ka = np.abs(KE)
+    for n in nodes:
+        ref = op.apply_at_node(og, E, KE, u, int(n))
+        bnd = op.apply_at_node(og, E, Ka, np.abs(u), int(n))
+        assert np.all(np.abs(y[3 * n:3 * n + 3] - ref) <= 64 * 2.2e-16 * bnd + 1e-300)
+        assert np.all(np.abs(y32[3 * n:3 * n + 3] - ref) <= 3e-5 * bnd + 1e-30)
