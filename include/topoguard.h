@@ -240,6 +240,29 @@ int tg_mlp_forward(const tg_mlp* m, const float* x_d, int B, float* logits_d, vo
 int tg_mlp_train_step(tg_mlp* m, const float* x_d, const int* y_d, int B, float lr,
                       float* loss_h, float* grads_d, void* stream);
 
+/* ---- instrumentation ----------------------------------------------------- */
+/* Kernel-class timer (process-wide): for every class whose bit is set in the
+ * mask given to tg_timer_enable (bit k = class k; 0 disables), each launch is
+ * bracketed by two HIP events on its own stream and its algorithmic HBM bytes
+ * (compulsory reads + writes of the launch, no cache reuse assumed) are
+ * accumulated.  tg_timer_read harvests (synchronizes on) the recorded events.
+ * Instrumentation only: not part of the method. */
+enum {
+  TG_KT_APPLY_F64 = 0,       /* fine-level FP64 operator: Arnoldi K z, residuals, guard */
+  TG_KT_VCYCLE_FINE = 1,     /* fine-level operator kernels inside the V-cycle          */
+  TG_KT_VCYCLE_COARSE = 2,   /* coarse-level operator kernels inside the V-cycle        */
+  TG_KT_TRANSFER = 3,        /* restriction, prolongation, first sweep, coarsest solve  */
+  TG_KT_MULTIDOT = 4,        /* Gram-Schmidt multi-dot partials                         */
+  TG_KT_UPDATE = 5,          /* vector updates (w -= V h, x += Z y, scaling)            */
+  TG_KT_SCALAR = 6,          /* reductions and per-problem scalar kernels               */
+  TG_KT_SETUP = 7,           /* set_density kernels                                     */
+  TG_KT_COUNT = 8
+};
+int tg_timer_enable(int mask);
+int tg_timer_reset(void);
+int tg_timer_read(int kind, double* total_ms, long long* launches, double* bytes);
+const char* tg_timer_name(int kind);
+
 #ifdef __cplusplus
 }
 #endif

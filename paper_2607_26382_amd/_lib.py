@@ -104,7 +104,12 @@ PROTOTYPES = {
     "tg_mlp_get_params": (_I, [_P, C.POINTER(C.c_float), _P]),
     "tg_mlp_forward": (_I, [_P, _P, _I, _P, _P]),
     "tg_mlp_train_step": (_I, [_P, _P, _P, _I, C.c_float, C.POINTER(C.c_float), _P, _P]),
+    "tg_timer_enable": (_I, [_I]),
+    "tg_timer_reset": (_I, []),
+    "tg_timer_read": (_I, [_I, C.POINTER(_D), C.POINTER(C.c_longlong), C.POINTER(_D)]),
+    "tg_timer_name": (C.c_char_p, [_I]),
 }
+TG_KT_COUNT = 8
 
 
 def header_symbols(path=HEADER):

@@ -188,9 +188,15 @@ int k_update(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, hipStream_t s
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s);
 int k_cycle_start(Batch* b, int k, int cap, double tol, hipStream_t s);
 int k_arnoldi(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s);
-int k_lsq_update(Batch* b, int mmax, hipStream_t s);
+int k_lsq_update(Batch* b, int mmax, int jmax, hipStream_t s);
 int k_true_eta(Batch* b, hipStream_t s);       // small[SC_TRUE] from R and F dots
 int k_init_small(Batch* b, hipStream_t s);
+
+// kernel-class timer (tg_timer.hip)
+bool timer_on();
+void* timer_begin(int kind, hipStream_t s);
+void timer_end(void* h, double bytes, hipStream_t s);
+void timer_harvest();
 
 // host helpers (tg_host.cpp)
 void build_ke(double E0, double nu, double* Ke);

@@ -827,7 +827,8 @@ __global__ void k_true_eta_(const ProbDesc* __restrict__ probs, const int2* __re
 }
 
 // ===========================================================================
-// Launch wrappers
+// Launch wrappers.  Each launch of a timed class is bracketed by timer events
+// (when the timer is on) and charged its algorithmic HBM bytes.
 static inline dim3 nblk(const DevList& d) { return dim3((unsigned)d.n); }
 
 static SmallOffs offs(const Batch* b) {
@@ -852,40 +853,93 @@ static int check_launch(const char* what) {
   return TG_OK;
 }
 
+// Sums over the active problems that take part in a level-l launch.
+// mode 0: every problem with level l; 1: l is not its coarsest; 2: l is its coarsest
+static void level_sums(const Batch* b, int l, int mode, double& nodes, double& elems, double& cdof2) {
+  nodes = elems = cdof2 = 0;
+  for (int p : b->active) {
+    const tg_grid* g = b->grids[p];
+    if (l >= g->nlev) continue;
+    if (mode == 1 && l == g->nlev - 1) continue;
+    if (mode == 2 && l != g->nlev - 1) continue;
+    nodes += (double)g->lv[l].n_nodes;
+    elems += (double)g->lv[l].n_elem;
+    cdof2 += (double)g->ncoarse * g->ncoarse;
+  }
+}
+static double dofs0(const Batch* b) {
+  double n = 0;
+  for (int p : b->active) n += 3.0 * b->grids[p]->lv[0].n_nodes;
+  return n;
+}
+
+#define TG_TIMED(kind, bytes_expr, ...)                 \
+  do {                                                  \
+    void* _th = timer_begin((kind), s);                 \
+    __VA_ARGS__;                                        \
+    if (_th) timer_end(_th, (double)(bytes_expr), s);   \
+  } while (0)
+
 int k_set_density(Batch* b, hipStream_t s) {
   int* bad = b->flag_d;
   TG_HIP(hipMemsetAsync(bad, 0, sizeof(int) * b->n, s));
-  if (b->elem[0].n) k_young<<<nblk(b->elem[0]), 256, 0, s>>>(b->desc_d, b->elem[0].ptr, b->p, bad);
-  if (b->elem[1].n) k_galerkin1<<<nblk(b->elem[1]), 256, 0, s>>>(b->desc_d, b->elem[1].ptr);
-  for (int l = 2; l < b->maxlev; ++l)
-    if (b->elem[l].n) k_galerkin_up<<<nblk(b->elem[l]), 256, 0, s>>>(b->desc_d, b->elem[l].ptr, l);
-  for (int l = 0; l < b->maxlev; ++l)
-    if (b->node[l].n) k_nodeblock<<<nblk(b->node[l]), 256, 0, s>>>(b->desc_d, b->node[l].ptr, l);
-  if (b->prob.n) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad);
+  TG_TIMED(TG_KT_SETUP, 0, {
+    if (b->elem[0].n) k_young<<<nblk(b->elem[0]), 256, 0, s>>>(b->desc_d, b->elem[0].ptr, b->p, bad);
+    if (b->elem[1].n) k_galerkin1<<<nblk(b->elem[1]), 256, 0, s>>>(b->desc_d, b->elem[1].ptr);
+    for (int l = 2; l < b->maxlev; ++l)
+      if (b->elem[l].n) k_galerkin_up<<<nblk(b->elem[l]), 256, 0, s>>>(b->desc_d, b->elem[l].ptr, l);
+    for (int l = 0; l < b->maxlev; ++l)
+      if (b->node[l].n) k_nodeblock<<<nblk(b->node[l]), 256, 0, s>>>(b->desc_d, b->node[l].ptr, l);
+    if (b->prob.n) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad);
+  });
   return check_launch("set_density kernels");
 }
 
+// fine-level operator of type T on list dl (mode: 0 apply, 1 resid, 2 smooth)
 template <class T>
-static void node_apply(Batch* b, int l, const DevList& dl, int sx, const void* ex, int sy, void* ey,
-                       hipStream_t s) {
-  if (!dl.n) return;
-  if (l == 0)
-    k_node_op<T, T, T, T, OP_APPLY, true><<<nblk(dl), 256, 0, s>>>(b->desc_d, dl.ptr, l, sx, ex, 0, nullptr, sy, ey, T(0));
-  else
-    k_node_op<T, T, T, T, OP_APPLY, false><<<nblk(dl), 256, 0, s>>>(b->desc_d, dl.ptr, l, sx, ex, 0, nullptr, sy, ey, T(0));
+static double op_bytes(const Batch* b, int l, int lmode, int op) {
+  double nodes, elems, c2;
+  level_sums(b, l, lmode, nodes, elems, c2);
+  const double vec = 3.0 * nodes * sizeof(T);
+  const double mat = (l == 0) ? elems * sizeof(T) : elems * 576.0 * sizeof(T);
+  const double dinv = (op == OP_SMOOTH) ? 9.0 * nodes * sizeof(T) : 0.0;
+  const int nvec = op == OP_APPLY ? 2 : 3;
+  return nvec * vec + mat + dinv;
 }
 
 int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s) {
-  if (prec == TG_F64) node_apply<double>(b, 0, b->node[0], sx, ex, sy, ey, s);
-  else node_apply<float>(b, 0, b->node[0], sx, ex, sy, ey, s);
+  const DevList& dl = b->node[0];
+  if (!dl.n) return TG_OK;
+  if (prec == TG_F64) {
+    TG_TIMED(TG_KT_APPLY_F64, (op_bytes<double>(b, 0, 0, OP_APPLY)),
+             k_node_op<double, double, double, double, OP_APPLY, true><<<nblk(dl), 256, 0, s>>>(
+                 b->desc_d, dl.ptr, 0, sx, ex, 0, nullptr, sy, ey, 0.0));
+  } else {
+    TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<float>(b, 0, 0, OP_APPLY)),
+             k_node_op<float, float, float, float, OP_APPLY, true><<<nblk(dl), 256, 0, s>>>(
+                 b->desc_d, dl.ptr, 0, sx, ex, 0, nullptr, sy, ey, 0.0f));
+  }
   return check_launch("apply_K");
 }
 
 int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
   if (b->node[0].n)
-    k_node_op<double, double, double, double, OP_RESID, true><<<nblk(b->node[0]), 256, 0, s>>>(
-        b->desc_d, b->node[0].ptr, 0, sx, nullptr, sb, nullptr, sy, nullptr, 0.0);
+    TG_TIMED(TG_KT_APPLY_F64, (op_bytes<double>(b, 0, 0, OP_RESID)),
+             k_node_op<double, double, double, double, OP_RESID, true><<<nblk(b->node[0]), 256, 0, s>>>(
+                 b->desc_d, b->node[0].ptr, 0, sx, nullptr, sb, nullptr, sy, nullptr, 0.0));
   return check_launch("residual");
+}
+
+template <class T, int OP>
+static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om, hipStream_t s) {
+  if (l == 0)
+    TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
+             k_node_op<T, T, T, T, OP, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, x, nullptr, bs,
+                                                                       nullptr, y, nullptr, om));
+  else
+    TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
+             k_node_op<T, T, T, T, OP, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, x, nullptr, bs,
+                                                                        nullptr, y, nullptr, om));
 }
 
 // One fixed V-cycle.  Level-0 input b (slot sb of the FP64 pool or external
@@ -897,49 +951,51 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   const tg_mg_opts& mg = b->grids[0]->mg;
   const T om = T(mg.omega);
   const bool f64 = sizeof(T) == 8;
-  // level-0 working slots (in the pool of type T)
   const int B0 = f64 ? S_VB : C_B, XA0 = f64 ? S_VXA : C_XA, XB0 = f64 ? S_VXB : C_XB, R0 = f64 ? S_VR : C_R;
   const int flips = (mg.nu_pre - 1) + mg.nu_post;
   const int FIN = (flips % 2 == 0) ? C_XA : C_XB;      // level >= 1 result slot
   const int FIN0 = (flips % 2 == 0) ? XA0 : XB0;
   int cur[TG_MAXLEV];
   const int L = b->maxlev;
+  double nodes, elems, c2;
+  const double sT = sizeof(T), sIn = in_is_f32 ? 4.0 : 8.0, sOut = out_is_f32 ? 4.0 : 8.0;
   // ---- descend
   for (int l = 0; l < L; ++l) {
     const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB, Rs = l == 0 ? R0 : C_R;
     const DevList& sm = b->smooth[l];
     const DevList& co = b->coarse[l];
-    if (l == 0) {
-      // copy b into the working slot of type T (also masks the clamped nodes)
-      if (b->node[0].n) {
-        if (in_is_f32)
-          k_copy_level<float, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr);
-        else
-          k_copy_level<double, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr);
-      }
+    if (l == 0 && b->node[0].n) {
+      // b into the working slot of type T (also masks the clamped nodes)
+      level_sums(b, 0, 0, nodes, elems, c2);
+      if (in_is_f32)
+        TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sIn + sT),
+                 k_copy_level<float, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr));
+      else
+        TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sIn + sT),
+                 k_copy_level<double, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr));
     }
     if (co.n) {
-      // coarsest for these problems: x = K^-1 b  (into the FIN slot)
       const int fin = l == 0 ? FIN0 : FIN;
-      k_coarse_solve<T, T, T><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, Bs, nullptr, fin, nullptr);
+      level_sums(b, l, 2, nodes, elems, c2);
+      TG_TIMED(TG_KT_TRANSFER, c2 * sT + 6.0 * nodes * sT,
+               k_coarse_solve<T, T, T><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, Bs, nullptr, fin, nullptr));
     }
     if (!sm.n) continue;
-    k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om);
+    level_sums(b, l, 1, nodes, elems, c2);
+    TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 9.0 * nodes * sT,
+             k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om));
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
-      if (l == 0)
-        k_node_op<T, T, T, T, OP_SMOOTH, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
-      else
-        k_node_op<T, T, T, T, OP_SMOOTH, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
+      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s);
       std::swap(c, o);
     }
-    if (l == 0)
-      k_node_op<T, T, T, T, OP_RESID, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, Rs, nullptr, om);
-    else
-      k_node_op<T, T, T, T, OP_RESID, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, Rs, nullptr, om);
-    // restrict into level l+1 for the problems that have it (node tiles of l+1)
-    if (b->node[l + 1].n)
-      k_restrict<T><<<nblk(b->node[l + 1]), 256, 0, s>>>(b->desc_d, b->node[l + 1].ptr, l + 1, Rs, C_B);
+    vc_op<T, OP_RESID>(b, l, sm, c, Bs, Rs, om, s);
+    if (b->node[l + 1].n) {
+      double cn, ce, cc;
+      level_sums(b, l + 1, 0, cn, ce, cc);
+      TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * sT + 3.0 * cn * sT,
+               k_restrict<T><<<nblk(b->node[l + 1]), 256, 0, s>>>(b->desc_d, b->node[l + 1].ptr, l + 1, Rs, C_B));
+    }
     cur[l] = c;
   }
   // ---- ascend
@@ -948,24 +1004,25 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     if (!sm.n) continue;
     const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB;
     int c = cur[l];
-    const int o0 = (c == XA) ? XB : XA;
-    int o = o0;
-    k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN);
+    int o = (c == XA) ? XB : XA;
+    level_sums(b, l, 1, nodes, elems, c2);
+    TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 3.0 * nodes / 8 * sT,
+             k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN));
     for (int it = 0; it < mg.nu_post; ++it) {
-      if (l == 0)
-        k_node_op<T, T, T, T, OP_SMOOTH, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
-      else
-        k_node_op<T, T, T, T, OP_SMOOTH, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, nullptr, Bs, nullptr, o, nullptr, om);
+      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s);
       std::swap(c, o);
     }
     cur[l] = c;
   }
   // ---- output (level 0): result in FIN0 for every problem
   if (b->node[0].n) {
+    level_sums(b, 0, 0, nodes, elems, c2);
     if (out_is_f32)
-      k_copy_level<T, float><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey);
+      TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sOut + sT),
+               k_copy_level<T, float><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey));
     else
-      k_copy_level<T, double><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey);
+      TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sOut + sT),
+               k_copy_level<T, double><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey));
   }
   return check_launch("vcycle");
 }
@@ -977,59 +1034,77 @@ int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_
 }
 
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s) {
-  if (b->vec.n) k_copy_ext_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, dir, slot);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 16.0 * dofs0(b), k_copy_ext_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, dir, slot));
   return check_launch("copy_ext");
 }
 int k_fill0(Batch* b, int slot, double v, hipStream_t s) {
-  if (b->vec.n) k_fill0_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, slot, v);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 8.0 * dofs0(b), k_fill0_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, slot, v));
   return check_launch("fill");
 }
 int k_copy0(Batch* b, int src, int dst, hipStream_t s) {
-  if (b->vec.n) k_copy0_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, src, dst);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 16.0 * dofs0(b), k_copy0_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, src, dst));
   return check_launch("copy");
 }
 int k_multidot(Batch* b, int sbase, int nv, int sw, int with_self, hipStream_t s) {
-  if (b->vec.n) k_multidot_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, with_self);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_MULTIDOT, 8.0 * (nv + 1) * dofs0(b),
+             k_multidot_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, with_self));
   return check_launch("multidot");
 }
 int k_reduce(Batch* b, int nv, int mode, int dst, int save_k, hipStream_t s) {
   const SmallOffs o = offs(b);
   if (b->prob.n && nv > 0)
-    k_reduce_<<<dim3(b->prob.n, nv), 256, 0, s>>>(b->desc_d, b->prob.ptr, o.h, o.tmp + dst,
-                                                 o.scal + SC_FLAG, mode, save_k);
+    TG_TIMED(TG_KT_SCALAR, 0,
+             k_reduce_<<<dim3(b->prob.n, nv), 256, 0, s>>>(b->desc_d, b->prob.ptr, o.h, o.tmp + dst,
+                                                          o.scal + SC_FLAG, mode, save_k));
   return check_launch("reduce");
 }
 int k_update(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, hipStream_t s) {
   const SmallOffs o = offs(b);
   const int coef_off = coef_is_tmp ? o.tmp : o.h;
-  if (b->vec.n) k_update_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, coef_off);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 8.0 * (nv + 2) * dofs0(b),
+             k_update_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, coef_off));
   return check_launch("update");
 }
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s) {
   const int sidx = offs(b).scal + sc_index;
-  if (b->vec.n) k_scale_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, src, dst, sidx);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 16.0 * dofs0(b), k_scale_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, src, dst, sidx));
   return check_launch("scale");
 }
 int k_cycle_start(Batch* b, int k, int cap, double tol, hipStream_t s) {
-  if (b->prob.n) k_cycle_start_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), k, cap, tol, b->sc_d);
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0,
+             k_cycle_start_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), k, cap, tol, b->sc_d));
   return check_launch("cycle_start");
 }
 int k_arnoldi(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s) {
-  if (b->prob.n) k_arnoldi_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, k, cap, tol, brk, b->sc_d);
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0,
+             k_arnoldi_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, k, cap, tol, brk, b->sc_d));
   return check_launch("arnoldi");
 }
-int k_lsq_update(Batch* b, int mmax, hipStream_t s) {
+int k_lsq_update(Batch* b, int mmax, int jmax, hipStream_t s) {
   const SmallOffs o = offs(b);
-  if (b->prob.n) k_lsq_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, o);
-  if (b->vec.n) k_xupdate_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, o, slot_Z(mmax, 0));
+  if (b->prob.n) TG_TIMED(TG_KT_SCALAR, 0, k_lsq_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, o));
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 8.0 * (jmax + 2) * dofs0(b),
+             k_xupdate_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, o, slot_Z(mmax, 0)));
   return check_launch("lsq_update");
 }
 int k_true_eta(Batch* b, hipStream_t s) {
-  if (b->prob.n) k_true_eta_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), b->sc_d);
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0, k_true_eta_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), b->sc_d));
   return check_launch("true_eta");
 }
 int k_init_small(Batch* b, hipStream_t s) {
-  if (b->prob.n) k_init_small_<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, b->grids[0]->sl.total);
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0,
+             k_init_small_<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, b->grids[0]->sl.total));
   return check_launch("init_small");
 }
 

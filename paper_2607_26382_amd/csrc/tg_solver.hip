@@ -96,7 +96,9 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
     if ((rc = batch_set_active(b, running, s))) return rc;
     if ((rc = k_scale_to(b, S_R, slot_V(0), SC_INV, s))) return rc;
     const std::vector<int> members = running;
+    int jmax = 0;
     for (int j = 0; j < m; ++j) {
+      jmax = j + 1;
       if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s))) return rc;
       if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
       // CGS pass 1 (also w.w before projection -> SC_FLAG for the breakdown test)
@@ -125,7 +127,7 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
     }
     // end of cycle: y = R^-1 g, x += Z y for every problem of this cycle
     if ((rc = batch_set_active(b, members, s))) return rc;
-    if ((rc = k_lsq_update(b, mmax, s))) return rc;
+    if ((rc = k_lsq_update(b, mmax, jmax, s))) return rc;
     if ((rc = batch_read_status(b, s))) return rc;
     running.clear();
     for (int i : members)

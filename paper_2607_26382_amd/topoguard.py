@@ -216,3 +216,43 @@ class Batch:
         check(lib().tg_batch_select_floor(self.handle, self._ptrs(rhos), self._ptrs(fs), C.byref(pol),
                                           self._ptrs(us), out, _stream()))
         return us, [policy_dict(r) for r in out]
+
+
+# ---- kernel-class timer (instrumentation) ----------------------------------
+def kernel_timer_enable(mask=(1 << L.TG_KT_COUNT) - 1):
+    check(lib().tg_timer_enable(int(mask)))
+
+
+def kernel_timer_reset():
+    check(lib().tg_timer_reset())
+
+
+def kernel_timer_read():
+    """{class name: dict(kind, count, ms, bytes, avg_us, gbs)} (harvests events)."""
+    out = {}
+    for k in range(L.TG_KT_COUNT):
+        ms, n, by = C.c_double(), C.c_longlong(), C.c_double()
+        check(lib().tg_timer_read(k, C.byref(ms), C.byref(n), C.byref(by)))
+        name = lib().tg_timer_name(k).decode()
+        avg = 1e3 * ms.value / n.value if n.value else 0.0
+        gbs = by.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else 0.0
+        out[name] = dict(kind=k, count=n.value, ms=ms.value, bytes=by.value, avg_us=avg, gbs=gbs)
+    return out
+
+
+def dominant_kernel(timers):
+    """The byte-accounted class with the largest total time."""
+    cands = [(v["ms"], k) for k, v in timers.items() if v["bytes"] > 0 and v["count"]]
+    return max(cands)[1] if cands else None
+
+
+def roofline_from_timers(timers, hbm_peak_gbs, traffic=None):
+    k = dominant_kernel(timers)
+    if k is None:
+        return None
+    v = timers[k]
+    achieved = v["gbs"]
+    return {"kernel": k, "bound": "hbm", "achieved": achieved, "peak": hbm_peak_gbs, "unit": "GB/s",
+            "frac": achieved / hbm_peak_gbs, "traffic": traffic,
+            "avg_launch_us": v["avg_us"], "launches": v["count"],
+            "alg_bytes_per_launch": v["bytes"] / v["count"]}
