@@ -1,0 +1,473 @@
+// Fine-level operator kernels: z-marching element columns, mode-basis Ke.
+//
+// A workgroup of 16x16 threads owns a 16x16 patch of element columns
+// (ex, ey) = (x0 - 1 + tx, y0 - 1 + ty) and marches over element layers k.
+// Thread (tx, ty) loads node (ex + 1, ey + 1) of every node layer; the other
+// three top-face nodes of its element come from LDS.  Each element's 24
+// outputs are formed in the polynomial-mode basis of the trilinear hex
+// (per component: modes 1, x, y, xy, z, xz, yz, xyz), where Ke of a cube has
+// 45 nonzeros (normal 3x3 block, rank-1 shear pairs, bilinear pairs and a
+// triple, trilinear diagonal): ~205 flops instead of 1152 for the dense 24x24.
+// The bottom-face outputs of layer k and the top-face outputs of layer k-1 are
+// summed in registers, staged in LDS, and node (ex + 1, ey + 1) gathers its
+// four in-plane element contributions: a complete, atomic-free, deterministic
+// K u at node layer k, fused with the residual or the damped node-block Jacobi
+// update.  Output nodes: 15 x 15 columns per workgroup, ZC node layers.
+#include <cmath>
+#include <cstring>
+
+#include "tg_internal.h"
+
+namespace tg {
+
+enum { FOP_APPLY = 0, FOP_RESID = 1, FOP_SMOOTH = 2 };
+
+// In-place 8-point transform along the three node-index bits:
+// forward: (v0, v1) -> (v0 + v1, v1 - v0); node index a -> mode index m.
+template <class T>
+__device__ __forceinline__ void wht_fwd(T* v) {
+#pragma unroll
+  for (int b = 1; b < 8; b <<= 1)
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!(a & b)) {
+        const T x0 = v[a], x1 = v[a | b];
+        v[a] = x0 + x1;
+        v[a | b] = x1 - x0;
+      }
+}
+// transpose transform: (b0, b1) -> (b0 - b1, b0 + b1); mode index -> node index
+template <class T>
+__device__ __forceinline__ void wht_inv(T* v) {
+#pragma unroll
+  for (int b = 1; b < 8; b <<= 1)
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!(a & b)) {
+        const T x0 = v[a], x1 = v[a | b];
+        v[a] = x0 - x1;
+        v[a | b] = x0 + x1;
+      }
+}
+
+// Mode-space contraction b = E * (K_H / 64) a on the three component vectors
+// (mode index m: 1 x, 2 y, 3 xy, 4 z, 5 xz, 6 yz, 7 xyz), in place.
+template <class T>
+__device__ __forceinline__ void mode_contract(T* ux, T* uy, T* uz, T E, const ModeCoef<T>& c) {
+  // normal block on (x.x, y.y, z.z) = (ux[1], uy[2], uz[4])
+  const T ns = ux[1] + uy[2] + uz[4];
+  const T dmo = c.d - c.o;
+  const T bxx = dmo * ux[1] + c.o * ns, byy = dmo * uy[2] + c.o * ns, bzz = dmo * uz[4] + c.o * ns;
+  // rank-1 shear pairs (x.y, y.x), (x.z, z.x), (y.z, z.y)
+  const T sxy = c.s * (uy[1] + ux[2]);
+  const T sxz = c.s * (uz[1] + ux[4]);
+  const T syz = c.s * (uz[2] + uy[4]);
+  // bilinear pairs (xy.x, yz.z), (xy.y, xz.z), (xz.x, yz.y)
+  const T p1a = c.p * ux[3] + c.q * uz[6], p1b = c.q * ux[3] + c.p * uz[6];
+  const T p2a = c.p * uy[3] + c.q * uz[5], p2b = c.q * uy[3] + c.p * uz[5];
+  const T p3a = c.p * ux[5] + c.q * uy[6], p3b = c.q * ux[5] + c.p * uy[6];
+  // bilinear triple (xy.z, xz.y, yz.x)
+  const T ts = uz[3] + uy[5] + ux[6];
+  const T rmt = c.r - c.t;
+  const T t1 = rmt * uz[3] + c.t * ts, t2 = rmt * uy[5] + c.t * ts, t3 = rmt * ux[6] + c.t * ts;
+  ux[0] = T(0); uy[0] = T(0); uz[0] = T(0);   // constant modes carry no energy
+  ux[1] = E * bxx; uy[1] = E * sxy; uz[1] = E * sxz;
+  ux[2] = E * sxy; uy[2] = E * byy; uz[2] = E * syz;
+  ux[3] = E * p1a; uy[3] = E * p2a; uz[3] = E * t1;
+  ux[4] = E * sxz; uy[4] = E * syz; uz[4] = E * bzz;
+  ux[5] = E * p3a; uy[5] = E * t2;  uz[5] = E * p2b;
+  ux[6] = E * t3;  uy[6] = E * p3b; uz[6] = E * p1b;
+  const T ew = E * c.w;   // trilinear modes: diagonal
+  ux[7] *= ew; uy[7] *= ew; uz[7] *= ew;
+}
+
+// Restriction of a polynomial-mode vector to a sub-cube: per dimension the
+// coarse coordinate is xi = h xi' + s, so (a0, a1) -> (a0 + s a1, h a1) on the
+// (inactive, active) pair of that dimension; the transpose maps
+// (b0, b1) -> (b0, s b0 + h b1).
+template <class T>
+__device__ __forceinline__ void mode_restrict(const T* v, T* o, T h, T sx, T sy, T sz) {
+#pragma unroll
+  for (int m = 0; m < 8; ++m) o[m] = v[m];
+  const T sd[3] = {sx, sy, sz};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int bit = 1 << b;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+      if (!(m & bit)) {
+        const T a0 = o[m], a1 = o[m | bit];
+        o[m] = a0 + sd[b] * a1;
+        o[m | bit] = h * a1;
+      }
+  }
+}
+template <class T>
+__device__ __forceinline__ void mode_restrict_t_add(T* o, T* acc, T h, T sx, T sy, T sz) {
+  const T sd[3] = {sx, sy, sz};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int bit = 1 << b;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+      if (!(m & bit)) {
+        const T b0 = o[m], b1 = o[m | bit];
+        o[m | bit] = sd[b] * b0 + h * b1;
+      }
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) acc[m] += o[m];
+}
+
+// Fine element: v = E Ke u; ux/uy/uz[a] = component at local node a.
+template <class T>
+__device__ __forceinline__ void elem_fine(T* ux, T* uy, T* uz, T E, const ModeCoef<T>& c) {
+  wht_fwd(ux);
+  wht_fwd(uy);
+  wht_fwd(uz);
+  mode_contract(ux, uy, uz, E, c);
+  wht_inv(ux);
+  wht_inv(uy);
+  wht_inv(uz);
+}
+
+// Galerkin element of level l >= 1 (matrix-free): with T the nodal-to-mode
+// transform and T_d the restriction to fine descendant d,
+//   Kel_l = T^T [ sum_d E_d T_d^T (K_H / 64) T_d ] T,
+// which equals the element-wise Galerkin product P^T ... P^T Ke P ... P of the
+// 2:1 trilinear hierarchy.  Descendant d = (fx, fy, fz) in [0, 2^l)^3 sits at
+// h = 2^-l, s = (2 f + 1) h - 1 per dimension.
+template <class T>
+__device__ __forceinline__ void elem_galerkin(T* ux, T* uy, T* uz, const T* __restrict__ E0, int nx0,
+                                              int ny0, int ex, int ey, int ez, int l,
+                                              const ModeCoef<T>& c) {
+  wht_fwd(ux);
+  wht_fwd(uy);
+  wht_fwd(uz);
+  T ax[8], ay[8], az[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    ax[m] = ux[m];
+    ay[m] = uy[m];
+    az[m] = uz[m];
+    ux[m] = uy[m] = uz[m] = T(0);
+  }
+  const int F = 1 << l;
+  const T h = T(1) / T(F);
+  for (int fz = 0; fz < F; ++fz) {
+    const T sz = T(2 * fz + 1) * h - T(1);
+    for (int fy = 0; fy < F; ++fy) {
+      const T sy = T(2 * fy + 1) * h - T(1);
+      const long long rowb = (long long)nx0 * ((F * ey + fy) + (long long)ny0 * (F * ez + fz)) + F * ex;
+      for (int fx = 0; fx < F; ++fx) {
+        const T sx = T(2 * fx + 1) * h - T(1);
+        const T E = E0[rowb + fx];
+        T bx[8], by[8], bz[8];
+        mode_restrict(ax, bx, h, sx, sy, sz);
+        mode_restrict(ay, by, h, sx, sy, sz);
+        mode_restrict(az, bz, h, sx, sy, sz);
+        mode_contract(bx, by, bz, E, c);
+        mode_restrict_t_add(bx, ux, h, sx, sy, sz);
+        mode_restrict_t_add(by, uy, h, sx, sy, sz);
+        mode_restrict_t_add(bz, uz, h, sx, sy, sz);
+      }
+    }
+  }
+  wht_inv(ux);
+  wht_inv(uy);
+  wht_inv(uz);
+}
+
+template <class T> __device__ __forceinline__ T* fpool(const LevelDesc& L);
+template <> __device__ __forceinline__ double* fpool<double>(const LevelDesc& L) { return L.vec64; }
+template <> __device__ __forceinline__ float* fpool<float>(const LevelDesc& L) { return L.vec32; }
+template <class T> __device__ __forceinline__ const T* fE(const ProbDesc& P);
+template <> __device__ __forceinline__ const double* fE<double>(const ProbDesc& P) { return P.E64; }
+template <> __device__ __forceinline__ const float* fE<float>(const ProbDesc& P) { return P.E32; }
+template <class T> __device__ __forceinline__ const T* fD(const LevelDesc& L);
+template <> __device__ __forceinline__ const double* fD<double>(const LevelDesc& L) { return L.Dinv64; }
+template <> __device__ __forceinline__ const float* fD<float>(const LevelDesc& L) { return L.Dinv32; }
+
+template <class T>
+__device__ __forceinline__ const T* fvec(const LevelDesc& L, int slot, const void* ext) {
+  return slot < 0 ? (const T*)ext : fpool<T>(L) + (long long)slot * L.stride;
+}
+
+#define FZ_TX 16
+#define FZ_OUT 15
+
+// z-tiles per grid: ceil(NZ / 16), balanced heights
+__host__ __device__ __forceinline__ int fz_ntz(int NZ) { return (NZ + 15) / 16; }
+__host__ __device__ __forceinline__ int fz_zc(int NZ) { const int t = fz_ntz(NZ); return (NZ + t - 1) / t; }
+__host__ __device__ __forceinline__ int fz_tiles(int NX, int NY, int NZ) {
+  return ((NX + FZ_OUT - 1) / FZ_OUT) * ((NY + FZ_OUT - 1) / FZ_OUT) * fz_ntz(NZ);
+}
+
+// KIND 0: fine level, element = E_e Ke; KIND 1: matrix-free Galerkin level l.
+template <class T, int OP, int KIND, class TY = T>
+__global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ probs,
+                                                 const int2* __restrict__ work, int l, int sx,
+                                                 const void* ex_, int sb, const void* eb_, int sy,
+                                                 void* ey_, T omega, ModeCoef<T> mc) {
+  // Single buffers suffice: every read of a layer's values happens between the
+  // two barriers of its step, every write of the next layer after them.
+  __shared__ T su[3][17][17];           // node values of the current top layer
+  __shared__ T ss[12][FZ_TX][FZ_TX];    // per element: 4 corners x 3 comps, layer sum
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
+  const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;
+  const int ntx = (NX + FZ_OUT - 1) / FZ_OUT, nty = (NY + FZ_OUT - 1) / FZ_OUT;
+  const int tile = wi.y;
+  const int tiz = tile / (ntx * nty), rem = tile - tiz * ntx * nty;
+  const int tiy = rem / ntx, tix = rem - tiy * ntx;
+  const int zc = fz_zc(NZ);
+  const int x0 = tix * FZ_OUT, y0 = tiy * FZ_OUT, z0 = tiz * zc;
+  const int zend = min(z0 + zc, NZ);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int ex = x0 - 1 + tx, ey = y0 - 1 + ty;         // this thread's element column
+  const int ni = ex + 1, nj = ey + 1;                   // this thread's node column
+  const T* u = fvec<T>(L, sx, ex_);
+  const T* Eg = fE<T>(P);
+  const bool elem_in = (ex >= 0 && ex < nx && ey >= 0 && ey < ny);
+  const bool owner = (tx < FZ_OUT && ty < FZ_OUT && ni < NX && nj < NY);
+  // extra node loads: tile row/column 0 (nodes x0-1 or y0-1)
+  const int xt = threadIdx.x;
+  int exi = -1, exj = -1, etx = 0, ety = 0;
+  if (xt < 17) { etx = 0; ety = xt; exi = x0 - 1; exj = y0 - 1 + xt; }
+  else if (xt < 33) { etx = xt - 16; ety = 0; exi = x0 - 1 + (xt - 16); exj = y0 - 1; }
+
+  auto load_node = [&](int i, int j, int k, T& a, T& b, T& c) {
+    if (i > 0 && i < NX && j >= 0 && j < NY && k >= 0 && k < NZ) {
+      const long long n = i + (long long)NX * (j + (long long)NY * k);
+      a = u[3 * n];
+      b = u[3 * n + 1];
+      c = u[3 * n + 2];
+    } else {
+      a = b = c = T(0);   // outside the grid, or clamped (i == 0)
+    }
+  };
+  auto stage_layer = [&](int k) {
+    T a, b, c;
+    load_node(ni, nj, k, a, b, c);
+    su[0][ty + 1][tx + 1] = a;
+    su[1][ty + 1][tx + 1] = b;
+    su[2][ty + 1][tx + 1] = c;
+    if (xt < 33) {
+      load_node(exi, exj, k, a, b, c);
+      su[0][ety][etx] = a;
+      su[1][ety][etx] = b;
+      su[2][ety][etx] = c;
+    }
+  };
+  // bottom face of the first element layer (node layer z0 - 1)
+  T bx[4], by[4], bz[4];     // bottom-face node values, corner c = di + 2 dj
+  T tpx[4], tpy[4], tpz[4];  // top-face outputs of the previous element layer
+#pragma unroll
+  for (int c = 0; c < 4; ++c) tpx[c] = tpy[c] = tpz[c] = T(0);
+  stage_layer(z0 - 1);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int di = c & 1, dj = c >> 1;
+    bx[c] = su[0][ty + dj][tx + di];
+    by[c] = su[1][ty + dj][tx + di];
+    bz[c] = su[2][ty + dj][tx + di];
+  }
+  __syncthreads();   // prologue reads done before the first layer is staged
+  for (int k = z0 - 1; k < zend; ++k) {
+    stage_layer(k + 1);
+    __syncthreads();
+    T ux[8], uy[8], uz[8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int di = c & 1, dj = c >> 1;
+      ux[c] = bx[c];
+      uy[c] = by[c];
+      uz[c] = bz[c];
+      ux[c + 4] = su[0][ty + dj][tx + di];
+      uy[c + 4] = su[1][ty + dj][tx + di];
+      uz[c + 4] = su[2][ty + dj][tx + di];
+    }
+    // next bottom face = this top face; own node value at layer k for the smoother
+    const T own0 = bx[3], own1 = by[3], own2 = bz[3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      bx[c] = ux[c + 4];
+      by[c] = uy[c + 4];
+      bz[c] = uz[c + 4];
+    }
+    const bool ein = elem_in && k >= 0 && k < nz;
+    if (KIND == 0) {
+      const T E = ein ? Eg[ex + (long long)nx * (ey + (long long)ny * k)] : T(0);
+      elem_fine<T>(ux, uy, uz, E, mc);
+    } else if (ein) {
+      elem_galerkin<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k, l, mc);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) ux[a] = uy[a] = uz[a] = T(0);
+    }
+    // layer-k node contributions: bottom of this element + top of the previous one
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ss[3 * c + 0][ty][tx] = ux[c] + tpx[c];
+      ss[3 * c + 1][ty][tx] = uy[c] + tpy[c];
+      ss[3 * c + 2][ty][tx] = uz[c] + tpz[c];
+      tpx[c] = ux[c + 4];
+      tpy[c] = uy[c + 4];
+      tpz[c] = uz[c + 4];
+    }
+    __syncthreads();
+    if (owner && k >= z0) {
+      // node (ni, nj, k) = corner 3 of element (tx,ty), corner 2 of (tx+1,ty),
+      // corner 1 of (tx,ty+1), corner 0 of (tx+1,ty+1)
+      T a[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        a[q] = (ss[9 + q][ty][tx] + ss[6 + q][ty][tx + 1]) +
+               (ss[3 + q][ty + 1][tx] + ss[0 + q][ty + 1][tx + 1]);
+      const long long n = ni + (long long)NX * (nj + (long long)NY * k);
+      TY* y = (sy < 0 ? (TY*)ey_ : fpool<TY>(L) + (long long)sy * L.stride) + 3 * n;
+      if (ni == 0) {
+        y[0] = y[1] = y[2] = TY(0);
+      } else if (OP == FOP_APPLY) {
+        y[0] = TY(a[0]);
+        y[1] = TY(a[1]);
+        y[2] = TY(a[2]);
+      } else {
+        const T* bb = fvec<T>(L, sb, eb_) + 3 * n;
+        const T r0 = bb[0] - a[0], r1 = bb[1] - a[1], r2 = bb[2] - a[2];
+        if (OP == FOP_RESID) {
+          y[0] = TY(r0);
+          y[1] = TY(r1);
+          y[2] = TY(r2);
+        } else {
+          const T* D = fD<T>(L) + 9 * n;
+          y[0] = TY(own0 + omega * (D[0] * r0 + D[1] * r1 + D[2] * r2));
+          y[1] = TY(own1 + omega * (D[3] * r0 + D[4] * r1 + D[5] * r2));
+          y[2] = TY(own2 + omega * (D[6] * r0 + D[7] * r1 + D[8] * r2));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: mode coefficients from Ke, launches
+// K_H = T Ke T^T with T = kron(H8, I3), H8[m][a] = prod over set bits b of m of
+// (2 a_b - 1).  For a cube the only nonzeros are the 8-coefficient pattern
+// used by elem_mode_apply; anything else is an error.
+int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>* out32) {
+  double H[8][8];
+  for (int m = 0; m < 8; ++m)
+    for (int a = 0; a < 8; ++a) {
+      double v = 1.0;
+      for (int b = 0; b < 3; ++b)
+        if (m & (1 << b)) v *= ((a >> b) & 1) ? 1.0 : -1.0;
+      H[m][a] = v;
+    }
+  double KH[24][24];
+  for (int r = 0; r < 24; ++r)
+    for (int c = 0; c < 24; ++c) {
+      double s = 0.0;
+      const int mr = r / 3, cr = r % 3, mc = c / 3, cc = c % 3;
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) s += H[mr][a] * Ke[(3 * a + cr) * 24 + 3 * b + cc] * H[mc][b];
+      KH[r][c] = s;
+    }
+  auto R = [](int m, int c) { return 3 * m + c; };
+  ModeCoef<double> k;
+  k.d = KH[R(1, 0)][R(1, 0)];
+  k.o = KH[R(1, 0)][R(2, 1)];
+  k.s = KH[R(1, 1)][R(1, 1)];
+  k.p = KH[R(3, 0)][R(3, 0)];
+  k.q = KH[R(3, 0)][R(6, 2)];
+  k.r = KH[R(3, 2)][R(3, 2)];
+  k.t = KH[R(3, 2)][R(5, 1)];
+  k.w = KH[R(7, 0)][R(7, 0)];
+  // rebuild the pattern and compare
+  double P[24][24] = {};
+  const int nrm[3] = {R(1, 0), R(2, 1), R(4, 2)};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[nrm[i]][nrm[j]] = (i == j) ? k.d : k.o;
+  const int sh[3][2] = {{R(1, 1), R(2, 0)}, {R(1, 2), R(4, 0)}, {R(2, 2), R(4, 1)}};
+  for (auto& pr : sh)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) P[pr[i]][pr[j]] = k.s;
+  const int b1[3][2] = {{R(3, 0), R(6, 2)}, {R(3, 1), R(5, 2)}, {R(5, 0), R(6, 1)}};
+  for (auto& pr : b1)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) P[pr[i]][pr[j]] = (i == j) ? k.p : k.q;
+  const int b2[3] = {R(3, 2), R(5, 1), R(6, 0)};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[b2[i]][b2[j]] = (i == j) ? k.r : k.t;
+  for (int c = 0; c < 3; ++c) P[R(7, c)][R(7, c)] = k.w;
+  double mx = 0.0, err = 0.0;
+  for (int r = 0; r < 24; ++r)
+    for (int c = 0; c < 24; ++c) {
+      mx = std::fmax(mx, std::fabs(KH[r][c]));
+      err = std::fmax(err, std::fabs(KH[r][c] - P[r][c]));
+    }
+  if (err > 1e-12 * mx) return fail(TG_EINVAL, "element stiffness does not have the cube mode-basis pattern");
+  const double sc = 1.0 / 64.0;
+  const ModeCoef<double> m64 = {k.d * sc, k.o * sc, k.s * sc, k.p * sc, k.q * sc, k.r * sc, k.t * sc, k.w * sc};
+  *out64 = m64;
+  *out32 = {(float)m64.d, (float)m64.o, (float)m64.s, (float)m64.p,
+            (float)m64.q, (float)m64.r, (float)m64.t, (float)m64.w};
+  return TG_OK;
+}
+
+int fine_tiles(const tg_grid* g) { return zm_tiles(g, 0); }
+int zm_tiles(const tg_grid* g, int l) {
+  return fz_tiles(g->lv[l].ex + 1, g->lv[l].ey + 1, g->lv[l].ez + 1);
+}
+
+template <class T> static ModeCoef<T> mcoef(const tg_grid* g);
+template <> ModeCoef<double> mcoef<double>(const tg_grid* g) { return g->mc64; }
+template <> ModeCoef<float> mcoef<float>(const tg_grid* g) { return g->mc32; }
+
+// OP: 0 apply, 1 residual, 2 smoothing sweep on level l with the z-march
+// kernel (level 0: E Ke; levels 1..TG_MF_LEVELS: matrix-free Galerkin).
+// Every grid of a batch shares one Ke (checked at batch creation).
+template <class T>
+int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
+                const void* eb, int sy, void* ey, double omega, hipStream_t s) {
+  if (!dl.n) return TG_OK;
+  const ModeCoef<T> mc = mcoef<T>(b->grids[0]);
+  const ProbDesc* desc = b->desc_d;
+  const T om = T(omega);
+  if (l == 0) {
+    if (op == FOP_APPLY)
+      k_fine_zm<T, FOP_APPLY, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
+    else if (op == FOP_RESID)
+      k_fine_zm<T, FOP_RESID, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
+    else
+      k_fine_zm<T, FOP_SMOOTH, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
+  } else {
+    if (op == FOP_APPLY)
+      k_fine_zm<T, FOP_APPLY, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
+    else if (op == FOP_RESID)
+      k_fine_zm<T, FOP_RESID, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
+    else
+      k_fine_zm<T, FOP_SMOOTH, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
+  }
+  return TG_OK;
+}
+template int launch_fine<double>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
+                                 int, void*, double, hipStream_t);
+
+// Level-0 smoothing sweep whose output goes to an FP64 slot (the V-cycle's
+// last post-sweep writing the Krylov vector z_j directly).
+int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, int sy, double omega,
+                             hipStream_t s) {
+  if (!dl.n) return TG_OK;
+  const ModeCoef<float> mc = mcoef<float>(b->grids[0]);
+  k_fine_zm<float, FOP_SMOOTH, 0, double><<<dl.n, 256, 0, s>>>(b->desc_d, dl.ptr, 0, sx, nullptr, sb, nullptr,
+                                                               sy, nullptr, float(omega), mc);
+  return TG_OK;
+}
+template int launch_fine<float>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
+                                int, void*, double, hipStream_t);
+
+}  // namespace tg

@@ -136,6 +136,8 @@ static size_t list_capacity(const std::vector<tg_grid*>& gs) {
       c += (l == 0) ? (g->lv[0].n_elem + 255) / 256 : g->lv[l].n_elem;
     }
     c += g->lv[0].n_chunks + 1;
+    for (int l = 0; l < g->nlev; ++l) c += zm_tiles(g, l);
+    c += fine_tiles(g);
   }
   return c;
 }
@@ -205,6 +207,8 @@ int batch_init(Batch* b, int n, tg_grid* const* grids) {
     if (!g || !g->bound) return fail(TG_ESTATE, "every grid of a batch needs a bound workspace");
     if (g->mmax != b->grids[0]->mmax)
       return fail(TG_EINVAL, "grids of one batch must be bound with the same max_restart");
+    if (std::memcmp(g->Ke, b->grids[0]->Ke, sizeof(g->Ke)) != 0)
+      return fail(TG_EINVAL, "grids of one batch must share E0 and nu (one element stiffness)");
     if (g->mg.omega != b->grids[0]->mg.omega || g->mg.nu_pre != b->grids[0]->mg.nu_pre ||
         g->mg.nu_post != b->grids[0]->mg.nu_post)
       return fail(TG_EINVAL, "grids of one batch must share the smoother options");
@@ -284,6 +288,18 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   o = begin();
   for (int p : active) H.push_back(make_int2(p, 0));
   finish(b->prob, o);
+  o = begin();
+  for (int p : active)
+    for (int t = 0, nt = fine_tiles(b->grids[p]); t < nt; ++t) H.push_back(make_int2(p, t));
+  finish(b->fine, o);
+  for (int l = 0; l < TG_MAXLEV; ++l) {
+    o = begin();
+    if (l <= TG_MF_LEVELS)
+      for (int p : active)
+        if (l < b->grids[p]->nlev - 1)
+          for (int t = 0, nt = zm_tiles(b->grids[p], l); t < nt; ++t) H.push_back(make_int2(p, t));
+    finish(b->zm_s[l], o);
+  }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");
   if (!H.empty())
     TG_HIP(hipMemcpyAsync(b->list_d, H.data(), H.size() * sizeof(int2), hipMemcpyHostToDevice, s));
@@ -357,6 +373,13 @@ int grid_setup(int nx, int ny, int nz, double E0, double nu, const tg_mg_opts* m
   g->ncoarse = g->coarse_ok ? cfree : 0;
   g->ncoarse_true = cfree;
   build_ke(E0, nu, g->Ke);
+  {
+    const int rc = mode_coef_from_ke(g->Ke, &g->mc64, &g->mc32);
+    if (rc) {
+      delete g;
+      return rc;
+    }
+  }
   build_child_prolong(g->Pc);
   build_child_galerkin(g->Ke, g->Pc, g->G);
   *out = g;

@@ -22,6 +22,7 @@
 #define TG_PART_W 128        // max vectors in one multi-dot
 #define TG_MAX_COARSE 512    // max free DOFs of the coarsest level
 #define TG_HIST_CAP 4096     // residual-history capacity per problem
+#define TG_MF_LEVELS 1       // levels 1..TG_MF_LEVELS apply the Galerkin operator matrix-free
 
 namespace tg {
 
@@ -104,6 +105,13 @@ enum { SC_BNORM = 0, SC_BETA = 1, SC_HN = 2, SC_STATUS = 3, SC_ITERS = 4, SC_JDO
        SC_EST = 6, SC_TRUE = 7, SC_INV = 8, SC_FLAG = 9 };
 #define TG_RUNNING (-1.0)
 
+// Ke of a cube in the per-component polynomial-mode basis has 8 distinct
+// coefficients (values divided by 64, the squared norm of a mode vector).
+template <class T>
+struct ModeCoef {
+  T d, o, s, p, q, r, t, w;
+};
+
 struct LevelHost {
   int ex, ey, ez;
   long long n_elem, n_nodes, n_dof, stride;
@@ -124,6 +132,8 @@ struct tg_grid {
   int ncoarse_true = 0;
   bool coarse_ok = true;
   double Ke[576];
+  tg::ModeCoef<double> mc64;
+  tg::ModeCoef<float> mc32;
   double G[8 * 576];
   double Pc[8 * 576];
   // workspace
@@ -162,6 +172,8 @@ struct Batch {
   size_t ws_bytes = 0;
   std::vector<int> active;
   DevList node[TG_MAXLEV], smooth[TG_MAXLEV], coarse[TG_MAXLEV], elem[TG_MAXLEV], vec, prob;
+  DevList fine;                   // level-0 z-march tiles, all problems
+  DevList zm_s[TG_MAXLEV];        // level-l z-march tiles, problems where l is not the coarsest
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
 };
@@ -185,6 +197,10 @@ int k_copy0(Batch* b, int src, int dst, hipStream_t s);
 int k_multidot(Batch* b, int sbase, int nv, int sw, int with_self, hipStream_t s);
 int k_reduce(Batch* b, int nv, int mode, int dst, int save_k, hipStream_t s);  // 0: h=tmp 1: h+=tmp 2: tmp
 int k_update(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, hipStream_t s);
+// fused sweep: w -= V coef, then partial dots of the updated w with V (ndot
+// vectors) and, if with_self, with itself (chunk-local, deterministic).
+int k_update_dots(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, int ndot, int with_self,
+                  hipStream_t s);
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s);
 int k_cycle_start(Batch* b, int k, int cap, double tol, hipStream_t s);
 int k_arnoldi(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s);
@@ -197,6 +213,16 @@ bool timer_on();
 void* timer_begin(int kind, hipStream_t s);
 void timer_end(void* h, double bytes, hipStream_t s);
 void timer_harvest();
+
+// fine-level z-march kernels (tg_fine.hip)
+int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>* out32);
+int fine_tiles(const tg_grid* g);
+int zm_tiles(const tg_grid* g, int l);
+template <class T>
+int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
+                const void* eb, int sy, void* ey, double omega, hipStream_t s);
+int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, int sy, double omega,
+                             hipStream_t s);
 
 // host helpers (tg_host.cpp)
 void build_ke(double E0, double nu, double* Ke);

@@ -648,6 +648,144 @@ __global__ __launch_bounds__(256) void k_update_(const ProbDesc* __restrict__ pr
   }
 }
 
+// Fused Gram-Schmidt sweep: w -= sum_k coef[k] V_k over the chunk, then the
+// chunk partials of V_k . w (k < ndot) and, if with_self, of w . w, written
+// like k_multidot_.  The update of one chunk only needs that chunk, so the
+// dots of the updated vector are exact chunk sums.
+__global__ __launch_bounds__(256) void k_update_dots_(const ProbDesc* __restrict__ probs,
+                                                      const int2* __restrict__ work, int sbase, int nv,
+                                                      int sw, int coef_off, int ndot, int with_self) {
+  __shared__ double sh[8][4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  double* w = L.vec64 + (long long)sw * L.stride;
+  const double* coef = P.small + coef_off;
+  double wr[TG_VCHUNK / 256];
+#pragma unroll
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    wr[q] = idx < hi ? w[idx] : 0.0;
+  }
+  {
+    double acc[TG_VCHUNK / 256];
+#pragma unroll
+    for (int q = 0; q < TG_VCHUNK / 256; ++q) acc[q] = 0.0;
+    for (int k = 0; k < nv; ++k) {
+      const double ck = coef[k];
+      const double* v = L.vec64 + (long long)(sbase + k) * L.stride;
+#pragma unroll
+      for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+        const long long idx = lo + threadIdx.x + 256LL * q;
+        if (idx < hi) acc[q] += ck * v[idx];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+      const long long idx = lo + threadIdx.x + 256LL * q;
+      wr[q] -= acc[q];
+      if (idx < hi) w[idx] = wr[q];
+    }
+  }
+  const int ntot = ndot + (with_self ? 1 : 0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < ntot; k0 += 8) {
+    double sacc[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      sacc[g] = 0.0;
+      const int k = k0 + g;
+      if (k < ntot) {
+        if (k < ndot) {
+          const double* v = L.vec64 + (long long)(sbase + k) * L.stride;
+#pragma unroll
+          for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+            const long long idx = lo + threadIdx.x + 256LL * q;
+            if (idx < hi) sacc[g] += v[idx] * wr[q];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < TG_VCHUNK / 256; ++q) sacc[g] += wr[q] * wr[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const double r = wave_sum(sacc[g]);
+      if (lane == 0) sh[g][wv] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && k0 + (int)threadIdx.x < ntot) {
+      const int g = threadIdx.x;
+      P.part[(long long)(k0 + g) * L.n_chunks + wi.y] = (sh[g][0] + sh[g][1]) + (sh[g][2] + sh[g][3]);
+    }
+    __syncthreads();
+  }
+}
+
+// Single-read form of the fused sweep for nv <= NVR: each thread keeps its
+// DOF's values of all V_k in registers, so V is read once for both the update
+// and the dots of the updated vector.
+template <int NVR>
+__global__ __launch_bounds__(256) void k_update_dots_reg_(const ProbDesc* __restrict__ probs,
+                                                          const int2* __restrict__ work, int sbase, int nv,
+                                                          int sw, int coef_off, int ndot, int with_self) {
+  __shared__ double sh[NVR + 1][4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  double* w = L.vec64 + (long long)sw * L.stride;
+  const double* V0 = L.vec64 + (long long)sbase * L.stride;
+  const long long st = L.stride;
+  const double* coef = P.small + coef_off;
+  double cf[NVR], acc[NVR + 1];
+#pragma unroll
+  for (int k = 0; k < NVR; ++k) {
+    cf[k] = k < nv ? coef[k] : 0.0;
+    acc[k] = 0.0;
+  }
+  acc[NVR] = 0.0;
+  for (int q = 0; q < TG_VCHUNK / 256; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    if (idx >= hi) break;
+    double v[NVR];
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NVR; ++k) {
+      v[k] = k < nv ? V0[k * st + idx] : 0.0;
+      t += cf[k] * v[k];
+    }
+    const double wn = w[idx] - t;
+    w[idx] = wn;
+#pragma unroll
+    for (int k = 0; k < NVR; ++k) acc[k] += v[k] * wn;
+    acc[NVR] += wn * wn;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NVR; ++k) {
+    if (k < ndot) {
+      const double r = wave_sum(acc[k]);
+      if (lane == 0) sh[k][wv] = r;
+    }
+  }
+  if (with_self) {
+    const double r = wave_sum(acc[NVR]);
+    if (lane == 0) sh[NVR][wv] = r;
+  }
+  __syncthreads();
+  const int ntot = ndot + (with_self ? 1 : 0);
+  if ((int)threadIdx.x < ntot) {
+    const int k = threadIdx.x;
+    const int src = k < ndot ? k : NVR;
+    P.part[(long long)k * L.n_chunks + wi.y] = (sh[src][0] + sh[src][1]) + (sh[src][2] + sh[src][3]);
+  }
+}
+
 // dst = src * small[scal + sc_index]
 __global__ __launch_bounds__(256) void k_scale_(const ProbDesc* __restrict__ probs,
                                                 const int2* __restrict__ work, int src, int dst,
@@ -901,32 +1039,27 @@ static double op_bytes(const Batch* b, int l, int lmode, int op) {
   double nodes, elems, c2;
   level_sums(b, l, lmode, nodes, elems, c2);
   const double vec = 3.0 * nodes * sizeof(T);
-  const double mat = (l == 0) ? elems * sizeof(T) : elems * 576.0 * sizeof(T);
+  // fine level and matrix-free Galerkin levels read the fine moduli; deeper
+  // levels read their stored element matrices
+  const double mat = (l <= TG_MF_LEVELS) ? elems * double(1 << (3 * l)) * sizeof(T) : elems * 576.0 * sizeof(T);
   const double dinv = (op == OP_SMOOTH) ? 9.0 * nodes * sizeof(T) : 0.0;
   const int nvec = op == OP_APPLY ? 2 : 3;
   return nvec * vec + mat + dinv;
 }
 
 int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s) {
-  const DevList& dl = b->node[0];
-  if (!dl.n) return TG_OK;
-  if (prec == TG_F64) {
+  if (prec == TG_F64)
     TG_TIMED(TG_KT_APPLY_F64, (op_bytes<double>(b, 0, 0, OP_APPLY)),
-             k_node_op<double, double, double, double, OP_APPLY, true><<<nblk(dl), 256, 0, s>>>(
-                 b->desc_d, dl.ptr, 0, sx, ex, 0, nullptr, sy, ey, 0.0));
-  } else {
+             launch_fine<double>(b, b->fine, 0, OP_APPLY, sx, ex, 0, nullptr, sy, ey, 0.0, s));
+  else
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<float>(b, 0, 0, OP_APPLY)),
-             k_node_op<float, float, float, float, OP_APPLY, true><<<nblk(dl), 256, 0, s>>>(
-                 b->desc_d, dl.ptr, 0, sx, ex, 0, nullptr, sy, ey, 0.0f));
-  }
+             launch_fine<float>(b, b->fine, 0, OP_APPLY, sx, ex, 0, nullptr, sy, ey, 0.0, s));
   return check_launch("apply_K");
 }
 
 int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
-  if (b->node[0].n)
-    TG_TIMED(TG_KT_APPLY_F64, (op_bytes<double>(b, 0, 0, OP_RESID)),
-             k_node_op<double, double, double, double, OP_RESID, true><<<nblk(b->node[0]), 256, 0, s>>>(
-                 b->desc_d, b->node[0].ptr, 0, sx, nullptr, sb, nullptr, sy, nullptr, 0.0));
+  TG_TIMED(TG_KT_APPLY_F64, (op_bytes<double>(b, 0, 0, OP_RESID)),
+           launch_fine<double>(b, b->fine, 0, OP_RESID, sx, nullptr, sb, nullptr, sy, nullptr, 0.0, s));
   return check_launch("residual");
 }
 
@@ -934,8 +1067,10 @@ template <class T, int OP>
 static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om, hipStream_t s) {
   if (l == 0)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
-             k_node_op<T, T, T, T, OP, true><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, x, nullptr, bs,
-                                                                       nullptr, y, nullptr, om));
+             launch_fine<T>(b, b->zm_s[0], 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
+  else if (l <= TG_MF_LEVELS)
+    TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
+             launch_fine<T>(b, b->zm_s[l], l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
   else
     TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
              k_node_op<T, T, T, T, OP, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, x, nullptr, bs,
@@ -959,12 +1094,19 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   const int L = b->maxlev;
   double nodes, elems, c2;
   const double sT = sizeof(T), sIn = in_is_f32 ? 4.0 : 8.0, sOut = out_is_f32 ? 4.0 : 8.0;
+  // Fast level-0 boundary: FGMRES calls with an FP64 slot in, an FP64 slot out,
+  // FP32 working precision and every problem multilevel.  The first sweep
+  // reads the FP64 vector directly and the last sweep writes the FP64 output.
+  bool all_multi = true;
+  for (int p : b->active) all_multi = all_multi && b->grids[p]->nlev > 1;
+  const bool fast_in = !f64 && !in_is_f32 && sb >= 0 && all_multi;
+  const bool fast_out = !f64 && !out_is_f32 && sy >= 0 && all_multi;
   // ---- descend
   for (int l = 0; l < L; ++l) {
     const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB, Rs = l == 0 ? R0 : C_R;
     const DevList& sm = b->smooth[l];
     const DevList& co = b->coarse[l];
-    if (l == 0 && b->node[0].n) {
+    if (l == 0 && b->node[0].n && !fast_in) {
       // b into the working slot of type T (also masks the clamped nodes)
       level_sums(b, 0, 0, nodes, elems, c2);
       if (in_is_f32)
@@ -982,8 +1124,12 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     }
     if (!sm.n) continue;
     level_sums(b, l, 1, nodes, elems, c2);
-    TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 9.0 * nodes * sT,
-             k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om));
+    if (l == 0 && fast_in)
+      TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (8.0 + 2 * sT) + 9.0 * nodes * sT,
+               k_jacobi_first<double, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, 0, sb, nullptr, Bs, XA, om));
+    else
+      TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 9.0 * nodes * sT,
+               k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om));
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
       vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s);
@@ -1009,13 +1155,19 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 3.0 * nodes / 8 * sT,
              k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN));
     for (int it = 0; it < mg.nu_post; ++it) {
+      if (l == 0 && fast_out && it == mg.nu_post - 1) {
+        TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP_SMOOTH) + 3.0 * nodes * (8.0 - sT)),
+                 launch_fine_smooth_out64(b, b->zm_s[0], c, Bs, sy, (double)om, s));
+        c = -1;   // result is in the output slot
+        break;
+      }
       vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s);
       std::swap(c, o);
     }
     cur[l] = c;
   }
   // ---- output (level 0): result in FIN0 for every problem
-  if (b->node[0].n) {
+  if (b->node[0].n && !fast_out) {
     level_sums(b, 0, 0, nodes, elems, c2);
     if (out_is_f32)
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sOut + sT),
@@ -1070,6 +1222,23 @@ int k_update(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, hipStream_t s
              k_update_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, coef_off));
   return check_launch("update");
 }
+int k_update_dots(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, int ndot, int with_self,
+                  hipStream_t s) {
+  const SmallOffs o = offs(b);
+  const int coef_off = coef_is_tmp ? o.tmp : o.h;
+  if (b->vec.n) {
+    if (nv <= 32 && ndot <= 32)
+      TG_TIMED(TG_KT_UPDATE, 8.0 * (nv + 2) * dofs0(b),
+               k_update_dots_reg_<32><<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw,
+                                                                  coef_off, ndot, with_self));
+    else
+      TG_TIMED(TG_KT_UPDATE, 8.0 * (nv + 2 + ndot) * dofs0(b),
+               k_update_dots_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sw, coef_off,
+                                                          ndot, with_self));
+  }
+  return check_launch("update_dots");
+}
+
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s) {
   const int sidx = offs(b).scal + sc_index;
   if (b->vec.n)

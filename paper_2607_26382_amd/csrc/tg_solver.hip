@@ -101,16 +101,18 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
       jmax = j + 1;
       if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s))) return rc;
       if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
-      // CGS pass 1 (also w.w before projection -> SC_FLAG for the breakdown test)
+      // Classical Gram-Schmidt, each pass h = V^T w then w -= V h, in fused
+      // sweeps: [dots1 (+ w.w before projection -> SC_FLAG, breakdown test)]
+      // [w -= V h1; dots2] [w -= V h2; w.w]  (CGS2), or [dots1] [w -= V h1; w.w].
       if ((rc = k_multidot(b, slot_V(0), j + 1, S_W, 1, s))) return rc;
       if ((rc = k_reduce(b, j + 2, 0, 0, j + 1, s))) return rc;
-      if ((rc = k_update(b, slot_V(0), j + 1, S_W, 0, s))) return rc;
       if (o->cgs_passes == 2) {
-        if ((rc = k_multidot(b, slot_V(0), j + 1, S_W, 0, s))) return rc;
+        if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 0, j + 1, 0, s))) return rc;
         if ((rc = k_reduce(b, j + 1, 1, 0, -1, s))) return rc;
-        if ((rc = k_update(b, slot_V(0), j + 1, S_W, 1, s))) return rc;
+        if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 1, 0, 1, s))) return rc;
+      } else {
+        if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 0, 0, 1, s))) return rc;
       }
-      if ((rc = k_multidot(b, 0, 0, S_W, 1, s))) return rc;
       if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
       if ((rc = k_arnoldi(b, j, k, cap, tol, brk, s))) return rc;
       if ((rc = k_scale_to(b, S_W, slot_V(j + 1), SC_INV, s))) return rc;

@@ -264,3 +264,45 @@ def test_full_size_apply_sampled(dims, gen):
         bnd = op.apply_at_node(og, E, Ka, np.abs(u), int(n))
         assert np.all(np.abs(y[3 * n:3 * n + 3] - ref) <= 64 * 2.2e-16 * bnd + 1e-300)
         assert np.all(np.abs(y32[3 * n:3 * n + 3] - ref) <= 3e-5 * bnd + 1e-30)
+
+
+@pytest.mark.parametrize("dims,kind,rmin", [((16, 8, 8), "uniform", 1e-3), ((32, 16, 16), "blob", 1e-4),
+                                            ((32, 16, 16), "blob", 1e-9)])
+def test_mixed_precision_solve_certified_by_oracle(dims, kind, rmin):
+    """FP32 V-cycle inside FP64 FGMRES: the result is judged only by the FP64
+    residual, recomputed here by the oracle; it must approach the FP64 solve."""
+    rho = _field(kind, dims, 1001)
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    K = op.free_block(op.assemble(og, op.young(rho, 3.0, rmin), KE), free)
+    ff = og.edge_load()[free]
+    g = _gpu_grid(dims, rho, 3.0, rmin)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u32, r32, h32 = g.fgmres_solve(f, tg.solver_opts(prec=tg.F32))
+    u64, r64, h64 = g.fgmres_solve(f, tg.solver_opts(prec=tg.F64))
+    eta32 = g.true_residual(f, u32)
+    eta32_o = op.relative_residual(K, ff, u32.cpu().numpy()[free])
+    assert abs(eta32 - eta32_o) <= 2 * op.residual_bound(K, ff, u32.cpu().numpy()[free])
+    if r32["outcome"] == "PROJ_CONVERGED" and eta32 <= 1e-6:
+        # both accepted: the two solutions agree to the conditioning of the solve
+        d = np.linalg.norm((u32 - u64).cpu().numpy()) / np.linalg.norm(u64.cpu().numpy())
+        assert d < 1e-2
+    # iteration counts stay close to the FP64 solve on these fields
+    assert r32["iterations"] <= r64["iterations"] + 10
+
+
+def test_mixed_policy_matches_oracle_rungs():
+    dims = (32, 16, 16)
+    rungs = [1e-9, 1e-6, 1e-4, 1e-3]
+    for seed in (1000, 1001):
+        rho = synth.blobs(*dims, seed)
+        ref = _oracle_select(dims, rho, rungs)
+        g = tg.Grid(*dims, max_restart=100, device=DEV)
+        f = torch.tensor(g.edge_load(), device=DEV)
+        pol = tg.policy(rungs=rungs, solve=tg.solver_opts(prec=tg.F32))
+        u, out = g.select_floor(torch.tensor(rho, device=DEV), f, pol)
+        assert out["rung"] == ref["rung"]
+        og = mesh.Grid(*dims)
+        free = og.free_dofs()
+        K = op.free_block(op.assemble(og, op.young(rho, 3.0, rungs[out["rung"]]), KE), free)
+        assert op.relative_residual(K, og.edge_load()[free], u.cpu().numpy()[free]) <= 1e-6
