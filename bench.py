@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--states", type=int, default=102)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-apply", action="store_true", help="skip the 256x128x128 apply_K bandwidth leg")
+    ap.add_argument("--apply-only", action="store_true", help="run only the apply_K bandwidth leg")
+    ap.add_argument("--mixed", default="bf16x3", choices=["f32", "bf16", "bf16x3"],
+                    help="fine-level contraction of the mixed form (FP32 vector, BF16 or split-BF16 matrix cores)")
+    ap.add_argument("--compare-mixed", action="store_true",
+                    help="also time the other mixed variants (one step each)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -86,6 +92,58 @@ def run_cpu_baseline(setups_per_state, iters_per_state):
     }
 
 
+def apply_leg(tg, torch, dev, reps=40):
+    """apply_K HBM bandwidth at 256x128x128 (12.8M DOF) on the strut field.
+
+    Rotates over buffer sets whose total exceeds the 256 MB Infinity Cache so
+    every launch streams from HBM.  Algorithmic bytes per apply: read u and
+    write y (3 DOF per node each) plus one modulus per element."""
+    from paper_2607_26382_amd import synth
+    nx, ny, nz = 256, 128, 128
+    g = tg.Grid(nx, ny, nz, max_restart=2, device=dev)
+    rho = torch.tensor(synth.struts(nx, ny, nz, 3000), device=dev)
+    g.set_density(rho, 3.0, 1e-3)
+    out = {}
+    for name, prec, dt, vb in (("f32", tg.F32, torch.float32, 4), ("f64", tg.F64, torch.float64, 8),
+                               ("bf16_mfma", tg.BF16MFMA, torch.float32, 4),
+                               ("bf16x3_mfma", tg.BF16X3MFMA, torch.float32, 4)):
+        nsets = max(3, int(np.ceil(600e6 / (2 * g.n_dof * vb))))
+        us = [torch.randn(g.n_dof, dtype=dt, device=dev) for _ in range(nsets)]
+        ys = [torch.empty_like(us[0]) for _ in range(nsets)]
+        try:
+            from paper_2607_26382_amd._lib import lib as _l
+            import ctypes as C
+            st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+            def run(i):
+                rc = _l().tg_apply_K(g.handle, C.c_void_p(us[i].data_ptr()), C.c_void_p(ys[i].data_ptr()),
+                                     prec, st)
+                if rc != 0:
+                    raise RuntimeError(_l().tg_last_error().decode())
+            for i in range(nsets):
+                run(i)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for r in range(reps):
+                run(r % nsets)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps * 1e-3
+        except RuntimeError as exc:
+            out[name] = {"error": str(exc)}
+            continue
+        alg = 2 * g.n_dof * vb + g.n_elem * vb
+        out[name] = {"us_per_apply": t * 1e6, "alg_bytes": alg, "GB/s": alg / t / 1e9,
+                     "frac_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS, "buffer_sets": nsets}
+        log(f"apply_K {name}: {t*1e6:.1f} us, {alg / t / 1e9:.0f} GB/s")
+        del us, ys
+    out["grid"] = [nx, ny, nz]
+    out["n_dof"] = g.n_dof
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.cpu_only:
@@ -103,6 +161,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    apply_res = None
+    if not args.no_apply:
+        apply_res = apply_leg(tg, torch, dev)
+        if args.apply_only:
+            print(json.dumps({"apply_K": apply_res}), flush=True)
+            return
     n = args.states
     grids = [tg.Grid(*GRID, max_restart=100, device=dev) for _ in range(n)]
     batch = tg.Batch(grids)
@@ -137,16 +201,19 @@ def main():
         tg.kernel_timer_enable(0)
         return dt, outs, timers
 
+    MIXED = {"f32": tg.F32, "bf16": tg.BF16MFMA, "bf16x3": tg.BF16X3MFMA}
+    mixed_prec = MIXED[args.mixed]
     # one untimed pass with every kernel class timed picks the dominant class;
     # the timed steps then carry events around that class only
-    _, _, probe_timers = run(tg.F32, 1, 0, (1 << 8) - 1)
+    _, _, probe_timers = run(mixed_prec, 1, 0, (1 << 8) - 1)
     dom = tg.dominant_kernel(probe_timers)
     dom_mask = 1 << probe_timers[dom]["kind"]
-    dt, outs, timers = run(tg.F32, args.steps, args.warmup, dom_mask)
+    dt, outs, timers = run(mixed_prec, args.steps, args.warmup, dom_mask)
     certified = sum(1 for o in outs if o["rung"] >= 0)
     value = certified * args.steps / dt
     result = {
         "metric": "certified solves/s at ||f-Ku||/||f||<=1e-6 (mixed precision)",
+        "mixed_form": args.mixed,
         "value": value, "unit": "certified solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
@@ -154,7 +221,7 @@ def main():
         "config": {"workload": "102 severe random states, 64x32x32 cantilever, guarded floor ladder",
                    "states": n, "grid": list(GRID), "rungs": list(RUNGS), "p": 3.0,
                    "probe": "100 its, restart 100", "solve": "FGMRES(30), cap 200, tol 1e-6",
-                   "preconditioner": "3-level+ GMG V-cycle, node-block Jacobi w=0.6 2/2, FP32"},
+                   "preconditioner": "5-level GMG V-cycle, node-block Jacobi w=0.6 2/2, FP32 vectors"},
     }
     acc = [o for o in outs if o["rung"] >= 0]
     result["policy"] = {
@@ -167,9 +234,20 @@ def main():
         "mean_iters_rejected": float(np.mean([o["iters_rejected"] for o in outs])),
     }
     result["roofline"] = tg.roofline_from_timers(timers, HBM_PEAK_GBS)
+    if apply_res is not None:
+        result["apply_K"] = apply_res
     result["kernel_classes"] = {k: {"launches": v["count"], "total_ms": v["ms"], "avg_us": v["avg_us"],
                                     "alg_GB/s": v["gbs"]}
                                 for k, v in probe_timers.items() if v["count"]}
+    if args.compare_mixed:
+        result["mixed_variants"] = {}
+        for name, pr in MIXED.items():
+            d, o, _ = run(pr, 1, 0, 0)
+            c = sum(1 for x in o if x["rung"] >= 0)
+            result["mixed_variants"][name] = {
+                "value": c / d, "ms_per_step": 1e3 * d, "certified": c,
+                "mean_iters": float(np.mean([x["iters_probe"] + x["iters_selected"] + x["iters_rejected"]
+                                             for x in o]))}
     if not args.no_fp64:
         dt64, outs64, _ = run(tg.F64, args.steps, args.warmup, 0)
         cert64 = sum(1 for o in outs64 if o["rung"] >= 0)

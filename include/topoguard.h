@@ -54,7 +54,10 @@ enum {
 enum {
   TG_F64 = 0,          /* FP64 vectors and arithmetic                          */
   TG_F32 = 1,          /* FP32 vectors and arithmetic                          */
-  TG_BF16MFMA = 2      /* FP32 vectors, Ke contraction on BF16 MFMA, FP32 acc. */
+  TG_BF16MFMA = 2,     /* FP32 vectors; fine-level Ke contraction on BF16
+                          matrix cores (inputs rounded to BF16), FP32 accumulate */
+  TG_BF16X3MFMA = 3    /* as TG_BF16MFMA with split BF16 (hi + lo) operands:
+                          Ke_hi u_hi + Ke_hi u_lo + Ke_lo u_hi, ~16 bits      */
 };
 
 /* FGMRES outcomes (the solver's internal flag semantics, Tab. residual-semantics). */
@@ -138,7 +141,8 @@ int tg_set_density(tg_grid* g, const double* rho_d, double p, double rho_min, vo
 
 /* ---- operator (Eq. frozen_operator) -------------------------------------- */
 /* y = K(rho_min) u on the free DOFs.  prec TG_F64: u_d, y_d are double;
- * TG_F32 / TG_BF16MFMA: float.  Needs tg_set_density first (TG_ESTATE). */
+ * TG_F32 / TG_BF16MFMA / TG_BF16X3MFMA: float.  Needs tg_set_density first
+ * (TG_ESTATE). */
 int tg_apply_K(const tg_grid* g, const void* u_d, void* y_d, int prec, void* stream);
 
 /* ---- preconditioner (Tab. solver-config, fixed V-cycle) ------------------ */
@@ -221,6 +225,21 @@ int tg_batch_solve(tg_batch* b, const double* const* f_d, double* const* u_d,
 int tg_batch_select_floor(tg_batch* b, const double* const* rho_d, const double* const* f_d,
                           const tg_policy* pol, double* const* u_d, tg_policy_result* out,
                           void* stream);
+
+/* ---- autotuner (addition (2)) -------------------------------------------- */
+/* Times the V-cycle smoothing sweep of the matrix-free levels for each
+ * candidate z-tile height {2,3,4,6,8,12,16} and keeps the fastest per level
+ * (the tile height trades one redundant element layer per tile against
+ * parallelism).  Needs set_density.  zc_out (may be NULL) receives the 8
+ * per-level heights, us_out (may be NULL) the best sweep time per level in
+ * microseconds (-1 where nothing was timed).  Choices are cached per batch
+ * signature (grid sizes in order, precision) for the process and, if the
+ * environment variable TG_AUTOTUNE_CACHE names a file, across runs; a cached
+ * choice is applied without timing unless force is nonzero.  Tile heights
+ * change only the work decomposition: results agree with untuned runs to
+ * rounding.  Synchronises the stream; TG_ESTATE before set_density. */
+int tg_batch_autotune(tg_batch* b, int prec, int force, int* zc_out, double* us_out, void* stream);
+int tg_autotune(tg_grid* g, int prec, int force, int* zc_out, double* us_out, void* stream);
 
 /* ---- learned first-floor selector (addition (4)) ------------------------- */
 /* 8 -> 64 -> 64 -> 4 MLP, exact-erf GELU, softmax cross-entropy, Adam.

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libtopoguard.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "topoguard.h")
 
 TG_OK, TG_EINVAL, TG_EHIP, TG_EWORKSPACE, TG_ESTATE, TG_ENUMERIC = 0, -1, -2, -3, -4, -5
-TG_F64, TG_F32, TG_BF16MFMA = 0, 1, 2
+TG_F64, TG_F32, TG_BF16MFMA, TG_BF16X3MFMA = 0, 1, 2, 3
 TG_PROJ_CONVERGED, TG_MAXIT, TG_BREAKDOWN, TG_NONFINITE = 0, 1, 2, 3
 TG_SELECT_RULE, TG_SELECT_MLP, TG_SELECT_FIXED = 0, 1, 2
 TG_MAX_RUNGS = 8
@@ -104,6 +104,8 @@ PROTOTYPES = {
     "tg_mlp_get_params": (_I, [_P, C.POINTER(C.c_float), _P]),
     "tg_mlp_forward": (_I, [_P, _P, _I, _P, _P]),
     "tg_mlp_train_step": (_I, [_P, _P, _P, _I, C.c_float, C.POINTER(C.c_float), _P, _P]),
+    "tg_batch_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
+    "tg_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),
     "tg_timer_read": (_I, [_I, C.POINTER(_D), C.POINTER(C.c_longlong), C.POINTER(_D)]),

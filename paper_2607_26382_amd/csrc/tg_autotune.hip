@@ -1,0 +1,141 @@
+// Autotuner for the z-march kernels: per level, time the V-cycle smoothing
+// sweep of the actual batch for each candidate z-tile height and keep the
+// fastest.  Results are cached per batch signature (grid dimensions of every
+// problem and the working precision) for the life of the process, and
+// optionally in a text file named by TG_AUTOTUNE_CACHE.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+#include "tg_internal.h"
+
+namespace tg {
+
+namespace {
+std::mutex g_mu;
+std::map<std::string, std::vector<int>> g_cache;
+bool g_loaded = false;
+
+void load_file() {
+  if (g_loaded) return;
+  g_loaded = true;
+  const char* path = std::getenv("TG_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[4096];
+  while (std::fscanf(f, "%4095s", key) == 1) {
+    std::vector<int> v(TG_MAXLEV);
+    for (int l = 0; l < TG_MAXLEV; ++l)
+      if (std::fscanf(f, "%d", &v[l]) != 1) v[l] = 0;
+    g_cache[key] = v;
+  }
+  std::fclose(f);
+}
+
+void save_file() {
+  const char* path = std::getenv("TG_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_cache) {
+    std::fprintf(f, "%s", kv.first.c_str());
+    for (int x : kv.second) std::fprintf(f, " %d", x);
+    std::fprintf(f, "\n");
+  }
+  std::fclose(f);
+}
+}  // namespace
+
+std::string batch_signature(const Batch* b, int prec) {
+  std::ostringstream o;
+  o << "p" << prec << "_n" << b->n;
+  // problems in order of appearance, run-length encoded by grid size
+  int i = 0;
+  while (i < b->n) {
+    int j = i;
+    const tg_grid* g = b->grids[i];
+    while (j < b->n && b->grids[j]->nx == g->nx && b->grids[j]->ny == g->ny && b->grids[j]->nz == g->nz) ++j;
+    o << "_" << (j - i) << "x" << g->nx << "." << g->ny << "." << g->nz;
+    i = j;
+  }
+  return o.str();
+}
+
+// Applies cached tile heights if this batch has been tuned before.
+bool autotune_lookup(Batch* b, int prec) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_file();
+  auto it = g_cache.find(batch_signature(b, prec));
+  if (it == g_cache.end()) return false;
+  for (int l = 0; l < TG_MAXLEV; ++l)
+    if (it->second[l] > 0) b->zc[l] = it->second[l];
+  return true;
+}
+
+int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool force) {
+  if (prec < TG_F64 || prec > TG_BF16X3MFMA) return fail(TG_EINVAL, "unknown precision");
+  for (int l = 0; l < TG_MAXLEV && best_us; ++l) best_us[l] = -1.0;
+  if (!force && autotune_lookup(b, prec)) return batch_upload_desc(b, s);
+  const int cand[7] = {2, 3, 4, 6, 8, 12, 16};
+  std::vector<int> all(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    all[i] = i;
+    if (!b->grids[i]->density_set) return fail(TG_ESTATE, "autotune needs set_density first");
+  }
+  hipEvent_t e0, e1;
+  TG_HIP(hipEventCreate(&e0));
+  TG_HIP(hipEventCreate(&e1));
+  int rc = TG_OK;
+  for (int l = 0; l <= TG_MF_LEVELS && rc == TG_OK; ++l) {
+    bool any = false;
+    for (auto* g : b->grids) any = any || (l < g->nlev - 1);
+    if (!any) continue;
+    double best = 1e30;
+    int pick = b->zc[l];
+    for (int c : cand) {
+      b->zc[l] = c;
+      if ((rc = batch_upload_desc(b, s)) || (rc = batch_set_active(b, all, s))) break;
+      const int mf = prec == TG_BF16MFMA ? 1 : prec == TG_BF16X3MFMA ? 2 : 0;
+      auto sweep = [&]() {
+        // damped Jacobi sweep on the level's scratch vectors (values irrelevant)
+        if (prec == TG_F64)
+          return launch_fine<double>(b, b->zm_s[l], l, 2, l == 0 ? S_VXA : C_XA, nullptr,
+                                     l == 0 ? S_VB : C_B, nullptr, l == 0 ? S_VXB : C_XB, nullptr, 0.6, s);
+        if (l == 0 && mf)
+          return launch_fine_mfma(b, b->zm_s[0], 2, mf == 2, C_XA, nullptr, C_B, nullptr, C_XB, nullptr, 0.6,
+                                  false, s);
+        return launch_fine<float>(b, b->zm_s[l], l, 2, C_XA, nullptr, C_B, nullptr, C_XB, nullptr, 0.6, s);
+      };
+      if ((rc = sweep())) break;
+      TG_HIP(hipEventRecord(e0, s));
+      const int reps = 5;
+      for (int r = 0; r < reps; ++r)
+        if ((rc = sweep())) break;
+      TG_HIP(hipEventRecord(e1, s));
+      TG_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / reps;
+      if (us < best) {
+        best = us;
+        pick = c;
+      }
+    }
+    b->zc[l] = pick;
+    if (best_us) best_us[l] = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if ((rc = batch_upload_desc(b, s))) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_file();
+  g_cache[batch_signature(b, prec)] = std::vector<int>(b->zc, b->zc + TG_MAXLEV);
+  save_file();
+  return TG_OK;
+}
+
+}  // namespace tg

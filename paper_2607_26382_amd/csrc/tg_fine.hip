@@ -138,7 +138,7 @@ __device__ __forceinline__ void elem_fine(T* ux, T* uy, T* uz, T E, const ModeCo
 // 2:1 trilinear hierarchy.  Descendant d = (fx, fy, fz) in [0, 2^l)^3 sits at
 // h = 2^-l, s = (2 f + 1) h - 1 per dimension.
 template <class T>
-__device__ __forceinline__ void elem_galerkin(T* ux, T* uy, T* uz, const T* __restrict__ E0, int nx0,
+__device__ __forceinline__ void elem_galerkin(T* ux, T* uy, T* uz, const T TG_GLOBAL* E0, int nx0,
                                               int ny0, int ex, int ey, int ez, int l,
                                               const ModeCoef<T>& c) {
   wht_fwd(ux);
@@ -178,6 +178,105 @@ __device__ __forceinline__ void elem_galerkin(T* ux, T* uy, T* uz, const T* __re
   wht_inv(uz);
 }
 
+// ---------------------------------------------------------------------------
+// BF16 matrix-core form of the fine element contraction v = E Ke u (FP32
+// accumulate).  A wave's 64 elements form the columns of U (24 DOFs padded to
+// K = 32); Ke (24 rows padded to 32, two 16-row tiles) is the A operand of
+// v_mfma_f32_16x16x32_bf16, held in registers for the whole kernel.  Lane
+// layout of that instruction (measured on gfx950): A[i][k] at lane i % 16 +
+// 16 (k / 8), element k % 8; B[k][n] at lane n + 16 (k / 8), element k % 8;
+// D[m][n] at lane n + 16 (m / 4), element m % 4.  Inputs go to the B layout
+// and results come back through a wave-private LDS block.  SPLIT adds the
+// low halves u_lo = bf16(u - u_hi), Ke_lo = bf16(Ke - Ke_hi): Ke_hi u_hi +
+// Ke_hi u_lo + Ke_lo u_hi, about 16 significant bits.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct MfmaA {
+  bf16x8 hi[2], lo[2];   // two 16-row tiles of Ke
+};
+
+__device__ __forceinline__ void mfma_load_ke(const float TG_GLOBAL* Ke, MfmaA& A) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = 16 * mt + (lane & 15), k = 8 * (lane >> 4) + j;
+      const float v = (row < 24 && k < 24) ? Ke[row * 24 + k] : 0.f;
+      const __bf16 h = (__bf16)v;
+      A.hi[mt][j] = h;
+      A.lo[mt][j] = (__bf16)(v - (float)h);
+    }
+}
+
+// ux/uy/uz[a]: this lane's element; wlds: this wave's LDS block
+// (SPLIT ? 2 : 1) * 64 * 32 bf16 = 4 KiB (8 KiB), reused for 64 x 24 floats.
+template <bool SPLIT>
+__device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float E, const MfmaA& A,
+                                          char* wlds) {
+  const int lane = threadIdx.x & 63;
+  __bf16* Bh = (__bf16*)wlds;                 // [64 elements][32]
+  __bf16* Bl = Bh + 64 * 32;
+  auto put = [&](int k, float v) {
+    const __bf16 h = (__bf16)v;
+    Bh[lane * 32 + k] = h;
+    if (SPLIT) Bl[lane * 32 + k] = (__bf16)(v - (float)h);
+  };
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    put(3 * a + 0, ux[a]);
+    put(3 * a + 1, uy[a]);
+    put(3 * a + 2, uz[a]);
+  }
+#pragma unroll
+  for (int k = 24; k < 32; ++k) {
+    Bh[lane * 32 + k] = (__bf16)0.f;
+    if (SPLIT) Bl[lane * 32 + k] = (__bf16)0.f;
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int el = 16 * nb + (lane & 15), k0 = 8 * (lane >> 4);
+    bf16x8 bh, bl;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      bh[j] = Bh[el * 32 + k0 + j];
+      if (SPLIT) bl[j] = Bl[el * 32 + k0 + j];
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bh, c, 0, 0, 0);
+      if (SPLIT) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[mt], bh, c, 0, 0, 0);
+      }
+      acc[nb][mt] = c;
+    }
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // B reads done before reuse
+  float* O = (float*)wlds;                              // [64 elements][24]
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * mt + 4 * (lane >> 4) + j;
+        if (row < 24) O[(16 * nb + (lane & 15)) * 24 + row] = acc[nb][mt][j];
+      }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    ux[a] = E * O[lane * 24 + 3 * a + 0];
+    uy[a] = E * O[lane * 24 + 3 * a + 1];
+    uz[a] = E * O[lane * 24 + 3 * a + 2];
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // reads done before the next layer's writes
+}
+
 template <class T> __device__ __forceinline__ T* fpool(const LevelDesc& L);
 template <> __device__ __forceinline__ double* fpool<double>(const LevelDesc& L) { return L.vec64; }
 template <> __device__ __forceinline__ float* fpool<float>(const LevelDesc& L) { return L.vec32; }
@@ -196,14 +295,22 @@ __device__ __forceinline__ const T* fvec(const LevelDesc& L, int slot, const voi
 #define FZ_TX 16
 #define FZ_OUT 15
 
-// z-tiles per grid: ceil(NZ / 16), balanced heights
-__host__ __device__ __forceinline__ int fz_ntz(int NZ) { return (NZ + 15) / 16; }
-__host__ __device__ __forceinline__ int fz_zc(int NZ) { const int t = fz_ntz(NZ); return (NZ + t - 1) / t; }
-__host__ __device__ __forceinline__ int fz_tiles(int NX, int NY, int NZ) {
-  return ((NX + FZ_OUT - 1) / FZ_OUT) * ((NY + FZ_OUT - 1) / FZ_OUT) * fz_ntz(NZ);
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// (lgkmcnt) and synchronizes, leaving global loads in flight (a plain
+// __syncthreads is a release fence that also drains every outstanding global
+// load, which defeats prefetching one layer ahead).  The memory clobber keeps
+// the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// KIND 0: fine level, element = E_e Ke; KIND 1: matrix-free Galerkin level l.
+// z-tiles of height zc node layers
+__host__ __device__ __forceinline__ int fz_tiles(int NX, int NY, int NZ, int zc) {
+  return ((NX + FZ_OUT - 1) / FZ_OUT) * ((NY + FZ_OUT - 1) / FZ_OUT) * ((NZ + zc - 1) / zc);
+}
+
+// KIND 0: fine level, element = E_e Ke; KIND 1: matrix-free Galerkin level l;
+// KIND 2 / 3: fine level with the BF16 matrix-core contraction (3: split BF16).
 template <class T, int OP, int KIND, class TY = T>
 __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ probs,
                                                  const int2* __restrict__ work, int l, int sx,
@@ -213,23 +320,26 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   // two barriers of its step, every write of the next layer after them.
   __shared__ T su[3][17][17];           // node values of the current top layer
   __shared__ T ss[12][FZ_TX][FZ_TX];    // per element: 4 corners x 3 comps, layer sum
+  __shared__ __attribute__((aligned(16))) char mf_lds[(KIND >= 2) ? 4 * (KIND == 3 ? 8192 : 6144) : 16];
+  MfmaA mfA;
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& L = P.lv[l];
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
   const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;
+  if constexpr (KIND >= 2) mfma_load_ke(gp(P.Ke32), mfA);
   const int ntx = (NX + FZ_OUT - 1) / FZ_OUT, nty = (NY + FZ_OUT - 1) / FZ_OUT;
   const int tile = wi.y;
+  const int zc = L.zc;
   const int tiz = tile / (ntx * nty), rem = tile - tiz * ntx * nty;
   const int tiy = rem / ntx, tix = rem - tiy * ntx;
-  const int zc = fz_zc(NZ);
   const int x0 = tix * FZ_OUT, y0 = tiy * FZ_OUT, z0 = tiz * zc;
   const int zend = min(z0 + zc, NZ);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int ex = x0 - 1 + tx, ey = y0 - 1 + ty;         // this thread's element column
   const int ni = ex + 1, nj = ey + 1;                   // this thread's node column
-  const T* u = fvec<T>(L, sx, ex_);
-  const T* Eg = fE<T>(P);
+  const auto* u = gp(fvec<T>(L, sx, ex_));
+  const auto* Eg = gp(fE<T>(P));
   const bool elem_in = (ex >= 0 && ex < nx && ey >= 0 && ey < ny);
   const bool owner = (tx < FZ_OUT && ty < FZ_OUT && ni < NX && nj < NY);
   // extra node loads: tile row/column 0 (nodes x0-1 or y0-1)
@@ -237,37 +347,56 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   int exi = -1, exj = -1, etx = 0, ety = 0;
   if (xt < 17) { etx = 0; ety = xt; exi = x0 - 1; exj = y0 - 1 + xt; }
   else if (xt < 33) { etx = xt - 16; ety = 0; exi = x0 - 1 + (xt - 16); exj = y0 - 1; }
+  const bool own_col = (ni > 0 && ni < NX && nj >= 0 && nj < NY);
+  const bool ext_col = (xt < 33) && (exi > 0 && exi < NX && exj >= 0 && exj < NY);
+  const long long own_base = 3LL * (ni + (long long)NX * nj);
+  const long long ext_base = 3LL * (exi + (long long)NX * exj);
+  const long long lstride = 3LL * NX * NY;             // DOFs per node layer
 
-  auto load_node = [&](int i, int j, int k, T& a, T& b, T& c) {
-    if (i > 0 && i < NX && j >= 0 && j < NY && k >= 0 && k < NZ) {
-      const long long n = i + (long long)NX * (j + (long long)NY * k);
-      a = u[3 * n];
-      b = u[3 * n + 1];
-      c = u[3 * n + 2];
+  // prefetch registers for one node layer (own column + extra column),
+  // returned by value so they stay in registers
+  struct Pre {
+    T a0, a1, a2, e0, e1, e2;
+  };
+  auto fetch = [&](int k) -> Pre {
+    Pre r;
+    const bool kin = (k >= 0 && k < NZ);
+    if (own_col && kin) {
+      const auto* p = u + own_base + lstride * k;
+      r.a0 = p[0];
+      r.a1 = p[1];
+      r.a2 = p[2];
     } else {
-      a = b = c = T(0);   // outside the grid, or clamped (i == 0)
+      r.a0 = r.a1 = r.a2 = T(0);
     }
+    if (ext_col && kin) {
+      const auto* p = u + ext_base + lstride * k;
+      r.e0 = p[0];
+      r.e1 = p[1];
+      r.e2 = p[2];
+    } else {
+      r.e0 = r.e1 = r.e2 = T(0);
+    }
+    return r;
   };
-  auto stage_layer = [&](int k) {
-    T a, b, c;
-    load_node(ni, nj, k, a, b, c);
-    su[0][ty + 1][tx + 1] = a;
-    su[1][ty + 1][tx + 1] = b;
-    su[2][ty + 1][tx + 1] = c;
+  auto stage = [&](const Pre& r) {
+    su[0][ty + 1][tx + 1] = r.a0;
+    su[1][ty + 1][tx + 1] = r.a1;
+    su[2][ty + 1][tx + 1] = r.a2;
     if (xt < 33) {
-      load_node(exi, exj, k, a, b, c);
-      su[0][ety][etx] = a;
-      su[1][ety][etx] = b;
-      su[2][ety][etx] = c;
+      su[0][ety][etx] = r.e0;
+      su[1][ety][etx] = r.e1;
+      su[2][ety][etx] = r.e2;
     }
   };
-  // bottom face of the first element layer (node layer z0 - 1)
   T bx[4], by[4], bz[4];     // bottom-face node values, corner c = di + 2 dj
   T tpx[4], tpy[4], tpz[4];  // top-face outputs of the previous element layer
 #pragma unroll
   for (int c = 0; c < 4; ++c) tpx[c] = tpy[c] = tpz[c] = T(0);
-  stage_layer(z0 - 1);
-  __syncthreads();
+  Pre pre = fetch(z0 - 1);
+  stage(pre);
+  pre = fetch(z0);           // in flight while the prologue reads LDS
+  lds_barrier();
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int di = c & 1, dj = c >> 1;
@@ -275,10 +404,33 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     by[c] = su[1][ty + dj][tx + di];
     bz[c] = su[2][ty + dj][tx + di];
   }
-  __syncthreads();   // prologue reads done before the first layer is staged
+  // element modulus of the first layer
+  T Enext = (KIND != 1 && elem_in && z0 - 1 >= 0 && z0 - 1 < nz)
+                ? Eg[ex + (long long)nx * (ey + (long long)ny * (z0 - 1))]
+                : T(0);
+  lds_barrier();           // prologue reads done before the first layer is staged
   for (int k = z0 - 1; k < zend; ++k) {
-    stage_layer(k + 1);
-    __syncthreads();
+    stage(pre);              // node layer k + 1 (fetched one step ahead)
+    pre = fetch(k + 2);      // next layer in flight during this step
+    const T Ecur = Enext;   // modulus of element layer k (0 outside the grid)
+    Enext = (KIND != 1 && elem_in && k + 1 >= 0 && k + 1 < nz)
+                ? Eg[ex + (long long)nx * (ey + (long long)ny * (k + 1))]
+                : T(0);
+    // output-side operands of node (ni, nj, k), loaded before the barrier
+    T rb0 = T(0), rb1 = T(0), rb2 = T(0);
+    T D[9];
+    const bool out_now = owner && k >= z0 && ni > 0;
+    const long long n = ni + (long long)NX * (nj + (long long)NY * k);
+    if (OP != FOP_APPLY && out_now) {
+      const auto* bb = gp(fvec<T>(L, sb, eb_)) + 3 * n;
+      rb0 = bb[0]; rb1 = bb[1]; rb2 = bb[2];
+    }
+    if (OP == FOP_SMOOTH && out_now) {
+      const auto* Dp = gp(fD<T>(L)) + 9 * n;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) D[q] = Dp[q];
+    }
+    lds_barrier();
     T ux[8], uy[8], uz[8];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -299,9 +451,11 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       bz[c] = uz[c + 4];
     }
     const bool ein = elem_in && k >= 0 && k < nz;
-    if (KIND == 0) {
-      const T E = ein ? Eg[ex + (long long)nx * (ey + (long long)ny * k)] : T(0);
-      elem_fine<T>(ux, uy, uz, E, mc);
+    if constexpr (KIND >= 2) {
+      elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, (float)Ecur, mfA,
+                           mf_lds + (threadIdx.x >> 6) * (KIND == 3 ? 8192 : 6144));
+    } else if (KIND == 0) {
+      elem_fine<T>(ux, uy, uz, Ecur, mc);
     } else if (ein) {
       elem_galerkin<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k, l, mc);
     } else {
@@ -318,7 +472,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       tpy[c] = uy[c + 4];
       tpz[c] = uz[c + 4];
     }
-    __syncthreads();
+    lds_barrier();
     if (owner && k >= z0) {
       // node (ni, nj, k) = corner 3 of element (tx,ty), corner 2 of (tx+1,ty),
       // corner 1 of (tx,ty+1), corner 0 of (tx+1,ty+1)
@@ -327,8 +481,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       for (int q = 0; q < 3; ++q)
         a[q] = (ss[9 + q][ty][tx] + ss[6 + q][ty][tx + 1]) +
                (ss[3 + q][ty + 1][tx] + ss[0 + q][ty + 1][tx + 1]);
-      const long long n = ni + (long long)NX * (nj + (long long)NY * k);
-      TY* y = (sy < 0 ? (TY*)ey_ : fpool<TY>(L) + (long long)sy * L.stride) + 3 * n;
+      auto* y = gp((sy < 0 ? (TY*)ey_ : fpool<TY>(L) + (long long)sy * L.stride)) + 3 * n;
       if (ni == 0) {
         y[0] = y[1] = y[2] = TY(0);
       } else if (OP == FOP_APPLY) {
@@ -336,14 +489,12 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         y[1] = TY(a[1]);
         y[2] = TY(a[2]);
       } else {
-        const T* bb = fvec<T>(L, sb, eb_) + 3 * n;
-        const T r0 = bb[0] - a[0], r1 = bb[1] - a[1], r2 = bb[2] - a[2];
+        const T r0 = rb0 - a[0], r1 = rb1 - a[1], r2 = rb2 - a[2];
         if (OP == FOP_RESID) {
           y[0] = TY(r0);
           y[1] = TY(r1);
           y[2] = TY(r2);
         } else {
-          const T* D = fD<T>(L) + 9 * n;
           y[0] = TY(own0 + omega * (D[0] * r0 + D[1] * r1 + D[2] * r2));
           y[1] = TY(own1 + omega * (D[3] * r0 + D[4] * r1 + D[5] * r2));
           y[2] = TY(own2 + omega * (D[6] * r0 + D[7] * r1 + D[8] * r2));
@@ -418,9 +569,35 @@ int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>
   return TG_OK;
 }
 
-int fine_tiles(const tg_grid* g) { return zm_tiles(g, 0); }
-int zm_tiles(const tg_grid* g, int l) {
-  return fz_tiles(g->lv[l].ex + 1, g->lv[l].ey + 1, g->lv[l].ez + 1);
+// Balanced height for a column of NZ node layers with at most zmax per tile.
+int zm_height(int NZ, int zmax) {
+  const int ntz = (NZ + zmax - 1) / zmax;
+  return (NZ + ntz - 1) / ntz;
+}
+int zm_tiles(const tg_grid* g, int l, int zmax) {
+  const int NZ = g->lv[l].ez + 1;
+  return fz_tiles(g->lv[l].ex + 1, g->lv[l].ey + 1, NZ, zm_height(NZ, zmax));
+}
+
+// Per level, the tallest z-tile in {16, 12, 8, 6, 4} that gives >= 2048
+// workgroups over the whole batch, else 4.  Every tile recomputes one element
+// layer, so taller tiles do less redundant work; shorter tiles give more
+// parallelism.
+void batch_choose_zc(Batch* b) {
+  const int cand[5] = {16, 12, 8, 6, 4};
+  for (int l = 0; l < TG_MAXLEV; ++l) {
+    int pick = 4;
+    for (int c : cand) {
+      long long tiles = 0;
+      for (auto* g : b->grids)
+        if (l < g->nlev) tiles += zm_tiles(g, l, c);
+      if (tiles >= 2048) {
+        pick = c;
+        break;
+      }
+    }
+    b->zc[l] = pick;
+  }
 }
 
 template <class T> static ModeCoef<T> mcoef(const tg_grid* g);
@@ -456,6 +633,28 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
 }
 template int launch_fine<double>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
                                  int, void*, double, hipStream_t);
+
+// Level 0 with the BF16 matrix-core contraction (FP32 vectors): op as above.
+int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,
+                     const void* eb, int sy, void* ey, double omega, bool out64, hipStream_t s) {
+  if (!dl.n) return TG_OK;
+  const ModeCoef<float> mc = mcoef<float>(b->grids[0]);
+  const ProbDesc* desc = b->desc_d;
+  const float om = float(omega);
+#define TG_MF(OPV, K, TYV) \
+  k_fine_zm<float, OPV, K, TYV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc)
+  if (out64) {
+    if (split) TG_MF(FOP_SMOOTH, 3, double); else TG_MF(FOP_SMOOTH, 2, double);
+  } else if (op == FOP_APPLY) {
+    if (split) TG_MF(FOP_APPLY, 3, float); else TG_MF(FOP_APPLY, 2, float);
+  } else if (op == FOP_RESID) {
+    if (split) TG_MF(FOP_RESID, 3, float); else TG_MF(FOP_RESID, 2, float);
+  } else {
+    if (split) TG_MF(FOP_SMOOTH, 3, float); else TG_MF(FOP_SMOOTH, 2, float);
+  }
+#undef TG_MF
+  return TG_OK;
+}
 
 // Level-0 smoothing sweep whose output goes to an FP64 slot (the V-cycle's
 // last post-sweep writing the Krylov vector z_j directly).

@@ -136,8 +136,8 @@ static size_t list_capacity(const std::vector<tg_grid*>& gs) {
       c += (l == 0) ? (g->lv[0].n_elem + 255) / 256 : g->lv[l].n_elem;
     }
     c += g->lv[0].n_chunks + 1;
-    for (int l = 0; l < g->nlev; ++l) c += zm_tiles(g, l);
-    c += fine_tiles(g);
+    for (int l = 0; l < g->nlev; ++l) c += zm_tiles(g, l, 1);
+    c += zm_tiles(g, 0, 1);
   }
   return c;
 }
@@ -215,6 +215,7 @@ int batch_init(Batch* b, int n, tg_grid* const* grids) {
   }
   b->sc_h.assign(n + 8, 0.0);
   b->host_desc.resize(n);
+  batch_choose_zc(b);
   return TG_OK;
 }
 
@@ -229,7 +230,11 @@ int batch_bind(Batch* b, void* ws, size_t bytes) {
 }
 
 int batch_upload_desc(Batch* b, hipStream_t s) {
-  for (int p = 0; p < b->n; ++p) b->host_desc[p] = b->grids[p]->desc;
+  for (int p = 0; p < b->n; ++p) {
+    b->host_desc[p] = b->grids[p]->desc;
+    for (int l = 0; l < b->grids[p]->nlev; ++l)
+      b->host_desc[p].lv[l].zc = zm_height(b->grids[p]->lv[l].ez + 1, b->zc[l]);
+  }
   TG_HIP(hipMemcpyAsync(b->desc_d, b->host_desc.data(), sizeof(ProbDesc) * b->n, hipMemcpyHostToDevice, s));
   return TG_OK;
 }
@@ -290,14 +295,14 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   finish(b->prob, o);
   o = begin();
   for (int p : active)
-    for (int t = 0, nt = fine_tiles(b->grids[p]); t < nt; ++t) H.push_back(make_int2(p, t));
+    for (int t = 0, nt = zm_tiles(b->grids[p], 0, b->zc[0]); t < nt; ++t) H.push_back(make_int2(p, t));
   finish(b->fine, o);
   for (int l = 0; l < TG_MAXLEV; ++l) {
     o = begin();
     if (l <= TG_MF_LEVELS)
       for (int p : active)
         if (l < b->grids[p]->nlev - 1)
-          for (int t = 0, nt = zm_tiles(b->grids[p], l); t < nt; ++t) H.push_back(make_int2(p, t));
+          for (int t = 0, nt = zm_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_s[l], o);
   }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");
@@ -369,6 +374,7 @@ int grid_setup(int nx, int ny, int nz, double E0, double nu, const tg_mg_opts* m
     H.n_dof = 3 * H.n_nodes;
     H.stride = stride_of(H.n_dof);
     H.n_chunks = (int)((H.n_dof + TG_VCHUNK - 1) / TG_VCHUNK);
+    H.zc = 16;
   }
   g->ncoarse = g->coarse_ok ? cfree : 0;
   g->ncoarse_true = cfree;

@@ -26,6 +26,19 @@
 
 namespace tg {
 
+// Device pointers taken from descriptors have no known address space, so the
+// compiler emits flat memory instructions for them (which also count against
+// the LDS wait counter).  gp() re-tags a pointer as global memory.
+#define TG_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const T TG_GLOBAL* gp(const T* p) {
+  return (const T TG_GLOBAL*)p;
+}
+template <class T>
+__device__ __forceinline__ T TG_GLOBAL* gp(T* p) {
+  return (T TG_GLOBAL*)p;
+}
+
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
@@ -43,6 +56,8 @@ struct LevelDesc {
   int NX, NY, NZ;           // nodes per dimension (= elements + 1)
   int n_nodes;
   int n_chunks;             // ceil(3 n_nodes / TG_VCHUNK)
+  int zc;                   // z-tile height (node layers) of the z-march kernels
+  int pad_;
   long long stride;         // slot stride in elements (>= 3 n_nodes, 64-aligned)
   double* vec64;
   float* vec32;
@@ -116,6 +131,7 @@ struct LevelHost {
   int ex, ey, ez;
   long long n_elem, n_nodes, n_dof, stride;
   int n_chunks;
+  int zc;                   // z-tile height of the z-march kernels
 };
 
 struct Batch;
@@ -176,6 +192,7 @@ struct Batch {
   DevList zm_s[TG_MAXLEV];        // level-l z-march tiles, problems where l is not the coarsest
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
+  int zc[TG_MAXLEV] = {};         // z-tile height per level for this batch
 };
 
 size_t batch_ws_bytes_for(const std::vector<tg_grid*>& grids);
@@ -216,13 +233,21 @@ void timer_harvest();
 
 // fine-level z-march kernels (tg_fine.hip)
 int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>* out32);
-int fine_tiles(const tg_grid* g);
-int zm_tiles(const tg_grid* g, int l);
+int zm_height(int NZ, int zmax);
+int zm_tiles(const tg_grid* g, int l, int zmax);
+void batch_choose_zc(Batch* b);
 template <class T>
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
                 const void* eb, int sy, void* ey, double omega, hipStream_t s);
 int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, int sy, double omega,
                              hipStream_t s);
+int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,
+                     const void* eb, int sy, void* ey, double omega, bool out64, hipStream_t s);
+
+// autotuner (tg_autotune.hip)
+std::string batch_signature(const Batch* b, int prec);
+bool autotune_lookup(Batch* b, int prec);
+int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool force);
 
 // host helpers (tg_host.cpp)
 void build_ke(double E0, double nu, double* Ke);

@@ -17,8 +17,8 @@ template <> __device__ __forceinline__ float* pool<float>(const LevelDesc& L) { 
 
 // slot >= 0: slot of the pool of type T at this level; slot < 0: external pointer
 template <class T>
-__device__ __forceinline__ T* vslot(const LevelDesc& L, int slot, const void* ext) {
-  return slot < 0 ? (T*)ext : pool<T>(L) + (long long)slot * L.stride;
+__device__ __forceinline__ T TG_GLOBAL* vslot(const LevelDesc& L, int slot, const void* ext) {
+  return gp(slot < 0 ? (T*)ext : pool<T>(L) + (long long)slot * L.stride);
 }
 template <class T> __device__ __forceinline__ const T* Kel(const LevelDesc& L);
 template <> __device__ __forceinline__ const double* Kel<double>(const LevelDesc& L) { return L.Kel64; }
@@ -287,14 +287,14 @@ __global__ __launch_bounds__(256) void k_node_op(const ProbDesc* __restrict__ pr
   if (n >= L.n_nodes) return;
   const int NX = L.NX, NY = L.NY;
   const int i = n % NX, t = n / NX, j = t % NY, k = t / NY;
-  TY* y = vslot<TY>(L, sy, ey_);
+  auto* y = vslot<TY>(L, sy, ey_);
   if (i == 0) {
     y[3LL * n] = TY(0);
     y[3LL * n + 1] = TY(0);
     y[3LL * n + 2] = TY(0);
     return;
   }
-  const TX* x = vslot<TX>(L, sx, ex_);
+  const auto* x = vslot<TX>(L, sx, ex_);
   T a0 = T(0), a1 = T(0), a2 = T(0);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_node_op(const ProbDesc* __restrict__ pr
     y[3LL * n + 1] = TY(a1);
     y[3LL * n + 2] = TY(a2);
   } else {
-    const TB* b = vslot<TB>(L, sb, eb_);
+    const auto* b = vslot<TB>(L, sb, eb_);
     const T r0 = T(b[3LL * n]) - a0, r1 = T(b[3LL * n + 1]) - a1, r2 = T(b[3LL * n + 2]) - a2;
     if (OP == OP_RESID) {
       y[3LL * n] = TY(r0);
@@ -355,12 +355,12 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict
   const LevelDesc& L = P.lv[l];
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
   if (n >= L.n_nodes) return;
-  const TB* b = vslot<TB>(L, sb, eb_);
-  T* x = vslot<T>(L, sx, nullptr);
+  const auto* b = vslot<TB>(L, sb, eb_);
+  auto* x = vslot<T>(L, sx, nullptr);
   T b0 = T(b[3LL * n]), b1 = T(b[3LL * n + 1]), b2 = T(b[3LL * n + 2]);
   if (n % L.NX == 0) b0 = b1 = b2 = T(0);
   if (sbT != INT_MIN) {
-    T* bT = vslot<T>(L, sbT, nullptr);
+    auto* bT = vslot<T>(L, sbT, nullptr);
     bT[3LL * n] = b0;
     bT[3LL * n + 1] = b1;
     bT[3LL * n + 2] = b2;
@@ -383,10 +383,10 @@ __global__ __launch_bounds__(256) void k_restrict(const ProbDesc* __restrict__ p
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
   if (n >= Lc.n_nodes) return;
   const int I = n % Lc.NX, t = n / Lc.NX, J = t % Lc.NY, K = t / Lc.NY;
-  T* b = vslot<T>(Lc, sb, nullptr);
+  auto* b = vslot<T>(Lc, sb, nullptr);
   T s0 = T(0), s1 = T(0), s2 = T(0);
   if (I > 0) {
-    const T* r = vslot<T>(Lf, sr, nullptr);
+    const auto* r = vslot<T>(Lf, sr, nullptr);
     for (int dk = -1; dk <= 1; ++dk) {
       const int fk = 2 * K + dk;
       if (fk < 0 || fk >= Lf.NZ) continue;
@@ -423,8 +423,8 @@ __global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ pr
   if (n >= Lf.n_nodes) return;
   const int i = n % Lf.NX, t = n / Lf.NX, j = t % Lf.NY, k = t / Lf.NY;
   if (i == 0) return;
-  const T* e = vslot<T>(Lc, se, nullptr);
-  T* x = vslot<T>(Lf, sx, nullptr);
+  const auto* e = vslot<T>(Lc, se, nullptr);
+  auto* x = vslot<T>(Lf, sx, nullptr);
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
   const T wi_ = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
   T s0 = T(0), s1 = T(0), s2 = T(0);
@@ -454,8 +454,8 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const ProbDesc* __restrict
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& L = P.lv[l];
   const int n = P.ncoarse;
-  const TB* b = vslot<TB>(L, sb, eb_);
-  TY* y = vslot<TY>(L, sy, ey_);
+  const auto* b = vslot<TB>(L, sb, eb_);
+  auto* y = vslot<TY>(L, sy, ey_);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const int c = q % 3, fn = q / 3;
     const int i = fn % (L.NX - 1) + 1, t = fn / (L.NX - 1);
@@ -489,8 +489,8 @@ __global__ __launch_bounds__(256) void k_copy_level(const ProbDesc* __restrict__
   const LevelDesc& L = P.lv[l];
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
   if (n >= L.n_nodes) return;
-  const TA* a = vslot<TA>(L, sa, ea);
-  TB* b = vslot<TB>(L, sb, eb);
+  const auto* a = vslot<TA>(L, sa, ea);
+  auto* b = vslot<TB>(L, sb, eb);
   const bool clamp = (n % L.NX) == 0;
   for (int c = 0; c < 3; ++c) b[3LL * n + c] = clamp ? TB(0) : TB(a[3LL * n + c]);
 }
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(256) void k_copy_ext_(const ProbDesc* __restrict__ 
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  double* v = L.vec64 + (long long)slot * L.stride;
+  auto* v = gp(L.vec64 + (long long)slot * L.stride);
   for (long long q = lo + threadIdx.x; q < hi; q += 256) {
     if (dir == 0) {
       const long long node = q / 3;
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void k_fill0_(const ProbDesc* __restrict__ pro
   const LevelDesc& L = probs[wi.x].lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  double* v = L.vec64 + (long long)slot * L.stride;
+  auto* v = gp(L.vec64 + (long long)slot * L.stride);
   for (long long q = lo + threadIdx.x; q < hi; q += 256) v[q] = val;
 }
 
@@ -539,8 +539,8 @@ __global__ __launch_bounds__(256) void k_copy0_(const ProbDesc* __restrict__ pro
   const LevelDesc& L = probs[wi.x].lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  const double* a = L.vec64 + (long long)src * L.stride;
-  double* b = L.vec64 + (long long)dst * L.stride;
+  const auto* a = gp(L.vec64 + (long long)src * L.stride);
+  auto* b = gp(L.vec64 + (long long)dst * L.stride);
   for (long long q = lo + threadIdx.x; q < hi; q += 256) b[q] = a[q];
 }
 
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_multidot_(const ProbDesc* __restrict__ 
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  const double* w = L.vec64 + (long long)sw * L.stride;
+  const auto* w = gp(L.vec64 + (long long)sw * L.stride);
   double wr[TG_VCHUNK / 256];
 #pragma unroll
   for (int q = 0; q < TG_VCHUNK / 256; ++q) {
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256) void k_multidot_(const ProbDesc* __restrict__ 
       s[g] = 0.0;
       const int k = k0 + g;
       if (k < ntot) {
-        const double* v = (k < nv) ? L.vec64 + (long long)(sbase + k) * L.stride : w;
+        const auto* v = (k < nv) ? gp(L.vec64 + (long long)(sbase + k) * L.stride) : w;
 #pragma unroll
         for (int q = 0; q < TG_VCHUNK / 256; ++q) {
           const long long idx = lo + threadIdx.x + 256LL * q;
@@ -627,14 +627,14 @@ __global__ __launch_bounds__(256) void k_update_(const ProbDesc* __restrict__ pr
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  double* w = L.vec64 + (long long)sw * L.stride;
+  auto* w = gp(L.vec64 + (long long)sw * L.stride);
   const double* coef = P.small + coef_off;
   double acc[TG_VCHUNK / 256];
 #pragma unroll
   for (int q = 0; q < TG_VCHUNK / 256; ++q) acc[q] = 0.0;
   for (int k = 0; k < nv; ++k) {
     const double ck = coef[k];
-    const double* v = L.vec64 + (long long)(sbase + k) * L.stride;
+    const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
 #pragma unroll
     for (int q = 0; q < TG_VCHUNK / 256; ++q) {
       const long long idx = lo + threadIdx.x + 256LL * q;
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(256) void k_update_dots_(const ProbDesc* __restrict
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  double* w = L.vec64 + (long long)sw * L.stride;
+  auto* w = gp(L.vec64 + (long long)sw * L.stride);
   const double* coef = P.small + coef_off;
   double wr[TG_VCHUNK / 256];
 #pragma unroll
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(256) void k_update_dots_(const ProbDesc* __restrict
     for (int q = 0; q < TG_VCHUNK / 256; ++q) acc[q] = 0.0;
     for (int k = 0; k < nv; ++k) {
       const double ck = coef[k];
-      const double* v = L.vec64 + (long long)(sbase + k) * L.stride;
+      const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
 #pragma unroll
       for (int q = 0; q < TG_VCHUNK / 256; ++q) {
         const long long idx = lo + threadIdx.x + 256LL * q;
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(256) void k_update_dots_(const ProbDesc* __restrict
       const int k = k0 + g;
       if (k < ntot) {
         if (k < ndot) {
-          const double* v = L.vec64 + (long long)(sbase + k) * L.stride;
+          const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
 #pragma unroll
           for (int q = 0; q < TG_VCHUNK / 256; ++q) {
             const long long idx = lo + threadIdx.x + 256LL * q;
@@ -738,8 +738,8 @@ __global__ __launch_bounds__(256) void k_update_dots_reg_(const ProbDesc* __rest
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
-  double* w = L.vec64 + (long long)sw * L.stride;
-  const double* V0 = L.vec64 + (long long)sbase * L.stride;
+  auto* w = gp(L.vec64 + (long long)sw * L.stride);
+  const auto* V0 = gp(L.vec64 + (long long)sbase * L.stride);
   const long long st = L.stride;
   const double* coef = P.small + coef_off;
   double cf[NVR], acc[NVR + 1];
@@ -796,8 +796,8 @@ __global__ __launch_bounds__(256) void k_scale_(const ProbDesc* __restrict__ pro
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
   const double a = P.small[sidx];
-  const double* s = L.vec64 + (long long)src * L.stride;
-  double* d = L.vec64 + (long long)dst * L.stride;
+  const auto* s = gp(L.vec64 + (long long)src * L.stride);
+  auto* d = gp(L.vec64 + (long long)dst * L.stride);
   for (long long q = lo + threadIdx.x; q < hi; q += 256) d[q] = s[q] * a;
 }
 
@@ -932,13 +932,13 @@ __global__ __launch_bounds__(256) void k_xupdate_(const ProbDesc* __restrict__ p
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
   const int jd = (int)P.small[o.scal + SC_JDONE];
-  double* x = L.vec64 + (long long)S_X * L.stride;
+  auto* x = gp(L.vec64 + (long long)S_X * L.stride);
   double acc[TG_VCHUNK / 256];
 #pragma unroll
   for (int q = 0; q < TG_VCHUNK / 256; ++q) acc[q] = 0.0;
   for (int jj = 0; jj < jd; ++jj) {
     const double yj = P.small[o.y + jj];
-    const double* z = L.vec64 + (long long)(sz0 + jj) * L.stride;
+    const auto* z = gp(L.vec64 + (long long)(sz0 + jj) * L.stride);
 #pragma unroll
     for (int q = 0; q < TG_VCHUNK / 256; ++q) {
       const long long idx = lo + threadIdx.x + 256LL * q;
@@ -1048,7 +1048,11 @@ static double op_bytes(const Batch* b, int l, int lmode, int op) {
 }
 
 int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s) {
-  if (prec == TG_F64)
+  if (prec == TG_BF16MFMA || prec == TG_BF16X3MFMA)
+    TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<float>(b, 0, 0, OP_APPLY)),
+             launch_fine_mfma(b, b->fine, OP_APPLY, prec == TG_BF16X3MFMA, sx, ex, 0, nullptr, sy, ey, 0.0,
+                              false, s));
+  else if (prec == TG_F64)
     TG_TIMED(TG_KT_APPLY_F64, (op_bytes<double>(b, 0, 0, OP_APPLY)),
              launch_fine<double>(b, b->fine, 0, OP_APPLY, sx, ex, 0, nullptr, sy, ey, 0.0, s));
   else
@@ -1063,9 +1067,14 @@ int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
   return check_launch("residual");
 }
 
+// mf: 0 = vector mode-basis contraction, 1 = BF16 matrix cores, 2 = split BF16
 template <class T, int OP>
-static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om, hipStream_t s) {
-  if (l == 0)
+static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om, hipStream_t s, int mf = 0) {
+  if (l == 0 && mf)
+    TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
+             launch_fine_mfma(b, b->zm_s[0], OP, mf == 2, x, nullptr, bs, nullptr, y, nullptr, (double)om,
+                              false, s));
+  else if (l == 0)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
              launch_fine<T>(b, b->zm_s[0], 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
   else if (l <= TG_MF_LEVELS)
@@ -1082,7 +1091,7 @@ static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om
 // external ey, double unless out_is_f32).
 template <class T>
 static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
-                    void* ey, hipStream_t s) {
+                    void* ey, hipStream_t s, int mf) {
   const tg_mg_opts& mg = b->grids[0]->mg;
   const T om = T(mg.omega);
   const bool f64 = sizeof(T) == 8;
@@ -1132,10 +1141,10 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
                k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om));
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
-      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s);
+      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s, mf);
       std::swap(c, o);
     }
-    vc_op<T, OP_RESID>(b, l, sm, c, Bs, Rs, om, s);
+    vc_op<T, OP_RESID>(b, l, sm, c, Bs, Rs, om, s, mf);
     if (b->node[l + 1].n) {
       double cn, ce, cc;
       level_sums(b, l + 1, 0, cn, ce, cc);
@@ -1156,12 +1165,17 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
              k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN));
     for (int it = 0; it < mg.nu_post; ++it) {
       if (l == 0 && fast_out && it == mg.nu_post - 1) {
-        TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP_SMOOTH) + 3.0 * nodes * (8.0 - sT)),
-                 launch_fine_smooth_out64(b, b->zm_s[0], c, Bs, sy, (double)om, s));
+        if (mf)
+          TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP_SMOOTH) + 3.0 * nodes * (8.0 - sT)),
+                   launch_fine_mfma(b, b->zm_s[0], OP_SMOOTH, mf == 2, c, nullptr, Bs, nullptr, sy, nullptr,
+                                    (double)om, true, s));
+        else
+          TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP_SMOOTH) + 3.0 * nodes * (8.0 - sT)),
+                   launch_fine_smooth_out64(b, b->zm_s[0], c, Bs, sy, (double)om, s));
         c = -1;   // result is in the output slot
         break;
       }
-      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s);
+      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s, mf);
       std::swap(c, o);
     }
     cur[l] = c;
@@ -1181,8 +1195,9 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
 
 int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
              void* ey, hipStream_t s) {
-  if (prec == TG_F64) return vcycle_t<double>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s);
-  return vcycle_t<float>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s);
+  if (prec == TG_F64) return vcycle_t<double>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, 0);
+  const int mf = prec == TG_BF16MFMA ? 1 : prec == TG_BF16X3MFMA ? 2 : 0;
+  return vcycle_t<float>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, mf);
 }
 
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s) {

@@ -69,8 +69,8 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
   if (m < 1 || m > mmax) return fail(TG_EINVAL, "restart must be in [1, bound max_restart]");
   if (cap < 0 || cap > TG_HIST_CAP - 1) return fail(TG_EINVAL, "max_iters out of range");
   if (o->cgs_passes < 1 || o->cgs_passes > 2) return fail(TG_EINVAL, "cgs_passes must be 1 or 2");
-  if (o->prec != TG_F64 && o->prec != TG_F32)
-    return fail(TG_EINVAL, "preconditioner precision not available");
+  if (o->prec < TG_F64 || o->prec > TG_BF16X3MFMA)
+    return fail(TG_EINVAL, "unknown preconditioner precision");
   const double tol = o->tol, brk = o->breakdown;
   int rc = check_ready(b, which, true);
   if (rc) return rc;
@@ -345,7 +345,7 @@ int tg_apply_K(const tg_grid* gc, const void* u_d, void* y_d, int prec, void* st
   tg_grid* g = const_cast<tg_grid*>(gc);
   if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
   if (!u_d || !y_d) return fail(TG_EINVAL, "NULL vector");
-  if (prec != TG_F64 && prec != TG_F32) return fail(TG_EINVAL, "precision not available");
+  if (prec < TG_F64 || prec > TG_BF16X3MFMA) return fail(TG_EINVAL, "unknown precision");
   int rc = check_ready(g->self, {0});
   if (rc) return rc;
   if ((rc = batch_set_active(g->self, {0}, S(stream)))) return rc;
@@ -355,7 +355,7 @@ int tg_apply_K(const tg_grid* gc, const void* u_d, void* y_d, int prec, void* st
 int tg_vcycle(tg_grid* g, const void* r_d, void* z_d, int prec, void* stream) {
   if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
   if (!r_d || !z_d) return fail(TG_EINVAL, "NULL vector");
-  if (prec != TG_F64 && prec != TG_F32) return fail(TG_EINVAL, "precision not available");
+  if (prec < TG_F64 || prec > TG_BF16X3MFMA) return fail(TG_EINVAL, "unknown precision");
   int rc = check_ready(g->self, {0}, true);
   if (rc) return rc;
   if ((rc = batch_set_active(g->self, {0}, S(stream)))) return rc;
@@ -499,6 +499,24 @@ int tg_batch_solve(tg_batch* tb, const double* const* f_d, double* const* u_d, c
   }
   return copy_out_batch(b, all, u_d, S_X, s);
 }
+int tg_batch_autotune(tg_batch* tb, int prec, int force, int* zc_out, double* us_out, void* stream) {
+  if (!tb) return fail(TG_EINVAL, "NULL batch");
+  if (!tb->b.ws) return fail(TG_EWORKSPACE, "batch workspace not bound");
+  const int rc = autotune_batch(&tb->b, prec, S(stream), us_out, force != 0);
+  if (rc) return rc;
+  if (zc_out)
+    for (int l = 0; l < TG_MAXLEV; ++l) zc_out[l] = tb->b.zc[l];
+  return TG_OK;
+}
+int tg_autotune(tg_grid* g, int prec, int force, int* zc_out, double* us_out, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  const int rc = autotune_batch(g->self, prec, S(stream), us_out, force != 0);
+  if (rc) return rc;
+  if (zc_out)
+    for (int l = 0; l < TG_MAXLEV; ++l) zc_out[l] = g->self->zc[l];
+  return TG_OK;
+}
+
 int tg_batch_select_floor(tg_batch* tb, const double* const* rho_d, const double* const* f_d,
                           const tg_policy* pol, double* const* u_d, tg_policy_result* out,
                           void* stream) {

@@ -13,7 +13,7 @@ import torch
 from . import _lib as L
 from ._lib import check, lib
 
-F64, F32, BF16MFMA = L.TG_F64, L.TG_F32, L.TG_BF16MFMA
+F64, F32, BF16MFMA, BF16X3MFMA = L.TG_F64, L.TG_F32, L.TG_BF16MFMA, L.TG_BF16X3MFMA
 OUTCOMES = {0: "PROJ_CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NONFINITE"}
 
 
@@ -164,6 +164,11 @@ class Grid:
                                       C.byref(r100), C.byref(ks), _stream()))
         return r50.value, r100.value, ks.value
 
+    def autotune(self, prec=F32, force=False):
+        zc, us = (C.c_int * 8)(), (C.c_double * 8)()
+        check(lib().tg_autotune(self.handle, prec, int(force), zc, us, _stream()))
+        return list(zc)[:self.n_levels], list(us)[:self.n_levels]
+
     def select_floor(self, rho, f, pol):
         u = torch.empty_like(f)
         out = L.PolicyResult()
@@ -209,6 +214,11 @@ class Batch:
         check(lib().tg_batch_solve(self.handle, self._ptrs(fs), self._ptrs(us), C.byref(opts), res,
                                    _stream()))
         return us, [result_dict(r) for r in res]
+
+    def autotune(self, prec=F32, force=False):
+        zc, us = (C.c_int * 8)(), (C.c_double * 8)()
+        check(lib().tg_batch_autotune(self.handle, prec, int(force), zc, us, _stream()))
+        return list(zc), list(us)
 
     def select_floor(self, rhos, fs, pol):
         us = [torch.empty_like(f) for f in fs]

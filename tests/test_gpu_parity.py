@@ -306,3 +306,105 @@ def test_mixed_policy_matches_oracle_rungs():
         free = og.free_dofs()
         K = op.free_block(op.assemble(og, op.young(rho, 3.0, rungs[out["rung"]]), KE), free)
         assert op.relative_residual(K, og.edge_load()[free], u.cpu().numpy()[free]) <= 1e-6
+
+
+@pytest.mark.parametrize("dims,kind,rmin", [((16, 8, 8), "uniform", 1e-3), ((17, 9, 7), "uniform", 1e-3),
+                                            ((24, 12, 12), "blob", 1e-6)])
+def test_apply_K_bf16_matrix_cores(dims, kind, rmin):
+    """BF16 inputs (u and Ke rounded to 8-bit significands) with FP32
+    accumulation: each product is off by at most ~2^-8 relative twice, so
+    |y - y_ref| <= 2^-7 (|K||u|); split BF16 keeps ~16 bits: 2^-13 (|K||u|)."""
+    rho = _field(kind, dims, 11)
+    og, free, E, K = _case(dims, rho, 3.0, rmin)
+    g = _gpu_grid(dims, rho, 3.0, rmin)
+    u = np.random.default_rng(5).standard_normal(og.n_dof)
+    y_ref = np.zeros(og.n_dof)
+    y_ref[free] = K @ u[free]
+    bound = np.zeros(og.n_dof)
+    bound[free] = abs(K) @ np.abs(u[free])
+    ut = torch.tensor(u, dtype=torch.float32, device=DEV)
+    y1 = g.apply_K(ut, tg.BF16MFMA).cpu().numpy()
+    y3 = g.apply_K(ut, tg.BF16X3MFMA).cpu().numpy()
+    assert np.all(np.abs(y1 - y_ref) <= 2.0 ** -7 * bound + 1e-30)
+    assert np.all(np.abs(y3 - y_ref) <= 2.0 ** -13 * bound + 1e-30)
+    assert np.all(y1[~free] == 0) and np.all(y3[~free] == 0)
+    # the BF16 result is not the FP32 result: the matrix cores really ran
+    y32 = g.apply_K(ut, tg.F32).cpu().numpy()
+    assert np.abs(y1 - y32).max() > 0
+
+
+@pytest.mark.parametrize("prec", ["BF16MFMA", "BF16X3MFMA"])
+def test_bf16_vcycle_and_solve_certified(prec):
+    """Plain BF16 rounds Ke, which breaks its exact rigid-body null space: on
+    high-contrast states the preconditioner may then stall.  Failure must be
+    visible (an outcome, not an acceptance) and the FP64 guard must agree with
+    the oracle.  Split BF16 (~16 bits) must converge and be certified."""
+    dims, rmin = (32, 16, 16), 1e-4
+    rho = synth.blobs(*dims, 1001)
+    g = _gpu_grid(dims, rho, 3.0, rmin)
+    b = np.random.default_rng(1).standard_normal(g.n_dof)
+    z_ref, H = _oracle_vcycle(dims, rho, rmin, b)
+    z = g.vcycle(torch.tensor(b, dtype=torch.float32, device=DEV), getattr(tg, prec)).cpu().numpy()
+    tol = 0.05 if prec == "BF16MFMA" else 2e-3
+    assert np.abs(z - z_ref).max() <= tol * np.abs(z_ref).max()
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    ff = og.edge_load()[free]
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist = g.fgmres_solve(f, tg.solver_opts(prec=getattr(tg, prec)))
+    uf = u.cpu().numpy()[free]
+    eta_o = op.relative_residual(H[0].K, ff, uf)
+    bnd = 2 * op.residual_bound(H[0].K, ff, uf)
+    assert abs(g.true_residual(f, u) - eta_o) <= bnd
+    if prec == "BF16X3MFMA" or res["outcome"] == "PROJ_CONVERGED":
+        assert res["outcome"] == "PROJ_CONVERGED"
+        assert eta_o <= 1e-6 + bnd
+    else:
+        assert res["outcome"] in ("MAXIT", "BREAKDOWN") and res["proj_eta"] > 1e-6
+
+
+AUTOTUNE_CANDIDATES = {2, 3, 4, 6, 8, 12, 16}
+
+
+def test_autotune_changes_only_the_decomposition():
+    dims = (32, 16, 16)
+    rho = _field("blob", dims, 21)
+    g = _gpu_grid(dims, rho, 3.0, 1e-4)
+    rng = np.random.default_rng(8)
+    u64 = torch.tensor(rng.standard_normal(g.n_dof), device=DEV)
+    u32 = u64.float()
+    before = [g.apply_K(u64, tg.F64), g.apply_K(u32, tg.F32), g.vcycle(u64, tg.F64), g.vcycle(u32, tg.F32)]
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u0, r0, _ = g.fgmres_solve(f, tg.solver_opts(prec=tg.F32))
+    zc, us = g.autotune(tg.F32, force=True)
+    assert all(z in AUTOTUNE_CANDIDATES for z in zc[:2])
+    assert us[0] > 0 and us[1] > 0
+    after = [g.apply_K(u64, tg.F64), g.apply_K(u32, tg.F32), g.vcycle(u64, tg.F64), g.vcycle(u32, tg.F32)]
+    for a, b in zip(before, after):
+        # every node sums its element contributions in one fixed order whatever the tiling
+        assert torch.equal(a, b)
+    u1, r1, _ = g.fgmres_solve(f, tg.solver_opts(prec=tg.F32))
+    assert r1["iterations"] == r0["iterations"] and torch.equal(u0, u1)
+    # a second call finds the cached choice and times nothing
+    zc2, us2 = g.autotune(tg.F32)
+    assert zc2 == zc and all(x == -1.0 for x in us2)
+
+
+def test_autotuned_uneven_batch_equals_untuned():
+    dims_list = [(32, 16, 16), (48, 24, 24), (16, 8, 8), (32, 16, 16)]
+    rhos = [synth.blobs(*d, 40 + i, blob=4) for i, d in enumerate(dims_list)]
+    floors = [1e-3, 1e-4, 1e-3, 1e-6]
+    fs, res = [], []
+    for tune in (False, True):
+        grids = [tg.Grid(*d, max_restart=30, device=DEV) for d in dims_list]
+        batch = tg.Batch(grids)
+        batch.set_density([torch.tensor(r, device=DEV) for r in rhos], 3.0, floors)
+        if tune:
+            zc, us = batch.autotune(tg.F32, force=True)
+            assert zc[0] in AUTOTUNE_CANDIDATES and us[0] > 0
+        fs = [torch.tensor(g.edge_load(), device=DEV) for g in grids]
+        res.append(batch.solve(fs, tg.solver_opts(prec=tg.F32)))
+    (ua, ra), (ub, rb) = res
+    for i in range(len(dims_list)):
+        assert ra[i]["iterations"] == rb[i]["iterations"]
+        assert torch.equal(ua[i], ub[i])
