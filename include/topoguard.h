@@ -183,6 +183,8 @@ typedef struct {
   int fixed_rung;                /* for TG_SELECT_FIXED                        */
   const tg_mlp* mlp;             /* for TG_SELECT_MLP (rule if NULL)           */
   tg_solver_opts solve;          /* per-rung solves (restart 30, cap 200, ...) */
+  int want_features;             /* nonzero: fill the six density statistics of
+                                    tg_policy_result.features with any selector */
 } tg_policy;
 
 typedef struct {
@@ -242,8 +244,13 @@ int tg_batch_autotune(tg_batch* b, int prec, int force, int* zc_out, double* us_
 int tg_autotune(tg_grid* g, int prec, int force, int* zc_out, double* us_out, void* stream);
 
 /* ---- learned first-floor selector (addition (4)) ------------------------- */
-/* 8 -> 64 -> 64 -> 4 MLP, exact-erf GELU, softmax cross-entropy, Adam.
- * Parameters and optimizer state live in the caller-bound workspace. */
+/* 8 -> 64 -> 64 -> 4 MLP, exact-erf GELU, softmax cross-entropy, Adam
+ * (beta = 0.9, 0.999, eps = 1e-8).  Input: log10 r50, log10 r100 and the six
+ * density statistics below, standardized as (x - mean) / std; output: logits
+ * over the ladder rungs, argmax with ties to the lower rung.  Parameters,
+ * optimizer state and staging live in the caller-bound workspace; max_batch
+ * bounds the selector's internal batch (forward/train take any B, train
+ * reduces over at most 256 per-wave partials).  set_params resets Adam. */
 int tg_mlp_workspace_bytes(int max_batch, size_t* bytes);
 int tg_mlp_create(void* ws_d, size_t bytes, int max_batch, tg_mlp** out);
 void tg_mlp_destroy(tg_mlp* m);
@@ -258,6 +265,14 @@ int tg_mlp_forward(const tg_mlp* m, const float* x_d, int B, float* logits_d, vo
  * grads_d (may be NULL) receives the 4996 parameter gradients. */
 int tg_mlp_train_step(tg_mlp* m, const float* x_d, const int* y_d, int B, float lr,
                       float* loss_h, float* grads_d, void* stream);
+/* The six density statistics of a stored density field rho_d (device, n_e
+ * doubles, x-fastest) at probe floor rho0 into stats_h[6]: fraction of voxels
+ * at 0, mean, smallest nonzero value (0 if none), log10(E_max/E_min) over the
+ * nonzero voxels, fraction of the loaded-edge elements (ex = nx-1, ez = 0)
+ * 6-connected through {rho >= 0.5} to an element with ex = 0, and
+ * log10(n_DOF).  Uses the grid's own label scratch; synchronises the stream. */
+int tg_density_features(tg_grid* g, const double* rho_d, double p, double rho0, double* stats_h,
+                        void* stream);
 
 /* ---- instrumentation ----------------------------------------------------- */
 /* Kernel-class timer (process-wide): for every class whose bit is set in the

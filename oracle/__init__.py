@@ -26,8 +26,7 @@ What it computes (citations are to arXiv 2607.26382):
 
 Every function is pinned by tests under ``tests/`` against facts the paper or
 mathematics fix (closed forms, invariants, printed values, library routines on
-special cases).  Functions without such a pin say "parity unpinned" here:
-
-* ``mlp.train`` / Adam bookkeeping - parity unpinned (no printed trajectory;
-  the gradients it consumes are pinned by finite differences).
+special cases).  A function without such a pin would say "parity unpinned"
+here; at present every function has one (Adam by its closed forms: first
+step, constant-gradient steps, geometric moment averages).
 """

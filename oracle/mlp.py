@@ -6,8 +6,10 @@ cross-entropy against the lowest admissible rung.  GELU is the exact erf form
 0.5 x (1 + erf(x / sqrt 2)).  Prediction = argmax, ties -> lower rung
 (preservation first).  Weights are stored row-major as W[out][in].
 
-Adam (lr, beta1=0.9, beta2=0.999, eps=1e-8) is the textbook update;
-``adam_step`` is parity unpinned beyond matching its formula.
+Adam (lr, beta1=0.9, beta2=0.999, eps=1e-8) is the textbook update, pinned by
+its closed forms: the first step and every step under a constant gradient move
+each parameter by lr * g / (|g| + eps), and the moments equal the geometric
+averages of the gradients seen.
 """
 import math
 

@@ -44,7 +44,7 @@ class Policy(C.Structure):
                 ("tau", C.c_double), ("probe_iters", C.c_int), ("probe_restart", C.c_int),
                 ("t_high", C.c_double), ("t_plateau", C.c_double), ("t_ratio", C.c_double),
                 ("selector", C.c_int), ("fixed_rung", C.c_int), ("mlp", C.c_void_p),
-                ("solve", SolverOpts)]
+                ("solve", SolverOpts), ("want_features", C.c_int)]
 
 
 class Attempt(C.Structure):
@@ -104,6 +104,7 @@ PROTOTYPES = {
     "tg_mlp_get_params": (_I, [_P, C.POINTER(C.c_float), _P]),
     "tg_mlp_forward": (_I, [_P, _P, _I, _P, _P]),
     "tg_mlp_train_step": (_I, [_P, _P, _P, _I, C.c_float, C.POINTER(C.c_float), _P, _P]),
+    "tg_density_features": (_I, [_P, _P, _D, _D, C.POINTER(_D), _P]),
     "tg_batch_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
     "tg_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
     "tg_timer_enable": (_I, [_I]),

@@ -147,6 +147,7 @@ static void batch_layout(Bump& bp, Batch* b, int n, size_t lcap) {
   b->list_d = bp.take<int2>(lcap);
   b->sc_d = bp.take<double>(n + 8);
   b->flag_d = bp.take<int>(n + 64);
+  b->feat_d = bp.take<double>(8 * (size_t)n);
   b->list_cap = lcap;
 }
 
@@ -161,6 +162,7 @@ static void grid_layout(tg_grid* g, Bump& bp, int mmax) {
   D.Pc64 = bp.take<double>(8 * 576);
   D.E64 = bp.take<double>(g->lv[0].n_elem);
   D.E32 = bp.take<float>(g->lv[0].n_elem);
+  D.cc = bp.take<int>(2 * (size_t)g->lv[0].n_elem);
   for (int l = 0; l < g->nlev; ++l) {
     LevelDesc& L = D.lv[l];
     const LevelHost& H = g->lv[l];

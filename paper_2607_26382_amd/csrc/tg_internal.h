@@ -84,6 +84,7 @@ struct ProbDesc {
   double* part;             // reduction partials: TG_PART_W x n_chunks(level 0)
   const double* ext0;       // per-call external vectors (batched copy in/out)
   double* ext1;
+  int* cc;                  // 2 x n_elem: component labels, clamped-face flags
   LevelDesc lv[TG_MAXLEV];
 };
 
@@ -182,6 +183,7 @@ struct Batch {
   size_t list_cap = 0;            // capacity in int2
   double* sc_d = nullptr;         // device status gather (n doubles)
   int* flag_d = nullptr;          // per-problem validation flags (set_density)
+  double* feat_d = nullptr;       // per-problem density statistics (8 each)
   double p = 3.0;                 // SIMP exponent of the current set_density
   std::vector<double> sc_h;
   void* ws = nullptr;

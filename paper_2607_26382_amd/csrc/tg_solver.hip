@@ -244,8 +244,10 @@ int select_floor_batch(Batch* b, const double* const* rho_d, const double* const
     feats[i][0] = (float)std::log10(std::max(out[i].r50, 1e-300));
     feats[i][1] = (float)std::log10(std::max(out[i].r100, 1e-300));
   }
-  if (pol->selector == TG_SELECT_MLP && pol->mlp) {
+  const bool use_mlp = pol->selector == TG_SELECT_MLP && pol->mlp;
+  if (use_mlp || pol->want_features)
     if ((rc = density_features(b, all, rho_d, pol->p, pol->rungs[0], feats, s))) return rc;
+  if (use_mlp) {
     std::vector<int> pred;
     if ((rc = mlp_select(pol->mlp, feats, pred, s))) return rc;
     for (int i = 0; i < n; ++i) k0[i] = std::min(std::max(pred[i], 0), pol->n_rungs - 1);
@@ -437,6 +439,7 @@ void tg_default_policy(tg_policy* pol) {
   pol->fixed_rung = 0;
   pol->mlp = nullptr;
   tg_default_solver_opts(&pol->solve);
+  pol->want_features = 0;
 }
 
 int tg_select_floor(tg_grid* g, const double* rho_d, const double* f_d, const tg_policy* pol,

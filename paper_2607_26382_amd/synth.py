@@ -16,6 +16,9 @@ Families (their shapes follow the workloads they stand in for):
                   Gaussian tubes around seeded segments, clipped at 1.
 * ``bernoulli`` - the paper's binary stress fields: u ~ U(0,1)^n_e, solid
                   (1) where u < q, floor (0) elsewhere.
+* ``selector_state`` - the mixture the learned first-floor selector is trained
+                  and evaluated on: blob fields with a random floor fraction and
+                  blob edge, or strut fields on an exact-floor background.
 """
 import numpy as np
 
@@ -45,6 +48,8 @@ def blobs(nx, ny, nz, seed, blob=4, floor_frac=0.5, lo=0.01, hi=1.0, per_voxel=F
 
 
 def struts(nx, ny, nz, seed, n_struts=8, background=1e-3, sigma=(2.0, 6.0)):
+    """Background plus Gaussian tubes (width sigma ~ U[sigma]) around seeded
+    segments, clipped at 1."""
     rng = np.random.default_rng(seed)
     A = rng.uniform([0, 0, 0], [nx, ny, nz], size=(n_struts, 3))
     B = rng.uniform([0, 0, 0], [nx, ny, nz], size=(n_struts, 3))
@@ -82,3 +87,28 @@ def severe(seed, nx=64, ny=32, nz=32):
 def strut_field(seed, nx=256, ny=128, nz=128):
     """Optimized-like smooth field: 8 seeded Gaussian struts on a 1e-3 floor."""
     return (nx, ny, nz), struts(nx, ny, nz, seed)
+
+
+SELECTOR_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32))
+
+
+def selector_state(seed, dims=None):
+    """One state of the selector's training / held-out mixture.
+
+    The grid is drawn from SELECTOR_GRIDS unless given.  With probability 3/4
+    a blob field: floor fraction q ~ U[0.3, 0.7], blob edge in {2, 4, 8},
+    blob values U[0.01, 1]; otherwise a strut field with 4-12 struts of width
+    sigma ~ U[0.05, 0.12] * ny on a zero background, where voxels below 1e-3
+    are set to the floor (0).  Returns (dims, rho, kind)."""
+    rng = np.random.default_rng(seed)
+    if dims is None:
+        dims = SELECTOR_GRIDS[int(rng.integers(len(SELECTOR_GRIDS)))]
+    sub = int(rng.integers(2 ** 31))
+    if rng.random() < 0.75:
+        q = float(rng.uniform(0.3, 0.7))
+        edge = (2, 4, 8)[int(rng.integers(3))]
+        return dims, blobs(*dims, sub, blob=edge, floor_frac=q), "blobs"
+    n = int(rng.integers(4, 13))
+    ny = dims[1]
+    rho = struts(*dims, sub, n_struts=n, background=0.0, sigma=(0.05 * ny, 0.12 * ny))
+    return dims, np.where(rho < 1e-3, 0.0, rho), "struts"

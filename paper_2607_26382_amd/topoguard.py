@@ -41,7 +41,7 @@ def solver_opts(restart=30, max_iters=200, tol=1e-6, prec=F64, cgs_passes=2, bre
 
 def policy(rungs=(1e-9, 1e-6, 1e-4, 1e-3), p=3.0, tau=1e-6, probe_iters=100, probe_restart=100,
            t_high=1e-2, t_plateau=1e-4, t_ratio=0.6, selector=L.TG_SELECT_RULE, fixed_rung=0,
-           mlp=None, solve=None):
+           mlp=None, solve=None, want_features=False):
     pol = L.Policy()
     lib().tg_default_policy(C.byref(pol))
     pol.n_rungs = len(rungs)
@@ -53,6 +53,7 @@ def policy(rungs=(1e-9, 1e-6, 1e-4, 1e-3), p=3.0, tau=1e-6, probe_iters=100, pro
     pol.selector, pol.fixed_rung = selector, fixed_rung
     pol.mlp = mlp.handle if mlp is not None else None
     pol.solve = solve if solve is not None else solver_opts()
+    pol.want_features = int(bool(want_features))
     return pol
 
 
@@ -164,6 +165,12 @@ class Grid:
                                       C.byref(r100), C.byref(ks), _stream()))
         return r50.value, r100.value, ks.value
 
+    def density_features(self, rho, p=3.0, rho0=1e-9):
+        """Six density statistics of rho (device FP64) at probe floor rho0."""
+        out = (C.c_double * 6)()
+        check(lib().tg_density_features(self.handle, _ptr(rho), float(p), float(rho0), out, _stream()))
+        return list(out)
+
     def autotune(self, prec=F32, force=False):
         zc, us = (C.c_int * 8)(), (C.c_double * 8)()
         check(lib().tg_autotune(self.handle, prec, int(force), zc, us, _stream()))
@@ -226,6 +233,80 @@ class Batch:
         check(lib().tg_batch_select_floor(self.handle, self._ptrs(rhos), self._ptrs(fs), C.byref(pol),
                                           self._ptrs(us), out, _stream()))
         return us, [policy_dict(r) for r in out]
+
+
+SELECT_RULE, SELECT_MLP, SELECT_FIXED = L.TG_SELECT_RULE, L.TG_SELECT_MLP, L.TG_SELECT_FIXED
+N_PARAMS = 4996
+
+
+class MLP:
+    """The 8-64-64-4 first-floor selector network (tg_mlp) with its device
+    workspace; parameters in the C ABI order W1, b1, W2, b2, W3, b3."""
+
+    def __init__(self, params=None, mean=None, std=None, max_batch=4096, device="cuda"):
+        nb = C.c_size_t()
+        check(lib().tg_mlp_workspace_bytes(max_batch, C.byref(nb)))
+        self.ws, ptr = _alloc_ws(nb.value, device)
+        self.handle = C.c_void_p()
+        check(lib().tg_mlp_create(C.c_void_p(ptr), nb.value, max_batch, C.byref(self.handle)))
+        self.device = device
+        if params is not None:
+            self.set_params(params, mean, std)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().tg_mlp_destroy(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+    @staticmethod
+    def flatten(params):
+        return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in params]).astype(np.float32)
+
+    @staticmethod
+    def unflatten(flat):
+        flat = np.asarray(flat, dtype=np.float64)
+        shapes = [(64, 8), (64,), (64, 64), (64,), (4, 64), (4,)]
+        out, o = [], 0
+        for sh in shapes:
+            n = int(np.prod(sh))
+            out.append(flat[o:o + n].reshape(sh))
+            o += n
+        return out
+
+    def set_params(self, params, mean=None, std=None):
+        flat = self.flatten(params) if isinstance(params, (list, tuple)) else params
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == N_PARAMS
+        fp = C.POINTER(C.c_float)
+        mu = None if mean is None else np.ascontiguousarray(mean, dtype=np.float32)
+        sd = None if std is None else np.ascontiguousarray(std, dtype=np.float32)
+        check(lib().tg_mlp_set_params(self.handle, flat.ctypes.data_as(fp),
+                                      mu.ctypes.data_as(fp) if mu is not None else None,
+                                      sd.ctypes.data_as(fp) if sd is not None else None, _stream()))
+
+    def get_params(self):
+        out = np.zeros(N_PARAMS, dtype=np.float32)
+        check(lib().tg_mlp_get_params(self.handle, out.ctypes.data_as(C.POINTER(C.c_float)), _stream()))
+        return out
+
+    def forward(self, x):
+        """x: (B, 8) raw features (device float32) -> (B, 4) logits."""
+        x = x.contiguous()
+        out = torch.empty((x.shape[0], 4), dtype=torch.float32, device=x.device)
+        check(lib().tg_mlp_forward(self.handle, _ptr(x), x.shape[0], _ptr(out), _stream()))
+        return out
+
+    def train_step(self, x, y, lr=1e-3, want_grads=False):
+        """One Adam step on (x (B,8) float32, y (B,) int32), both on the device."""
+        x, y = x.contiguous(), y.contiguous()
+        loss = C.c_float()
+        g = torch.empty(N_PARAMS, dtype=torch.float32, device=x.device) if want_grads else None
+        check(lib().tg_mlp_train_step(self.handle, _ptr(x), _ptr(y), x.shape[0], float(lr), C.byref(loss),
+                                      _ptr(g) if g is not None else None, _stream()))
+        return (loss.value, g) if want_grads else loss.value
 
 
 # ---- kernel-class timer (instrumentation) ----------------------------------

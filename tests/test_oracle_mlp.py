@@ -77,3 +77,29 @@ def test_adam_first_step():
 def test_he_init_scale():
     params = mlp.init_params(3, sizes=(8, 4096, 2))
     assert abs(params[0].std() - math.sqrt(2 / 8)) < 0.02
+
+
+def test_adam_constant_gradient_steps_are_lr_sign():
+    # with a constant gradient the bias-corrected moments are exactly g and g^2
+    # at every step, so each step moves by lr * g / (|g| + eps); a wrong bias
+    # correction (or none) breaks this from the second step on
+    p = [np.array([0.0, 0.0, 0.0])]
+    g = [np.array([0.3, -2.0, 1e-3])]
+    st = {}
+    for t in range(1, 6):
+        mlp.adam_step(p, g, st, lr=0.01)
+        step = 0.01 * g[0] / (np.abs(g[0]) + 1e-8)
+        assert np.allclose(p[0], -t * step, rtol=1e-12, atol=1e-15)
+    assert st["t"] == 5
+
+
+def test_adam_moments_follow_exponential_averages():
+    # alternating gradients: m_t and v_t are the closed-form geometric sums
+    p = [np.array([0.0])]
+    st = {}
+    gs = [1.0, -1.0, 1.0, -1.0]
+    for g in gs:
+        mlp.adam_step(p, [np.array([g])], st, lr=0.0)
+    m = sum((1 - 0.9) * 0.9 ** (len(gs) - 1 - i) * gs[i] for i in range(len(gs)))
+    v = sum((1 - 0.999) * 0.999 ** (len(gs) - 1 - i) * gs[i] ** 2 for i in range(len(gs)))
+    assert abs(st["m"][0][0] - m) < 1e-15 and abs(st["v"][0][0] - v) < 1e-15

@@ -32,3 +32,17 @@ def test_uniform_and_struts_ranges():
 def test_bernoulli_binary():
     b = synth.bernoulli(10, 5, 5, 7, 0.3)
     assert set(np.unique(b)) <= {0.0, 1.0}
+
+
+def test_selector_mixture():
+    kinds = set()
+    for seed in range(5_000_000, 5_000_040):
+        dims, rho, kind = synth.selector_state(seed)
+        assert dims in synth.SELECTOR_GRIDS and rho.size == dims[0] * dims[1] * dims[2]
+        assert rho.min() >= 0.0 and rho.max() <= 1.0
+        kinds.add(kind)
+        d2, r2, k2 = synth.selector_state(seed)
+        assert d2 == dims and k2 == kind and np.array_equal(r2, rho)
+    assert kinds == {"blobs", "struts"}
+    dims, rho, _ = synth.selector_state(6_000_000, dims=(64, 32, 32))
+    assert dims == (64, 32, 32) and rho.size == 65536
