@@ -4,11 +4,14 @@ Workload (one "step" = one pass of the whole hot path): 102 severe random
 states on the 64x32x32 cantilever (212,355 DOF each; 50% of 4^3-voxel blobs at
 the floor, the rest U[0.01, 1]; seeds 1000-1101), p = 3, solved in one batch by
 the guarded policy: 100-iteration probe at rho_0 = 1e-9 (restart 100), the
-two-feature rule, then independent FGMRES(30) solves (cap 200) on the ladder
+first rung from the stored learned selector (or the two-feature rule), then
+independent FGMRES(30) solves (cap 200) on the ladder
 {1e-9, 1e-6, 1e-4, 1e-3} with the recomputed FP64 residual guard
 ||f - K u|| / ||f|| <= 1e-6 on every rung.  A state is certified when the
 policy returns an accepted solve.  The headline runs the mixed form (FP32
-V-cycle, FP64 Arnoldi / least squares / guard); the plain FP64 form is timed
+V-cycle with the split-BF16 matrix-core fine operator, FP64 Arnoldi / least
+squares / guard) with the learned selector; the same mixed form with the
+rule, and the plain FP64 form with the rule (the published method), are timed
 beside it.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.
@@ -49,6 +52,10 @@ def parse():
                     help="fine-level contraction of the mixed form (FP32 vector, BF16 or split-BF16 matrix cores)")
     ap.add_argument("--compare-mixed", action="store_true",
                     help="also time the other mixed variants (one step each)")
+    ap.add_argument("--selector", default="mlp", choices=["mlp", "rule"],
+                    help="first-rung selector of the headline run (stored network or two-feature rule)")
+    ap.add_argument("--no-rule-leg", action="store_true",
+                    help="skip the mixed-precision run with the two-feature rule")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -176,11 +183,20 @@ def main():
     torch.cuda.synchronize()
     log(f"{n} grids bound ({sum(g.ws_bytes for g in grids) / 2**30:.1f} GiB workspace)")
 
-    def policy(prec):
-        return tg.policy(rungs=RUNGS, p=3.0, solve=tg.solver_opts(restart=30, max_iters=200, prec=prec))
+    mlp = None
+    if args.selector == "mlp":
+        from paper_2607_26382_amd import selector as sel
+        mlp, model = sel.load_model(device=dev)
+        log("stored first-floor selector loaded ({} training states)".format(model["meta"]["train_states"]))
 
-    def run(prec, steps, warmup, timer_mask):
-        pol = policy(prec)
+    def policy(prec, use_mlp):
+        solve = tg.solver_opts(restart=30, max_iters=200, prec=prec)
+        if use_mlp:
+            return tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_MLP, mlp=mlp)
+        return tg.policy(rungs=RUNGS, p=3.0, solve=solve)
+
+    def run(prec, steps, warmup, timer_mask, use_mlp):
+        pol = policy(prec, use_mlp)
         for w in range(warmup):
             t = time.perf_counter()
             batch.select_floor(rhos, fs, pol)
@@ -205,15 +221,17 @@ def main():
     mixed_prec = MIXED[args.mixed]
     # one untimed pass with every kernel class timed picks the dominant class;
     # the timed steps then carry events around that class only
-    _, _, probe_timers = run(mixed_prec, 1, 0, (1 << 8) - 1)
+    use_mlp = args.selector == "mlp"
+    _, _, probe_timers = run(mixed_prec, 1, 0, (1 << 8) - 1, use_mlp)
     dom = tg.dominant_kernel(probe_timers)
     dom_mask = 1 << probe_timers[dom]["kind"]
-    dt, outs, timers = run(mixed_prec, args.steps, args.warmup, dom_mask)
+    dt, outs, timers = run(mixed_prec, args.steps, args.warmup, dom_mask, use_mlp)
     certified = sum(1 for o in outs if o["rung"] >= 0)
     value = certified * args.steps / dt
     result = {
         "metric": "certified solves/s at ||f-Ku||/||f||<=1e-6 (mixed precision)",
         "mixed_form": args.mixed,
+        "selector": args.selector,
         "value": value, "unit": "certified solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
@@ -227,7 +245,8 @@ def main():
     result["policy"] = {
         "certified": certified, "states": n,
         "selected_rungs": {str(r): sum(1 for o in outs if o["rung"] == r) for r in range(-1, len(RUNGS))},
-        "rule_fired": sum(1 for o in outs if o["k0"] > 0),
+        "first_rung": {str(r): sum(1 for o in outs if o["k0"] == r) for r in range(len(RUNGS))},
+        "first_attempt_accepted": sum(1 for o in outs if len(o["attempts"]) == 1 and o["rung"] >= 0),
         "max_accepted_true_eta": max((o["attempts"][-1]["true_eta"] for o in acc), default=None),
         "mean_iters_probe": float(np.mean([o["iters_probe"] for o in outs])),
         "mean_iters_selected": float(np.mean([o["iters_selected"] for o in acc])) if acc else None,
@@ -242,22 +261,36 @@ def main():
     if args.compare_mixed:
         result["mixed_variants"] = {}
         for name, pr in MIXED.items():
-            d, o, _ = run(pr, 1, 0, 0)
+            d, o, _ = run(pr, 1, 0, 0, use_mlp)
             c = sum(1 for x in o if x["rung"] >= 0)
             result["mixed_variants"][name] = {
                 "value": c / d, "ms_per_step": 1e3 * d, "certified": c,
                 "mean_iters": float(np.mean([x["iters_probe"] + x["iters_selected"] + x["iters_rejected"]
                                              for x in o]))}
+    def brief(o, d, steps):
+        c = sum(1 for x in o if x["rung"] >= 0)
+        return {"value": c * steps / d, "ms_per_step": 1e3 * d / steps, "certified": c,
+                "mean_iters": float(np.mean([x["iters_probe"] + x["iters_selected"] + x["iters_rejected"]
+                                             for x in o])),
+                "mean_attempts": float(np.mean([len(x["attempts"]) for x in o]))}
+
+    result["policy"]["mean_attempts"] = float(np.mean([len(o["attempts"]) for o in outs]))
+    if use_mlp and not args.no_rule_leg:
+        d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
+        result["mixed_rule"] = brief(o, d, args.steps)
+        result["mixed_rule"]["same_rung"] = sum(1 for a, b in zip(outs, o) if a["rung"] == b["rung"])
+        result["selector_gain"] = value / result["mixed_rule"]["value"]
     if not args.no_fp64:
-        dt64, outs64, _ = run(tg.F64, args.steps, args.warmup, 0)
+        # the paper's method as published: every kernel in FP64, two-feature rule
+        dt64, outs64, _ = run(tg.F64, args.steps, args.warmup, 0, False)
         cert64 = sum(1 for o in outs64 if o["rung"] >= 0)
-        result["fp64"] = {"value": cert64 * args.steps / dt64, "ms_per_step": 1e3 * dt64 / args.steps,
-                          "certified": cert64,
-                          "same_rung": sum(1 for a, b in zip(outs, outs64) if a["rung"] == b["rung"])}
+        result["fp64"] = brief(outs64, dt64, args.steps)
+        result["fp64"]["selector"] = "rule"
+        result["fp64"]["same_rung"] = sum(1 for a, b in zip(outs, outs64) if a["rung"] == b["rung"])
+        assert cert64 == result["fp64"]["certified"]
         result["mixed_over_fp64"] = value / result["fp64"]["value"]
     if not args.no_cpu:
-        setups = float(np.mean([1 + o["n_attempts"] if "n_attempts" in o else 1 + len(o["attempts"])
-                                for o in outs]))
+        setups = float(np.mean([1 + len(o["attempts"]) for o in outs]))
         iters = float(np.mean([o["iters_probe"] + o["iters_selected"] + o["iters_rejected"] for o in outs]))
         result["cpu_baseline"] = run_cpu_baseline(setups, iters)
     print(json.dumps(result), flush=True)

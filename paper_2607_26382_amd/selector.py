@@ -163,15 +163,16 @@ def summarize(data, k0):
         wasted_iters_per_state=float(np.mean(rp["iters_rejected"])),
         total_iters_per_state=float(np.mean(total)),
         at_lowest_admissible=float(np.mean(rp["rung"][admissible] == label[admissible])) if admissible.any() else 1.0,
+        first_at_lowest=float(np.mean(np.asarray(k0)[admissible] == label[admissible])) if admissible.any() else 1.0,
         above_lowest_admissible=int(np.count_nonzero(rp["rung"][admissible] > label[admissible])),
         k0_hist=np.bincount(np.asarray(k0), minlength=len(RUNGS)).tolist(),
     )
 
 
 def cost_key(s):
-    """Ordering of policies: fewest iterations per state, then most decisions
-    at the lowest admissible rung."""
-    return (s["total_iters_per_state"], -s["at_lowest_admissible"])
+    """Ordering of policies: most first attempts at the lowest admissible rung
+    (accepted at once and nothing preserved lost), then fewest iterations."""
+    return (-s["first_at_lowest"], s["total_iters_per_state"])
 
 
 def tune_rule(data):

@@ -217,3 +217,59 @@ def test_policy_features_equal_density_features():
         st = g.density_features(r, 3.0, 1e-9)
         assert np.allclose(out["features"][2:], np.float32(st), rtol=0, atol=0)
         assert out["features"][0] == pytest.approx(np.log10(out["r50"]), abs=1e-6)
+
+
+def _oracle_eta(dims, rho, floor, u):
+    """eta = ||f - K u|| / ||f|| on free DOFs by the oracle's matrix-free
+    element loop, with the FP64 evaluation bound n_row * eps * || |K||u| + |f| ||."""
+    from oracle import ke as oke
+    from oracle import mesh
+    from oracle import operator as op
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    E = op.young(rho, 3.0, floor)
+    Ke = oke.ke()
+    f = og.edge_load()
+    r = (f - op.apply_full(og, E, Ke, u))[free]
+    fa = np.linalg.norm(f[free])
+    bound = 81 * np.finfo(float).eps * np.linalg.norm((op.apply_full(og, E, np.abs(Ke), np.abs(u)) +
+                                                        np.abs(f))[free]) / fa
+    return float(np.linalg.norm(r) / fa), float(bound)
+
+
+def test_learned_selector_gain_online_and_exact_replay():
+    """On held-out mixture states, the stored network's first rungs put more
+    first attempts at the lowest admissible rung and spend fewer iterations
+    than the two-feature rule; the online policies make exactly the attempts
+    the offline replay predicts; no accepted solution fails the oracle's
+    residual (false acceptances: 0)."""
+    mlp, _ = sel.load_model()
+    dims = (32, 16, 16)
+    seeds = list(range(6_100_000, 6_100_048))
+    states = [synth.selector_state(s, dims) for s in seeds]
+    grids = [tg.Grid(*dims, max_restart=100, device=DEV) for _ in seeds]
+    batch = tg.Batch(grids)
+    rhos = [torch.tensor(r, device=DEV) for _, r, _ in states]
+    f = torch.tensor(grids[0].edge_load(), device=DEV)
+    solve = tg.solver_opts(prec=tg.BF16X3MFMA)
+    runs = {}
+    for name, pol in (("rule", tg.policy(solve=solve)),
+                      ("mlp", tg.policy(selector=tg.SELECT_MLP, mlp=mlp, solve=solve))):
+        us, res = batch.select_floor(rhos, [f] * len(seeds), pol)
+        runs[name] = ([u.cpu().numpy() for u in us], res)
+    del batch
+    labels = sel.label_states(seeds, dims, log=lambda *a, **k: None)
+    summ = {}
+    for name, (us, res) in runs.items():
+        k0 = np.array([r["k0"] for r in res])
+        rp = sel.replay(labels, k0)
+        for i, r in enumerate(res):
+            assert r["rung"] == rp["rung"][i] and len(r["attempts"]) == rp["attempts"][i], (name, i)
+            assert r["iters_rejected"] == rp["iters_rejected"][i]
+            if r["rung"] >= 0:
+                eta, bound = _oracle_eta(dims, states[i][1], r["floor"], us[i])
+                assert eta <= 1e-6 + bound, (name, i, eta)
+        summ[name] = sel.summarize(labels, k0)
+    assert summ["mlp"]["first_at_lowest"] > summ["rule"]["first_at_lowest"]
+    assert summ["mlp"]["total_iters_per_state"] < summ["rule"]["total_iters_per_state"]
+    assert summ["mlp"]["certified"] == summ["rule"]["certified"] == int(np.count_nonzero(labels["label"] >= 0))
