@@ -54,8 +54,12 @@ def parse():
                     help="also time the other mixed variants (one step each)")
     ap.add_argument("--selector", default="mlp", choices=["mlp", "rule"],
                     help="first-rung selector of the headline run (stored network or two-feature rule)")
+    ap.add_argument("--cgs-passes", type=int, default=2, choices=[1, 2, 3],
+                    help="orthogonalization: 1 CGS, 2 CGS2 with delayed reorthogonalization, 3 CGS2 in place")
     ap.add_argument("--no-rule-leg", action="store_true",
                     help="skip the mixed-precision run with the two-feature rule")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -129,19 +133,27 @@ def apply_leg(tg, torch, dev, reps=40):
             for i in range(nsets):
                 run(i)
             torch.cuda.synchronize()
+            # per-launch HIP events on the launch stream (library kernel timer)
+            cls = "apply_f64" if prec == tg.F64 else "vcycle_fine_op"
+            tg.kernel_timer_enable(1 << (0 if prec == tg.F64 else 1))
+            tg.kernel_timer_reset()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             for r in range(reps):
                 run(r % nsets)
             e1.record()
             torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / reps * 1e-3
+            kt = tg.kernel_timer_read()[cls]
+            tg.kernel_timer_enable(0)
+            t_wall = e0.elapsed_time(e1) / reps * 1e-3
+            t = kt["avg_us"] * 1e-6
         except RuntimeError as exc:
             out[name] = {"error": str(exc)}
             continue
         alg = 2 * g.n_dof * vb + g.n_elem * vb
         out[name] = {"us_per_apply": t * 1e6, "alg_bytes": alg, "GB/s": alg / t / 1e9,
-                     "frac_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS, "buffer_sets": nsets}
+                     "frac_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS, "buffer_sets": nsets,
+                     "launches_timed": kt["count"], "us_per_call_wall": t_wall * 1e6}
         log(f"apply_K {name}: {t*1e6:.1f} us, {alg / t / 1e9:.0f} GB/s")
         del us, ys
     out["grid"] = [nx, ny, nz]
@@ -168,6 +180,19 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        # 1 GiB read + 1 GiB written per copy, 4 copies
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 4
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                          "copies": 4, "GB/s": 2 * a.numel() * 4 / dt / 1e9}), flush=True)
+        return
     apply_res = None
     if not args.no_apply:
         apply_res = apply_leg(tg, torch, dev)
@@ -190,7 +215,7 @@ def main():
         log("stored first-floor selector loaded ({} training states)".format(model["meta"]["train_states"]))
 
     def policy(prec, use_mlp):
-        solve = tg.solver_opts(restart=30, max_iters=200, prec=prec)
+        solve = tg.solver_opts(restart=30, max_iters=200, prec=prec, cgs_passes=args.cgs_passes)
         if use_mlp:
             return tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_MLP, mlp=mlp)
         return tg.policy(rungs=RUNGS, p=3.0, solve=solve)
@@ -232,6 +257,7 @@ def main():
         "metric": "certified solves/s at ||f-Ku||/||f||<=1e-6 (mixed precision)",
         "mixed_form": args.mixed,
         "selector": args.selector,
+        "orthogonalization": {1: "CGS", 2: "CGS2, delayed reorthogonalization", 3: "CGS2 in place"}[args.cgs_passes],
         "value": value, "unit": "certified solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",

@@ -82,7 +82,10 @@ typedef struct {
   int max_iters;       /* cap across restarts, default 200              */
   double tol;          /* stopping tolerance on the history value, 1e-6 */
   int prec;            /* preconditioner precision TG_F64/F32/BF16MFMA  */
-  int cgs_passes;      /* 1 = CGS, 2 = CGS2 (default)                   */
+  int cgs_passes;      /* 1 = CGS; 2 = CGS2 with the reorthogonalization
+                          delayed into the next step (default: two sweeps
+                          over the basis per step); 3 = CGS2 in place
+                          (three sweeps per step)                        */
   double breakdown;    /* subdiagonal <= breakdown * ||w|| -> BREAKDOWN, 1e-14 */
 } tg_solver_opts;
 

@@ -225,6 +225,7 @@ int batch_bind(Batch* b, void* ws, size_t bytes) {
   const size_t need = batch_ws_bytes_for(b->grids);
   if (!ws || bytes < need) return fail(TG_EWORKSPACE, "batch workspace too small");
   Bump bp(ws, bytes, false);
+  b->lists_valid = false;
   batch_layout(bp, b, b->n, list_capacity(b->grids));
   b->ws = ws;
   b->ws_bytes = bytes;
@@ -242,6 +243,12 @@ int batch_upload_desc(Batch* b, hipStream_t s) {
 }
 
 int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bool with_elem) {
+  if (b->lists_valid && b->lists_active == active && (b->lists_elem || !with_elem) &&
+      std::memcmp(b->lists_zc, b->zc, sizeof(b->zc)) == 0) {
+    b->active = active;
+    return TG_OK;   // the lists on the device already describe this set
+  }
+  b->lists_valid = false;
   // the previous host list buffer may still be in flight: synchronize first
   TG_HIP(hipStreamSynchronize(s));
   b->active = active;
@@ -310,6 +317,10 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");
   if (!H.empty())
     TG_HIP(hipMemcpyAsync(b->list_d, H.data(), H.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  b->lists_valid = true;
+  b->lists_elem = with_elem;
+  b->lists_active = active;
+  std::memcpy(b->lists_zc, b->zc, sizeof(b->zc));
   return TG_OK;
 }
 
@@ -404,7 +415,7 @@ size_t grid_ws_bytes(const tg_grid* g, int mmax) {
 }
 
 int grid_bind(tg_grid* g, void* ws, size_t bytes, int mmax) {
-  if (mmax < 1 || mmax > TG_PART_W - 2) return fail(TG_EINVAL, "max_restart must be in [1, 126]");
+  if (mmax < 1 || mmax > TG_MAX_RESTART) return fail(TG_EINVAL, "max_restart must be in [1, 126]");
   const size_t need = grid_ws_bytes(g, mmax);
   if (!ws || bytes < need)
     return fail(TG_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -515,7 +526,7 @@ int tg_edge_load(const tg_grid* g, double* f_h) {
 
 int tg_workspace_bytes(const tg_grid* g, int max_restart, size_t* bytes) {
   if (!g || !bytes) return fail(TG_EINVAL, "NULL argument");
-  if (max_restart < 1 || max_restart > TG_PART_W - 2) return fail(TG_EINVAL, "max_restart must be in [1, 126]");
+  if (max_restart < 1 || max_restart > TG_MAX_RESTART) return fail(TG_EINVAL, "max_restart must be in [1, 126]");
   *bytes = grid_ws_bytes(g, max_restart);
   return TG_OK;
 }

@@ -19,7 +19,8 @@
 #define TG_NODE_TILE 256     // nodes per workgroup for node-centred kernels
 #define TG_VCHUNK 2048       // DOFs per workgroup for vector kernels
 #define TG_VBLOCK 256        // threads per vector workgroup
-#define TG_PART_W 128        // max vectors in one multi-dot
+#define TG_PART_W 256        // max partial sums of one sweep (2 max_restart + 3)
+#define TG_MAX_RESTART 126
 #define TG_MAX_COARSE 512    // max free DOFs of the coarsest level
 #define TG_HIST_CAP 4096     // residual-history capacity per problem
 #define TG_MF_LEVELS 1       // levels 1..TG_MF_LEVELS apply the Galerkin operator matrix-free
@@ -118,7 +119,7 @@ struct SmallLayout {
 };
 // scalar slots inside small + scal
 enum { SC_BNORM = 0, SC_BETA = 1, SC_HN = 2, SC_STATUS = 3, SC_ITERS = 4, SC_JDONE = 5,
-       SC_EST = 6, SC_TRUE = 7, SC_INV = 8, SC_FLAG = 9 };
+       SC_EST = 6, SC_TRUE = 7, SC_INV = 8, SC_FLAG = 9, SC_RHO = 10, SC_GJ = 11 };
 #define TG_RUNNING (-1.0)
 
 // Ke of a cube in the per-component polynomial-mode basis has 8 distinct
@@ -195,6 +196,11 @@ struct Batch {
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
   int zc[TG_MAXLEV] = {};         // z-tile height per level for this batch
+  // key of the work lists currently on the device (rebuilt only when it changes)
+  bool lists_valid = false;
+  bool lists_elem = false;
+  std::vector<int> lists_active;
+  int lists_zc[TG_MAXLEV] = {};
 };
 
 size_t batch_ws_bytes_for(const std::vector<tg_grid*>& grids);
@@ -208,8 +214,12 @@ int batch_read_status(Batch* b, hipStream_t s);   // fills sc_h from small[SC_ST
 int k_set_density(Batch* b, hipStream_t s);
 int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s);
 int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s);
+int k_dots2(Batch* b, int sbase, int nv, int sq, int sw, hipStream_t s);
+int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, hipStream_t s);
+int k_dcgs_a(Batch* b, int j, hipStream_t s);
+int k_dcgs_b(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s);
 int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
-             void* ey, hipStream_t s);
+             void* ey, hipStream_t s, int in_scale_sc = -1);   // input scaled by small[scal + in_scale_sc]
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s);  // dir 0: ext0 -> slot; 1: slot -> ext1
 int k_fill0(Batch* b, int slot, double v, hipStream_t s);
 int k_copy0(Batch* b, int src, int dst, hipStream_t s);

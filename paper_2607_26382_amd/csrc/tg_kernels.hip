@@ -349,7 +349,8 @@ __global__ __launch_bounds__(256) void k_node_op(const ProbDesc* __restrict__ pr
 template <class TB, class T>
 __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict__ probs,
                                                       const int2* __restrict__ work, int l, int sb,
-                                                      const void* eb_, int sbT, int sx, T omega) {
+                                                      const void* eb_, int sbT, int sx, T omega,
+                                                      int scale_off) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& L = P.lv[l];
@@ -357,7 +358,9 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict
   if (n >= L.n_nodes) return;
   const auto* b = vslot<TB>(L, sb, eb_);
   auto* x = vslot<T>(L, sx, nullptr);
-  T b0 = T(b[3LL * n]), b1 = T(b[3LL * n + 1]), b2 = T(b[3LL * n + 2]);
+  // optional per-problem input scale (small[scale_off]), applied in FP64
+  const double sc = scale_off >= 0 ? P.small[scale_off] : 1.0;
+  T b0 = T(double(b[3LL * n]) * sc), b1 = T(double(b[3LL * n + 1]) * sc), b2 = T(double(b[3LL * n + 2]) * sc);
   if (n % L.NX == 0) b0 = b1 = b2 = T(0);
   if (sbT != INT_MIN) {
     auto* bT = vslot<T>(L, sbT, nullptr);
@@ -483,7 +486,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const ProbDesc* __restrict
 template <class TA, class TB>
 __global__ __launch_bounds__(256) void k_copy_level(const ProbDesc* __restrict__ probs,
                                                     const int2* __restrict__ work, int l, int sa,
-                                                    const void* ea, int sb, void* eb) {
+                                                    const void* ea, int sb, void* eb, int scale_off) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& L = P.lv[l];
@@ -492,7 +495,8 @@ __global__ __launch_bounds__(256) void k_copy_level(const ProbDesc* __restrict__
   const auto* a = vslot<TA>(L, sa, ea);
   auto* b = vslot<TB>(L, sb, eb);
   const bool clamp = (n % L.NX) == 0;
-  for (int c = 0; c < 3; ++c) b[3LL * n + c] = clamp ? TB(0) : TB(a[3LL * n + c]);
+  const double sc = scale_off >= 0 ? P.small[scale_off] : 1.0;
+  for (int c = 0; c < 3; ++c) b[3LL * n + c] = clamp ? TB(0) : TB(double(a[3LL * n + c]) * sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -786,6 +790,139 @@ __global__ __launch_bounds__(256) void k_update_dots_reg_(const ProbDesc* __rest
   }
 }
 
+// CGS2 with delayed reorthogonalization, sweep A.  For k < nv the chunk
+// partials of V_k . q and V_k . w, then q . q, q . w, w . w: 2 nv + 3 entries
+// in the order [V.q (nv) | V.w (nv) | q.q, q.w, w.w].  One read of V, q, w.
+__global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ probs,
+                                                const int2* __restrict__ work, int sbase, int nv, int sq,
+                                                int sw) {
+  __shared__ double sh[16][4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  const long long nc = L.n_chunks;
+  const auto* qv = gp(L.vec64 + (long long)sq * L.stride);
+  const auto* wv = gp(L.vec64 + (long long)sw * L.stride);
+  constexpr int NQ = TG_VCHUNK / 256;
+  double qr[NQ], wr[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    qr[q] = idx < hi ? qv[idx] : 0.0;
+    wr[q] = idx < hi ? wv[idx] : 0.0;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < nv; k0 += 8) {
+    double a[8], c[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      a[g] = c[g] = 0.0;
+      const int k = k0 + g;
+      if (k < nv) {
+        const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const long long idx = lo + threadIdx.x + 256LL * q;
+          if (idx < hi) {
+            const double x = v[idx];
+            a[g] += x * qr[q];
+            c[g] += x * wr[q];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const double ra = wave_sum(a[g]);
+      const double rc = wave_sum(c[g]);
+      if (lane == 0) {
+        sh[g][wave] = ra;
+        sh[8 + g][wave] = rc;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      const int t = threadIdx.x, k = k0 + (t & 7), which = t >> 3;
+      if (k < nv) P.part[((long long)which * nv + k) * nc + wi.y] = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
+    }
+    __syncthreads();
+  }
+  double qq = 0.0, qw = 0.0, ww = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    qq += qr[q] * qr[q];
+    qw += qr[q] * wr[q];
+    ww += wr[q] * wr[q];
+  }
+  qq = wave_sum(qq);
+  qw = wave_sum(qw);
+  ww = wave_sum(ww);
+  if (lane == 0) {
+    sh[0][wave] = qq;
+    sh[1][wave] = qw;
+    sh[2][wave] = ww;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int t = threadIdx.x;
+    P.part[(2LL * nv + t) * nc + wi.y] = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
+  }
+}
+
+// CGS2 with delayed reorthogonalization, sweep B (coefficients at small+coef):
+//   q     <- cq * q - sum_k a_k V_k        (the reorthogonalized, normalized q)
+//   qnext <- w - sum_k c_k V_k - cw * q_old (the next vector, projected once)
+// with a = coef[0, nv), c = coef[nv, 2 nv), cq = coef[2 nv], cw = coef[2 nv + 1];
+// chunk partial of qnext . qnext into part row 0.  One read of V, q, w.
+__global__ __launch_bounds__(256) void k_update2_(const ProbDesc* __restrict__ probs,
+                                                  const int2* __restrict__ work, int sbase, int nv, int sq,
+                                                  int sw, int snext, int coef_off) {
+  __shared__ double sh[4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[0];
+  long long lo, hi;
+  chunk_range(L, wi.y, lo, hi);
+  const double* cf = P.small + coef_off;
+  constexpr int NQ = TG_VCHUNK / 256;
+  double ta[NQ], tc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) ta[q] = tc[q] = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const double ak = cf[k], ck = cf[nv + k];
+    const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const long long idx = lo + threadIdx.x + 256LL * q;
+      if (idx < hi) {
+        const double x = v[idx];
+        ta[q] += ak * x;
+        tc[q] += ck * x;
+      }
+    }
+  }
+  const double cq = cf[2 * nv], cw = cf[2 * nv + 1];
+  auto* qv = gp(L.vec64 + (long long)sq * L.stride);
+  const auto* wv = gp(L.vec64 + (long long)sw * L.stride);
+  auto* nv_ = gp(L.vec64 + (long long)snext * L.stride);
+  double nn = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const long long idx = lo + threadIdx.x + 256LL * q;
+    if (idx < hi) {
+      const double qo = qv[idx];
+      const double nx = wv[idx] - tc[q] - cw * qo;
+      qv[idx] = cq * qo - ta[q];
+      nv_[idx] = nx;
+      nn += nx * nx;
+    }
+  }
+  nn = block_sum256(nn, sh);
+  if (threadIdx.x == 0) P.part[wi.y] = nn;
+}
+
 // dst = src * small[scal + sc_index]
 __global__ __launch_bounds__(256) void k_scale_(const ProbDesc* __restrict__ probs,
                                                 const int2* __restrict__ work, int src, int dst,
@@ -839,6 +976,7 @@ __global__ void k_cycle_start_(const ProbDesc* __restrict__ probs, const int2* _
   sc[SC_JDONE] = 0;
   sc[SC_EST] = rel;
   sc[SC_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
+  sc[SC_RHO] = beta;   // delayed form: V_0 holds r itself, first-pass norm beta
   for (int q = 0; q <= o.mmax; ++q) S[o.g + q] = 0.0;
   S[o.g] = beta;
   status_out[wi.x] = st;
@@ -902,6 +1040,147 @@ __global__ void k_arnoldi_(const ProbDesc* __restrict__ probs, const int2* __res
   sc[SC_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
   if (est <= tol) st = TG_PROJ_CONVERGED;
   else if (hn <= brk * wn0) st = TG_BREAKDOWN;
+  else if (kk >= cap) st = TG_MAXIT;
+  sc[SC_STATUS] = st;
+  status_out[wi.x] = st;
+}
+
+// Delayed reorthogonalization, after sweep A of step j.  V_0..V_{j-1} hold
+// the final orthonormal q_i, V_j the once-projected q~_j with first-pass norm
+// rho = scal[SC_RHO]; tmp holds [Q^T q~ | Q^T w | q~.q~, q~.w, w.w] with
+// w = K z_j, z_j = M^-1 (q~_j / rho).  With S = Q^T q~ / rho:
+//   nu = sqrt(q~.q~ / rho^2 - |S|^2),  q_j = (q~_j / rho - Q S) / nu.
+// Column j-1 of H becomes final: [h1 + rho S ; rho nu] (h1 = its first-pass
+// coefficients), replacing the tentative column and rotation of step j-1.
+// The first-pass coefficients of column j are h1 = [Q^T w ; q_j . w]; the
+// coefficients of sweep B go to tmp (see k_update2_).
+__global__ void k_dcgs_a_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work, SmallOffs o,
+                          int j, double* status_out) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  if (threadIdx.x != 0) return;
+  double* S = P.small;
+  double* sc = S + o.scal;
+  if (sc[SC_STATUS] != TG_RUNNING) return;
+  double* tmp = S + o.tmp;
+  double* h1 = S + o.h;
+  const int ldh = o.mmax + 1;
+  const double rho = sc[SC_RHO];
+  const double alpha = tmp[2 * j] / (rho * rho), qw = tmp[2 * j + 1] / rho, ww = tmp[2 * j + 2];
+  double ss = 0.0, sz = 0.0;
+  for (int k = 0; k < j; ++k) {
+    const double sk = tmp[k] / rho;
+    ss += sk * sk;
+    sz += sk * tmp[j + k];
+  }
+  const double nu2 = alpha - ss;
+  double st = TG_RUNNING;
+  if (!isfinite(nu2) || !isfinite(qw) || !isfinite(sz)) st = TG_NONFINITE;
+  else if (!(nu2 > 0.0)) st = TG_BREAKDOWN;   // q~_j lies in span(Q): nothing new
+  if (st != TG_RUNNING) {
+    sc[SC_STATUS] = st;
+    status_out[wi.x] = st;
+    return;
+  }
+  const double nu = sqrt(nu2);
+  sc[SC_FLAG] = ww;
+  if (j >= 1) {
+    double* Hc = S + o.H + (long long)ldh * (j - 1);
+    for (int i = 0; i < j; ++i) Hc[i] = h1[i] + tmp[i];
+    Hc[j] = rho * nu;
+    for (int i = 0; i < j - 1; ++i) {
+      const double c = S[o.cs + i], sn = S[o.sn + i];
+      const double t = c * Hc[i] + sn * Hc[i + 1];
+      Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
+      Hc[i] = t;
+    }
+    const double d = hypot(Hc[j - 1], Hc[j]);
+    if (!(d > 0.0) || !isfinite(d)) {
+      sc[SC_STATUS] = TG_NONFINITE;
+      status_out[wi.x] = TG_NONFINITE;
+      return;
+    }
+    const double c = Hc[j - 1] / d, sn = Hc[j] / d;
+    S[o.cs + j - 1] = c;
+    S[o.sn + j - 1] = sn;
+    Hc[j - 1] = d;
+    Hc[j] = 0.0;
+    const double gj = sc[SC_GJ];
+    S[o.g + j - 1] = c * gj;
+    S[o.g + j] = -sn * gj;
+  }
+  const double hjj = (qw - sz) / nu;
+  for (int k = 0; k < j; ++k) {
+    const double sk = tmp[k] / rho, zk = tmp[j + k];
+    h1[k] = zk;
+    tmp[j + k] = zk - sk * hjj / nu;
+    tmp[k] = sk / nu;
+  }
+  h1[j] = hjj;
+  tmp[2 * j] = 1.0 / (rho * nu);
+  tmp[2 * j + 1] = hjj / (nu * rho);
+}
+
+// After sweep B of step j: rho' = ||q~_{j+1}|| (tmp[0]).  Column j enters
+// tentatively as [h1 ; rho'] (its reorthogonalization correction is known
+// only after the next sweep A): rotations, projected residual estimate,
+// history and stop tests as in the immediate form.
+__global__ void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work, SmallOffs o,
+                          int j, int k, int cap, double tol, double brk, double* status_out) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  if (threadIdx.x != 0) return;
+  double* S = P.small;
+  double* sc = S + o.scal;
+  if (sc[SC_STATUS] != TG_RUNNING) return;   // stopped in sweep A of this step
+  const double* h1 = S + o.h;
+  const int ldh = o.mmax + 1;
+  const double rn = sqrt(S[o.tmp]);
+  double* Hc = S + o.H + (long long)ldh * j;
+  bool finite = isfinite(rn);
+  for (int i = 0; i <= j; ++i) {
+    Hc[i] = h1[i];
+    finite = finite && isfinite(Hc[i]);
+  }
+  Hc[j + 1] = rn;
+  if (!finite) {
+    sc[SC_STATUS] = TG_NONFINITE;
+    status_out[wi.x] = TG_NONFINITE;
+    return;
+  }
+  for (int i = 0; i < j; ++i) {
+    const double c = S[o.cs + i], sn = S[o.sn + i];
+    const double t = c * Hc[i] + sn * Hc[i + 1];
+    Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
+    Hc[i] = t;
+  }
+  const double d = hypot(Hc[j], Hc[j + 1]);
+  if (!(d > 0.0) || !isfinite(d)) {
+    sc[SC_STATUS] = TG_NONFINITE;
+    status_out[wi.x] = TG_NONFINITE;
+    return;
+  }
+  const double c = Hc[j] / d, sn = Hc[j + 1] / d;
+  S[o.cs + j] = c;
+  S[o.sn + j] = sn;
+  Hc[j] = d;
+  Hc[j + 1] = 0.0;
+  const double gj = S[o.g + j];
+  sc[SC_GJ] = gj;
+  S[o.g + j + 1] = -sn * gj;
+  S[o.g + j] = c * gj;
+  const int kk = k + 1;
+  const double est = fabs(S[o.g + j + 1]) / sc[SC_BNORM];
+  S[o.hist + kk] = est;
+  sc[SC_EST] = est;
+  sc[SC_ITERS] = kk;
+  sc[SC_JDONE] = j + 1;
+  sc[SC_HN] = rn;
+  sc[SC_RHO] = rn;
+  sc[SC_INV] = rn > 0.0 ? 1.0 / rn : 0.0;
+  double st = TG_RUNNING;
+  if (est <= tol) st = TG_PROJ_CONVERGED;
+  else if (rn <= brk * sqrt(fmax(sc[SC_FLAG], 0.0))) st = TG_BREAKDOWN;
   else if (kk >= cap) st = TG_MAXIT;
   sc[SC_STATUS] = st;
   status_out[wi.x] = st;
@@ -1091,7 +1370,7 @@ static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om
 // external ey, double unless out_is_f32).
 template <class T>
 static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
-                    void* ey, hipStream_t s, int mf) {
+                    void* ey, hipStream_t s, int mf, int in_scale) {
   const tg_mg_opts& mg = b->grids[0]->mg;
   const T om = T(mg.omega);
   const bool f64 = sizeof(T) == 8;
@@ -1120,10 +1399,10 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
       level_sums(b, 0, 0, nodes, elems, c2);
       if (in_is_f32)
         TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sIn + sT),
-                 k_copy_level<float, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr));
+                 k_copy_level<float, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr, in_scale));
       else
         TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sIn + sT),
-                 k_copy_level<double, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr));
+                 k_copy_level<double, T><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, sb, eb, Bs, nullptr, in_scale));
     }
     if (co.n) {
       const int fin = l == 0 ? FIN0 : FIN;
@@ -1135,10 +1414,11 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     level_sums(b, l, 1, nodes, elems, c2);
     if (l == 0 && fast_in)
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (8.0 + 2 * sT) + 9.0 * nodes * sT,
-               k_jacobi_first<double, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, 0, sb, nullptr, Bs, XA, om));
+               k_jacobi_first<double, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, 0, sb, nullptr, Bs, XA, om,
+                                                                    in_scale));
     else
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 9.0 * nodes * sT,
-               k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om));
+               k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om, -1));
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
       vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s, mf);
@@ -1185,19 +1465,20 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     level_sums(b, 0, 0, nodes, elems, c2);
     if (out_is_f32)
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sOut + sT),
-               k_copy_level<T, float><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey));
+               k_copy_level<T, float><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey, -1));
     else
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (sOut + sT),
-               k_copy_level<T, double><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey));
+               k_copy_level<T, double><<<nblk(b->node[0]), 256, 0, s>>>(b->desc_d, b->node[0].ptr, 0, FIN0, nullptr, sy, ey, -1));
   }
   return check_launch("vcycle");
 }
 
 int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
-             void* ey, hipStream_t s) {
-  if (prec == TG_F64) return vcycle_t<double>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, 0);
+             void* ey, hipStream_t s, int in_scale_sc) {
+  const int in_scale = in_scale_sc >= 0 ? offs(b).scal + in_scale_sc : -1;
+  if (prec == TG_F64) return vcycle_t<double>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, 0, in_scale);
   const int mf = prec == TG_BF16MFMA ? 1 : prec == TG_BF16X3MFMA ? 2 : 0;
-  return vcycle_t<float>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, mf);
+  return vcycle_t<float>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, mf, in_scale);
 }
 
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s) {
@@ -1254,6 +1535,30 @@ int k_update_dots(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, int ndot
   return check_launch("update_dots");
 }
 
+int k_dots2(Batch* b, int sbase, int nv, int sq, int sw, hipStream_t s) {
+  if (b->vec.n)
+    TG_TIMED(TG_KT_MULTIDOT, 8.0 * (nv + 2) * dofs0(b),
+             k_dots2_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sq, sw));
+  return check_launch("dots2");
+}
+int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, hipStream_t s) {
+  const SmallOffs o = offs(b);
+  if (b->vec.n)
+    TG_TIMED(TG_KT_UPDATE, 8.0 * (nv + 4) * dofs0(b),
+             k_update2_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sq, sw, snext, o.tmp));
+  return check_launch("update2");
+}
+int k_dcgs_a(Batch* b, int j, hipStream_t s) {
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0, k_dcgs_a_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, b->sc_d));
+  return check_launch("dcgs_a");
+}
+int k_dcgs_b(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s) {
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0,
+             k_dcgs_b_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, k, cap, tol, brk, b->sc_d));
+  return check_launch("dcgs_b");
+}
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s) {
   const int sidx = offs(b).scal + sc_index;
   if (b->vec.n)

@@ -68,7 +68,8 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
   const int mmax = b->grids[0]->mmax;
   if (m < 1 || m > mmax) return fail(TG_EINVAL, "restart must be in [1, bound max_restart]");
   if (cap < 0 || cap > TG_HIST_CAP - 1) return fail(TG_EINVAL, "max_iters out of range");
-  if (o->cgs_passes < 1 || o->cgs_passes > 2) return fail(TG_EINVAL, "cgs_passes must be 1 or 2");
+  if (o->cgs_passes < 1 || o->cgs_passes > 3) return fail(TG_EINVAL, "cgs_passes must be 1, 2 or 3");
+  const bool delayed = o->cgs_passes == 2;
   if (o->prec < TG_F64 || o->prec > TG_BF16X3MFMA)
     return fail(TG_EINVAL, "unknown preconditioner precision");
   const double tol = o->tol, brk = o->breakdown;
@@ -78,13 +79,15 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
   if (rc) return rc;
   if ((rc = k_init_small(b, s))) return rc;
   if ((rc = k_fill0(b, S_X, 0.0, s))) return rc;
-  if ((rc = k_copy0(b, S_F, S_R, s))) return rc;
+  // cycle-start residual: the delayed form keeps it unnormalized in V_0
+  const int SR = delayed ? slot_V(0) : S_R;
+  if ((rc = k_copy0(b, S_F, SR, s))) return rc;
   std::vector<int> running = which;
   int k = 0;
   while (true) {
     if ((rc = batch_set_active(b, running, s))) return rc;
-    if (k > 0 && (rc = k_residual64(b, S_F, S_X, S_R, s))) return rc;
-    if ((rc = k_multidot(b, 0, 0, S_R, 1, s))) return rc;
+    if (k > 0 && (rc = k_residual64(b, S_F, S_X, SR, s))) return rc;
+    if ((rc = k_multidot(b, 0, 0, SR, 1, s))) return rc;
     if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
     if ((rc = k_cycle_start(b, k, cap, tol, s))) return rc;
     if ((rc = batch_read_status(b, s))) return rc;
@@ -94,11 +97,37 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
     running.swap(nr);
     if (running.empty()) break;
     if ((rc = batch_set_active(b, running, s))) return rc;
-    if ((rc = k_scale_to(b, S_R, slot_V(0), SC_INV, s))) return rc;
+    if (!delayed && (rc = k_scale_to(b, S_R, slot_V(0), SC_INV, s))) return rc;
     const std::vector<int> members = running;
     int jmax = 0;
     for (int j = 0; j < m; ++j) {
       jmax = j + 1;
+      if (delayed) {
+        // CGS2 with delayed reorthogonalization: V_j holds q~_j (projected
+        // once, first-pass norm rho_j in SC_RHO); z_j = M^-1 (q~_j / rho_j).
+        // Sweep A: dots of [V_0..V_{j-1}, q~_j] with q~_j and w = K z_j;
+        // sweep B: reorthogonalized q_j into V_j and q~_{j+1} into V_{j+1}.
+        if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s, SC_INV)))
+          return rc;
+        if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
+        if ((rc = k_dots2(b, slot_V(0), j, slot_V(j), S_W, s))) return rc;
+        if ((rc = k_reduce(b, 2 * j + 3, 2, 0, -1, s))) return rc;
+        if ((rc = k_dcgs_a(b, j, s))) return rc;
+        if ((rc = k_update2(b, slot_V(0), j, slot_V(j), S_W, slot_V(j + 1), s))) return rc;
+        if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
+        if ((rc = k_dcgs_b(b, j, k, cap, tol, brk, s))) return rc;
+        ++k;
+        if ((rc = batch_read_status(b, s))) return rc;
+        std::vector<int> still;
+        for (int i : running)
+          if (b->sc_h[i] == TG_RUNNING) still.push_back(i);
+        if (still.empty() || j == m - 1) break;
+        if (still.size() != running.size()) {
+          running.swap(still);
+          if ((rc = batch_set_active(b, running, s))) return rc;
+        }
+        continue;
+      }
       if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s))) return rc;
       if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
       // Classical Gram-Schmidt, each pass h = V^T w then w -= V h, in fused
@@ -106,7 +135,7 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
       // [w -= V h1; dots2] [w -= V h2; w.w]  (CGS2), or [dots1] [w -= V h1; w.w].
       if ((rc = k_multidot(b, slot_V(0), j + 1, S_W, 1, s))) return rc;
       if ((rc = k_reduce(b, j + 2, 0, 0, j + 1, s))) return rc;
-      if (o->cgs_passes == 2) {
+      if (o->cgs_passes == 3) {
         if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 0, j + 1, 0, s))) return rc;
         if ((rc = k_reduce(b, j + 1, 1, 0, -1, s))) return rc;
         if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 1, 0, 1, s))) return rc;

@@ -107,15 +107,18 @@ def _oracle_fgmres(dims, rho, rmin, restart, cap, tol=1e-6):
     return res, H, f, og
 
 
+@pytest.mark.parametrize("cgs", [2, 3])
 @pytest.mark.parametrize("dims,kind,rmin,restart", [((16, 8, 8), "uniform", 1e-3, 30),
                                                     ((16, 8, 8), "uniform", 1e-3, 7),
                                                     ((32, 16, 16), "blob", 1e-4, 30)])
-def test_fgmres_history_and_solution(dims, kind, rmin, restart):
+def test_fgmres_history_and_solution(dims, kind, rmin, restart, cgs):
+    """Both CGS2 forms (reorthogonalization delayed into the next step, or in
+    place) follow the oracle's FGMRES (Saad, CGS2)."""
     rho = _field(kind, dims, 1001)
     ref, H, f_free, og = _oracle_fgmres(dims, rho, rmin, restart, 200)
     g = _gpu_grid(dims, rho, 3.0, rmin)
     f = torch.tensor(g.edge_load(), device=DEV)
-    u, res, hist = g.fgmres_solve(f, tg.solver_opts(restart=restart))
+    u, res, hist = g.fgmres_solve(f, tg.solver_opts(restart=restart, cgs_passes=cgs))
     n = min(len(hist), len(ref.hist), 25)
     assert np.allclose(hist[:n], ref.hist[:n], rtol=1e-8, atol=0)
     assert abs(res["iterations"] - ref.iters) <= 1
