@@ -114,10 +114,13 @@ def apply_leg(tg, torch, dev, reps=40):
     g = tg.Grid(nx, ny, nz, max_restart=2, device=dev)
     rho = torch.tensor(synth.struts(nx, ny, nz, 3000), device=dev)
     g.set_density(rho, 3.0, 1e-3)
-    out = {}
+    out = {"autotuned_zc": {}}
     for name, prec, dt, vb in (("f32", tg.F32, torch.float32, 4), ("f64", tg.F64, torch.float64, 8),
                                ("bf16_mfma", tg.BF16MFMA, torch.float32, 4),
                                ("bf16x3_mfma", tg.BF16X3MFMA, torch.float32, 4)):
+        # z-tile heights from the autotuner (smoothing sweep timing, per precision)
+        zc, _ = g.autotune(prec)
+        out["autotuned_zc"][name] = zc[0]
         nsets = max(3, int(np.ceil(600e6 / (2 * g.n_dof * vb))))
         us = [torch.randn(g.n_dof, dtype=dt, device=dev) for _ in range(nsets)]
         ys = [torch.empty_like(us[0]) for _ in range(nsets)]
@@ -244,6 +247,10 @@ def main():
 
     MIXED = {"f32": tg.F32, "bf16": tg.BF16MFMA, "bf16x3": tg.BF16X3MFMA}
     mixed_prec = MIXED[args.mixed]
+    # tile heights of the z-march kernels for this batch, from the autotuner
+    batch.set_density(rhos, 3.0, [RUNGS[0]] * n)
+    zc_mixed, _ = batch.autotune(mixed_prec)
+    log(f"autotuned z-tile heights (levels 0, 1): {zc_mixed[:2]}")
     # one untimed pass with every kernel class timed picks the dominant class;
     # the timed steps then carry events around that class only
     use_mlp = args.selector == "mlp"
@@ -279,6 +286,7 @@ def main():
         "mean_iters_rejected": float(np.mean([o["iters_rejected"] for o in outs])),
     }
     result["roofline"] = tg.roofline_from_timers(timers, HBM_PEAK_GBS)
+    result["autotuned_zc"] = zc_mixed[:2]
     if apply_res is not None:
         result["apply_K"] = apply_res
     result["kernel_classes"] = {k: {"launches": v["count"], "total_ms": v["ms"], "avg_us": v["avg_us"],

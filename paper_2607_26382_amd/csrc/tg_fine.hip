@@ -50,6 +50,67 @@ __device__ __forceinline__ void wht_inv(T* v) {
       }
 }
 
+// The x and y stages of wht_fwd / wht_inv on one z-face (corner c = di + 2 dj).
+// A face shared by two element layers is transformed once: the top face of
+// layer k is the bottom face of layer k + 1, and the two layers' outputs on
+// it are summed before its inverse stages.
+template <class T>
+__device__ __forceinline__ void face_fwd(T* v) {
+#pragma unroll
+  for (int b = 1; b < 4; b <<= 1)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (!(a & b)) {
+        const T x0 = v[a], x1 = v[a | b];
+        v[a] = x0 + x1;
+        v[a | b] = x1 - x0;
+      }
+}
+template <class T>
+__device__ __forceinline__ void face_inv(T* v) {
+#pragma unroll
+  for (int b = 1; b < 4; b <<= 1)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (!(a & b)) {
+        const T x0 = v[a], x1 = v[a | b];
+        v[a] = x0 - x1;
+        v[a | b] = x0 + x1;
+      }
+}
+
+// mode_contract with the element modulus folded into the coefficients:
+// c = (d - o, o, s, p, q, r - t, t, w) already multiplied by E.
+template <class T>
+struct ModeCoefE {
+  T dmo, o, s, p, q, rmt, t, w;
+};
+template <class T>
+__device__ __forceinline__ ModeCoefE<T> coef_times(const ModeCoefE<T>& c, T E) {
+  return {c.dmo * E, c.o * E, c.s * E, c.p * E, c.q * E, c.rmt * E, c.t * E, c.w * E};
+}
+template <class T>
+__device__ __forceinline__ void mode_contract_e(T* ux, T* uy, T* uz, const ModeCoefE<T>& c) {
+  const T ns = ux[1] + uy[2] + uz[4];
+  const T bxx = c.dmo * ux[1] + c.o * ns, byy = c.dmo * uy[2] + c.o * ns, bzz = c.dmo * uz[4] + c.o * ns;
+  const T sxy = c.s * (uy[1] + ux[2]);
+  const T sxz = c.s * (uz[1] + ux[4]);
+  const T syz = c.s * (uz[2] + uy[4]);
+  const T p1a = c.p * ux[3] + c.q * uz[6], p1b = c.q * ux[3] + c.p * uz[6];
+  const T p2a = c.p * uy[3] + c.q * uz[5], p2b = c.q * uy[3] + c.p * uz[5];
+  const T p3a = c.p * ux[5] + c.q * uy[6], p3b = c.q * ux[5] + c.p * uy[6];
+  const T ts = uz[3] + uy[5] + ux[6];
+  const T t1 = c.rmt * uz[3] + c.t * ts, t2 = c.rmt * uy[5] + c.t * ts, t3 = c.rmt * ux[6] + c.t * ts;
+  ux[0] = T(0); uy[0] = T(0); uz[0] = T(0);
+  ux[1] = bxx; uy[1] = sxy; uz[1] = sxz;
+  ux[2] = sxy; uy[2] = byy; uz[2] = syz;
+  ux[3] = p1a; uy[3] = p2a; uz[3] = t1;
+  ux[4] = sxz; uy[4] = syz; uz[4] = bzz;
+  ux[5] = p3a; uy[5] = t2;  uz[5] = p2b;
+  ux[6] = t3;  uy[6] = p3b; uz[6] = p1b;
+  ux[7] *= c.w; uy[7] *= c.w; uz[7] *= c.w;
+}
+
 // Mode-space contraction b = E * (K_H / 64) a on the three component vectors
 // (mode index m: 1 x, 2 y, 3 xy, 4 z, 5 xz, 6 yz, 7 xyz), in place.
 template <class T>
@@ -119,31 +180,17 @@ __device__ __forceinline__ void mode_restrict_t_add(T* o, T* acc, T h, T sx, T s
   for (int m = 0; m < 8; ++m) acc[m] += o[m];
 }
 
-// Fine element: v = E Ke u; ux/uy/uz[a] = component at local node a.
-template <class T>
-__device__ __forceinline__ void elem_fine(T* ux, T* uy, T* uz, T E, const ModeCoef<T>& c) {
-  wht_fwd(ux);
-  wht_fwd(uy);
-  wht_fwd(uz);
-  mode_contract(ux, uy, uz, E, c);
-  wht_inv(ux);
-  wht_inv(uy);
-  wht_inv(uz);
-}
-
 // Galerkin element of level l >= 1 (matrix-free): with T the nodal-to-mode
 // transform and T_d the restriction to fine descendant d,
 //   Kel_l = T^T [ sum_d E_d T_d^T (K_H / 64) T_d ] T,
 // which equals the element-wise Galerkin product P^T ... P^T Ke P ... P of the
 // 2:1 trilinear hierarchy.  Descendant d = (fx, fy, fz) in [0, 2^l)^3 sits at
 // h = 2^-l, s = (2 f + 1) h - 1 per dimension.
+// (in and out in the element's mode basis: the caller applies the transforms)
 template <class T>
-__device__ __forceinline__ void elem_galerkin(T* ux, T* uy, T* uz, const T TG_GLOBAL* E0, int nx0,
-                                              int ny0, int ex, int ey, int ez, int l,
-                                              const ModeCoef<T>& c) {
-  wht_fwd(ux);
-  wht_fwd(uy);
-  wht_fwd(uz);
+__device__ __forceinline__ void elem_galerkin_modes(T* ux, T* uy, T* uz, const T TG_GLOBAL* E0, int nx0,
+                                                    int ny0, int ex, int ey, int ez, int l,
+                                                    const ModeCoef<T>& c) {
   T ax[8], ay[8], az[8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -173,9 +220,6 @@ __device__ __forceinline__ void elem_galerkin(T* ux, T* uy, T* uz, const T TG_GL
       }
     }
   }
-  wht_inv(ux);
-  wht_inv(uy);
-  wht_inv(uz);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,33 +262,36 @@ __device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float
   const int lane = threadIdx.x & 63;
   __bf16* Bh = (__bf16*)wlds;                 // [64 elements][32]
   __bf16* Bl = Bh + 64 * 32;
-  auto put = [&](int k, float v) {
-    const __bf16 h = (__bf16)v;
-    Bh[lane * 32 + k] = h;
-    if (SPLIT) Bl[lane * 32 + k] = (__bf16)(v - (float)h);
-  };
+  // this lane's 24 DOFs (3 a + c) and 8 zeros as four 8-wide BF16 vectors,
+  // written with 16-byte stores
+  float v[32];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    put(3 * a + 0, ux[a]);
-    put(3 * a + 1, uy[a]);
-    put(3 * a + 2, uz[a]);
+    v[3 * a + 0] = ux[a];
+    v[3 * a + 1] = uy[a];
+    v[3 * a + 2] = uz[a];
   }
 #pragma unroll
-  for (int k = 24; k < 32; ++k) {
-    Bh[lane * 32 + k] = (__bf16)0.f;
-    if (SPLIT) Bl[lane * 32 + k] = (__bf16)0.f;
+  for (int k = 24; k < 32; ++k) v[k] = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    bf16x8 h, lo;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      h[j] = (__bf16)v[8 * q + j];
+      if (SPLIT) lo[j] = (__bf16)(v[8 * q + j] - (float)h[j]);
+    }
+    *(bf16x8*)(Bh + lane * 32 + 8 * q) = h;
+    if (SPLIT) *(bf16x8*)(Bl + lane * 32 + 8 * q) = lo;
   }
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   f32x4 acc[4][2];
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
     const int el = 16 * nb + (lane & 15), k0 = 8 * (lane >> 4);
-    bf16x8 bh, bl;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      bh[j] = Bh[el * 32 + k0 + j];
-      if (SPLIT) bl[j] = Bl[el * 32 + k0 + j];
-    }
+    const bf16x8 bh = *(const bf16x8*)(Bh + el * 32 + k0);
+    bf16x8 bl;
+    if (SPLIT) bl = *(const bf16x8*)(Bl + el * 32 + k0);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       f32x4 c = {0.f, 0.f, 0.f, 0.f};
@@ -258,21 +305,28 @@ __device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float
   }
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // B reads done before reuse
   float* O = (float*)wlds;                              // [64 elements][24]
+  const int g4 = 4 * (lane >> 4);
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = 16 * mt + 4 * (lane >> 4) + j;
-        if (row < 24) O[(16 * nb + (lane & 15)) * 24 + row] = acc[nb][mt][j];
-      }
+  for (int nb = 0; nb < 4; ++nb) {
+    float* row = O + (16 * nb + (lane & 15)) * 24;
+    *(f32x4*)(row + g4) = acc[nb][0];                   // rows 0..15
+    if (g4 < 8) *(f32x4*)(row + 16 + g4) = acc[nb][1];  // rows 16..23
+  }
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  float o[24];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const f32x4 t = *(const f32x4*)(O + lane * 24 + 4 * q);
+    o[4 * q + 0] = t[0];
+    o[4 * q + 1] = t[1];
+    o[4 * q + 2] = t[2];
+    o[4 * q + 3] = t[3];
+  }
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    ux[a] = E * O[lane * 24 + 3 * a + 0];
-    uy[a] = E * O[lane * 24 + 3 * a + 1];
-    uz[a] = E * O[lane * 24 + 3 * a + 2];
+    ux[a] = E * o[3 * a + 0];
+    uy[a] = E * o[3 * a + 1];
+    uz[a] = E * o[3 * a + 2];
   }
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // reads done before the next layer's writes
 }
@@ -304,6 +358,15 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup i runs on XCD
+// i mod 8) and each XCD has its own L2.  Giving every XCD a contiguous range
+// of the work list keeps neighbouring tiles, which share halo nodes and
+// partly used cache lines, in one L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // z-tiles of height zc node layers
 __host__ __device__ __forceinline__ int fz_tiles(int NX, int NY, int NZ, int zc) {
   return ((NX + FZ_OUT - 1) / FZ_OUT) * ((NY + FZ_OUT - 1) / FZ_OUT) * ((NZ + zc - 1) / zc);
@@ -322,7 +385,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   __shared__ T ss[12][FZ_TX][FZ_TX];    // per element: 4 corners x 3 comps, layer sum
   __shared__ __attribute__((aligned(16))) char mf_lds[(KIND >= 2) ? 4 * (KIND == 3 ? 8192 : 6144) : 16];
   MfmaA mfA;
-  const int2 wi = work[blockIdx.x];
+  const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& L = P.lv[l];
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
@@ -404,6 +467,15 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     by[c] = su[1][ty + dj][tx + di];
     bz[c] = su[2][ty + dj][tx + di];
   }
+  // vector forms carry the bottom face in face-mode form, plus the raw value
+  // of node (ni, nj, k) for the smoother
+  T ownv[3] = {bx[3], by[3], bz[3]};
+  if constexpr (KIND <= 1) {
+    face_fwd(bx);
+    face_fwd(by);
+    face_fwd(bz);
+  }
+  const ModeCoefE<T> mce = {mc.d - mc.o, mc.o, mc.s, mc.p, mc.q, mc.r - mc.t, mc.t, mc.w};
   // element modulus of the first layer
   T Enext = (KIND != 1 && elem_in && z0 - 1 >= 0 && z0 - 1 < nz)
                 ? Eg[ex + (long long)nx * (ey + (long long)ny * (z0 - 1))]
@@ -432,45 +504,97 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     }
     lds_barrier();
     T ux[8], uy[8], uz[8];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int di = c & 1, dj = c >> 1;
-      ux[c] = bx[c];
-      uy[c] = by[c];
-      uz[c] = bz[c];
-      ux[c + 4] = su[0][ty + dj][tx + di];
-      uy[c + 4] = su[1][ty + dj][tx + di];
-      uz[c + 4] = su[2][ty + dj][tx + di];
-    }
-    // next bottom face = this top face; own node value at layer k for the smoother
-    const T own0 = bx[3], own1 = by[3], own2 = bz[3];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      bx[c] = ux[c + 4];
-      by[c] = uy[c + 4];
-      bz[c] = uz[c + 4];
-    }
+    // own node value at layer k for the smoother (corner 3 of the bottom face)
+    const T own0 = ownv[0], own1 = ownv[1], own2 = ownv[2];
     const bool ein = elem_in && k >= 0 && k < nz;
-    if constexpr (KIND >= 2) {
-      elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, (float)Ecur, mfA,
-                           mf_lds + (threadIdx.x >> 6) * (KIND == 3 ? 8192 : 6144));
-    } else if (KIND == 0) {
-      elem_fine<T>(ux, uy, uz, Ecur, mc);
-    } else if (ein) {
-      elem_galerkin<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k, l, mc);
+    if constexpr (KIND <= 1) {
+      T fx[4], fy[4], fz[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int di = c & 1, dj = c >> 1;
+        fx[c] = su[0][ty + dj][tx + di];
+        fy[c] = su[1][ty + dj][tx + di];
+        fz[c] = su[2][ty + dj][tx + di];
+      }
+      ownv[0] = fx[3];
+      ownv[1] = fy[3];
+      ownv[2] = fz[3];
+      face_fwd(fx);
+      face_fwd(fy);
+      face_fwd(fz);
+      // z stage of the mode transform; the top face becomes the next bottom face
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        ux[c] = bx[c] + fx[c];
+        ux[c + 4] = fx[c] - bx[c];
+        uy[c] = by[c] + fy[c];
+        uy[c + 4] = fy[c] - by[c];
+        uz[c] = bz[c] + fz[c];
+        uz[c + 4] = fz[c] - bz[c];
+        bx[c] = fx[c];
+        by[c] = fy[c];
+        bz[c] = fz[c];
+      }
+      if constexpr (KIND == 0) {
+        mode_contract_e(ux, uy, uz, coef_times(mce, Ecur));
+      } else if (ein) {
+        elem_galerkin_modes<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k, l, mc);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) ux[a] = uy[a] = uz[a] = T(0);
+      }
+      // inverse z stage; face k = bottom of this element + top of the previous
+      // one, summed in face-mode form, then the face's inverse x, y stages
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        fx[c] = (ux[c] - ux[c + 4]) + tpx[c];
+        fy[c] = (uy[c] - uy[c + 4]) + tpy[c];
+        fz[c] = (uz[c] - uz[c + 4]) + tpz[c];
+        tpx[c] = ux[c] + ux[c + 4];
+        tpy[c] = uy[c] + uy[c + 4];
+        tpz[c] = uz[c] + uz[c + 4];
+      }
+      face_inv(fx);
+      face_inv(fy);
+      face_inv(fz);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        ss[3 * c + 0][ty][tx] = fx[c];
+        ss[3 * c + 1][ty][tx] = fy[c];
+        ss[3 * c + 2][ty][tx] = fz[c];
+      }
     } else {
 #pragma unroll
-      for (int a = 0; a < 8; ++a) ux[a] = uy[a] = uz[a] = T(0);
-    }
-    // layer-k node contributions: bottom of this element + top of the previous one
+      for (int c = 0; c < 4; ++c) {
+        const int di = c & 1, dj = c >> 1;
+        ux[c] = bx[c];
+        uy[c] = by[c];
+        uz[c] = bz[c];
+        ux[c + 4] = su[0][ty + dj][tx + di];
+        uy[c + 4] = su[1][ty + dj][tx + di];
+        uz[c + 4] = su[2][ty + dj][tx + di];
+      }
+      ownv[0] = ux[7];
+      ownv[1] = uy[7];
+      ownv[2] = uz[7];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      ss[3 * c + 0][ty][tx] = ux[c] + tpx[c];
-      ss[3 * c + 1][ty][tx] = uy[c] + tpy[c];
-      ss[3 * c + 2][ty][tx] = uz[c] + tpz[c];
-      tpx[c] = ux[c + 4];
-      tpy[c] = uy[c + 4];
-      tpz[c] = uz[c + 4];
+      for (int c = 0; c < 4; ++c) {
+        bx[c] = ux[c + 4];
+        by[c] = uy[c + 4];
+        bz[c] = uz[c + 4];
+      }
+      elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, (float)Ecur, mfA,
+                           mf_lds + (threadIdx.x >> 6) * (KIND == 3 ? 8192 : 6144));
+      // layer-k node contributions: bottom of this element + top of the previous one
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        ss[3 * c + 0][ty][tx] = ux[c] + tpx[c];
+        ss[3 * c + 1][ty][tx] = uy[c] + tpy[c];
+        ss[3 * c + 2][ty][tx] = uz[c] + tpz[c];
+        tpx[c] = ux[c + 4];
+        tpy[c] = uy[c + 4];
+        tpz[c] = uz[c + 4];
+      }
     }
     lds_barrier();
     if (owner && k >= z0) {
