@@ -233,9 +233,11 @@ int tg_batch_select_floor(tg_batch* b, const double* const* rho_d, const double*
 
 /* ---- autotuner (addition (2)) -------------------------------------------- */
 /* Times the V-cycle smoothing sweep of the matrix-free levels for each
- * candidate z-tile height {2,3,4,6,8,12,16} and keeps the fastest per level
- * (the tile height trades one redundant element layer per tile against
- * parallelism).  Needs set_density.  zc_out (may be NULL) receives the 8
+ * candidate z-tile height and keeps the fastest per level: the tile height
+ * trades one redundant element layer per tile against parallelism and
+ * against the last, partly filled round of resident workgroups.  Candidates:
+ * 2, 3, 4, 6, 8 and every balanced height ceil(NZ / t), t = 1..64, of the
+ * batch's grids at that level.  Needs set_density.  zc_out (may be NULL) receives the 8
  * per-level heights, us_out (may be NULL) the best sweep time per level in
  * microseconds (-1 where nothing was timed).  Choices are cached per batch
  * signature (grid sizes in order, precision) for the process and, if the

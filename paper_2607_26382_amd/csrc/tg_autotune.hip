@@ -3,6 +3,7 @@
 // fastest.  Results are cached per batch signature (grid dimensions of every
 // problem and the working precision) for the life of the process, and
 // optionally in a text file named by TG_AUTOTUNE_CACHE.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -79,7 +80,6 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
   if (prec < TG_F64 || prec > TG_BF16X3MFMA) return fail(TG_EINVAL, "unknown precision");
   for (int l = 0; l < TG_MAXLEV && best_us; ++l) best_us[l] = -1.0;
   if (!force && autotune_lookup(b, prec)) return batch_upload_desc(b, s);
-  const int cand[7] = {2, 3, 4, 6, 8, 12, 16};
   std::vector<int> all(b->n);
   for (int i = 0; i < b->n; ++i) {
     all[i] = i;
@@ -93,6 +93,17 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
     bool any = false;
     for (auto* g : b->grids) any = any || (l < g->nlev - 1);
     if (!any) continue;
+    // candidate heights: the balanced heights ceil(NZ / t) of every grid at
+    // this level (t z-tiles, so the tile count can match the number of
+    // resident workgroups) plus a few small ones
+    std::vector<int> cand = {2, 3, 4, 6, 8};
+    for (auto* g : b->grids) {
+      if (l >= g->nlev - 1) continue;
+      const int NZ = g->lv[l].ez + 1;
+      for (int t = 1; t <= std::min(NZ, 64); ++t) cand.push_back((NZ + t - 1) / t);
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
     double best = 1e30;
     int pick = b->zc[l];
     for (int c : cand) {
@@ -111,7 +122,7 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
       };
       if ((rc = sweep())) break;
       TG_HIP(hipEventRecord(e0, s));
-      const int reps = 5;
+      const int reps = 3;
       for (int r = 0; r < reps; ++r)
         if ((rc = sweep())) break;
       TG_HIP(hipEventRecord(e1, s));

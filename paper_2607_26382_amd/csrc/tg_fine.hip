@@ -254,16 +254,22 @@ __device__ __forceinline__ void mfma_load_ke(const float TG_GLOBAL* Ke, MfmaA& A
     }
 }
 
-// ux/uy/uz[a]: this lane's element; wlds: this wave's LDS block
-// (SPLIT ? 2 : 1) * 64 * 32 bf16 = 4 KiB (8 KiB), reused for 64 x 24 floats.
+// ux/uy/uz[a]: this lane's element; wlds: this wave's LDS block of
+// MF_WAVE_BYTES (7 KiB).
+// Row strides of the wave-private staging block, padded so that 16-byte
+// accesses of consecutive lanes spread over the LDS banks.  The block holds
+// the high BF16 parts, then (split form) the low parts, then the outputs.
+#define MF_BROW 40    // bf16 per element row of B (32 used)
+#define MF_OROW 28    // floats per element row of the output (24 used)
+#define MF_WAVE_BYTES (64 * MF_OROW * 4)
+static_assert(64 * MF_BROW * 2 <= MF_WAVE_BYTES, "staging block");
+
 template <bool SPLIT>
 __device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float E, const MfmaA& A,
                                           char* wlds) {
   const int lane = threadIdx.x & 63;
-  __bf16* Bh = (__bf16*)wlds;                 // [64 elements][32]
-  __bf16* Bl = Bh + 64 * 32;
-  // this lane's 24 DOFs (3 a + c) and 8 zeros as four 8-wide BF16 vectors,
-  // written with 16-byte stores
+  __bf16* Bs = (__bf16*)wlds;                 // [64 elements][MF_BROW]
+  // this lane's 24 DOFs (3 a + c) and 8 zeros, high (and low) BF16 parts
   float v[32];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -273,42 +279,49 @@ __device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float
   }
 #pragma unroll
   for (int k = 24; k < 32; ++k) v[k] = 0.f;
+  bf16x8 hv[4], lv[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    bf16x8 h, lo;
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      h[j] = (__bf16)v[8 * q + j];
-      if (SPLIT) lo[j] = (__bf16)(v[8 * q + j] - (float)h[j]);
+      hv[q][j] = (__bf16)v[8 * q + j];
+      if (SPLIT) lv[q][j] = (__bf16)(v[8 * q + j] - (float)hv[q][j]);
     }
-    *(bf16x8*)(Bh + lane * 32 + 8 * q) = h;
-    if (SPLIT) *(bf16x8*)(Bl + lane * 32 + 8 * q) = lo;
-  }
+  const int k0 = 8 * (lane >> 4);
+  // B operand of group nb: element 16 nb + lane % 16, DOFs k0 .. k0 + 7
+  bf16x8 bh[4], bl[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) *(bf16x8*)(Bs + lane * MF_BROW + 8 * q) = hv[q];
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) bh[nb] = *(const bf16x8*)(Bs + (16 * nb + (lane & 15)) * MF_BROW + k0);
+  if (SPLIT) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // high parts read before the low parts land
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *(bf16x8*)(Bs + lane * MF_BROW + 8 * q) = lv[q];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) bl[nb] = *(const bf16x8*)(Bs + (16 * nb + (lane & 15)) * MF_BROW + k0);
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // B reads done before the block is reused
   f32x4 acc[4][2];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int el = 16 * nb + (lane & 15), k0 = 8 * (lane >> 4);
-    const bf16x8 bh = *(const bf16x8*)(Bh + el * 32 + k0);
-    bf16x8 bl;
-    if (SPLIT) bl = *(const bf16x8*)(Bl + el * 32 + k0);
+  for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       f32x4 c = {0.f, 0.f, 0.f, 0.f};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bh, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bh[nb], c, 0, 0, 0);
       if (SPLIT) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bl, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[mt], bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bl[nb], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[mt], bh[nb], c, 0, 0, 0);
       }
       acc[nb][mt] = c;
     }
-  }
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // B reads done before reuse
-  float* O = (float*)wlds;                              // [64 elements][24]
+  float* O = (float*)wlds;                              // [64 elements][MF_OROW]
   const int g4 = 4 * (lane >> 4);
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
-    float* row = O + (16 * nb + (lane & 15)) * 24;
+    float* row = O + (16 * nb + (lane & 15)) * MF_OROW;
     *(f32x4*)(row + g4) = acc[nb][0];                   // rows 0..15
     if (g4 < 8) *(f32x4*)(row + 16 + g4) = acc[nb][1];  // rows 16..23
   }
@@ -316,7 +329,7 @@ __device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float
   float o[24];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    const f32x4 t = *(const f32x4*)(O + lane * 24 + 4 * q);
+    const f32x4 t = *(const f32x4*)(O + lane * MF_OROW + 4 * q);
     o[4 * q + 0] = t[0];
     o[4 * q + 1] = t[1];
     o[4 * q + 2] = t[2];
@@ -383,7 +396,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   // two barriers of its step, every write of the next layer after them.
   __shared__ T su[3][17][17];           // node values of the current top layer
   __shared__ T ss[12][FZ_TX][FZ_TX];    // per element: 4 corners x 3 comps, layer sum
-  __shared__ __attribute__((aligned(16))) char mf_lds[(KIND >= 2) ? 4 * (KIND == 3 ? 8192 : 6144) : 16];
+  __shared__ __attribute__((aligned(16))) char mf_lds[(KIND >= 2) ? 4 * MF_WAVE_BYTES : 16];
   MfmaA mfA;
   const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
@@ -584,7 +597,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         bz[c] = uz[c + 4];
       }
       elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, (float)Ecur, mfA,
-                           mf_lds + (threadIdx.x >> 6) * (KIND == 3 ? 8192 : 6144));
+                           mf_lds + (threadIdx.x >> 6) * MF_WAVE_BYTES);
       // layer-k node contributions: bottom of this element + top of the previous one
 #pragma unroll
       for (int c = 0; c < 4; ++c) {

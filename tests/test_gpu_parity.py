@@ -366,7 +366,8 @@ def test_bf16_vcycle_and_solve_certified(prec):
         assert res["outcome"] in ("MAXIT", "BREAKDOWN") and res["proj_eta"] > 1e-6
 
 
-AUTOTUNE_CANDIDATES = {2, 3, 4, 6, 8, 12, 16}
+def _valid_height(z, nz_nodes):
+    return 1 <= z <= max(nz_nodes, 8)
 
 
 def test_autotune_changes_only_the_decomposition():
@@ -380,7 +381,7 @@ def test_autotune_changes_only_the_decomposition():
     f = torch.tensor(g.edge_load(), device=DEV)
     u0, r0, _ = g.fgmres_solve(f, tg.solver_opts(prec=tg.F32))
     zc, us = g.autotune(tg.F32, force=True)
-    assert all(z in AUTOTUNE_CANDIDATES for z in zc[:2])
+    assert _valid_height(zc[0], 17) and _valid_height(zc[1], 9)
     assert us[0] > 0 and us[1] > 0
     after = [g.apply_K(u64, tg.F64), g.apply_K(u32, tg.F32), g.vcycle(u64, tg.F64), g.vcycle(u32, tg.F32)]
     for a, b in zip(before, after):
@@ -404,7 +405,7 @@ def test_autotuned_uneven_batch_equals_untuned():
         batch.set_density([torch.tensor(r, device=DEV) for r in rhos], 3.0, floors)
         if tune:
             zc, us = batch.autotune(tg.F32, force=True)
-            assert zc[0] in AUTOTUNE_CANDIDATES and us[0] > 0
+            assert _valid_height(zc[0], 25) and us[0] > 0
         fs = [torch.tensor(g.edge_load(), device=DEV) for g in grids]
         res.append(batch.solve(fs, tg.solver_opts(prec=tg.F32)))
     (ua, ra), (ub, rb) = res
