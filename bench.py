@@ -56,6 +56,8 @@ def parse():
                     help="first-rung selector of the headline run (stored network or two-feature rule)")
     ap.add_argument("--cgs-passes", type=int, default=2, choices=[1, 2, 3],
                     help="orthogonalization: 1 CGS, 2 CGS2 with delayed reorthogonalization, 3 CGS2 in place")
+    ap.add_argument("--no-batch4", action="store_true", help="skip the 192 uneven batched solves")
+    ap.add_argument("--no-small", action="store_true", help="skip the 16x8x8 plain-method leg")
     ap.add_argument("--no-rule-leg", action="store_true",
                     help="skip the mixed-precision run with the two-feature rule")
     ap.add_argument("--copy-probe", action="store_true",
@@ -163,6 +165,106 @@ def apply_leg(tg, torch, dev, reps=40):
     out["n_dof"] = g.n_dof
     del g
     torch.cuda.empty_cache()
+    return out
+
+
+B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
+
+
+def batch4_leg(tg, torch, dev, mixed_prec):
+    """Batched uneven solves: 48 blob states (seeds 4000-4047, grid
+    B4_GRIDS[i % 4], the severe-state generator at that size) x 4 ladder
+    floors = 192 independent solves in one batch (FP32 V-cycle, FP64 guard),
+    against the same 192 solves one at a time and the FP64 batch.  Rate =
+    guard-passing solves / wall time of set_density + solve + guard."""
+    from paper_2607_26382_amd import synth
+    grids, rhos, floors, fs = [], [], [], []
+    loads = {}
+    for i in range(48):
+        d = B4_GRIDS[i % 4]
+        rt = torch.tensor(synth.blobs(*d, 4000 + i, blob=4, floor_frac=0.5), device=dev)
+        for r in RUNGS:
+            g = tg.Grid(*d, max_restart=30, device=dev)
+            if d not in loads:
+                loads[d] = torch.tensor(g.edge_load(), device=dev)
+            grids.append(g)
+            rhos.append(rt)
+            floors.append(r)
+            fs.append(loads[d])
+    batch = tg.Batch(grids)
+    log(f"batch of {len(grids)} uneven solves bound")
+    batch.set_density(rhos, 3.0, floors)
+    zc, _ = batch.autotune(mixed_prec)
+
+    def batched(prec):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.set_density(rhos, 3.0, floors)
+        _, res = batch.solve(fs, tg.solver_opts(prec=prec))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(1 for r in res if r["true_eta"] <= 1e-6)
+        return {"value": ok / dt, "seconds": dt, "guard_passing": ok,
+                "mean_iters": float(np.mean([r["iterations"] for r in res]))}
+
+    batched(mixed_prec)   # warm-up
+    out = {"solves": len(grids), "grids": [list(d) for d in B4_GRIDS], "autotuned_zc": zc[:2],
+           "mixed_batched": batched(mixed_prec), "fp64_batched": batched(tg.F64)}
+    # the same solves one at a time (each grid alone)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok = 0
+    for g, r, fl, f in zip(grids, rhos, floors, fs):
+        g.set_density(r, 3.0, fl)
+        u, res, _ = g.fgmres_solve(f, tg.solver_opts(prec=mixed_prec), want_hist=False)
+        ok += int(g.true_residual(f, u) <= 1e-6)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["mixed_serial"] = {"value": ok / dt, "seconds": dt, "guard_passing": ok}
+    out["batched_over_serial"] = out["mixed_batched"]["value"] / out["mixed_serial"]["value"]
+    out["mixed_over_fp64"] = out["mixed_batched"]["value"] / out["fp64_batched"]["value"]
+    log(f"uneven batch: {out['mixed_batched']['value']:.1f} solves/s batched, "
+        f"{out['mixed_serial']['value']:.1f} serial, {out['fp64_batched']['value']:.1f} FP64 batched")
+    del batch, grids
+    torch.cuda.empty_cache()
+    return out
+
+
+def small_leg(tg, torch, dev, reps=3):
+    """The plain method on the small cantilever: 16x8x8, densities U[0,1)
+    (seeds 0-9), rho_min = 1e-3, FP64 throughout, FGMRES(30) cap 200.  A
+    launch-latency-bound case: set_density + solve + guard per state, with
+    each Arnoldi step launched directly or replayed as a captured graph."""
+    from paper_2607_26382_amd import synth
+    g = tg.Grid(16, 8, 8, max_restart=30, device=dev)
+    f = torch.tensor(g.edge_load(), device=dev)
+    rhos = [torch.tensor(synth.uniform(16, 8, 8, sd), device=dev) for sd in range(10)]
+    out = {"grid": [16, 8, 8], "states": len(rhos), "dtype": "f64", "levels": g.n_levels}
+
+    def run(graphs):
+        o = tg.solver_opts(prec=tg.F64, graphs=graphs)
+        ok = its = 0
+        for r in rhos:   # warm-up (and graph capture)
+            g.set_density(r, 3.0, 1e-3)
+            g.fgmres_solve(f, o, want_hist=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for r in rhos:
+                g.set_density(r, 3.0, 1e-3)
+                u, res, _ = g.fgmres_solve(f, o, want_hist=False)
+                ok += int(g.true_residual(f, u) <= 1e-6)
+                its += res["iterations"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return {"value": ok / dt, "certified": ok, "solves": reps * len(rhos),
+                "mean_iters": its / (reps * len(rhos)), "us_per_iteration": 1e6 * dt / its}
+
+    out["direct_launches"] = run(False)
+    out["graph_replay"] = run(True)
+    out["graph_speedup"] = out["graph_replay"]["value"] / out["direct_launches"]["value"]
+    log(f"small cantilever: {out['direct_launches']['value']:.0f} solves/s direct, "
+        f"{out['graph_replay']['value']:.0f} with graph replay")
     return out
 
 
@@ -323,6 +425,12 @@ def main():
         result["fp64"]["same_rung"] = sum(1 for a, b in zip(outs, outs64) if a["rung"] == b["rung"])
         assert cert64 == result["fp64"]["certified"]
         result["mixed_over_fp64"] = value / result["fp64"]["value"]
+    if not args.no_small:
+        result["small_plain"] = small_leg(tg, torch, dev)
+    if not args.no_batch4:
+        del batch, grids
+        torch.cuda.empty_cache()
+        result["batch_uneven"] = batch4_leg(tg, torch, dev, mixed_prec)
     if not args.no_cpu:
         setups = float(np.mean([1 + len(o["attempts"]) for o in outs]))
         iters = float(np.mean([o["iters_probe"] + o["iters_selected"] + o["iters_rejected"] for o in outs]))

@@ -87,6 +87,11 @@ typedef struct {
                           over the basis per step); 3 = CGS2 in place
                           (three sweeps per step)                        */
   double breakdown;    /* subdiagonal <= breakdown * ||w|| -> BREAKDOWN, 1e-14 */
+  int graphs;          /* nonzero (with cgs_passes = 2): each Arnoldi step
+                          (V-cycle, K z, both sweeps, scalar kernels) is
+                          captured once as a HIP graph per work-list state
+                          and step index and replayed; results are bitwise
+                          those of direct launches.  Default 0.          */
 } tg_solver_opts;
 
 typedef struct {

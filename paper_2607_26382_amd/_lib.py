@@ -24,7 +24,8 @@ class MgOpts(C.Structure):
 
 class SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("tol", C.c_double),
-                ("prec", C.c_int), ("cgs_passes", C.c_int), ("breakdown", C.c_double)]
+                ("prec", C.c_int), ("cgs_passes", C.c_int), ("breakdown", C.c_double),
+                ("graphs", C.c_int)]
 
 
 class SolveResult(C.Structure):

@@ -201,6 +201,16 @@ size_t batch_ws_bytes_for(const std::vector<tg_grid*>& gs) {
   return bp.off + 256;
 }
 
+static void drop_graphs(Batch* b) {
+  for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+Batch::~Batch() {
+  drop_graphs(this);
+  if (cap_stream) hipStreamDestroy(cap_stream);
+}
+
 int batch_init(Batch* b, int n, tg_grid* const* grids) {
   if (n <= 0) return fail(TG_EINVAL, "batch needs at least one grid");
   b->grids.assign(grids, grids + n);
@@ -226,6 +236,7 @@ int batch_bind(Batch* b, void* ws, size_t bytes) {
   if (!ws || bytes < need) return fail(TG_EWORKSPACE, "batch workspace too small");
   Bump bp(ws, bytes, false);
   b->lists_valid = false;
+  drop_graphs(b);
   batch_layout(bp, b, b->n, list_capacity(b->grids));
   b->ws = ws;
   b->ws_bytes = bytes;
@@ -321,6 +332,20 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   b->lists_elem = with_elem;
   b->lists_active = active;
   std::memcpy(b->lists_zc, b->zc, sizeof(b->zc));
+  // the list layout is a function of (active set, zc, elem flag): equal
+  // signatures mean identical device lists at identical addresses
+  unsigned long long h = 1469598103934665603ull;
+  auto mix = [&](long long v) {
+    for (int q = 0; q < 8; ++q) {
+      h ^= (unsigned long long)((v >> (8 * q)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix((long long)active.size());
+  for (int p : active) mix(p);
+  for (int l = 0; l < TG_MAXLEV; ++l) mix(b->zc[l]);
+  mix(with_elem ? 1 : 0);
+  b->lists_sig = h;
   return TG_OK;
 }
 
@@ -471,6 +496,7 @@ void tg_default_solver_opts(tg_solver_opts* o) {
   o->tol = 1e-6;
   o->prec = TG_F64;
   o->cgs_passes = 2;
+  o->graphs = 0;
   o->breakdown = 1e-14;
 }
 

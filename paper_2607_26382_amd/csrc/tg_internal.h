@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <array>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -201,6 +202,11 @@ struct Batch {
   bool lists_elem = false;
   std::vector<int> lists_active;
   int lists_zc[TG_MAXLEV] = {};
+  unsigned long long lists_sig = 0;     // hash of what the device lists encode (set, zc, elem)
+  // captured FGMRES steps (graph replay), keyed by lists epoch and step shape
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+  ~Batch();
 };
 
 size_t batch_ws_bytes_for(const std::vector<tg_grid*>& grids);
@@ -217,7 +223,7 @@ int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s);
 int k_dots2(Batch* b, int sbase, int nv, int sq, int sw, hipStream_t s);
 int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, hipStream_t s);
 int k_dcgs_a(Batch* b, int j, hipStream_t s);
-int k_dcgs_b(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s);
+int k_dcgs_b(Batch* b, int j, int cap, double tol, double brk, hipStream_t s);
 int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
              void* ey, hipStream_t s, int in_scale_sc = -1);   // input scaled by small[scal + in_scale_sc]
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s);  // dir 0: ext0 -> slot; 1: slot -> ext1
@@ -239,6 +245,7 @@ int k_init_small(Batch* b, hipStream_t s);
 
 // kernel-class timer (tg_timer.hip)
 bool timer_on();
+void timer_suspend(bool on);
 void* timer_begin(int kind, hipStream_t s);
 void timer_end(void* h, double bytes, hipStream_t s);
 void timer_harvest();

@@ -1126,7 +1126,7 @@ __global__ void k_dcgs_a_(const ProbDesc* __restrict__ probs, const int2* __rest
 // only after the next sweep A): rotations, projected residual estimate,
 // history and stop tests as in the immediate form.
 __global__ void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work, SmallOffs o,
-                          int j, int k, int cap, double tol, double brk, double* status_out) {
+                          int j, int cap, double tol, double brk, double* status_out) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   if (threadIdx.x != 0) return;
@@ -1169,7 +1169,7 @@ __global__ void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __rest
   sc[SC_GJ] = gj;
   S[o.g + j + 1] = -sn * gj;
   S[o.g + j] = c * gj;
-  const int kk = k + 1;
+  const int kk = (int)sc[SC_ITERS] + 1;   // iterations so far live on the device
   const double est = fabs(S[o.g + j + 1]) / sc[SC_BNORM];
   S[o.hist + kk] = est;
   sc[SC_EST] = est;
@@ -1553,10 +1553,10 @@ int k_dcgs_a(Batch* b, int j, hipStream_t s) {
     TG_TIMED(TG_KT_SCALAR, 0, k_dcgs_a_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, b->sc_d));
   return check_launch("dcgs_a");
 }
-int k_dcgs_b(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s) {
+int k_dcgs_b(Batch* b, int j, int cap, double tol, double brk, hipStream_t s) {
   if (b->prob.n)
     TG_TIMED(TG_KT_SCALAR, 0,
-             k_dcgs_b_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, k, cap, tol, brk, b->sc_d));
+             k_dcgs_b_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, cap, tol, brk, b->sc_d));
   return check_launch("dcgs_b");
 }
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s) {

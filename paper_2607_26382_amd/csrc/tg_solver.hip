@@ -3,6 +3,7 @@
 // one).  Host code only sequences kernels and reads per-problem status words.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "tg_internal.h"
@@ -61,6 +62,45 @@ static int check_ready(Batch* b, const std::vector<int>& which, bool need_mg = f
   return TG_OK;
 }
 
+// One FGMRES step as a captured graph.  The step's kernels depend only on the
+// device work lists (their signature), the step index j and the options, never on
+// host values that change between replays (the iteration count lives on the
+// device), so a graph is captured once per key and replayed on the caller's
+// stream.  Capture runs on a private stream (default priority); nothing
+// executes during capture and the timer records no events.
+template <class F>
+static int graph_step(Batch* b, F&& step, const tg_solver_opts* o, int j, hipStream_t s) {
+  char key[160];
+  std::snprintf(key, sizeof(key), "%llx|%d|%d|%d|%.17g|%.17g|%d", b->lists_sig, o->prec, j, o->max_iters,
+                o->tol, o->breakdown, b->grids[0]->mmax);
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    if (b->graphs.size() >= 1024) {
+      for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+      b->graphs.clear();
+    }
+    if (!b->cap_stream) TG_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    TG_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    timer_suspend(true);
+    const int rc = step(b->cap_stream);
+    timer_suspend(false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+    it = b->graphs.emplace(key, ex).first;
+  }
+  TG_HIP(hipGraphLaunch(it->second, s));
+  return TG_OK;
+}
+
 // Right-preconditioned FGMRES on every problem in `which` (Sec. 3.5), x0 = 0,
 // rhs in slot S_F, solution in slot S_X, history in small + hist.
 int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s) {
@@ -107,15 +147,23 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
         // once, first-pass norm rho_j in SC_RHO); z_j = M^-1 (q~_j / rho_j).
         // Sweep A: dots of [V_0..V_{j-1}, q~_j] with q~_j and w = K z_j;
         // sweep B: reorthogonalized q_j into V_j and q~_{j+1} into V_{j+1}.
-        if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s, SC_INV)))
+        auto step = [&](hipStream_t st) -> int {
+          int r;
+          if ((r = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, st, SC_INV)))
+            return r;
+          if ((r = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, st))) return r;
+          if ((r = k_dots2(b, slot_V(0), j, slot_V(j), S_W, st))) return r;
+          if ((r = k_reduce(b, 2 * j + 3, 2, 0, -1, st))) return r;
+          if ((r = k_dcgs_a(b, j, st))) return r;
+          if ((r = k_update2(b, slot_V(0), j, slot_V(j), S_W, slot_V(j + 1), st))) return r;
+          if ((r = k_reduce(b, 1, 2, 0, -1, st))) return r;
+          return k_dcgs_b(b, j, cap, tol, brk, st);
+        };
+        if (o->graphs) {
+          if ((rc = graph_step(b, step, o, j, s))) return rc;
+        } else if ((rc = step(s))) {
           return rc;
-        if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
-        if ((rc = k_dots2(b, slot_V(0), j, slot_V(j), S_W, s))) return rc;
-        if ((rc = k_reduce(b, 2 * j + 3, 2, 0, -1, s))) return rc;
-        if ((rc = k_dcgs_a(b, j, s))) return rc;
-        if ((rc = k_update2(b, slot_V(0), j, slot_V(j), S_W, slot_V(j + 1), s))) return rc;
-        if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
-        if ((rc = k_dcgs_b(b, j, k, cap, tol, brk, s))) return rc;
+        }
         ++k;
         if ((rc = batch_read_status(b, s))) return rc;
         std::vector<int> still;

@@ -42,9 +42,13 @@ hipEvent_t get_event(Timer& t) {
 
 bool timer_on() { return T().mask != 0; }
 
+// While a stream is being captured into a graph no events are recorded.
+static thread_local bool g_suspended = false;
+void timer_suspend(bool on) { g_suspended = on; }
+
 void* timer_begin(int kind, hipStream_t s) {
   Timer& t = T();
-  if (!((t.mask >> kind) & 1u)) return nullptr;
+  if (g_suspended || !((t.mask >> kind) & 1u)) return nullptr;
   std::lock_guard<std::mutex> g(t.mu);
   hipEvent_t a = get_event(t), b = get_event(t);
   if (!a || !b) return nullptr;

@@ -35,8 +35,8 @@ def mg_opts(max_levels=0, max_coarse_dof=300, omega=0.6, nu_pre=2, nu_post=2):
     return L.MgOpts(max_levels, max_coarse_dof, omega, nu_pre, nu_post)
 
 
-def solver_opts(restart=30, max_iters=200, tol=1e-6, prec=F64, cgs_passes=2, breakdown=1e-14):
-    return L.SolverOpts(restart, max_iters, tol, prec, cgs_passes, breakdown)
+def solver_opts(restart=30, max_iters=200, tol=1e-6, prec=F64, cgs_passes=2, breakdown=1e-14, graphs=False):
+    return L.SolverOpts(restart, max_iters, tol, prec, cgs_passes, breakdown, int(bool(graphs)))
 
 
 def policy(rungs=(1e-9, 1e-6, 1e-4, 1e-3), p=3.0, tau=1e-6, probe_iters=100, probe_restart=100,

@@ -412,3 +412,36 @@ def test_autotuned_uneven_batch_equals_untuned():
     for i in range(len(dims_list)):
         assert ra[i]["iterations"] == rb[i]["iterations"]
         assert torch.equal(ua[i], ub[i])
+
+
+@pytest.mark.parametrize("prec", [tg.F64, tg.F32])
+def test_graph_replay_equals_direct_launches(prec):
+    """Captured FGMRES steps replay bitwise like direct launches, replay after
+    replay, with eager work and synchronizations in between."""
+    dims = (16, 8, 8)
+    g = _gpu_grid(dims, synth.uniform(*dims, 0), 3.0, 1e-3)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u0, r0, h0 = g.fgmres_solve(f, tg.solver_opts(prec=prec, restart=7))
+    for rep in range(3):
+        u1, r1, h1 = g.fgmres_solve(f, tg.solver_opts(prec=prec, restart=7, graphs=True))
+        assert r1 == r0 and torch.equal(u1, u0) and np.array_equal(h1, h0), rep
+        # eager work between replays
+        y = g.apply_K(u1, tg.F64)
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+
+
+def test_graph_replay_in_uneven_batch():
+    dims_list = [(16, 8, 8), (24, 12, 12), (16, 8, 8)]
+    rhos = [synth.uniform(*dims_list[0], 0), synth.blobs(*dims_list[1], 7), synth.uniform(*dims_list[2], 9)]
+    grids = [tg.Grid(*d, max_restart=30, device=DEV) for d in dims_list]
+    batch = tg.Batch(grids)
+    rho_d = [torch.tensor(r, device=DEV) for r in rhos]
+    fs = [torch.tensor(g.edge_load(), device=DEV) for g in grids]
+    batch.set_density(rho_d, 3.0, [1e-3, 1e-4, 1e-2])
+    ref_u, ref_r = batch.solve(fs, tg.solver_opts(prec=tg.F32))
+    for rep in range(3):
+        batch.set_density(rho_d, 3.0, [1e-3, 1e-4, 1e-2])
+        us, res = batch.solve(fs, tg.solver_opts(prec=tg.F32, graphs=True))
+        for a, b, ra, rb in zip(us, ref_u, res, ref_r):
+            assert ra == rb and torch.equal(a, b), rep
