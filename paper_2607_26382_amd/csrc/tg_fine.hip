@@ -15,6 +15,7 @@
 // update.  Output nodes: 15 x 15 columns per workgroup, ZC node layers.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "tg_internal.h"
 
@@ -219,6 +220,56 @@ __device__ __forceinline__ void elem_galerkin_modes(T* ux, T* uy, T* uz, const T
         mode_restrict_t_add(bz, uz, h, sx, sy, sz);
       }
     }
+  }
+}
+
+template <class T> __device__ __forceinline__ const T* G1V(const ProbDesc& P);
+template <> __device__ __forceinline__ const double* G1V<double>(const ProbDesc& P) { return P.G1v64; }
+template <> __device__ __forceinline__ const float* G1V<float>(const ProbDesc& P) { return P.G1v32; }
+
+// Level-1 Galerkin element in moment form (modes in, modes out): with mu the
+// eight Walsh moments of the children's moduli (mu_G = sum_c chi_G(c) E_c),
+// sum_c E_c T_c^T Khat T_c = sum_G mu_G M_G, eight fixed matrices with 279
+// nonzeros in all taking 21 distinct values (pattern kG1Pattern, values v from
+// the host, held in scalar registers).  About 430 multiply-adds instead of
+// eight child restrictions and contractions.
+template <class T>
+__device__ __forceinline__ void elem_galerkin1(T* ux, T* uy, T* uz, const T TG_GLOBAL* E0, int nx0, int ny0,
+                                               int ex, int ey, int ez,
+                                               const T __attribute__((address_space(4)))* v) {
+  T mu[8];
+  const long long base = 2LL * ex + (long long)nx0 * (2LL * ey + (long long)ny0 * 2LL * ez);
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    mu[c] = E0[base + (c & 1) + (long long)nx0 * (((c >> 1) & 1) + (long long)ny0 * (c >> 2))];
+  wht_fwd(mu);
+  T a[24], y[24];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    a[3 * m + 0] = ux[m];
+    a[3 * m + 1] = uy[m];
+    a[3 * m + 2] = uz[m];
+  }
+  // -0.0 is the exact additive identity, so untouched sums fold away
+#pragma unroll
+  for (int r = 0; r < 24; ++r) y[r] = T(-0.0);
+#pragma unroll
+  for (int G = 0; G < 8; ++G) {
+    T t[24];
+#pragma unroll
+    for (int r = 0; r < 24; ++r) t[r] = T(-0.0);
+#pragma unroll
+    for (int e = 0; e < TG_G1_NNZ; ++e)
+      if (kG1Pattern[e].g == G) t[kG1Pattern[e].r] += v[kG1Pattern[e].k] * a[kG1Pattern[e].c];
+#pragma unroll
+    for (int r = 0; r < 24; ++r)
+      if ((kG1RowMask[G] >> r) & 1u) y[r] += mu[G] * t[r];
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    ux[m] = y[3 * m + 0];
+    uy[m] = y[3 * m + 1];
+    uz[m] = y[3 * m + 2];
   }
 }
 
@@ -550,6 +601,10 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       }
       if constexpr (KIND == 0) {
         mode_contract_e(ux, uy, uz, coef_times(mce, Ecur));
+      } else if (ein && l == 1) {
+        // read-only table: constant address space, so the loads are scalar
+        elem_galerkin1<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k,
+                          (const T __attribute__((address_space(4)))*)G1V<T>(P));
       } else if (ein) {
         elem_galerkin_modes<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k, l, mc);
       } else {
@@ -703,6 +758,84 @@ int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>
   *out64 = m64;
   *out32 = {(float)m64.d, (float)m64.o, (float)m64.s, (float)m64.p,
             (float)m64.q, (float)m64.r, (float)m64.t, (float)m64.w};
+  return TG_OK;
+}
+
+// Level-1 moment matrices M_G = (1/8) sum_c chi_G(c) T_c^T Khat T_c (the
+// children c of a coarse element, T_c the per-dimension restriction
+// (a0, a1) -> (a0 + s a1, a1 / 2), s = -1/2 or +1/2, Khat = T Ke T^T / 64), read
+// out at the pattern kG1Pattern (one value per class of equal entries);
+// entries outside it must vanish.
+int galerkin1_values(const double* Ke, double* out) {
+  double H[8][8];
+  for (int m = 0; m < 8; ++m)
+    for (int a = 0; a < 8; ++a) {
+      double v = 1.0;
+      for (int b = 0; b < 3; ++b)
+        if (m & (1 << b)) v *= ((a >> b) & 1) ? 1.0 : -1.0;
+      H[m][a] = v;
+    }
+  std::vector<double> Kh(576, 0.0);   // Khat, index 3 m + comp
+  for (int r = 0; r < 24; ++r)
+    for (int c = 0; c < 24; ++c) {
+      double s = 0.0;
+      const int mr = r / 3, cr = r % 3, mc = c / 3, cc = c % 3;
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) s += H[mr][a] * Ke[(3 * a + cr) * 24 + 3 * b + cc] * H[mc][b];
+      Kh[r * 24 + c] = s / 64.0;
+    }
+  std::vector<double> M(8 * 576, 0.0), T(576), KT(576);
+  for (int c = 0; c < 8; ++c) {
+    // T_c: 24 x 24 on index 3 m + comp; per dimension b the 2x2 block
+    // [[1, s_b], [0, 1/2]] on (bit b clear, bit b set)
+    double sd[3];
+    for (int b = 0; b < 3; ++b) sd[b] = ((c >> b) & 1) ? 0.5 : -0.5;
+    for (int r = 0; r < 24; ++r)
+      for (int q = 0; q < 24; ++q) {
+        // child mode r / 3 from coarse mode q / 3, same component: per
+        // dimension t(0,0) = 1, t(0,1) = s, t(1,1) = 1/2, t(1,0) = 0
+        const int mr = r / 3, mq = q / 3;
+        double v = (r % 3 == q % 3) ? 1.0 : 0.0;
+        for (int b = 0; b < 3; ++b) {
+          const int br = (mr >> b) & 1, bq = (mq >> b) & 1;
+          v *= br ? (bq ? 0.5 : 0.0) : (bq ? sd[b] : 1.0);
+        }
+        T[r * 24 + q] = v;
+      }
+    for (int r = 0; r < 24; ++r)
+      for (int q = 0; q < 24; ++q) {
+        double s = 0.0;
+        for (int t = 0; t < 24; ++t) s += Kh[r * 24 + t] * T[t * 24 + q];
+        KT[r * 24 + q] = s;
+      }
+    for (int G = 0; G < 8; ++G) {
+      double chi = 1.0;
+      for (int b = 0; b < 3; ++b)
+        if ((G >> b) & 1) chi *= ((c >> b) & 1) ? 1.0 : -1.0;
+      for (int r = 0; r < 24; ++r)
+        for (int q = 0; q < 24; ++q) {
+          double s = 0.0;
+          for (int t = 0; t < 24; ++t) s += T[t * 24 + r] * KT[t * 24 + q];
+          M[G * 576 + r * 24 + q] += chi * s / 8.0;
+        }
+    }
+  }
+  std::vector<char> in(8 * 576, 0), set(TG_G1_NVAL, 0);
+  for (int e = 0; e < TG_G1_NNZ; ++e) {
+    const G1Entry& p = kG1Pattern[e];
+    if (!set[p.k]) out[p.k] = M[p.g * 576 + p.r * 24 + p.c];
+    set[p.k] = 1;
+    in[p.g * 576 + p.r * 24 + p.c] = 1;
+  }
+  double mx = 0.0, err = 0.0;
+  for (int q = 0; q < 8 * 576; ++q) mx = std::fmax(mx, std::fabs(M[q]));
+  for (int q = 0; q < 8 * 576; ++q)
+    if (!in[q]) err = std::fmax(err, std::fabs(M[q]));
+  for (int e = 0; e < TG_G1_NNZ; ++e) {
+    const G1Entry& p = kG1Pattern[e];
+    err = std::fmax(err, std::fabs(M[p.g * 576 + p.r * 24 + p.c] - out[p.k]));
+  }
+  if (err > 1e-12 * mx) return fail(TG_EINVAL, "level-1 Galerkin moments fall outside the cube pattern");
   return TG_OK;
 }
 

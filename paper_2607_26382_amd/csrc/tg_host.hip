@@ -160,6 +160,8 @@ static void grid_layout(tg_grid* g, Bump& bp, int mmax) {
   D.Ke32 = bp.take<float>(576);
   D.G64 = bp.take<double>(8 * 576);
   D.Pc64 = bp.take<double>(8 * 576);
+  D.G1v64 = bp.take<double>(TG_G1_NVAL);
+  D.G1v32 = bp.take<float>(TG_G1_NVAL);
   D.E64 = bp.take<double>(g->lv[0].n_elem);
   D.E32 = bp.take<float>(g->lv[0].n_elem);
   D.cc = bp.take<int>(2 * (size_t)g->lv[0].n_elem);
@@ -418,7 +420,8 @@ int grid_setup(int nx, int ny, int nz, double E0, double nu, const tg_mg_opts* m
   g->ncoarse_true = cfree;
   build_ke(E0, nu, g->Ke);
   {
-    const int rc = mode_coef_from_ke(g->Ke, &g->mc64, &g->mc32);
+    int rc = mode_coef_from_ke(g->Ke, &g->mc64, &g->mc32);
+    if (!rc) rc = galerkin1_values(g->Ke, g->g1v);
     if (rc) {
       delete g;
       return rc;
@@ -459,6 +462,10 @@ int grid_bind(tg_grid* g, void* ws, size_t bytes, int mmax) {
   TG_HIP(hipMemcpy((void*)g->desc.Ke32, ke32, sizeof(ke32), hipMemcpyHostToDevice));
   TG_HIP(hipMemcpy((void*)g->desc.G64, g->G, sizeof(g->G), hipMemcpyHostToDevice));
   TG_HIP(hipMemcpy((void*)g->desc.Pc64, g->Pc, sizeof(g->Pc), hipMemcpyHostToDevice));
+  float g1v32[TG_G1_NVAL];
+  for (int q = 0; q < TG_G1_NVAL; ++q) g1v32[q] = (float)g->g1v[q];
+  TG_HIP(hipMemcpy((void*)g->desc.G1v64, g->g1v, sizeof(g->g1v), hipMemcpyHostToDevice));
+  TG_HIP(hipMemcpy((void*)g->desc.G1v32, g1v32, sizeof(g1v32), hipMemcpyHostToDevice));
   // batch of one inside the same workspace
   delete g->self;
   g->self = new Batch();

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/topoguard.h"
+#include "tg_galerkin1_pattern.h"
 
 #define TG_MAXLEV 8
 #define TG_NODE_TILE 256     // nodes per workgroup for node-centred kernels
@@ -82,6 +83,8 @@ struct ProbDesc {
   const float* Ke32;
   const double* G64;        // 8 x 576: child Galerkin matrices P_c^T Ke P_c
   const double* Pc64;       // 8 x 576: child prolongations P_c (fine 24 x coarse 24)
+  const double* G1v64;      // TG_G1_NVAL values of the level-1 moment matrices
+  const float* G1v32;
   double* small;            // per-problem FGMRES scalars (SmallLayout)
   double* part;             // reduction partials: TG_PART_W x n_chunks(level 0)
   const double* ext0;       // per-call external vectors (batched copy in/out)
@@ -155,6 +158,7 @@ struct tg_grid {
   tg::ModeCoef<float> mc32;
   double G[8 * 576];
   double Pc[8 * 576];
+  double g1v[TG_G1_NVAL];  // level-1 moment-matrix values (pattern kG1Pattern)
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -252,6 +256,7 @@ void timer_harvest();
 
 // fine-level z-march kernels (tg_fine.hip)
 int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>* out32);
+int galerkin1_values(const double* Ke, double* out);
 int zm_height(int NZ, int zmax);
 int zm_tiles(const tg_grid* g, int l, int zmax);
 void batch_choose_zc(Batch* b);
