@@ -58,6 +58,7 @@ def parse():
                     help="orthogonalization: 1 CGS, 2 CGS2 with delayed reorthogonalization, 3 CGS2 in place")
     ap.add_argument("--no-batch4", action="store_true", help="skip the 192 uneven batched solves")
     ap.add_argument("--no-small", action="store_true", help="skip the 16x8x8 plain-method leg")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 256x128x128 mixed-vs-FP64 solve")
     ap.add_argument("--no-rule-leg", action="store_true",
                     help="skip the mixed-precision run with the two-feature rule")
     ap.add_argument("--copy-probe", action="store_true",
@@ -226,6 +227,46 @@ def batch4_leg(tg, torch, dev, mixed_prec):
     log(f"uneven batch: {out['mixed_batched']['value']:.1f} solves/s batched, "
         f"{out['mixed_serial']['value']:.1f} serial, {out['fp64_batched']['value']:.1f} FP64 batched")
     del batch, grids
+    torch.cuda.empty_cache()
+    return out
+
+
+def scale_leg(tg, torch, dev, mixed_prec):
+    """Mixed precision at scale: one solve on 256x128x128 (12.8M DOF), the
+    8-strut optimized-like field (seed 3000), p = 3, rho_min = 1e-3,
+    FGMRES(30) cap 200, in the mixed form and in FP64; error of the mixed
+    solution against the FP64 one, guard values and compliance of both."""
+    from paper_2607_26382_amd import synth
+    nx, ny, nz = 256, 128, 128
+    g = tg.Grid(nx, ny, nz, max_restart=30, device=dev)
+    rho = torch.tensor(synth.struts(nx, ny, nz, 3000), device=dev)
+    g.set_density(rho, 3.0, 1e-3)
+    g.autotune(mixed_prec)
+    f = torch.tensor(g.edge_load(), device=dev)
+    out = {"grid": [nx, ny, nz], "n_dof": g.n_dof, "rho_min": 1e-3}
+    sols = {}
+    for name, prec in (("mixed", mixed_prec), ("fp64", tg.F64)):
+        o = tg.solver_opts(prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, res, _ = g.fgmres_solve(f, o, want_hist=False)
+        eta = g.true_residual(f, u)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sols[name] = u
+        out[name] = {"seconds": dt, "iterations": res["iterations"], "outcome": res["outcome"],
+                     "true_eta": eta, "certified": bool(eta <= 1e-6),
+                     "compliance": float(torch.dot(f, u).item()),
+                     "ms_per_iteration": 1e3 * dt / max(res["iterations"], 1)}
+    d = sols["mixed"] - sols["fp64"]
+    out["rel_error_vs_fp64"] = float((d.norm() / sols["fp64"].norm()).item())
+    out["compliance_rel_diff"] = abs(out["mixed"]["compliance"] - out["fp64"]["compliance"]) / abs(
+        out["fp64"]["compliance"])
+    out["mixed_speedup"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    log(f"256x128x128 solve: mixed {out['mixed']['iterations']} its {out['mixed']['seconds']:.2f} s, "
+        f"fp64 {out['fp64']['iterations']} its {out['fp64']['seconds']:.2f} s, "
+        f"|u_mix - u_64| / |u_64| = {out['rel_error_vs_fp64']:.2e}")
+    del g, sols, d
     torch.cuda.empty_cache()
     return out
 
@@ -427,8 +468,12 @@ def main():
         result["mixed_over_fp64"] = value / result["fp64"]["value"]
     if not args.no_small:
         result["small_plain"] = small_leg(tg, torch, dev)
-    if not args.no_batch4:
+    if not args.no_scale:
         del batch, grids
+        torch.cuda.empty_cache()
+        result["mixed_at_scale"] = scale_leg(tg, torch, dev, mixed_prec)
+    if not args.no_batch4:
+        batch = grids = None
         torch.cuda.empty_cache()
         result["batch_uneven"] = batch4_leg(tg, torch, dev, mixed_prec)
     if not args.no_cpu:

@@ -125,7 +125,10 @@ struct Bump {
   }
 };
 
-static long long stride_of(long long n_dof) { return (n_dof + 63) & ~63LL; }
+// Slot stride: a whole number of reduction chunks, so the Krylov sweeps can
+// read every chunk in full (the tail stays zero: the workspace is cleared at
+// bind and those sweeps write zeros there).
+static long long stride_of(long long n_dof) { return (n_dof + TG_VCHUNK - 1) / TG_VCHUNK * TG_VCHUNK; }
 
 static size_t list_capacity(const std::vector<tg_grid*>& gs) {
   size_t c = 64;
@@ -450,6 +453,7 @@ int grid_bind(tg_grid* g, void* ws, size_t bytes, int mmax) {
   if (((uintptr_t)ws) & 255) return fail(TG_EINVAL, "workspace must be 256-byte aligned");
   Bump bp(ws, bytes, false);
   grid_layout(g, bp, mmax);
+  TG_HIP(hipMemset(ws, 0, bp.off));   // vector padding must read as zero
   g->mmax = mmax;
   g->ws = ws;
   g->ws_bytes = bytes;

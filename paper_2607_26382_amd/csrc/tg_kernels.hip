@@ -42,6 +42,35 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sixteen wave sums at once: each butterfly stage pairs a lane with its
+// partner across one lane bit and keeps half of the values, so 15 exchanges
+// leave every lane with one value summed over 16 lanes, and two more finish the
+// sum over the wave.  Lane l < 16 returns the total of value rev4(l), where
+// rev4 reverses the four low bits (a fixed order: deterministic).
+template <int H, int M>
+__device__ __forceinline__ void sum16_stage(double* v, int lane) {
+  const bool up = lane & M;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double keep = up ? v[i + H] : v[i];
+    const double send = up ? v[i] : v[i + H];
+    v[i] = keep + __shfl_xor(send, M, 64);
+  }
+}
+__device__ __forceinline__ double wave_sum16(double* v, int lane) {
+  sum16_stage<8, 1>(v, lane);
+  sum16_stage<4, 2>(v, lane);
+  sum16_stage<2, 4>(v, lane);
+  sum16_stage<1, 8>(v, lane);
+  double r = v[0];
+  r += __shfl_xor(r, 16, 64);
+  r += __shfl_xor(r, 32, 64);
+  return r;
+}
+__device__ __forceinline__ int rev4(int l) {
+  return ((l & 1) << 3) | ((l & 2) << 1) | ((l & 4) >> 1) | ((l & 8) >> 3);
+}
+
 // Deterministic block sum over 256 threads (4 waves); result valid in thread 0.
 __device__ __forceinline__ double block_sum256(double v, double* sh) {
   v = wave_sum(v);
@@ -805,13 +834,15 @@ __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ pro
   const long long nc = L.n_chunks;
   const auto* qv = gp(L.vec64 + (long long)sq * L.stride);
   const auto* wv = gp(L.vec64 + (long long)sw * L.stride);
+  // whole chunks: the slot stride is a multiple of the chunk and the tail
+  // beyond 3 n_nodes holds zeros
   constexpr int NQ = TG_VCHUNK / 256;
   double qr[NQ], wr[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const long long idx = lo + threadIdx.x + 256LL * q;
-    qr[q] = idx < hi ? qv[idx] : 0.0;
-    wr[q] = idx < hi ? wv[idx] : 0.0;
+    qr[q] = qv[idx];
+    wr[q] = wv[idx];
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k0 = 0; k0 < nv; k0 += 8) {
@@ -824,24 +855,20 @@ __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ pro
         const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const long long idx = lo + threadIdx.x + 256LL * q;
-          if (idx < hi) {
-            const double x = v[idx];
-            a[g] += x * qr[q];
-            c[g] += x * wr[q];
-          }
+          const double x = v[lo + threadIdx.x + 256LL * q];
+          a[g] += x * qr[q];
+          c[g] += x * wr[q];
         }
       }
     }
+    double v16[16];
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
-      const double ra = wave_sum(a[g]);
-      const double rc = wave_sum(c[g]);
-      if (lane == 0) {
-        sh[g][wave] = ra;
-        sh[8 + g][wave] = rc;
-      }
+      v16[g] = a[g];
+      v16[8 + g] = c[g];
     }
+    const double r = wave_sum16(v16, lane);
+    if (lane < 16) sh[rev4(lane)][wave] = r;
     __syncthreads();
     if (threadIdx.x < 16) {
       const int t = threadIdx.x, k = k0 + (t & 7), which = t >> 3;
@@ -890,17 +917,15 @@ __global__ __launch_bounds__(256) void k_update2_(const ProbDesc* __restrict__ p
   double ta[NQ], tc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) ta[q] = tc[q] = 0.0;
+  // whole chunks (see k_dots2_); on the zero tail every value written is 0
   for (int k = 0; k < nv; ++k) {
     const double ak = cf[k], ck = cf[nv + k];
     const auto* v = gp(L.vec64 + (long long)(sbase + k) * L.stride);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const long long idx = lo + threadIdx.x + 256LL * q;
-      if (idx < hi) {
-        const double x = v[idx];
-        ta[q] += ak * x;
-        tc[q] += ck * x;
-      }
+      const double x = v[lo + threadIdx.x + 256LL * q];
+      ta[q] += ak * x;
+      tc[q] += ck * x;
     }
   }
   const double cq = cf[2 * nv], cw = cf[2 * nv + 1];
@@ -911,13 +936,11 @@ __global__ __launch_bounds__(256) void k_update2_(const ProbDesc* __restrict__ p
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const long long idx = lo + threadIdx.x + 256LL * q;
-    if (idx < hi) {
-      const double qo = qv[idx];
-      const double nx = wv[idx] - tc[q] - cw * qo;
-      qv[idx] = cq * qo - ta[q];
-      nv_[idx] = nx;
-      nn += nx * nx;
-    }
+    const double qo = qv[idx];
+    const double nx = wv[idx] - tc[q] - cw * qo;
+    qv[idx] = cq * qo - ta[q];
+    nv_[idx] = nx;
+    nn += nx * nx;
   }
   nn = block_sum256(nn, sh);
   if (threadIdx.x == 0) P.part[wi.y] = nn;

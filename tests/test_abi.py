@@ -82,9 +82,10 @@ def test_workspace_accounting_grows_with_restart():
     a, b = C.c_size_t(), C.c_size_t()
     L.check(L.lib().tg_workspace_bytes(h, 30, C.byref(a)))
     L.check(L.lib().tg_workspace_bytes(h, 100, C.byref(b)))
-    # two FP64 Krylov bases: 2 * 70 extra vectors of 3 * 70785 doubles (64-padded),
-    # plus the (m+1) x m Hessenberg and Givens scalars
-    per_vec = ((3 * 33 * 33 * 65 + 63) // 64) * 64 * 8
+    # two FP64 Krylov bases: 2 * 70 extra vectors of 3 * 70785 doubles (padded
+    # to whole 2048-value reduction chunks), plus the (m+1) x m Hessenberg and
+    # Givens scalars
+    per_vec = ((3 * 33 * 33 * 65 + 2047) // 2048) * 2048 * 8
     small = 8 * (101 * 100 - 31 * 30 + 4 * 70)
     assert abs((b.value - a.value) - 140 * per_vec - small) < 4096
     L.lib().tg_destroy(h)
