@@ -89,7 +89,7 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
   TG_HIP(hipEventCreate(&e0));
   TG_HIP(hipEventCreate(&e1));
   int rc = TG_OK;
-  for (int l = 0; l <= TG_MF_LEVELS && rc == TG_OK; ++l) {
+  for (int l = 0; l < TG_MAXLEV && rc == TG_OK; ++l) {
     bool any = false;
     for (auto* g : b->grids) any = any || (l < g->nlev - 1);
     if (!any) continue;

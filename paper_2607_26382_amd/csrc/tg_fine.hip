@@ -19,7 +19,16 @@
 
 #include "tg_internal.h"
 
+// No implicit multiply-add contraction in this file: the z-march is unrolled,
+// and the compiler could otherwise fuse a*b + c*d differently in the copies,
+// making results depend on where a tile starts.  Fused operations are written
+// out with mad_.
+#pragma clang fp contract(off)
+
 namespace tg {
+
+__host__ __device__ __forceinline__ float mad_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double mad_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 enum { FOP_APPLY = 0, FOP_RESID = 1, FOP_SMOOTH = 2 };
 
@@ -93,15 +102,17 @@ __device__ __forceinline__ ModeCoefE<T> coef_times(const ModeCoefE<T>& c, T E) {
 template <class T>
 __device__ __forceinline__ void mode_contract_e(T* ux, T* uy, T* uz, const ModeCoefE<T>& c) {
   const T ns = ux[1] + uy[2] + uz[4];
-  const T bxx = c.dmo * ux[1] + c.o * ns, byy = c.dmo * uy[2] + c.o * ns, bzz = c.dmo * uz[4] + c.o * ns;
+  const T ons = c.o * ns;
+  const T bxx = mad_(c.dmo, ux[1], ons), byy = mad_(c.dmo, uy[2], ons), bzz = mad_(c.dmo, uz[4], ons);
   const T sxy = c.s * (uy[1] + ux[2]);
   const T sxz = c.s * (uz[1] + ux[4]);
   const T syz = c.s * (uz[2] + uy[4]);
-  const T p1a = c.p * ux[3] + c.q * uz[6], p1b = c.q * ux[3] + c.p * uz[6];
-  const T p2a = c.p * uy[3] + c.q * uz[5], p2b = c.q * uy[3] + c.p * uz[5];
-  const T p3a = c.p * ux[5] + c.q * uy[6], p3b = c.q * ux[5] + c.p * uy[6];
+  const T p1a = mad_(c.p, ux[3], c.q * uz[6]), p1b = mad_(c.q, ux[3], c.p * uz[6]);
+  const T p2a = mad_(c.p, uy[3], c.q * uz[5]), p2b = mad_(c.q, uy[3], c.p * uz[5]);
+  const T p3a = mad_(c.p, ux[5], c.q * uy[6]), p3b = mad_(c.q, ux[5], c.p * uy[6]);
   const T ts = uz[3] + uy[5] + ux[6];
-  const T t1 = c.rmt * uz[3] + c.t * ts, t2 = c.rmt * uy[5] + c.t * ts, t3 = c.rmt * ux[6] + c.t * ts;
+  const T tts = c.t * ts;
+  const T t1 = mad_(c.rmt, uz[3], tts), t2 = mad_(c.rmt, uy[5], tts), t3 = mad_(c.rmt, ux[6], tts);
   ux[0] = T(0); uy[0] = T(0); uz[0] = T(0);
   ux[1] = bxx; uy[1] = sxy; uz[1] = sxz;
   ux[2] = sxy; uy[2] = byy; uz[2] = syz;
@@ -112,114 +123,63 @@ __device__ __forceinline__ void mode_contract_e(T* ux, T* uy, T* uz, const ModeC
   ux[7] *= c.w; uy[7] *= c.w; uz[7] *= c.w;
 }
 
-// Mode-space contraction b = E * (K_H / 64) a on the three component vectors
-// (mode index m: 1 x, 2 y, 3 xy, 4 z, 5 xz, 6 yz, 7 xyz), in place.
+// Galerkin element of a level l >= 2, stored in the mode basis (modes in,
+// modes out).  Restricting the level-1 moment matrices to a child keeps their
+// joint pattern, so every deeper Galerkin element matrix lives on the same 279
+// symmetric positions; it is held as its 150 entries with row <= col
+// (kGMPairs), padded to TG_GM_STRIDE, element e at Km[e * TG_GM_STRIDE].  The
+// entries are read in 16-byte pieces, a few pieces ahead of their use, so that
+// few registers hold them at a time.  279 multiply-adds per element.
 template <class T>
-__device__ __forceinline__ void mode_contract(T* ux, T* uy, T* uz, T E, const ModeCoef<T>& c) {
-  // normal block on (x.x, y.y, z.z) = (ux[1], uy[2], uz[4])
-  const T ns = ux[1] + uy[2] + uz[4];
-  const T dmo = c.d - c.o;
-  const T bxx = dmo * ux[1] + c.o * ns, byy = dmo * uy[2] + c.o * ns, bzz = dmo * uz[4] + c.o * ns;
-  // rank-1 shear pairs (x.y, y.x), (x.z, z.x), (y.z, z.y)
-  const T sxy = c.s * (uy[1] + ux[2]);
-  const T sxz = c.s * (uz[1] + ux[4]);
-  const T syz = c.s * (uz[2] + uy[4]);
-  // bilinear pairs (xy.x, yz.z), (xy.y, xz.z), (xz.x, yz.y)
-  const T p1a = c.p * ux[3] + c.q * uz[6], p1b = c.q * ux[3] + c.p * uz[6];
-  const T p2a = c.p * uy[3] + c.q * uz[5], p2b = c.q * uy[3] + c.p * uz[5];
-  const T p3a = c.p * ux[5] + c.q * uy[6], p3b = c.q * ux[5] + c.p * uy[6];
-  // bilinear triple (xy.z, xz.y, yz.x)
-  const T ts = uz[3] + uy[5] + ux[6];
-  const T rmt = c.r - c.t;
-  const T t1 = rmt * uz[3] + c.t * ts, t2 = rmt * uy[5] + c.t * ts, t3 = rmt * ux[6] + c.t * ts;
-  ux[0] = T(0); uy[0] = T(0); uz[0] = T(0);   // constant modes carry no energy
-  ux[1] = E * bxx; uy[1] = E * sxy; uz[1] = E * sxz;
-  ux[2] = E * sxy; uy[2] = E * byy; uz[2] = E * syz;
-  ux[3] = E * p1a; uy[3] = E * p2a; uz[3] = E * t1;
-  ux[4] = E * sxz; uy[4] = E * syz; uz[4] = E * bzz;
-  ux[5] = E * p3a; uy[5] = E * t2;  uz[5] = E * p2b;
-  ux[6] = E * t3;  uy[6] = E * p3b; uz[6] = E * p1b;
-  const T ew = E * c.w;   // trilinear modes: diagonal
-  ux[7] *= ew; uy[7] *= ew; uz[7] *= ew;
-}
-
-// Restriction of a polynomial-mode vector to a sub-cube: per dimension the
-// coarse coordinate is xi = h xi' + s, so (a0, a1) -> (a0 + s a1, h a1) on the
-// (inactive, active) pair of that dimension; the transpose maps
-// (b0, b1) -> (b0, s b0 + h b1).
-template <class T>
-__device__ __forceinline__ void mode_restrict(const T* v, T* o, T h, T sx, T sy, T sz) {
-#pragma unroll
-  for (int m = 0; m < 8; ++m) o[m] = v[m];
-  const T sd[3] = {sx, sy, sz};
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int bit = 1 << b;
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-      if (!(m & bit)) {
-        const T a0 = o[m], a1 = o[m | bit];
-        o[m] = a0 + sd[b] * a1;
-        o[m | bit] = h * a1;
-      }
-  }
-}
-template <class T>
-__device__ __forceinline__ void mode_restrict_t_add(T* o, T* acc, T h, T sx, T sy, T sz) {
-  const T sd[3] = {sx, sy, sz};
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int bit = 1 << b;
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-      if (!(m & bit)) {
-        const T b0 = o[m], b1 = o[m | bit];
-        o[m | bit] = sd[b] * b0 + h * b1;
-      }
-  }
-#pragma unroll
-  for (int m = 0; m < 8; ++m) acc[m] += o[m];
-}
-
-// Galerkin element of level l >= 1 (matrix-free): with T the nodal-to-mode
-// transform and T_d the restriction to fine descendant d,
-//   Kel_l = T^T [ sum_d E_d T_d^T (K_H / 64) T_d ] T,
-// which equals the element-wise Galerkin product P^T ... P^T Ke P ... P of the
-// 2:1 trilinear hierarchy.  Descendant d = (fx, fy, fz) in [0, 2^l)^3 sits at
-// h = 2^-l, s = (2 f + 1) h - 1 per dimension.
-// (in and out in the element's mode basis: the caller applies the transforms)
-template <class T>
-__device__ __forceinline__ void elem_galerkin_modes(T* ux, T* uy, T* uz, const T TG_GLOBAL* E0, int nx0,
-                                                    int ny0, int ex, int ey, int ez, int l,
-                                                    const ModeCoef<T>& c) {
-  T ax[8], ay[8], az[8];
+__device__ __forceinline__ void elem_mode_stored(T* ux, T* uy, T* uz, const T* __restrict__ Km, int e) {
+  constexpr int W = 16 / sizeof(T);                  // entries per piece
+  constexpr int NP = TG_GM_STRIDE / W;               // pieces per element
+  constexpr int G = 4;                               // pieces per group
+  constexpr int NG = (NP + G - 1) / G;
+  typedef T vecT __attribute__((ext_vector_type(W)));
+  const vecT* kp = (const vecT*)gp(Km + (long long)e * TG_GM_STRIDE);
+  T a[24], y[24];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    ax[m] = ux[m];
-    ay[m] = uy[m];
-    az[m] = uz[m];
-    ux[m] = uy[m] = uz[m] = T(0);
+    a[3 * m + 0] = ux[m];
+    a[3 * m + 1] = uy[m];
+    a[3 * m + 2] = uz[m];
   }
-  const int F = 1 << l;
-  const T h = T(1) / T(F);
-  for (int fz = 0; fz < F; ++fz) {
-    const T sz = T(2 * fz + 1) * h - T(1);
-    for (int fy = 0; fy < F; ++fy) {
-      const T sy = T(2 * fy + 1) * h - T(1);
-      const long long rowb = (long long)nx0 * ((F * ey + fy) + (long long)ny0 * (F * ez + fz)) + F * ex;
-      for (int fx = 0; fx < F; ++fx) {
-        const T sx = T(2 * fx + 1) * h - T(1);
-        const T E = E0[rowb + fx];
-        T bx[8], by[8], bz[8];
-        mode_restrict(ax, bx, h, sx, sy, sz);
-        mode_restrict(ay, by, h, sx, sy, sz);
-        mode_restrict(az, bz, h, sx, sy, sz);
-        mode_contract(bx, by, bz, E, c);
-        mode_restrict_t_add(bx, ux, h, sx, sy, sz);
-        mode_restrict_t_add(by, uy, h, sx, sy, sz);
-        mode_restrict_t_add(bz, uz, h, sx, sy, sz);
-      }
+#pragma unroll
+  for (int r = 0; r < 24; ++r) y[r] = T(-0.0);
+  vecT buf[2][G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) buf[0][i] = kp[i];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g + 1 < NG) {
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        if ((g + 1) * G + i < NP) buf[(g + 1) & 1][i] = kp[(g + 1) * G + i];
     }
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int v = (g * G + i) * W + w;
+        if (v < TG_GM_NU) {
+          const int r = kGMPairs[v][0], c = kGMPairs[v][1];
+          const T k = buf[g & 1][i][w];
+          y[r] = mad_(k, a[c], y[r]);
+          if (r != c) y[c] = mad_(k, a[r], y[c]);
+        }
+      }
+    // Ordering point: the next group's loads are not issued before this
+    // group's products are formed, which bounds the registers in use.
+    asm volatile("" ::"v"(y[3]), "v"(y[4]), "v"(y[5]), "v"(y[6]), "v"(y[7]), "v"(y[8]), "v"(y[9]),
+                 "v"(y[10]), "v"(y[11]), "v"(y[12]), "v"(y[13]), "v"(y[14]), "v"(y[15]), "v"(y[16]),
+                 "v"(y[17]), "v"(y[18]), "v"(y[19]), "v"(y[20]), "v"(y[21]), "v"(y[22]), "v"(y[23]));
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    ux[m] = y[3 * m + 0];
+    uy[m] = y[3 * m + 1];
+    uz[m] = y[3 * m + 2];
   }
 }
 
@@ -260,10 +220,10 @@ __device__ __forceinline__ void elem_galerkin1(T* ux, T* uy, T* uz, const T TG_G
     for (int r = 0; r < 24; ++r) t[r] = T(-0.0);
 #pragma unroll
     for (int e = 0; e < TG_G1_NNZ; ++e)
-      if (kG1Pattern[e].g == G) t[kG1Pattern[e].r] += v[kG1Pattern[e].k] * a[kG1Pattern[e].c];
+      if (kG1Pattern[e].g == G) t[kG1Pattern[e].r] = mad_(v[kG1Pattern[e].k], a[kG1Pattern[e].c], t[kG1Pattern[e].r]);
 #pragma unroll
     for (int r = 0; r < 24; ++r)
-      if ((kG1RowMask[G] >> r) & 1u) y[r] += mu[G] * t[r];
+      if ((kG1RowMask[G] >> r) & 1u) y[r] = mad_(mu[G], t[r], y[r]);
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -274,8 +234,8 @@ __device__ __forceinline__ void elem_galerkin1(T* ux, T* uy, T* uz, const T TG_G
 }
 
 // ---------------------------------------------------------------------------
-// BF16 matrix-core form of the fine element contraction v = E Ke u (FP32
-// accumulate).  A wave's 64 elements form the columns of U (24 DOFs padded to
+// BF16 matrix-core form of the fine element contraction v = Ke u (FP32
+// accumulate; the caller scales by E).  A wave's 64 elements form the columns of U (24 DOFs padded to
 // K = 32); Ke (24 rows padded to 32, two 16-row tiles) is the A operand of
 // v_mfma_f32_16x16x32_bf16, held in registers for the whole kernel.  Lane
 // layout of that instruction (measured on gfx950): A[i][k] at lane i % 16 +
@@ -316,8 +276,7 @@ __device__ __forceinline__ void mfma_load_ke(const float TG_GLOBAL* Ke, MfmaA& A
 static_assert(64 * MF_BROW * 2 <= MF_WAVE_BYTES, "staging block");
 
 template <bool SPLIT>
-__device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float E, const MfmaA& A,
-                                          char* wlds) {
+__device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, const MfmaA& A, char* wlds) {
   const int lane = threadIdx.x & 63;
   __bf16* Bs = (__bf16*)wlds;                 // [64 elements][MF_BROW]
   // this lane's 24 DOFs (3 a + c) and 8 zeros, high (and low) BF16 parts
@@ -388,9 +347,9 @@ __device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, float
   }
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    ux[a] = E * o[3 * a + 0];
-    uy[a] = E * o[3 * a + 1];
-    uz[a] = E * o[3 * a + 2];
+    ux[a] = o[3 * a + 0];
+    uy[a] = o[3 * a + 1];
+    uz[a] = o[3 * a + 2];
   }
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // reads done before the next layer's writes
 }
@@ -401,6 +360,9 @@ template <> __device__ __forceinline__ float* fpool<float>(const LevelDesc& L) {
 template <class T> __device__ __forceinline__ const T* fE(const ProbDesc& P);
 template <> __device__ __forceinline__ const double* fE<double>(const ProbDesc& P) { return P.E64; }
 template <> __device__ __forceinline__ const float* fE<float>(const ProbDesc& P) { return P.E32; }
+template <class T> __device__ __forceinline__ const T* fKm(const LevelDesc& L);
+template <> __device__ __forceinline__ const double* fKm<double>(const LevelDesc& L) { return L.Km64; }
+template <> __device__ __forceinline__ const float* fKm<float>(const LevelDesc& L) { return L.Km32; }
 template <class T> __device__ __forceinline__ const T* fD(const LevelDesc& L);
 template <> __device__ __forceinline__ const double* fD<double>(const LevelDesc& L) { return L.Dinv64; }
 template <> __device__ __forceinline__ const float* fD<float>(const LevelDesc& L) { return L.Dinv32; }
@@ -436,8 +398,9 @@ __host__ __device__ __forceinline__ int fz_tiles(int NX, int NY, int NZ, int zc)
   return ((NX + FZ_OUT - 1) / FZ_OUT) * ((NY + FZ_OUT - 1) / FZ_OUT) * ((NZ + zc - 1) / zc);
 }
 
-// KIND 0: fine level, element = E_e Ke; KIND 1: matrix-free Galerkin level l;
-// KIND 2 / 3: fine level with the BF16 matrix-core contraction (3: split BF16).
+// KIND 0: fine level, element = E_e Ke; KIND 1: level 1, matrix-free Galerkin
+// (moment form); KIND 2 / 3: fine level with the BF16 matrix-core contraction
+// (3: split BF16); KIND 4: level l >= 2, stored mode-basis Galerkin elements.
 template <class T, int OP, int KIND, class TY = T>
 __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ probs,
                                                  const int2* __restrict__ work, int l, int sx,
@@ -447,14 +410,15 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   // two barriers of its step, every write of the next layer after them.
   __shared__ T su[3][17][17];           // node values of the current top layer
   __shared__ T ss[12][FZ_TX][FZ_TX];    // per element: 4 corners x 3 comps, layer sum
-  __shared__ __attribute__((aligned(16))) char mf_lds[(KIND >= 2) ? 4 * MF_WAVE_BYTES : 16];
+  constexpr bool MF = (KIND == 2 || KIND == 3);   // matrix-core forms
+  __shared__ __attribute__((aligned(16))) char mf_lds[MF ? 4 * MF_WAVE_BYTES : 16];
   MfmaA mfA;
   const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& L = P.lv[l];
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
   const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;
-  if constexpr (KIND >= 2) mfma_load_ke(gp(P.Ke32), mfA);
+  if constexpr (MF) mfma_load_ke(gp(P.Ke32), mfA);
   const int ntx = (NX + FZ_OUT - 1) / FZ_OUT, nty = (NY + FZ_OUT - 1) / FZ_OUT;
   const int tile = wi.y;
   const int zc = L.zc;
@@ -516,10 +480,21 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       su[2][ety][etx] = r.e2;
     }
   };
-  T bx[4], by[4], bz[4];     // bottom-face node values, corner c = di + 2 dj
-  T tpx[4], tpy[4], tpz[4];  // top-face outputs of the previous element layer
+  // State carried from one element layer to the next: the shared face in the
+  // form the contraction takes it (face-mode for the vector forms, raw node
+  // values for the matrix-core forms), the previous layer's top-face outputs,
+  // the raw value of node (ni, nj, k) for the smoother and the next layer's
+  // modulus.  The vector forms unroll the march by two with the roles of two
+  // such states alternating, so nothing is copied between layers.
+  struct St {
+    T bx[4], by[4], bz[4];     // bottom face, corner c = di + 2 dj
+    T tpx[4], tpy[4], tpz[4];  // top-face outputs of the previous element layer
+    T own[3];
+    T E;
+  };
+  St s0, s1;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) tpx[c] = tpy[c] = tpz[c] = T(0);
+  for (int c = 0; c < 4; ++c) s0.tpx[c] = s0.tpy[c] = s0.tpz[c] = T(0);
   Pre pre = fetch(z0 - 1);
   stage(pre);
   pre = fetch(z0);           // in flight while the prologue reads LDS
@@ -527,31 +502,35 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int di = c & 1, dj = c >> 1;
-    bx[c] = su[0][ty + dj][tx + di];
-    by[c] = su[1][ty + dj][tx + di];
-    bz[c] = su[2][ty + dj][tx + di];
+    s0.bx[c] = su[0][ty + dj][tx + di];
+    s0.by[c] = su[1][ty + dj][tx + di];
+    s0.bz[c] = su[2][ty + dj][tx + di];
   }
-  // vector forms carry the bottom face in face-mode form, plus the raw value
-  // of node (ni, nj, k) for the smoother
-  T ownv[3] = {bx[3], by[3], bz[3]};
-  if constexpr (KIND <= 1) {
-    face_fwd(bx);
-    face_fwd(by);
-    face_fwd(bz);
+  s0.own[0] = s0.bx[3];
+  s0.own[1] = s0.by[3];
+  s0.own[2] = s0.bz[3];
+  if constexpr (!MF) {
+    face_fwd(s0.bx);
+    face_fwd(s0.by);
+    face_fwd(s0.bz);
   }
   const ModeCoefE<T> mce = {mc.d - mc.o, mc.o, mc.s, mc.p, mc.q, mc.r - mc.t, mc.t, mc.w};
-  // element modulus of the first layer
-  T Enext = (KIND != 1 && elem_in && z0 - 1 >= 0 && z0 - 1 < nz)
-                ? Eg[ex + (long long)nx * (ey + (long long)ny * (z0 - 1))]
-                : T(0);
+  // element moduli of this column: index ecol + elay * k for element layer k
+  const long long ecol = ex + (long long)nx * ey, elay = (long long)nx * ny;
+  auto modulus = [&](int k) -> T {
+    return ((KIND == 0 || MF) && elem_in && k >= 0 && k < nz) ? Eg[ecol + elay * k] : T(0);
+  };
+  s0.E = modulus(z0 - 1);
   lds_barrier();           // prologue reads done before the first layer is staged
-  for (int k = z0 - 1; k < zend; ++k) {
+
+  // one element layer k: A holds the state entering it, B receives the state
+  // for layer k + 1
+  auto step = [&](const int k, St& A, St& B) {
+    const T own0 = A.own[0], own1 = A.own[1], own2 = A.own[2];   // node (ni, nj, k)
     stage(pre);              // node layer k + 1 (fetched one step ahead)
     pre = fetch(k + 2);      // next layer in flight during this step
-    const T Ecur = Enext;   // modulus of element layer k (0 outside the grid)
-    Enext = (KIND != 1 && elem_in && k + 1 >= 0 && k + 1 < nz)
-                ? Eg[ex + (long long)nx * (ey + (long long)ny * (k + 1))]
-                : T(0);
+    const T Ecur = A.E;      // modulus of element layer k (0 outside the grid)
+    B.E = modulus(k + 1);
     // output-side operands of node (ni, nj, k), loaded before the barrier
     T rb0 = T(0), rb1 = T(0), rb2 = T(0);
     T D[9];
@@ -568,10 +547,8 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     }
     lds_barrier();
     T ux[8], uy[8], uz[8];
-    // own node value at layer k for the smoother (corner 3 of the bottom face)
-    const T own0 = ownv[0], own1 = ownv[1], own2 = ownv[2];
     const bool ein = elem_in && k >= 0 && k < nz;
-    if constexpr (KIND <= 1) {
+    if constexpr (!MF) {
       T fx[4], fy[4], fz[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -580,33 +557,33 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         fy[c] = su[1][ty + dj][tx + di];
         fz[c] = su[2][ty + dj][tx + di];
       }
-      ownv[0] = fx[3];
-      ownv[1] = fy[3];
-      ownv[2] = fz[3];
+      B.own[0] = fx[3];
+      B.own[1] = fy[3];
+      B.own[2] = fz[3];
       face_fwd(fx);
       face_fwd(fy);
       face_fwd(fz);
       // z stage of the mode transform; the top face becomes the next bottom face
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        ux[c] = bx[c] + fx[c];
-        ux[c + 4] = fx[c] - bx[c];
-        uy[c] = by[c] + fy[c];
-        uy[c + 4] = fy[c] - by[c];
-        uz[c] = bz[c] + fz[c];
-        uz[c + 4] = fz[c] - bz[c];
-        bx[c] = fx[c];
-        by[c] = fy[c];
-        bz[c] = fz[c];
+        ux[c] = A.bx[c] + fx[c];
+        ux[c + 4] = fx[c] - A.bx[c];
+        uy[c] = A.by[c] + fy[c];
+        uy[c + 4] = fy[c] - A.by[c];
+        uz[c] = A.bz[c] + fz[c];
+        uz[c + 4] = fz[c] - A.bz[c];
+        B.bx[c] = fx[c];
+        B.by[c] = fy[c];
+        B.bz[c] = fz[c];
       }
       if constexpr (KIND == 0) {
         mode_contract_e(ux, uy, uz, coef_times(mce, Ecur));
-      } else if (ein && l == 1) {
+      } else if (KIND == 1 && ein) {
         // read-only table: constant address space, so the loads are scalar
         elem_galerkin1<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k,
                           (const T __attribute__((address_space(4)))*)G1V<T>(P));
-      } else if (ein) {
-        elem_galerkin_modes<T>(ux, uy, uz, Eg, nx0, ny0, ex, ey, k, l, mc);
+      } else if (KIND == 4 && ein) {
+        elem_mode_stored<T>(ux, uy, uz, fKm<T>(L), (int)(ecol + elay * k));
       } else {
 #pragma unroll
         for (int a = 0; a < 8; ++a) ux[a] = uy[a] = uz[a] = T(0);
@@ -615,12 +592,12 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       // one, summed in face-mode form, then the face's inverse x, y stages
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        fx[c] = (ux[c] - ux[c + 4]) + tpx[c];
-        fy[c] = (uy[c] - uy[c + 4]) + tpy[c];
-        fz[c] = (uz[c] - uz[c + 4]) + tpz[c];
-        tpx[c] = ux[c] + ux[c + 4];
-        tpy[c] = uy[c] + uy[c + 4];
-        tpz[c] = uz[c] + uz[c + 4];
+        fx[c] = (ux[c] - ux[c + 4]) + A.tpx[c];
+        fy[c] = (uy[c] - uy[c + 4]) + A.tpy[c];
+        fz[c] = (uz[c] - uz[c + 4]) + A.tpz[c];
+        B.tpx[c] = ux[c] + ux[c + 4];
+        B.tpy[c] = uy[c] + uy[c + 4];
+        B.tpz[c] = uz[c] + uz[c + 4];
       }
       face_inv(fx);
       face_inv(fy);
@@ -635,33 +612,33 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int di = c & 1, dj = c >> 1;
-        ux[c] = bx[c];
-        uy[c] = by[c];
-        uz[c] = bz[c];
+        ux[c] = A.bx[c];
+        uy[c] = A.by[c];
+        uz[c] = A.bz[c];
         ux[c + 4] = su[0][ty + dj][tx + di];
         uy[c + 4] = su[1][ty + dj][tx + di];
         uz[c + 4] = su[2][ty + dj][tx + di];
       }
-      ownv[0] = ux[7];
-      ownv[1] = uy[7];
-      ownv[2] = uz[7];
+      B.own[0] = ux[7];
+      B.own[1] = uy[7];
+      B.own[2] = uz[7];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        bx[c] = ux[c + 4];
-        by[c] = uy[c + 4];
-        bz[c] = uz[c + 4];
+        B.bx[c] = ux[c + 4];
+        B.by[c] = uy[c + 4];
+        B.bz[c] = uz[c + 4];
       }
-      elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, (float)Ecur, mfA,
+      elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, mfA,
                            mf_lds + (threadIdx.x >> 6) * MF_WAVE_BYTES);
       // layer-k node contributions: bottom of this element + top of the previous one
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        ss[3 * c + 0][ty][tx] = ux[c] + tpx[c];
-        ss[3 * c + 1][ty][tx] = uy[c] + tpy[c];
-        ss[3 * c + 2][ty][tx] = uz[c] + tpz[c];
-        tpx[c] = ux[c + 4];
-        tpy[c] = uy[c + 4];
-        tpz[c] = uz[c + 4];
+        ss[3 * c + 0][ty][tx] = mad_(Ecur, ux[c], A.tpx[c]);
+        ss[3 * c + 1][ty][tx] = mad_(Ecur, uy[c], A.tpy[c]);
+        ss[3 * c + 2][ty][tx] = mad_(Ecur, uz[c], A.tpz[c]);
+        B.tpx[c] = Ecur * ux[c + 4];
+        B.tpy[c] = Ecur * uy[c + 4];
+        B.tpz[c] = Ecur * uz[c + 4];
       }
     }
     lds_barrier();
@@ -687,12 +664,23 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
           y[1] = TY(r1);
           y[2] = TY(r2);
         } else {
-          y[0] = TY(own0 + omega * (D[0] * r0 + D[1] * r1 + D[2] * r2));
-          y[1] = TY(own1 + omega * (D[3] * r0 + D[4] * r1 + D[5] * r2));
-          y[2] = TY(own2 + omega * (D[6] * r0 + D[7] * r1 + D[8] * r2));
+          y[0] = TY(mad_(omega, mad_(D[2], r2, mad_(D[1], r1, D[0] * r0)), own0));
+          y[1] = TY(mad_(omega, mad_(D[5], r2, mad_(D[4], r1, D[3] * r0)), own1));
+          y[2] = TY(mad_(omega, mad_(D[8], r2, mad_(D[7], r1, D[6] * r0)), own2));
         }
       }
     }
+  };
+  if constexpr (MF || KIND == 4) {
+    // register-bound forms: one state, updated in place
+    for (int k = z0 - 1; k < zend; ++k) step(k, s0, s0);
+  } else {
+    int k = z0 - 1;
+    for (; k + 1 < zend; k += 2) {
+      step(k, s0, s1);
+      step(k + 1, s1, s0);
+    }
+    if (k < zend) step(k, s0, s1);
   }
 }
 
@@ -875,7 +863,8 @@ template <> ModeCoef<double> mcoef<double>(const tg_grid* g) { return g->mc64; }
 template <> ModeCoef<float> mcoef<float>(const tg_grid* g) { return g->mc32; }
 
 // OP: 0 apply, 1 residual, 2 smoothing sweep on level l with the z-march
-// kernel (level 0: E Ke; levels 1..TG_MF_LEVELS: matrix-free Galerkin).
+// kernel (level 0: E Ke; levels 1..TG_MF_LEVELS: matrix-free Galerkin; deeper
+// levels: stored mode-basis Galerkin elements).
 // Every grid of a batch shares one Ke (checked at batch creation).
 template <class T>
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
@@ -891,13 +880,20 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
       k_fine_zm<T, FOP_RESID, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
     else
       k_fine_zm<T, FOP_SMOOTH, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
-  } else {
+  } else if (l <= TG_MF_LEVELS) {
     if (op == FOP_APPLY)
       k_fine_zm<T, FOP_APPLY, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
     else if (op == FOP_RESID)
       k_fine_zm<T, FOP_RESID, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
     else
       k_fine_zm<T, FOP_SMOOTH, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
+  } else {
+    if (op == FOP_APPLY)
+      k_fine_zm<T, FOP_APPLY, 4><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
+    else if (op == FOP_RESID)
+      k_fine_zm<T, FOP_RESID, 4><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
+    else
+      k_fine_zm<T, FOP_SMOOTH, 4><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
   }
   return TG_OK;
 }

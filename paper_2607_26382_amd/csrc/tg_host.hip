@@ -187,6 +187,10 @@ static void grid_layout(tg_grid* g, Bump& bp, int mmax) {
       L.Kel64 = bp.take<double>((size_t)H.n_elem * 576);
       L.Kel32 = bp.take<float>((size_t)H.n_elem * 576);
     }
+    if (l > TG_MF_LEVELS) {
+      L.Km64 = bp.take<double>((size_t)H.n_elem * TG_GM_STRIDE);
+      L.Km32 = bp.take<float>((size_t)H.n_elem * TG_GM_STRIDE);
+    }
     L.Dinv64 = bp.take<double>((size_t)9 * H.n_nodes);
     L.Dinv32 = bp.take<float>((size_t)9 * H.n_nodes);
   }
@@ -324,10 +328,9 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   finish(b->fine, o);
   for (int l = 0; l < TG_MAXLEV; ++l) {
     o = begin();
-    if (l <= TG_MF_LEVELS)
-      for (int p : active)
-        if (l < b->grids[p]->nlev - 1)
-          for (int t = 0, nt = zm_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
+    for (int p : active)
+      if (l < b->grids[p]->nlev - 1)
+        for (int t = 0, nt = zm_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_s[l], o);
   }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");

@@ -25,6 +25,7 @@
 #define TG_MAX_RESTART 126
 #define TG_MAX_COARSE 512    // max free DOFs of the coarsest level
 #define TG_HIST_CAP 4096     // residual-history capacity per problem
+#define TG_GM_STRIDE 152    // stored entries per mode-basis element matrix (TG_GM_NU = 150, padded)
 #define TG_MF_LEVELS 1       // levels 1..TG_MF_LEVELS apply the Galerkin operator matrix-free
 
 namespace tg {
@@ -66,6 +67,8 @@ struct LevelDesc {
   float* vec32;
   double* Kel64;            // levels >= 1: 576 values per element (row-major 24x24)
   float* Kel32;
+  double* Km64;             // levels > TG_MF_LEVELS: the element matrix in the mode
+  float* Km32;              // basis, TG_GM_NU values padded to TG_GM_STRIDE per element
   double* Dinv64;           // 9 values per node (3x3 inverse of the node block)
   float* Dinv32;
 };

@@ -20,18 +20,9 @@ template <class T>
 __device__ __forceinline__ T TG_GLOBAL* vslot(const LevelDesc& L, int slot, const void* ext) {
   return gp(slot < 0 ? (T*)ext : pool<T>(L) + (long long)slot * L.stride);
 }
-template <class T> __device__ __forceinline__ const T* Kel(const LevelDesc& L);
-template <> __device__ __forceinline__ const double* Kel<double>(const LevelDesc& L) { return L.Kel64; }
-template <> __device__ __forceinline__ const float* Kel<float>(const LevelDesc& L) { return L.Kel32; }
 template <class T> __device__ __forceinline__ const T* Dinv(const LevelDesc& L);
 template <> __device__ __forceinline__ const double* Dinv<double>(const LevelDesc& L) { return L.Dinv64; }
 template <> __device__ __forceinline__ const float* Dinv<float>(const LevelDesc& L) { return L.Dinv32; }
-template <class T> __device__ __forceinline__ const T* KeP(const ProbDesc& P);
-template <> __device__ __forceinline__ const double* KeP<double>(const ProbDesc& P) { return P.Ke64; }
-template <> __device__ __forceinline__ const float* KeP<float>(const ProbDesc& P) { return P.Ke32; }
-template <class T> __device__ __forceinline__ const T* EP(const ProbDesc& P);
-template <> __device__ __forceinline__ const double* EP<double>(const ProbDesc& P) { return P.E64; }
-template <> __device__ __forceinline__ const float* EP<float>(const ProbDesc& P) { return P.E32; }
 template <class T> __device__ __forceinline__ const T* CinvP(const ProbDesc& P);
 template <> __device__ __forceinline__ const double* CinvP<double>(const ProbDesc& P) { return P.Cinv64; }
 template <> __device__ __forceinline__ const float* CinvP<float>(const ProbDesc& P) { return P.Cinv32; }
@@ -177,6 +168,51 @@ __global__ __launch_bounds__(256) void k_galerkin_up(const ProbDesc* __restrict_
   }
 }
 
+// Mode-basis form of the level-l Galerkin element matrices (l > TG_MF_LEVELS):
+// Khat = H Kel H^T / 64 with H the per-component 8-point +-1 transform of
+// the node index (DOF 3 a + c -> 3 m + c, H[m][a] = prod over the bits b of m
+// of (2 bit_b(a) - 1)), symmetrized, and its TG_GM_NU pattern entries stored
+// at Km[e * TG_GM_STRIDE + v] (padding zero).  Entries off the pattern vanish
+// in exact arithmetic.
+__global__ __launch_bounds__(256) void k_mode_pack(const ProbDesc* __restrict__ probs,
+                                                   const int2* __restrict__ work, int l) {
+  __shared__ double sK[576];
+  __shared__ double sX[576];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const LevelDesc& L = P.lv[l];
+  const long long e = wi.y;   // one element per workgroup
+  auto H = [](int m, int a) { return (__popc(m & ~a) & 1) ? -1.0 : 1.0; };
+  for (int q = threadIdx.x; q < 576; q += 256) sK[q] = L.Kel64[e * 576 + q];
+  __syncthreads();
+  // X = (H x I3) Kel
+  for (int q = threadIdx.x; q < 576; q += 256) {
+    const int r = q / 24, c = q % 24, m = r / 3, i = r % 3;
+    double t = 0.0;
+    for (int a = 0; a < 8; ++a) t += H(m, a) * sK[(3 * a + i) * 24 + c];
+    sX[q] = t;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < TG_GM_STRIDE; v += 256) {
+    if (v >= TG_GM_NU) {
+      L.Km64[e * TG_GM_STRIDE + v] = 0.0;
+      L.Km32[e * TG_GM_STRIDE + v] = 0.f;
+      continue;
+    }
+    const int r = kGMPairs[v][0], c = kGMPairs[v][1];
+    // Khat[r][c] = sum_b X[r][3 b + j] H[n][b] / 64, and its transpose
+    const int n = c / 3, j = c % 3, m = r / 3, i = r % 3;
+    double t1 = 0.0, t2 = 0.0;
+    for (int b = 0; b < 8; ++b) {
+      t1 += sX[r * 24 + 3 * b + j] * H(n, b);
+      t2 += sX[c * 24 + 3 * b + i] * H(m, b);
+    }
+    const double k = 0.5 * (t1 + t2) / 64.0;
+    L.Km64[e * TG_GM_STRIDE + v] = k;
+    L.Km32[e * TG_GM_STRIDE + v] = (float)k;
+  }
+}
+
 // Node-block diagonal (3x3, coupling u_x, u_y, u_z of one node) and its inverse.
 __global__ __launch_bounds__(256) void k_nodeblock(const ProbDesc* __restrict__ probs,
                                                    const int2* __restrict__ work, int l) {
@@ -298,81 +334,11 @@ __global__ __launch_bounds__(256) void k_coarse_factor(const ProbDesc* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Operator kernels (node-centred gather, one thread per node).
+// Operator modes of the level kernels (the z-march kernels of tg_fine.hip):
 //   OP_APPLY : y = K x
 //   OP_RESID : y = b - K x
 //   OP_SMOOTH: y = x + w D^-1 (b - K x)      (damped node-block Jacobi)
 enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2 };
-
-template <class T, class TX, class TB, class TY, int OP, bool FINE>
-__global__ __launch_bounds__(256) void k_node_op(const ProbDesc* __restrict__ probs,
-                                                 const int2* __restrict__ work, int l, int sx,
-                                                 const void* ex_, int sb, const void* eb_, int sy,
-                                                 void* ey_, T omega) {
-  const int2 wi = work[blockIdx.x];
-  const ProbDesc& P = probs[wi.x];
-  const LevelDesc& L = P.lv[l];
-  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
-  if (n >= L.n_nodes) return;
-  const int NX = L.NX, NY = L.NY;
-  const int i = n % NX, t = n / NX, j = t % NY, k = t / NY;
-  auto* y = vslot<TY>(L, sy, ey_);
-  if (i == 0) {
-    y[3LL * n] = TY(0);
-    y[3LL * n + 1] = TY(0);
-    y[3LL * n + 2] = TY(0);
-    return;
-  }
-  const auto* x = vslot<TX>(L, sx, ex_);
-  T a0 = T(0), a1 = T(0), a2 = T(0);
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int exx = i - (a & 1), eyy = j - ((a >> 1) & 1), ezz = k - ((a >> 2) & 1);
-    if (exx < 0 || exx >= L.ex || eyy < 0 || eyy >= L.ey || ezz < 0 || ezz >= L.ez) continue;
-    const long long e = exx + (long long)L.ex * (eyy + (long long)L.ey * ezz);
-    const T* K = FINE ? KeP<T>(P) + 72 * a : Kel<T>(L) + e * 576 + 72 * a;
-    T s0 = T(0), s1 = T(0), s2 = T(0);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int mi = exx + (b & 1);
-      const long long m = mi + (long long)NX * ((eyy + ((b >> 1) & 1)) + (long long)NY * (ezz + ((b >> 2) & 1)));
-      T u0 = T(x[3 * m]), u1 = T(x[3 * m + 1]), u2 = T(x[3 * m + 2]);
-      if (mi == 0) u0 = u1 = u2 = T(0);
-      s0 += K[3 * b] * u0 + K[3 * b + 1] * u1 + K[3 * b + 2] * u2;
-      s1 += K[24 + 3 * b] * u0 + K[24 + 3 * b + 1] * u1 + K[24 + 3 * b + 2] * u2;
-      s2 += K[48 + 3 * b] * u0 + K[48 + 3 * b + 1] * u1 + K[48 + 3 * b + 2] * u2;
-    }
-    if (FINE) {
-      const T E = EP<T>(P)[e];
-      a0 += E * s0;
-      a1 += E * s1;
-      a2 += E * s2;
-    } else {
-      a0 += s0;
-      a1 += s1;
-      a2 += s2;
-    }
-  }
-  if (OP == OP_APPLY) {
-    y[3LL * n] = TY(a0);
-    y[3LL * n + 1] = TY(a1);
-    y[3LL * n + 2] = TY(a2);
-  } else {
-    const auto* b = vslot<TB>(L, sb, eb_);
-    const T r0 = T(b[3LL * n]) - a0, r1 = T(b[3LL * n + 1]) - a1, r2 = T(b[3LL * n + 2]) - a2;
-    if (OP == OP_RESID) {
-      y[3LL * n] = TY(r0);
-      y[3LL * n + 1] = TY(r1);
-      y[3LL * n + 2] = TY(r2);
-    } else {
-      const T* D = Dinv<T>(L) + 9LL * n;
-      const T x0 = T(x[3LL * n]), x1 = T(x[3LL * n + 1]), x2 = T(x[3LL * n + 2]);
-      y[3LL * n] = TY(x0 + omega * (D[0] * r0 + D[1] * r1 + D[2] * r2));
-      y[3LL * n + 1] = TY(x1 + omega * (D[3] * r0 + D[4] * r1 + D[5] * r2));
-      y[3LL * n + 2] = TY(x2 + omega * (D[6] * r0 + D[7] * r1 + D[8] * r2));
-    }
-  }
-}
 
 // First pre-sweep from x = 0: x = w D^-1 b; optionally keep b in type T.
 template <class TB, class T>
@@ -1328,6 +1294,8 @@ int k_set_density(Batch* b, hipStream_t s) {
     if (b->elem[1].n) k_galerkin1<<<nblk(b->elem[1]), 256, 0, s>>>(b->desc_d, b->elem[1].ptr);
     for (int l = 2; l < b->maxlev; ++l)
       if (b->elem[l].n) k_galerkin_up<<<nblk(b->elem[l]), 256, 0, s>>>(b->desc_d, b->elem[l].ptr, l);
+    for (int l = TG_MF_LEVELS + 1; l < b->maxlev; ++l)
+      if (b->elem[l].n) k_mode_pack<<<nblk(b->elem[l]), 256, 0, s>>>(b->desc_d, b->elem[l].ptr, l);
     for (int l = 0; l < b->maxlev; ++l)
       if (b->node[l].n) k_nodeblock<<<nblk(b->node[l]), 256, 0, s>>>(b->desc_d, b->node[l].ptr, l);
     if (b->prob.n) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad);
@@ -1342,8 +1310,8 @@ static double op_bytes(const Batch* b, int l, int lmode, int op) {
   level_sums(b, l, lmode, nodes, elems, c2);
   const double vec = 3.0 * nodes * sizeof(T);
   // fine level and matrix-free Galerkin levels read the fine moduli; deeper
-  // levels read their stored element matrices
-  const double mat = (l <= TG_MF_LEVELS) ? elems * double(1 << (3 * l)) * sizeof(T) : elems * 576.0 * sizeof(T);
+  // levels read their stored mode-basis element matrices
+  const double mat = (l <= TG_MF_LEVELS) ? elems * double(1 << (3 * l)) * sizeof(T) : elems * double(TG_GM_NU) * sizeof(T);
   const double dinv = (op == OP_SMOOTH) ? 9.0 * nodes * sizeof(T) : 0.0;
   const int nvec = op == OP_APPLY ? 2 : 3;
   return nvec * vec + mat + dinv;
@@ -1379,13 +1347,9 @@ static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om
   else if (l == 0)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
              launch_fine<T>(b, b->zm_s[0], 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
-  else if (l <= TG_MF_LEVELS)
-    TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
-             launch_fine<T>(b, b->zm_s[l], l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
   else
     TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
-             k_node_op<T, T, T, T, OP, false><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, x, nullptr, bs,
-                                                                        nullptr, y, nullptr, om));
+             launch_fine<T>(b, b->zm_s[l], l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
 }
 
 // One fixed V-cycle.  Level-0 input b (slot sb of the FP64 pool or external
