@@ -235,15 +235,16 @@ __device__ __forceinline__ void elem_galerkin1(T* ux, T* uy, T* uz, const T TG_G
 
 // ---------------------------------------------------------------------------
 // BF16 matrix-core form of the fine element contraction v = Ke u (FP32
-// accumulate; the caller scales by E).  A wave's 64 elements form the columns of U (24 DOFs padded to
-// K = 32); Ke (24 rows padded to 32, two 16-row tiles) is the A operand of
-// v_mfma_f32_16x16x32_bf16, held in registers for the whole kernel.  Lane
-// layout of that instruction (measured on gfx950): A[i][k] at lane i % 16 +
-// 16 (k / 8), element k % 8; B[k][n] at lane n + 16 (k / 8), element k % 8;
-// D[m][n] at lane n + 16 (m / 4), element m % 4.  Inputs go to the B layout
-// and results come back through a wave-private LDS block.  SPLIT adds the
-// low halves u_lo = bf16(u - u_hi), Ke_lo = bf16(Ke - Ke_hi): Ke_hi u_hi +
-// Ke_hi u_lo + Ke_lo u_hi, about 16 significant bits.
+// accumulate; the caller scales by E).  A wave's 64 elements form the columns
+// of U (24 DOFs padded to K = 32); Ke (24 rows padded to 32, two 16-row
+// tiles) is the A operand of v_mfma_f32_16x16x32_bf16, held in registers for
+// the whole kernel.  Lane layout of that instruction (measured on gfx950):
+// A[i][k] at lane i % 16 + 16 (k / 8), element k % 8; B[k][n] at lane
+// n + 16 (k / 8), element k % 8; D[m][n] at lane n + 16 (m / 4), element
+// m % 4.  Inputs reach the B layout and results leave the D layout by
+// lane-row transposes in registers.  SPLIT adds the low halves
+// u_lo = bf16(u - u_hi), Ke_lo = bf16(Ke - Ke_hi): Ke_hi u_hi + Ke_hi u_lo +
+// Ke_lo u_hi, about 16 significant bits.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -257,101 +258,102 @@ __device__ __forceinline__ void mfma_load_ke(const float TG_GLOBAL* Ke, MfmaA& A
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int row = 16 * mt + (lane & 15), k = 8 * (lane >> 4) + j;
-      const float v = (row < 24 && k < 24) ? Ke[row * 24 + k] : 0.f;
+      // tile mt holds Ke rows 12 mt .. 12 mt + 11 (bottom, then top face) and
+      // four zero rows; K slot 8 g + j is DOF 6 g + j (j < 6), slots 6, 7 of
+      // each group are zero
+      const int i = lane & 15, row = 12 * mt + i, g = lane >> 4;
+      const float v = (i < 12 && j < 6) ? Ke[row * 24 + 6 * g + j] : 0.f;
       const __bf16 h = (__bf16)v;
       A.hi[mt][j] = h;
       A.lo[mt][j] = (__bf16)(v - (float)h);
     }
 }
 
-// ux/uy/uz[a]: this lane's element; wlds: this wave's LDS block of
-// MF_WAVE_BYTES (7 KiB).
-// Row strides of the wave-private staging block, padded so that 16-byte
-// accesses of consecutive lanes spread over the LDS banks.  The block holds
-// the high BF16 parts, then (split form) the low parts, then the outputs.
-#define MF_BROW 40    // bf16 per element row of B (32 used)
-#define MF_OROW 28    // floats per element row of the output (24 used)
-#define MF_WAVE_BYTES (64 * MF_OROW * 4)
-static_assert(64 * MF_BROW * 2 <= MF_WAVE_BYTES, "staging block");
+// 4 x 4 transpose of 16-lane rows across four registers: afterwards register
+// q, row r holds what register r, row q held.  Two cross-half swaps
+// (v_permlane32_swap: rows 2, 3 of the first operand <-> rows 0, 1 of the
+// second) then two odd/even row swaps (v_permlane16_swap: rows 1, 3 of the
+// first <-> rows 0, 2 of the second), all in registers.
+__device__ __forceinline__ void xpose_rows4(unsigned& r0, unsigned& r1, unsigned& r2, unsigned& r3) {
+  const auto a = __builtin_amdgcn_permlane32_swap(r0, r2, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(r1, r3, false, false);
+  const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+  const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+  r0 = c[0];
+  r1 = c[1];
+  r2 = d[0];
+  r3 = d[1];
+}
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// (x0, x1) rounded to BF16 and packed (x0 in the low half)
+__device__ __forceinline__ unsigned pack_bf16(float x0, float x1) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){x0, x1}, bf16x2));
+}
+
+// x = E u for this lane's element (the wave's 64 elements are its 4 rows of
+// 16 lanes; DOF 3 a + c).  Lane row r holds DOF groups q = 0..3 (DOFs
+// 6 q .. 6 q + 5, K slots 8 q .. 8 q + 5; slots 8 q + 6, 8 q + 7 are zero) of
+// its element; the B operand of the product for element row nb needs group g
+// of that row's elements in lane row g: the row/register transpose of the
+// groups, three registers per group (the fourth is zero throughout).  With
+// Ke's rows ordered bottom face (tile 0) then top face (tile 1), the results
+// stay where the matrix cores leave them: lane n + 16 g, component w of
+// D0[nb] / D1[nb] is face DOF 4 g + w (g < 3) of the bottom / top face of
+// element (row nb, column n).
 template <bool SPLIT>
-__device__ __forceinline__ void elem_mfma(float* ux, float* uy, float* uz, const MfmaA& A, char* wlds) {
-  const int lane = threadIdx.x & 63;
-  __bf16* Bs = (__bf16*)wlds;                 // [64 elements][MF_BROW]
-  // this lane's 24 DOFs (3 a + c) and 8 zeros, high (and low) BF16 parts
-  float v[32];
+__device__ __forceinline__ void elem_mfma(const float* ux, const float* uy, const float* uz, float E,
+                                          const MfmaA& A, f32x4* D0, f32x4* D1) {
+  float x[24];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    v[3 * a + 0] = ux[a];
-    v[3 * a + 1] = uy[a];
-    v[3 * a + 2] = uz[a];
+    x[3 * a + 0] = E * ux[a];
+    x[3 * a + 1] = E * uy[a];
+    x[3 * a + 2] = E * uz[a];
   }
-#pragma unroll
-  for (int k = 24; k < 32; ++k) v[k] = 0.f;
-  bf16x8 hv[4], lv[4];
+  // packed pairs: dword w of group q holds DOFs 6 q + 2 w, 6 q + 2 w + 1
+  unsigned hp[4][3], lp[4][3];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      hv[q][j] = (__bf16)v[8 * q + j];
-      if (SPLIT) lv[q][j] = (__bf16)(v[8 * q + j] - (float)hv[q][j]);
+    for (int w = 0; w < 3; ++w) {
+      const int d = 6 * q + 2 * w;
+      const unsigned h = pack_bf16(x[d], x[d + 1]);
+      hp[q][w] = h;
+      if (SPLIT) {
+        // the low parts: exact remainders x - bf16(x), rounded to BF16
+        const float h0 = __builtin_bit_cast(float, h << 16);
+        const float h1 = __builtin_bit_cast(float, h & 0xffff0000u);
+        lp[q][w] = pack_bf16(x[d] - h0, x[d + 1] - h1);
+      }
     }
-  const int k0 = 8 * (lane >> 4);
-  // B operand of group nb: element 16 nb + lane % 16, DOFs k0 .. k0 + 7
-  bf16x8 bh[4], bl[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) *(bf16x8*)(Bs + lane * MF_BROW + 8 * q) = hv[q];
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) bh[nb] = *(const bf16x8*)(Bs + (16 * nb + (lane & 15)) * MF_BROW + k0);
-  if (SPLIT) {
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // high parts read before the low parts land
-#pragma unroll
-    for (int q = 0; q < 4; ++q) *(bf16x8*)(Bs + lane * MF_BROW + 8 * q) = lv[q];
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) bl[nb] = *(const bf16x8*)(Bs + (16 * nb + (lane & 15)) * MF_BROW + k0);
+  for (int w = 0; w < 3; ++w) {
+    xpose_rows4(hp[0][w], hp[1][w], hp[2][w], hp[3][w]);
+    if (SPLIT) xpose_rows4(lp[0][w], lp[1][w], lp[2][w], lp[3][w]);
   }
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // B reads done before the block is reused
-  f32x4 acc[4][2];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb)
+  for (int nb = 0; nb < 4; ++nb) {
+    const u32x4 th = {hp[nb][0], hp[nb][1], hp[nb][2], 0u};
+    const bf16x8 bh = __builtin_bit_cast(bf16x8, th);
+    bf16x8 bl;
+    if (SPLIT) {
+      const u32x4 tl = {lp[nb][0], lp[nb][1], lp[nb][2], 0u};
+      bl = __builtin_bit_cast(bf16x8, tl);
+    }
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       f32x4 c = {0.f, 0.f, 0.f, 0.f};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bh[nb], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bh, c, 0, 0, 0);
       if (SPLIT) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bl[nb], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[mt], bh[nb], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[mt], bh, c, 0, 0, 0);
       }
-      acc[nb][mt] = c;
+      (mt == 0 ? D0 : D1)[nb] = c;
     }
-  float* O = (float*)wlds;                              // [64 elements][MF_OROW]
-  const int g4 = 4 * (lane >> 4);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    float* row = O + (16 * nb + (lane & 15)) * MF_OROW;
-    *(f32x4*)(row + g4) = acc[nb][0];                   // rows 0..15
-    if (g4 < 8) *(f32x4*)(row + 16 + g4) = acc[nb][1];  // rows 16..23
   }
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  float o[24];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const f32x4 t = *(const f32x4*)(O + lane * MF_OROW + 4 * q);
-    o[4 * q + 0] = t[0];
-    o[4 * q + 1] = t[1];
-    o[4 * q + 2] = t[2];
-    o[4 * q + 3] = t[3];
-  }
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    ux[a] = o[3 * a + 0];
-    uy[a] = o[3 * a + 1];
-    uz[a] = o[3 * a + 2];
-  }
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // reads done before the next layer's writes
 }
 
 template <class T> __device__ __forceinline__ T* fpool(const LevelDesc& L);
@@ -409,9 +411,11 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   // Single buffers suffice: every read of a layer's values happens between the
   // two barriers of its step, every write of the next layer after them.
   __shared__ T su[3][17][17];           // node values of the current top layer
-  __shared__ T ss[12][FZ_TX][FZ_TX];    // per element: 4 corners x 3 comps, layer sum
   constexpr bool MF = (KIND == 2 || KIND == 3);   // matrix-core forms
-  __shared__ __attribute__((aligned(16))) char mf_lds[MF ? 4 * MF_WAVE_BYTES : 16];
+  // per element: 4 corners x 3 comps, layer sum (the matrix-core forms also
+  // write four planes that are never read, from the padding rows of their
+  // products)
+  __shared__ T ss[MF ? 16 : 12][FZ_TX][FZ_TX];
   MfmaA mfA;
   const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
@@ -491,10 +495,13 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     T tpx[4], tpy[4], tpz[4];  // top-face outputs of the previous element layer
     T own[3];
     T E;
+    T cr[16];                  // matrix-core forms: the same outputs in the D layout
   };
   St s0, s1;
 #pragma unroll
   for (int c = 0; c < 4; ++c) s0.tpx[c] = s0.tpy[c] = s0.tpz[c] = T(0);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s0.cr[q] = T(0);
   Pre pre = fetch(z0 - 1);
   stage(pre);
   pre = fetch(z0);           // in flight while the prologue reads LDS
@@ -628,18 +635,19 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         B.by[c] = uy[c + 4];
         B.bz[c] = uz[c + 4];
       }
-      elem_mfma<KIND == 3>((float*)ux, (float*)uy, (float*)uz, mfA,
-                           mf_lds + (threadIdx.x >> 6) * MF_WAVE_BYTES);
-      // layer-k node contributions: bottom of this element + top of the previous one
+      f32x4 D0[4], D1[4];
+      elem_mfma<KIND == 3>((const float*)ux, (const float*)uy, (const float*)uz, (float)Ecur, mfA, D0, D1);
+      // layer-k node contributions: bottom of this element + top of the
+      // previous one, face DOF j = 3 corner + component of element row nb
+      const int lg = (threadIdx.x >> 4) & 3, row0 = 4 * (threadIdx.x >> 6);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        ss[3 * c + 0][ty][tx] = mad_(Ecur, ux[c], A.tpx[c]);
-        ss[3 * c + 1][ty][tx] = mad_(Ecur, uy[c], A.tpy[c]);
-        ss[3 * c + 2][ty][tx] = mad_(Ecur, uz[c], A.tpz[c]);
-        B.tpx[c] = Ecur * ux[c + 4];
-        B.tpy[c] = Ecur * uy[c + 4];
-        B.tpz[c] = Ecur * uz[c + 4];
-      }
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const T v = T(D0[nb][w]) + A.cr[4 * nb + w];
+          ss[4 * lg + w][row0 + nb][tx] = v;
+          B.cr[4 * nb + w] = T(D1[nb][w]);
+        }
     }
     lds_barrier();
     if (owner && k >= z0) {
