@@ -30,7 +30,17 @@ namespace tg {
 __host__ __device__ __forceinline__ float mad_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __host__ __device__ __forceinline__ double mad_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-enum { FOP_APPLY = 0, FOP_RESID = 1, FOP_SMOOTH = 2 };
+enum { FOP_APPLY = 0, FOP_RESID = 1, FOP_SMOOTH = 2, FOP_RESTRICT = 3 };
+
+// Tiling of the residual sweep fused with the restriction (OP = FOP_RESTRICT):
+// a tile owns 7 x 7 coarse node columns and m coarse node layers, and computes
+// the fine residual on the 15 x 15 fine node columns and 2 m + 1 fine layers
+// their 27-point stencils cover (fine columns 14 t - 1 .. 14 t + 13, layers
+// 2 m t_z - 1 .. 2 m t_z + 2 m - 1).  Neighbouring tiles recompute one shared
+// fine column / layer, so every coarse node is summed by one thread in one
+// fixed order.
+#define RZ_C 7
+__host__ __device__ __forceinline__ int rz_layers(int zc) { return zc > 1 ? (zc + 1) / 2 : 1; }
 
 // In-place 8-point transform along the three node-index bits:
 // forward: (v0, v1) -> (v0 + v1, v1 - v0); node index a -> mode index m.
@@ -423,13 +433,20 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
   const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;
   if constexpr (MF) mfma_load_ke(gp(P.Ke32), mfA);
-  const int ntx = (NX + FZ_OUT - 1) / FZ_OUT, nty = (NY + FZ_OUT - 1) / FZ_OUT;
+  constexpr bool RST = (OP == FOP_RESTRICT);
+  // coarse level (restriction only)
+  const int NXc = RST ? P.lv[l + 1].NX : 0, NYc = RST ? P.lv[l + 1].NY : 0, NZc = RST ? P.lv[l + 1].NZ : 0;
+  const int rzm = rz_layers(L.zc);
+  const int ntx = RST ? (NXc + RZ_C - 1) / RZ_C : (NX + FZ_OUT - 1) / FZ_OUT;
+  const int nty = RST ? (NYc + RZ_C - 1) / RZ_C : (NY + FZ_OUT - 1) / FZ_OUT;
   const int tile = wi.y;
   const int zc = L.zc;
   const int tiz = tile / (ntx * nty), rem = tile - tiz * ntx * nty;
   const int tiy = rem / ntx, tix = rem - tiy * ntx;
-  const int x0 = tix * FZ_OUT, y0 = tiy * FZ_OUT, z0 = tiz * zc;
-  const int zend = min(z0 + zc, NZ);
+  const int x0 = RST ? 2 * RZ_C * tix - 1 : tix * FZ_OUT;
+  const int y0 = RST ? 2 * RZ_C * tiy - 1 : tiy * FZ_OUT;
+  const int z0 = RST ? 2 * rzm * tiz - 1 : tiz * zc;
+  const int zend = RST ? min(2 * rzm * (tiz + 1), NZ) : min(z0 + zc, NZ);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int ex = x0 - 1 + tx, ey = y0 - 1 + ty;         // this thread's element column
   const int ni = ex + 1, nj = ey + 1;                   // this thread's node column
@@ -437,6 +454,10 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   const auto* Eg = gp(fE<T>(P));
   const bool elem_in = (ex >= 0 && ex < nx && ey >= 0 && ey < ny);
   const bool owner = (tx < FZ_OUT && ty < FZ_OUT && ni < NX && nj < NY);
+  // fine residuals of the restriction tile, coarse accumulators of its 7 x 7
+  // coarse columns (threads 0..48)
+  __shared__ T rl[RST ? 3 : 1][FZ_OUT][FZ_OUT];
+  T racc[3] = {T(0), T(0), T(0)};
   // extra node loads: tile row/column 0 (nodes x0-1 or y0-1)
   const int xt = threadIdx.x;
   int exi = -1, exj = -1, etx = 0, ety = 0;
@@ -541,7 +562,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     // output-side operands of node (ni, nj, k), loaded before the barrier
     T rb0 = T(0), rb1 = T(0), rb2 = T(0);
     T D[9];
-    const bool out_now = owner && k >= z0 && ni > 0;
+    const bool out_now = owner && own_col && k >= z0 && k >= 0;
     const long long n = ni + (long long)NX * (nj + (long long)NY * k);
     if (OP != FOP_APPLY && out_now) {
       const auto* bb = gp(fvec<T>(L, sb, eb_)) + 3 * n;
@@ -650,7 +671,8 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         }
     }
     lds_barrier();
-    if (owner && k >= z0) {
+    // (the restriction needs every fine column of its tile, zero outside the grid)
+    if ((RST ? (tx < FZ_OUT && ty < FZ_OUT) : owner) && k >= z0) {
       // node (ni, nj, k) = corner 3 of element (tx,ty), corner 2 of (tx+1,ty),
       // corner 1 of (tx,ty+1), corner 0 of (tx+1,ty+1)
       T a[3];
@@ -658,6 +680,11 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       for (int q = 0; q < 3; ++q)
         a[q] = (ss[9 + q][ty][tx] + ss[6 + q][ty][tx + 1]) +
                (ss[3 + q][ty + 1][tx] + ss[0 + q][ty + 1][tx + 1]);
+      if constexpr (RST) {
+        // free-DOF residual; zero at clamped nodes and outside the grid
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rl[q][ty][tx] = out_now ? (q == 0 ? rb0 : q == 1 ? rb1 : rb2) - a[q] : T(0);
+      } else {
       auto* y = gp((sy < 0 ? (TY*)ey_ : fpool<TY>(L) + (long long)sy * L.stride)) + 3 * n;
       if (ni == 0) {
         y[0] = y[1] = y[2] = TY(0);
@@ -675,6 +702,48 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
           y[0] = TY(mad_(omega, mad_(D[2], r2, mad_(D[1], r1, D[0] * r0)), own0));
           y[1] = TY(mad_(omega, mad_(D[5], r2, mad_(D[4], r1, D[3] * r0)), own1));
           y[2] = TY(mad_(omega, mad_(D[8], r2, mad_(D[7], r1, D[6] * r0)), own2));
+        }
+      }
+      }
+    }
+    if constexpr (RST) {
+      lds_barrier();
+      if (k >= z0 && threadIdx.x < RZ_C * RZ_C) {
+        // 3 x 3 in-layer part of the full weighting around fine node
+        // (1 + 2 il, 1 + 2 jl) of the tile, then the layer's weight for the
+        // coarse layers it touches: 1 for K = k / 2 (k even), 1/2 for
+        // K = (k -+ 1) / 2 (k odd); coarse layer (k - 1) / 2 is complete after
+        // odd layer k, the last coarse layer after the last fine layer
+        const int il = threadIdx.x % RZ_C, jl = threadIdx.x / RZ_C;
+        T sxy[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 1; ++di) {
+            const T w = T(1) / T(1 << ((dj != 0) + (di != 0)));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sxy[q] = mad_(w, rl[q][1 + 2 * jl + dj][1 + 2 * il + di], sxy[q]);
+          }
+        int K = -1;
+        if (k & 1) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) racc[q] = mad_(T(0.5), sxy[q], racc[q]);
+          K = (k - 1) / 2;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) racc[q] += sxy[q];
+          if (k == NZ - 1) K = k / 2;
+        }
+        const int I = RZ_C * tix + il, J = RZ_C * tiy + jl;
+        if (K >= rzm * tiz && K < NZc && I < NXc && J < NYc) {
+          const LevelDesc& Lc = P.lv[l + 1];
+          auto* bc = gp(fpool<TY>(Lc) + (long long)sy * Lc.stride) + 3 * (I + (long long)NXc * (J + (long long)NYc * K));
+#pragma unroll
+          for (int q = 0; q < 3; ++q) bc[q] = I == 0 ? TY(0) : TY(racc[q]);   // coarse x = 0 clamped
+        }
+        if (k & 1) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) racc[q] = T(0.5) * sxy[q];
         }
       }
     }
@@ -844,6 +913,12 @@ int zm_tiles(const tg_grid* g, int l, int zmax) {
   const int NZ = g->lv[l].ez + 1;
   return fz_tiles(g->lv[l].ex + 1, g->lv[l].ey + 1, NZ, zm_height(NZ, zmax));
 }
+// tiles of the fused residual-restriction sweep on level l (l + 1 must exist)
+int rz_tiles(const tg_grid* g, int l, int zmax) {
+  const int m = rz_layers(zm_height(g->lv[l].ez + 1, zmax));
+  const int NXc = g->lv[l + 1].ex + 1, NYc = g->lv[l + 1].ey + 1, NZc = g->lv[l + 1].ez + 1;
+  return ((NXc + RZ_C - 1) / RZ_C) * ((NYc + RZ_C - 1) / RZ_C) * ((NZc + m - 1) / m);
+}
 
 // Per level, the tallest z-tile in {16, 12, 8, 6, 4} that gives >= 2048
 // workgroups over the whole batch, else 4.  Every tile recomputes one element
@@ -881,28 +956,24 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
   const ModeCoef<T> mc = mcoef<T>(b->grids[0]);
   const ProbDesc* desc = b->desc_d;
   const T om = T(omega);
-  if (l == 0) {
-    if (op == FOP_APPLY)
-      k_fine_zm<T, FOP_APPLY, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
-    else if (op == FOP_RESID)
-      k_fine_zm<T, FOP_RESID, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
-    else
-      k_fine_zm<T, FOP_SMOOTH, 0><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc);
-  } else if (l <= TG_MF_LEVELS) {
-    if (op == FOP_APPLY)
-      k_fine_zm<T, FOP_APPLY, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
-    else if (op == FOP_RESID)
-      k_fine_zm<T, FOP_RESID, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
-    else
-      k_fine_zm<T, FOP_SMOOTH, 1><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
-  } else {
-    if (op == FOP_APPLY)
-      k_fine_zm<T, FOP_APPLY, 4><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
-    else if (op == FOP_RESID)
-      k_fine_zm<T, FOP_RESID, 4><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
-    else
-      k_fine_zm<T, FOP_SMOOTH, 4><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);
-  }
+#define TG_ZM(KV)                                                                                         \
+  do {                                                                                                    \
+    if (op == FOP_APPLY)                                                                                  \
+      k_fine_zm<T, FOP_APPLY, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);    \
+    else if (op == FOP_RESID)                                                                             \
+      k_fine_zm<T, FOP_RESID, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);    \
+    else if (op == FOP_SMOOTH)                                                                            \
+      k_fine_zm<T, FOP_SMOOTH, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);   \
+    else                                                                                                  \
+      k_fine_zm<T, FOP_RESTRICT, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc); \
+  } while (0)
+  if (l == 0)
+    TG_ZM(0);
+  else if (l <= TG_MF_LEVELS)
+    TG_ZM(1);
+  else
+    TG_ZM(4);
+#undef TG_ZM
   return TG_OK;
 }
 template int launch_fine<double>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
@@ -923,8 +994,10 @@ int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int 
     if (split) TG_MF(FOP_APPLY, 3, float); else TG_MF(FOP_APPLY, 2, float);
   } else if (op == FOP_RESID) {
     if (split) TG_MF(FOP_RESID, 3, float); else TG_MF(FOP_RESID, 2, float);
-  } else {
+  } else if (op == FOP_SMOOTH) {
     if (split) TG_MF(FOP_SMOOTH, 3, float); else TG_MF(FOP_SMOOTH, 2, float);
+  } else {
+    if (split) TG_MF(FOP_RESTRICT, 3, float); else TG_MF(FOP_RESTRICT, 2, float);
   }
 #undef TG_MF
   return TG_OK;

@@ -140,6 +140,7 @@ static size_t list_capacity(const std::vector<tg_grid*>& gs) {
     }
     c += g->lv[0].n_chunks + 1;
     for (int l = 0; l < g->nlev; ++l) c += zm_tiles(g, l, 1);
+    for (int l = 0; l + 1 < g->nlev; ++l) c += rz_tiles(g, l, 1);
     c += zm_tiles(g, 0, 1);
   }
   return c;
@@ -332,6 +333,11 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
       if (l < b->grids[p]->nlev - 1)
         for (int t = 0, nt = zm_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_s[l], o);
+    o = begin();
+    for (int p : active)
+      if (l < b->grids[p]->nlev - 1)
+        for (int t = 0, nt = rz_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
+    finish(b->zm_r[l], o);
   }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");
   if (!H.empty())

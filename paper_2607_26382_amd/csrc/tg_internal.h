@@ -201,6 +201,7 @@ struct Batch {
   DevList node[TG_MAXLEV], smooth[TG_MAXLEV], coarse[TG_MAXLEV], elem[TG_MAXLEV], vec, prob;
   DevList fine;                   // level-0 z-march tiles, all problems
   DevList zm_s[TG_MAXLEV];        // level-l z-march tiles, problems where l is not the coarsest
+  DevList zm_r[TG_MAXLEV];        // level-l residual-restriction tiles (same problems)
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
   int zc[TG_MAXLEV] = {};         // z-tile height per level for this batch
@@ -262,6 +263,7 @@ int mode_coef_from_ke(const double* Ke, ModeCoef<double>* out64, ModeCoef<float>
 int galerkin1_values(const double* Ke, double* out);
 int zm_height(int NZ, int zmax);
 int zm_tiles(const tg_grid* g, int l, int zmax);
+int rz_tiles(const tg_grid* g, int l, int zmax);
 void batch_choose_zc(Batch* b);
 template <class T>
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,

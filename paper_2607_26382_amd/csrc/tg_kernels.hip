@@ -338,7 +338,8 @@ __global__ __launch_bounds__(256) void k_coarse_factor(const ProbDesc* __restric
 //   OP_APPLY : y = K x
 //   OP_RESID : y = b - K x
 //   OP_SMOOTH: y = x + w D^-1 (b - K x)      (damped node-block Jacobi)
-enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2 };
+//   OP_RESTRICT: b_{l+1} = P^T (b - K x)     (residual fused with the restriction)
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_RESTRICT = 3 };
 
 // First pre-sweep from x = 0: x = w D^-1 b; optionally keep b in type T.
 template <class TB, class T>
@@ -367,45 +368,6 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict
   x[3LL * n] = omega * (D[0] * b0 + D[1] * b1 + D[2] * b2);
   x[3LL * n + 1] = omega * (D[3] * b0 + D[4] * b1 + D[5] * b2);
   x[3LL * n + 2] = omega * (D[6] * b0 + D[7] * b1 + D[8] * b2);
-}
-
-// Restriction b_c = P^T r (27-point full weighting per component), coarse x=0 clamped.
-template <class T>
-__global__ __launch_bounds__(256) void k_restrict(const ProbDesc* __restrict__ probs,
-                                                  const int2* __restrict__ work, int lc, int sr,
-                                                  int sb) {
-  const int2 wi = work[blockIdx.x];
-  const ProbDesc& P = probs[wi.x];
-  const LevelDesc& Lc = P.lv[lc];
-  const LevelDesc& Lf = P.lv[lc - 1];
-  const int n = wi.y * TG_NODE_TILE + threadIdx.x;
-  if (n >= Lc.n_nodes) return;
-  const int I = n % Lc.NX, t = n / Lc.NX, J = t % Lc.NY, K = t / Lc.NY;
-  auto* b = vslot<T>(Lc, sb, nullptr);
-  T s0 = T(0), s1 = T(0), s2 = T(0);
-  if (I > 0) {
-    const auto* r = vslot<T>(Lf, sr, nullptr);
-    for (int dk = -1; dk <= 1; ++dk) {
-      const int fk = 2 * K + dk;
-      if (fk < 0 || fk >= Lf.NZ) continue;
-      for (int dj = -1; dj <= 1; ++dj) {
-        const int fj = 2 * J + dj;
-        if (fj < 0 || fj >= Lf.NY) continue;
-        for (int di = -1; di <= 1; ++di) {
-          const int fi = 2 * I + di;
-          if (fi < 0 || fi >= Lf.NX) continue;
-          const T w = T(1.0 / (double)(1 << ((di != 0) + (dj != 0) + (dk != 0))));
-          const long long m = fi + (long long)Lf.NX * (fj + (long long)Lf.NY * fk);
-          s0 += w * r[3 * m];
-          s1 += w * r[3 * m + 1];
-          s2 += w * r[3 * m + 2];
-        }
-      }
-    }
-  }
-  b[3LL * n] = s0;
-  b[3LL * n + 1] = s1;
-  b[3LL * n + 2] = s2;
 }
 
 // Prolongation and correction x_f += P e_c (trilinear).
@@ -1314,6 +1276,8 @@ static double op_bytes(const Batch* b, int l, int lmode, int op) {
   const double mat = (l <= TG_MF_LEVELS) ? elems * double(1 << (3 * l)) * sizeof(T) : elems * double(TG_GM_NU) * sizeof(T);
   const double dinv = (op == OP_SMOOTH) ? 9.0 * nodes * sizeof(T) : 0.0;
   const int nvec = op == OP_APPLY ? 2 : 3;
+  // the fused restriction reads x and b and writes the coarse right-hand side
+  if (op == OP_RESTRICT) return 2 * vec + mat + vec / 8.0;
   return nvec * vec + mat + dinv;
 }
 
@@ -1339,17 +1303,18 @@ int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
 
 // mf: 0 = vector mode-basis contraction, 1 = BF16 matrix cores, 2 = split BF16
 template <class T, int OP>
-static void vc_op(Batch* b, int l, const DevList& sm, int x, int bs, int y, T om, hipStream_t s, int mf = 0) {
+// (y: slot of level l, or of level l + 1 for OP_RESTRICT)
+static void vc_op(Batch* b, int l, int x, int bs, int y, T om, hipStream_t s, int mf = 0) {
+  const DevList& dl = (OP == OP_RESTRICT) ? b->zm_r[l] : b->zm_s[l];
   if (l == 0 && mf)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
-             launch_fine_mfma(b, b->zm_s[0], OP, mf == 2, x, nullptr, bs, nullptr, y, nullptr, (double)om,
-                              false, s));
+             launch_fine_mfma(b, dl, OP, mf == 2, x, nullptr, bs, nullptr, y, nullptr, (double)om, false, s));
   else if (l == 0)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
-             launch_fine<T>(b, b->zm_s[0], 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
+             launch_fine<T>(b, dl, 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
   else
     TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
-             launch_fine<T>(b, b->zm_s[l], l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
+             launch_fine<T>(b, dl, l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
 }
 
 // One fixed V-cycle.  Level-0 input b (slot sb of the FP64 pool or external
@@ -1361,7 +1326,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   const tg_mg_opts& mg = b->grids[0]->mg;
   const T om = T(mg.omega);
   const bool f64 = sizeof(T) == 8;
-  const int B0 = f64 ? S_VB : C_B, XA0 = f64 ? S_VXA : C_XA, XB0 = f64 ? S_VXB : C_XB, R0 = f64 ? S_VR : C_R;
+  const int B0 = f64 ? S_VB : C_B, XA0 = f64 ? S_VXA : C_XA, XB0 = f64 ? S_VXB : C_XB;
   const int flips = (mg.nu_pre - 1) + mg.nu_post;
   const int FIN = (flips % 2 == 0) ? C_XA : C_XB;      // level >= 1 result slot
   const int FIN0 = (flips % 2 == 0) ? XA0 : XB0;
@@ -1378,7 +1343,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   const bool fast_out = !f64 && !out_is_f32 && sy >= 0 && all_multi;
   // ---- descend
   for (int l = 0; l < L; ++l) {
-    const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB, Rs = l == 0 ? R0 : C_R;
+    const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB;
     const DevList& sm = b->smooth[l];
     const DevList& co = b->coarse[l];
     if (l == 0 && b->node[0].n && !fast_in) {
@@ -1408,16 +1373,11 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
                k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om, -1));
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
-      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s, mf);
+      vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf);
       std::swap(c, o);
     }
-    vc_op<T, OP_RESID>(b, l, sm, c, Bs, Rs, om, s, mf);
-    if (b->node[l + 1].n) {
-      double cn, ce, cc;
-      level_sums(b, l + 1, 0, cn, ce, cc);
-      TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * sT + 3.0 * cn * sT,
-               k_restrict<T><<<nblk(b->node[l + 1]), 256, 0, s>>>(b->desc_d, b->node[l + 1].ptr, l + 1, Rs, C_B));
-    }
+    // residual, restricted straight into the next level's right-hand side
+    vc_op<T, OP_RESTRICT>(b, l, c, Bs, C_B, om, s, mf);
     cur[l] = c;
   }
   // ---- ascend
@@ -1442,7 +1402,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
         c = -1;   // result is in the output slot
         break;
       }
-      vc_op<T, OP_SMOOTH>(b, l, sm, c, Bs, o, om, s, mf);
+      vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf);
       std::swap(c, o);
     }
     cur[l] = c;
