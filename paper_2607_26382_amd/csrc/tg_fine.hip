@@ -417,7 +417,7 @@ template <class T, int OP, int KIND, class TY = T>
 __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ probs,
                                                  const int2* __restrict__ work, int l, int sx,
                                                  const void* ex_, int sb, const void* eb_, int sy,
-                                                 void* ey_, T omega, ModeCoef<T> mc) {
+                                                 void* ey_, int sy2, T omega, ModeCoef<T> mc) {
   // Single buffers suffice: every read of a layer's values happens between the
   // two barriers of its step, every write of the next layer after them.
   __shared__ T su[3][17][17];           // node values of the current top layer
@@ -738,8 +738,21 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         if (K >= rzm * tiz && K < NZc && I < NXc && J < NYc) {
           const LevelDesc& Lc = P.lv[l + 1];
           auto* bc = gp(fpool<TY>(Lc) + (long long)sy * Lc.stride) + 3 * (I + (long long)NXc * (J + (long long)NYc * K));
+          T bv[3];
 #pragma unroll
-          for (int q = 0; q < 3; ++q) bc[q] = I == 0 ? TY(0) : TY(racc[q]);   // coarse x = 0 clamped
+          for (int q = 0; q < 3; ++q) {
+            bv[q] = I == 0 ? T(0) : racc[q];   // coarse x = 0 clamped
+            bc[q] = TY(bv[q]);
+          }
+          if (sy2 >= 0 && l + 1 < P.nlev - 1) {
+            // the coarse level's first Jacobi sweep from zero, x = w D^-1 b
+            const long long nc = I + (long long)NXc * (J + (long long)NYc * K);
+            const auto* Dc = gp(fD<T>(Lc)) + 9 * nc;
+            auto* xc = gp(fpool<TY>(Lc) + (long long)sy2 * Lc.stride) + 3 * nc;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+              xc[q] = TY(omega * mad_(Dc[3 * q + 2], bv[2], mad_(Dc[3 * q + 1], bv[1], Dc[3 * q] * bv[0])));
+          }
         }
         if (k & 1) {
 #pragma unroll
@@ -951,7 +964,7 @@ template <> ModeCoef<float> mcoef<float>(const tg_grid* g) { return g->mc32; }
 // Every grid of a batch shares one Ke (checked at batch creation).
 template <class T>
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
-                const void* eb, int sy, void* ey, double omega, hipStream_t s) {
+                const void* eb, int sy, void* ey, double omega, hipStream_t s, int sy2) {
   if (!dl.n) return TG_OK;
   const ModeCoef<T> mc = mcoef<T>(b->grids[0]);
   const ProbDesc* desc = b->desc_d;
@@ -959,13 +972,13 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
 #define TG_ZM(KV)                                                                                         \
   do {                                                                                                    \
     if (op == FOP_APPLY)                                                                                  \
-      k_fine_zm<T, FOP_APPLY, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);    \
+      k_fine_zm<T, FOP_APPLY, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc);    \
     else if (op == FOP_RESID)                                                                             \
-      k_fine_zm<T, FOP_RESID, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);    \
+      k_fine_zm<T, FOP_RESID, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc);    \
     else if (op == FOP_SMOOTH)                                                                            \
-      k_fine_zm<T, FOP_SMOOTH, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc);   \
+      k_fine_zm<T, FOP_SMOOTH, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc);   \
     else                                                                                                  \
-      k_fine_zm<T, FOP_RESTRICT, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, om, mc); \
+      k_fine_zm<T, FOP_RESTRICT, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc); \
   } while (0)
   if (l == 0)
     TG_ZM(0);
@@ -977,17 +990,17 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
   return TG_OK;
 }
 template int launch_fine<double>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
-                                 int, void*, double, hipStream_t);
+                                 int, void*, double, hipStream_t, int);
 
 // Level 0 with the BF16 matrix-core contraction (FP32 vectors): op as above.
 int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,
-                     const void* eb, int sy, void* ey, double omega, bool out64, hipStream_t s) {
+                     const void* eb, int sy, void* ey, double omega, bool out64, hipStream_t s, int sy2) {
   if (!dl.n) return TG_OK;
   const ModeCoef<float> mc = mcoef<float>(b->grids[0]);
   const ProbDesc* desc = b->desc_d;
   const float om = float(omega);
 #define TG_MF(OPV, K, TYV) \
-  k_fine_zm<float, OPV, K, TYV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, om, mc)
+  k_fine_zm<float, OPV, K, TYV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, sy2, om, mc)
   if (out64) {
     if (split) TG_MF(FOP_SMOOTH, 3, double); else TG_MF(FOP_SMOOTH, 2, double);
   } else if (op == FOP_APPLY) {
@@ -1010,10 +1023,10 @@ int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, 
   if (!dl.n) return TG_OK;
   const ModeCoef<float> mc = mcoef<float>(b->grids[0]);
   k_fine_zm<float, FOP_SMOOTH, 0, double><<<dl.n, 256, 0, s>>>(b->desc_d, dl.ptr, 0, sx, nullptr, sb, nullptr,
-                                                               sy, nullptr, float(omega), mc);
+                                                               sy, nullptr, -1, float(omega), mc);
   return TG_OK;
 }
 template int launch_fine<float>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
-                                int, void*, double, hipStream_t);
+                                int, void*, double, hipStream_t, int);
 
 }  // namespace tg

@@ -266,12 +266,16 @@ int zm_tiles(const tg_grid* g, int l, int zmax);
 int rz_tiles(const tg_grid* g, int l, int zmax);
 void batch_choose_zc(Batch* b);
 template <class T>
+// op 3 (residual fused with the restriction): sy is the next level's
+// right-hand-side slot; sy2 >= 0 also writes that level's first Jacobi sweep
+// from zero into slot sy2
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
-                const void* eb, int sy, void* ey, double omega, hipStream_t s);
+                const void* eb, int sy, void* ey, double omega, hipStream_t s, int sy2 = -1);
 int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, int sy, double omega,
                              hipStream_t s);
 int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,
-                     const void* eb, int sy, void* ey, double omega, bool out64, hipStream_t s);
+                     const void* eb, int sy, void* ey, double omega, bool out64, hipStream_t s,
+                     int sy2 = -1);
 
 // autotuner (tg_autotune.hip)
 std::string batch_signature(const Batch* b, int prec);

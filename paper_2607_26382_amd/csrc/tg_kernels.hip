@@ -1303,18 +1303,19 @@ int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
 
 // mf: 0 = vector mode-basis contraction, 1 = BF16 matrix cores, 2 = split BF16
 template <class T, int OP>
-// (y: slot of level l, or of level l + 1 for OP_RESTRICT)
-static void vc_op(Batch* b, int l, int x, int bs, int y, T om, hipStream_t s, int mf = 0) {
+// (y: slot of level l, or for OP_RESTRICT the right-hand-side slot of level
+// l + 1, with y2 that level's first-sweep slot)
+static void vc_op(Batch* b, int l, int x, int bs, int y, T om, hipStream_t s, int mf = 0, int y2 = -1) {
   const DevList& dl = (OP == OP_RESTRICT) ? b->zm_r[l] : b->zm_s[l];
   if (l == 0 && mf)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
-             launch_fine_mfma(b, dl, OP, mf == 2, x, nullptr, bs, nullptr, y, nullptr, (double)om, false, s));
+             launch_fine_mfma(b, dl, OP, mf == 2, x, nullptr, bs, nullptr, y, nullptr, (double)om, false, s, y2));
   else if (l == 0)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
-             launch_fine<T>(b, dl, 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
+             launch_fine<T>(b, dl, 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s, y2));
   else
     TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
-             launch_fine<T>(b, dl, l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s));
+             launch_fine<T>(b, dl, l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s, y2));
 }
 
 // One fixed V-cycle.  Level-0 input b (slot sb of the FP64 pool or external
@@ -1368,16 +1369,18 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (8.0 + 2 * sT) + 9.0 * nodes * sT,
                k_jacobi_first<double, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, 0, sb, nullptr, Bs, XA, om,
                                                                     in_scale));
-    else
+    else if (l == 0)
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 9.0 * nodes * sT,
                k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om, -1));
+    // (levels >= 1: the restriction above already wrote the first sweep)
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
       vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf);
       std::swap(c, o);
     }
-    // residual, restricted straight into the next level's right-hand side
-    vc_op<T, OP_RESTRICT>(b, l, c, Bs, C_B, om, s, mf);
+    // residual, restricted straight into the next level's right-hand side,
+    // and that level's first Jacobi sweep from zero
+    vc_op<T, OP_RESTRICT>(b, l, c, Bs, C_B, om, s, mf, C_XA);
     cur[l] = c;
   }
   // ---- ascend
