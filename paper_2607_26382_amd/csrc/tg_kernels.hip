@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_galerkin_up(const ProbDesc* __restrict_
                                                      const int2* __restrict__ work, int lc) {
   __shared__ double sK[576];
   __shared__ double sT[576];
+  __shared__ double Pc[576];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& Lf = P.lv[lc - 1];
@@ -140,8 +141,11 @@ __global__ __launch_bounds__(256) void k_galerkin_up(const ProbDesc* __restrict_
   for (int c = 0; c < 8; ++c) {
     const int fx = 2 * cx + (c & 1), fy = 2 * cy + ((c >> 1) & 1), fz = 2 * cz + ((c >> 2) & 1);
     const long long fe = fx + (long long)Lf.ex * (fy + (long long)Lf.ey * fz);
-    const double* Pc = P.Pc64 + c * 576;
-    for (int q = threadIdx.x; q < 576; q += 256) sK[q] = Lf.Kel64[fe * 576 + q];
+    // child matrix and prolongation staged in LDS
+    for (int q = threadIdx.x; q < 576; q += 256) {
+      sK[q] = Lf.Kel64[fe * 576 + q];
+      Pc[q] = P.Pc64[c * 576 + q];
+    }
     __syncthreads();
     // T = Kel_child * P_c   (24 x 24)
     for (int q = threadIdx.x; q < 576; q += 256) {
@@ -1005,11 +1009,16 @@ __global__ void k_arnoldi_(const ProbDesc* __restrict__ probs, const int2* __res
 // coefficients), replacing the tentative column and rotation of step j-1.
 // The first-pass coefficients of column j are h1 = [Q^T w ; q_j . w]; the
 // coefficients of sweep B go to tmp (see k_update2_).
-__global__ void k_dcgs_a_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work, SmallOffs o,
-                          int j, double* status_out) {
+__global__ __launch_bounds__(64) void k_dcgs_a_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                                                SmallOffs o, int j, double* status_out) {
+  // one wave per problem: the column and the rotations are read in parallel
+  // and rotated in LDS by lane 0 (a chain of register operations rather than
+  // of round trips through memory)
+  __shared__ double sH[TG_MAX_RESTART + 2], sC[TG_MAX_RESTART + 1], sS[TG_MAX_RESTART + 1];
+  __shared__ int bad;
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
-  if (threadIdx.x != 0) return;
+  const int lane = threadIdx.x;
   double* S = P.small;
   double* sc = S + o.scal;
   if (sc[SC_STATUS] != TG_RUNNING) return;
@@ -1019,68 +1028,89 @@ __global__ void k_dcgs_a_(const ProbDesc* __restrict__ probs, const int2* __rest
   const double rho = sc[SC_RHO];
   const double alpha = tmp[2 * j] / (rho * rho), qw = tmp[2 * j + 1] / rho, ww = tmp[2 * j + 2];
   double ss = 0.0, sz = 0.0;
-  for (int k = 0; k < j; ++k) {
+  for (int k = lane; k < j; k += 64) {
     const double sk = tmp[k] / rho;
     ss += sk * sk;
     sz += sk * tmp[j + k];
   }
+  ss = wave_sum(ss);
+  sz = wave_sum(sz);
   const double nu2 = alpha - ss;
   double st = TG_RUNNING;
   if (!isfinite(nu2) || !isfinite(qw) || !isfinite(sz)) st = TG_NONFINITE;
   else if (!(nu2 > 0.0)) st = TG_BREAKDOWN;   // q~_j lies in span(Q): nothing new
   if (st != TG_RUNNING) {
-    sc[SC_STATUS] = st;
-    status_out[wi.x] = st;
+    if (lane == 0) {
+      sc[SC_STATUS] = st;
+      status_out[wi.x] = st;
+    }
     return;
   }
   const double nu = sqrt(nu2);
-  sc[SC_FLAG] = ww;
+  if (lane == 0) sc[SC_FLAG] = ww;
   if (j >= 1) {
     double* Hc = S + o.H + (long long)ldh * (j - 1);
-    for (int i = 0; i < j; ++i) Hc[i] = h1[i] + tmp[i];
-    Hc[j] = rho * nu;
-    for (int i = 0; i < j - 1; ++i) {
-      const double c = S[o.cs + i], sn = S[o.sn + i];
-      const double t = c * Hc[i] + sn * Hc[i + 1];
-      Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
-      Hc[i] = t;
+    for (int i = lane; i < j; i += 64) sH[i] = h1[i] + tmp[i];
+    for (int i = lane; i < j - 1; i += 64) {
+      sC[i] = S[o.cs + i];
+      sS[i] = S[o.sn + i];
     }
-    const double d = hypot(Hc[j - 1], Hc[j]);
-    if (!(d > 0.0) || !isfinite(d)) {
-      sc[SC_STATUS] = TG_NONFINITE;
-      status_out[wi.x] = TG_NONFINITE;
-      return;
+    __syncthreads();
+    if (lane == 0) {
+      sH[j] = rho * nu;
+      double carry = sH[0];
+      for (int i = 0; i < j - 1; ++i) {
+        const double c = sC[i], sn = sS[i], b = sH[i + 1];
+        sH[i] = c * carry + sn * b;
+        carry = -sn * carry + c * b;
+      }
+      sH[j - 1] = carry;
+      const double d = hypot(sH[j - 1], sH[j]);
+      bad = !(d > 0.0) || !isfinite(d);
+      if (bad) {
+        sc[SC_STATUS] = TG_NONFINITE;
+        status_out[wi.x] = TG_NONFINITE;
+      } else {
+        const double c = sH[j - 1] / d, sn = sH[j] / d;
+        S[o.cs + j - 1] = c;
+        S[o.sn + j - 1] = sn;
+        sH[j - 1] = d;
+        sH[j] = 0.0;
+        const double gj = sc[SC_GJ];
+        S[o.g + j - 1] = c * gj;
+        S[o.g + j] = -sn * gj;
+      }
     }
-    const double c = Hc[j - 1] / d, sn = Hc[j] / d;
-    S[o.cs + j - 1] = c;
-    S[o.sn + j - 1] = sn;
-    Hc[j - 1] = d;
-    Hc[j] = 0.0;
-    const double gj = sc[SC_GJ];
-    S[o.g + j - 1] = c * gj;
-    S[o.g + j] = -sn * gj;
+    __syncthreads();
+    for (int i = lane; i <= j; i += 64) Hc[i] = sH[i];
+    if (bad) return;
   }
   const double hjj = (qw - sz) / nu;
-  for (int k = 0; k < j; ++k) {
+  for (int k = lane; k < j; k += 64) {
     const double sk = tmp[k] / rho, zk = tmp[j + k];
     h1[k] = zk;
     tmp[j + k] = zk - sk * hjj / nu;
     tmp[k] = sk / nu;
   }
-  h1[j] = hjj;
-  tmp[2 * j] = 1.0 / (rho * nu);
-  tmp[2 * j + 1] = hjj / (nu * rho);
+  if (lane == 0) {
+    h1[j] = hjj;
+    tmp[2 * j] = 1.0 / (rho * nu);
+    tmp[2 * j + 1] = hjj / (nu * rho);
+  }
 }
 
 // After sweep B of step j: rho' = ||q~_{j+1}|| (tmp[0]).  Column j enters
 // tentatively as [h1 ; rho'] (its reorthogonalization correction is known
 // only after the next sweep A): rotations, projected residual estimate,
 // history and stop tests as in the immediate form.
-__global__ void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work, SmallOffs o,
-                          int j, int cap, double tol, double brk, double* status_out) {
+__global__ __launch_bounds__(64) void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                                                SmallOffs o, int j, int cap, double tol, double brk,
+                                                double* status_out) {
+  __shared__ double sH[TG_MAX_RESTART + 2], sC[TG_MAX_RESTART + 1], sS[TG_MAX_RESTART + 1];
+  __shared__ int bad;
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
-  if (threadIdx.x != 0) return;
+  const int lane = threadIdx.x;
   double* S = P.small;
   double* sc = S + o.scal;
   if (sc[SC_STATUS] != TG_RUNNING) return;   // stopped in sweep A of this step
@@ -1088,53 +1118,69 @@ __global__ void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __rest
   const int ldh = o.mmax + 1;
   const double rn = sqrt(S[o.tmp]);
   double* Hc = S + o.H + (long long)ldh * j;
-  bool finite = isfinite(rn);
-  for (int i = 0; i <= j; ++i) {
-    Hc[i] = h1[i];
-    finite = finite && isfinite(Hc[i]);
+  bool finite = true;
+  for (int i = lane; i <= j; i += 64) {
+    sH[i] = h1[i];
+    finite = finite && isfinite(sH[i]);
   }
-  Hc[j + 1] = rn;
+  for (int i = lane; i < j; i += 64) {
+    sC[i] = S[o.cs + i];
+    sS[i] = S[o.sn + i];
+  }
+  finite = __all(finite) && isfinite(rn);
   if (!finite) {
-    sc[SC_STATUS] = TG_NONFINITE;
-    status_out[wi.x] = TG_NONFINITE;
+    for (int i = lane; i <= j; i += 64) Hc[i] = sH[i];
+    if (lane == 0) {
+      Hc[j + 1] = rn;
+      sc[SC_STATUS] = TG_NONFINITE;
+      status_out[wi.x] = TG_NONFINITE;
+    }
     return;
   }
-  for (int i = 0; i < j; ++i) {
-    const double c = S[o.cs + i], sn = S[o.sn + i];
-    const double t = c * Hc[i] + sn * Hc[i + 1];
-    Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
-    Hc[i] = t;
+  __syncthreads();
+  if (lane == 0) {
+    sH[j + 1] = rn;
+    double carry = sH[0];
+    for (int i = 0; i < j; ++i) {
+      const double c = sC[i], sn = sS[i], b = sH[i + 1];
+      sH[i] = c * carry + sn * b;
+      carry = -sn * carry + c * b;
+    }
+    sH[j] = carry;
+    const double d = hypot(sH[j], sH[j + 1]);
+    bad = !(d > 0.0) || !isfinite(d);
+    if (bad) {
+      sc[SC_STATUS] = TG_NONFINITE;
+      status_out[wi.x] = TG_NONFINITE;
+    } else {
+      const double c = sH[j] / d, sn = sH[j + 1] / d;
+      S[o.cs + j] = c;
+      S[o.sn + j] = sn;
+      sH[j] = d;
+      sH[j + 1] = 0.0;
+      const double gj = S[o.g + j];
+      sc[SC_GJ] = gj;
+      S[o.g + j + 1] = -sn * gj;
+      S[o.g + j] = c * gj;
+      const int kk = (int)sc[SC_ITERS] + 1;   // iterations so far live on the device
+      const double est = fabs(S[o.g + j + 1]) / sc[SC_BNORM];
+      S[o.hist + kk] = est;
+      sc[SC_EST] = est;
+      sc[SC_ITERS] = kk;
+      sc[SC_JDONE] = j + 1;
+      sc[SC_HN] = rn;
+      sc[SC_RHO] = rn;
+      sc[SC_INV] = rn > 0.0 ? 1.0 / rn : 0.0;
+      double st = TG_RUNNING;
+      if (est <= tol) st = TG_PROJ_CONVERGED;
+      else if (rn <= brk * sqrt(fmax(sc[SC_FLAG], 0.0))) st = TG_BREAKDOWN;
+      else if (kk >= cap) st = TG_MAXIT;
+      sc[SC_STATUS] = st;
+      status_out[wi.x] = st;
+    }
   }
-  const double d = hypot(Hc[j], Hc[j + 1]);
-  if (!(d > 0.0) || !isfinite(d)) {
-    sc[SC_STATUS] = TG_NONFINITE;
-    status_out[wi.x] = TG_NONFINITE;
-    return;
-  }
-  const double c = Hc[j] / d, sn = Hc[j + 1] / d;
-  S[o.cs + j] = c;
-  S[o.sn + j] = sn;
-  Hc[j] = d;
-  Hc[j + 1] = 0.0;
-  const double gj = S[o.g + j];
-  sc[SC_GJ] = gj;
-  S[o.g + j + 1] = -sn * gj;
-  S[o.g + j] = c * gj;
-  const int kk = (int)sc[SC_ITERS] + 1;   // iterations so far live on the device
-  const double est = fabs(S[o.g + j + 1]) / sc[SC_BNORM];
-  S[o.hist + kk] = est;
-  sc[SC_EST] = est;
-  sc[SC_ITERS] = kk;
-  sc[SC_JDONE] = j + 1;
-  sc[SC_HN] = rn;
-  sc[SC_RHO] = rn;
-  sc[SC_INV] = rn > 0.0 ? 1.0 / rn : 0.0;
-  double st = TG_RUNNING;
-  if (est <= tol) st = TG_PROJ_CONVERGED;
-  else if (rn <= brk * sqrt(fmax(sc[SC_FLAG], 0.0))) st = TG_BREAKDOWN;
-  else if (kk >= cap) st = TG_MAXIT;
-  sc[SC_STATUS] = st;
-  status_out[wi.x] = st;
+  __syncthreads();
+  for (int i = lane; i <= j + 1; i += 64) Hc[i] = sH[i];
 }
 
 // Least squares: y = R^{-1} g over the jdone columns (back substitution).
