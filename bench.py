@@ -224,11 +224,11 @@ def batch4_leg(tg, torch, dev, mixed_prec):
     batch.set_density(rhos, 3.0, floors)
     zc, _ = batch.autotune(mixed_prec)
 
-    def batched(prec):
+    def batched(prec, graphs=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch.set_density(rhos, 3.0, floors)
-        _, res = batch.solve(fs, tg.solver_opts(prec=prec))
+        _, res = batch.solve(fs, tg.solver_opts(prec=prec, graphs=graphs))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ok = sum(1 for r in res if r["true_eta"] <= 1e-6)
@@ -238,6 +238,13 @@ def batch4_leg(tg, torch, dev, mixed_prec):
     batched(mixed_prec)   # warm-up
     out = {"solves": len(grids), "grids": [list(d) for d in B4_GRIDS], "autotuned_zc": zc[:2],
            "mixed_batched": batched(mixed_prec), "fp64_batched": batched(tg.F64)}
+    # the same batch with every FGMRES step (V-cycle, operator, Gram-Schmidt)
+    # replayed from a captured HIP graph; the first pass captures one graph
+    # per (active set, step) and is not timed
+    t0 = time.perf_counter()
+    batched(mixed_prec, graphs=True)
+    out["graph_capture_pass_s"] = time.perf_counter() - t0
+    out["mixed_batched_graphs"] = batched(mixed_prec, graphs=True)
     # the same solves one at a time (each grid alone)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -251,7 +258,8 @@ def batch4_leg(tg, torch, dev, mixed_prec):
     out["mixed_serial"] = {"value": ok / dt, "seconds": dt, "guard_passing": ok}
     out["batched_over_serial"] = out["mixed_batched"]["value"] / out["mixed_serial"]["value"]
     out["mixed_over_fp64"] = out["mixed_batched"]["value"] / out["fp64_batched"]["value"]
-    log(f"uneven batch: {out['mixed_batched']['value']:.1f} solves/s batched, "
+    log(f"uneven batch: {out['mixed_batched']['value']:.1f} solves/s batched "
+        f"({out['mixed_batched_graphs']['value']:.1f} with graph replay), "
         f"{out['mixed_serial']['value']:.1f} serial, {out['fp64_batched']['value']:.1f} FP64 batched")
     del batch, grids
     torch.cuda.empty_cache()
