@@ -30,28 +30,45 @@ sys.path.insert(0, ROOT)
 
 # HBM bytes per launch of kernel classes on this workload, from rocprofv3
 # --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (FETCH_SIZE scaled by 2.000, the
-# factor a plain 1 GiB copy needs); each entry holds while the listed kernel
-# sources are unchanged (sha256 prefix), else the traffic is reported as null.
+# factor a plain 1 GiB copy needs).  Each entry holds while the source of the
+# kernels it measured is unchanged (sha256 prefix of the listed files, or of
+# the listed kernel definitions within a file), else the traffic is reported
+# as null.
 MEASURED_TRAFFIC = {
-    "vcycle_fine_op": {"bytes_per_launch": 194.6e6, "sources": {"tg_fine.hip": "ccc5988ec0d34ef9"},
+    "vcycle_fine_op": {"bytes_per_launch": 192.9e6, "sources": {"tg_fine.hip": "89396403ba2d182e"},
                        "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
-    "multidot": {"bytes_per_launch": 1818.4e6, "sources": {"tg_kernels.hip": "843194a743d9d389"},
+    "multidot": {"bytes_per_launch": 1818.3e6, "sources": {"tg_kernels.hip:k_dots2_": "413b15d1d0705f54"},
                  "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
-    "vector_update": {"bytes_per_launch": 1938.1e6, "sources": {"tg_kernels.hip": "843194a743d9d389"},
+    "vector_update": {"bytes_per_launch": 1938.0e6, "sources": {"tg_kernels.hip:k_update2_": "e3884c42c4c540bf"},
                       "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
 }
 
 
-def measured_traffic(cls):
+def source_hash(spec):
+    """sha256 prefix of a source file under csrc/, or ("file:name") of the
+    definition of kernel `name` in it (from its signature to the first line
+    that closes it at column 0)."""
     import hashlib
+    fname, _, name = spec.partition(":")
+    with open(os.path.join(ROOT, "paper_2607_26382_amd", "csrc", fname)) as fh:
+        text = fh.read()
+    if name:
+        i = text.find(" " + name + "(")
+        if i < 0:
+            return None
+        i = text.rfind("\n", 0, i) + 1
+        j = text.find("\n}\n", i)
+        text = text[i:j + 3]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def measured_traffic(cls):
     e = MEASURED_TRAFFIC.get(cls)
     if not e:
         return None
-    for name, sha in e["sources"].items():
-        path = os.path.join(ROOT, "paper_2607_26382_amd", "csrc", name)
-        with open(path, "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest()[:16] != sha:
-                return None
+    for spec, sha in e["sources"].items():
+        if source_hash(spec) != sha:
+            return None
     return e["bytes_per_launch"]
 
 
