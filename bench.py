@@ -18,6 +18,7 @@ Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import subprocess
 import sys
@@ -105,13 +106,18 @@ def parse():
     ap.add_argument("--no-scale", action="store_true", help="skip the 256x128x128 mixed-vs-FP64 solve")
     ap.add_argument("--no-rule-leg", action="store_true",
                     help="skip the mixed-precision run with the two-feature rule")
+    ap.add_argument("--no-labels", action="store_true",
+                    help="skip the reference labels (independent solves at every rung) and the policy statistics")
+    ap.add_argument("--no-fixed-legs", action="store_true",
+                    help="skip the fixed-first-rung baselines (original floor first; always the top rung)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-seed", type=int, default=1000, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
-def cpu_baseline_child():
+def cpu_baseline_child(seed):
     """Oracle timing sample (runs in a child process with one BLAS thread)."""
     from oracle import fgmres as ofg
     from oracle import ke, mesh
@@ -119,7 +125,7 @@ def cpu_baseline_child():
     from oracle import operator as op
     from paper_2607_26382_amd import synth
 
-    (nx, ny, nz), rho = synth.severe(SEED0)
+    (nx, ny, nz), rho = synth.severe(seed)
     g = mesh.Grid(nx, ny, nz)
     free = g.free_dofs()
     f = g.edge_load()[free]
@@ -132,21 +138,85 @@ def cpu_baseline_child():
     print(json.dumps({"t_setup": t1 - t0, "t_iter": (t2 - t1) / n_it}), flush=True)
 
 
-def run_cpu_baseline(setups_per_state, iters_per_state):
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only"], env=env,
-                         capture_output=True, text=True, timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
-    d = json.loads(out.stdout.strip().splitlines()[-1])
-    sec_per_state = setups_per_state * d["t_setup"] + iters_per_state * d["t_iter"]
+def wilson(k, n, z=1.959963984540054):
+    """Wilson score interval for k successes in n trials (95 % by default)."""
+    if n == 0:
+        return None
+    p = k / n
+    den = 1.0 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * math.sqrt(p * (1.0 - p) / n + z * z / (4.0 * n * n)) / den
+    return [c - h, c + h]
+
+
+def policy_stats(outs, labels, tau=1e-6, cap=200):
+    """Held-out statistics of one policy run against reference labels (the
+    lowest rung whose independent solve passes the guard, -1 if none):
+    confusion with escalation as the positive class and Wilson intervals,
+    guard fallbacks, projected convergences the guard rejected, accepted
+    solves above the tolerance (must be 0) and the preserve margin."""
+    n = len(outs)
+    pred = [o["k0"] > 0 for o in outs]
+    ref = [lab != 0 for lab in labels]
+    tp = sum(1 for p, r in zip(pred, ref) if p and r)
+    tn = sum(1 for p, r in zip(pred, ref) if not p and not r)
+    fp = sum(1 for p, r in zip(pred, ref) if p and not r)
+    fn = sum(1 for p, r in zip(pred, ref) if not p and r)
+    cert = sum(1 for o in outs if o["rung"] >= 0)
+    atts = [a for o in outs for a in o["attempts"]]
+    kept = [o for o in outs if o["rung"] == 0]
+    its = [o["attempts"][-1]["iterations"] for o in kept]
     return {
-        "value": 1.0 / sec_per_state, "unit": "certified solves/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle (assembled CSR, FP64) on state seed {SEED0} at 64x32x32: one hierarchy "
-                   f"build ({d['t_setup']:.1f} s) and 20 FGMRES(30) iterations "
-                   f"({d['t_iter']*1e3:.0f} ms each) timed on 1 core, scaled by the GPU run's "
-                   f"mean {setups_per_state:.2f} set_density calls and {iters_per_state:.1f} "
-                   f"FGMRES iterations per state"),
+        "reference": {"escalate": sum(ref), "preserve": n - sum(ref),
+                      "none_admissible": sum(1 for lab in labels if lab < 0)},
+        "confusion": {"TP": tp, "TN": tn, "FP": fp, "FN": fn},
+        "sensitivity": {"k": tp, "n": tp + fn, "wilson95": wilson(tp, tp + fn)},
+        "specificity": {"k": tn, "n": tn + fp, "wilson95": wilson(tn, tn + fp)},
+        "guard_fallbacks": sum(1 for o in outs if o["k0"] == 0 and o["rung"] != 0),
+        "selected_meet_tolerance": {"k": cert, "n": n, "wilson95": wilson(cert, n)},
+        "lowest_admissible_selected": sum(1 for o, lab in zip(outs, labels) if o["rung"] == lab),
+        "projected_converged_rejected_by_guard": sum(
+            1 for a in atts if a["outcome"] == "PROJ_CONVERGED" and not a["true_eta"] <= tau),
+        "accepted_above_tolerance": sum(1 for a in atts if a["accepted"] and not a["true_eta"] <= tau),
+        "preserve_margin": {"preserved": len(kept), "cap": cap, "max_iterations": max(its, default=None),
+                            "at_least_80pct_of_cap": sum(1 for i in its if i >= 0.8 * cap)},
+    }
+
+
+def cpu_cores():
+    """Host cores this process may use, capped at the 16 a one-GPU share offers."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def run_cpu_baseline(setups_per_state, iters_per_state):
+    """One oracle process per host core (one BLAS thread each), each timing the
+    sample on its own state concurrently; the rate is the sum of the per-process
+    state rates."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cores = cpu_cores()
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-only", "--cpu-seed",
+                               str(SEED0 + i)], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                              text=True) for i in range(cores)]
+    samples = []
+    for pr in procs:
+        out, err = pr.communicate(timeout=900)
+        if pr.returncode != 0:
+            raise RuntimeError("cpu baseline failed: " + err[-2000:])
+        samples.append(json.loads(out.strip().splitlines()[-1]))
+    rates = [1.0 / (setups_per_state * d["t_setup"] + iters_per_state * d["t_iter"]) for d in samples]
+    ts = float(np.median([d["t_setup"] for d in samples]))
+    ti = float(np.median([d["t_iter"] for d in samples]))
+    return {
+        "value": float(sum(rates)), "unit": "certified solves/s", "cores": cores, "kind": "oracle",
+        "sample": (f"oracle (assembled CSR, FP64), one process per core on states {SEED0}-{SEED0 + cores - 1} "
+                   f"at 64x32x32: each times one hierarchy build (median {ts:.1f} s) and 20 FGMRES(30) "
+                   f"iterations (median {ti*1e3:.0f} ms each) concurrently; per-process rates scaled by the "
+                   f"GPU run's mean {setups_per_state:.2f} set_density calls and {iters_per_state:.1f} "
+                   f"FGMRES iterations per state and summed"),
     }
 
 
@@ -364,7 +434,7 @@ def small_leg(tg, torch, dev, reps=3):
 def main():
     args = parse()
     if args.cpu_only:
-        cpu_baseline_child()
+        cpu_baseline_child(args.cpu_seed)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -418,8 +488,8 @@ def main():
             return tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_MLP, mlp=mlp)
         return tg.policy(rungs=RUNGS, p=3.0, solve=solve)
 
-    def run(prec, steps, warmup, timer_mask, use_mlp):
-        pol = policy(prec, use_mlp)
+    def run(prec, steps, warmup, timer_mask, use_mlp, pol=None):
+        pol = pol if pol is not None else policy(prec, use_mlp)
         for w in range(warmup):
             t = time.perf_counter()
             batch.select_floor(rhos, fs, pol)
@@ -506,11 +576,35 @@ def main():
                 "mean_attempts": float(np.mean([len(x["attempts"]) for x in o]))}
 
     result["policy"]["mean_attempts"] = float(np.mean([len(o["attempts"]) for o in outs]))
+    # reference labels (untimed): independent guarded solves at every rung
+    labels = None
+    if not args.no_labels:
+        ok = []
+        for r in RUNGS:
+            batch.set_density(rhos, 3.0, [r] * n)
+            _, res = batch.solve(fs, tg.solver_opts(restart=30, max_iters=200, prec=mixed_prec,
+                                                    cgs_passes=args.cgs_passes))
+            ok.append([x["true_eta"] <= 1e-6 for x in res])
+        labels = [next((k for k in range(len(RUNGS)) if ok[k][i]), -1) for i in range(n)]
+        result["policy"]["stats"] = policy_stats(outs, labels)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)
         result["mixed_rule"]["same_rung"] = sum(1 for a, b in zip(outs, o) if a["rung"] == b["rung"])
+        if labels is not None:
+            result["mixed_rule"]["stats"] = policy_stats(o, labels)
         result["selector_gain"] = value / result["mixed_rule"]["value"]
+    if not args.no_fixed_legs:
+        # the two fixed baselines: the original floor first, then the ladder;
+        # always the top rung (the conventional floor 1e-3)
+        for name, k in (("always_rho0_then_ladder", 0), ("fixed_top_rung", len(RUNGS) - 1)):
+            solve = tg.solver_opts(restart=30, max_iters=200, prec=mixed_prec, cgs_passes=args.cgs_passes)
+            pol = tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_FIXED, fixed_rung=k)
+            d, o, _ = run(mixed_prec, 1, 0, 0, False, pol)
+            result[name] = brief(o, d, 1)
+            result[name]["preserved"] = sum(1 for x in o if x["rung"] == 0)
+            if labels is not None:
+                result[name]["lowest_admissible_selected"] = sum(1 for x, lab in zip(o, labels) if x["rung"] == lab)
     if not args.no_fp64:
         # the paper's method as published: every kernel in FP64, two-feature rule
         dt64, outs64, _ = run(tg.F64, args.steps, args.warmup, 0, False)
