@@ -23,6 +23,9 @@ What it computes (citations are to arXiv 2607.26382):
 * ``features``   - density statistics used by the learned first-floor selector.
 * ``mlp``        - forward/backward of the 8-64-64-4 GELU selector network.
 * ``stats``      - Wilson score intervals (Sec. 4.3.1 held-out reference test).
+* ``fidelity``   - compliance, element energies and the compliance sensitivity
+                   of Sec. 3.1, and the raised-floor perturbation metrics of
+                   Sec. 4.4.1 / Tab. perturbation.
 
 Every function is pinned by tests under ``tests/`` against facts the paper or
 mathematics fix (closed forms, invariants, printed values, library routines on
