@@ -15,7 +15,7 @@ What it computes (citations are to arXiv 2607.26382):
                    direct solve and the relative residual (Eq. relative_residual).
 * ``multigrid``  - 2:1 trilinear transfers, Galerkin coarse operators, damped
                    node-block Jacobi, fixed V-cycle (Tab. solver-config and the
-                   fixed linear V-cycle of Sec. 4.6.3 "Fixed-preconditioner control").
+                   fixed linear V-cycle of Sec. 4.5.3 "Fixed-preconditioner control").
 * ``fgmres``     - right-preconditioned flexible GMRES with the residual-history
                    semantics of Tab. residual-semantics.
 * ``policy``     - probe features, the two-feature rule (Eq. trigger) and the

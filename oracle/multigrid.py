@@ -1,4 +1,4 @@
-"""Geometric multigrid preconditioner (Tab. solver-config; Sec. 4.6.3).
+"""Geometric multigrid preconditioner (Tab. solver-config; Sec. 4.5.3).
 
 The paper's hierarchy uses 2:1 trilinear transfers and Galerkin coarse
 operators.  The preconditioner built here is the fixed linear V-cycle of the
