@@ -284,6 +284,41 @@ int tg_mlp_train_step(tg_mlp* m, const float* x_d, const int* y_d, int B, float 
 int tg_density_features(tg_grid* g, const double* rho_d, double p, double rho0, double* stats_h,
                         void* stream);
 
+/* ---- operator fidelity (Sec. 3.1 sensitivities; Sec. 4.4.1, Tab. perturbation) */
+/* For a displacement u_d (full length, double; clamped DOFs read as 0) on
+ * this grid:
+ *   energy_d[e] = u_e^T K_e u_e                       (may be NULL)
+ *   dc_d[e]     = -p (1 - rho_min) rho_e^(p-1) u_e^T K_e u_e, the compliance
+ *                 sensitivity dC/drho_e of Sec. 3.1 at the densities rho_d
+ *                 (n_elem doubles, the densities that enter Eq. floor_scaling;
+ *                 used as given, not validated)       (may be NULL)
+ *   *compliance_h = f^T u over the free DOFs (f_d full length, double)
+ *                 (may be NULL; then f_d may be NULL too)
+ * p > 0 and 0 <= rho_min <= 1 are those of the solve u came from; they need
+ * not match the last set_density.  At least one output must be requested.
+ * Works in FP64 in a fixed summation order (bitwise reproducible); uses the
+ * grid's reduction scratch, so it must not overlap another call on the same
+ * grid.  Synchronizes `stream` when compliance_h is requested. */
+int tg_compliance_sensitivity(const tg_grid* g, const double* rho_d, double p, double rho_min,
+                              const double* f_d, const double* u_d, double* energy_d, double* dc_d,
+                              double* compliance_h, void* stream);
+
+typedef struct {
+  int64_t n_solid;     /* elements with rho >= solid_min                      */
+  double rel_l2;       /* ||g1 - g0|| / ||g0|| over those elements             */
+  double pearson;      /* Pearson correlation of g0 and g1 over them (NaN if
+                          either is constant there)                           */
+  double norm0, norm1; /* ||g0||, ||g1|| over them                             */
+} tg_gradient_change_result;
+
+/* The gradient columns of Tab. perturbation: two sensitivity fields dc0_d
+ * (reference floor) and dc1_d (raised floor), n_elem doubles each, compared
+ * over the solid elements rho_d[e] >= solid_min (two FP64 passes: sums, then
+ * centred sums; fixed order).  TG_EINVAL if no element is solid.
+ * Synchronizes `stream`. */
+int tg_gradient_change(const tg_grid* g, const double* rho_d, double solid_min, const double* dc0_d,
+                       const double* dc1_d, tg_gradient_change_result* out, void* stream);
+
 /* ---- instrumentation ----------------------------------------------------- */
 /* Kernel-class timer (process-wide): for every class whose bit is set in the
  * mask given to tg_timer_enable (bit k = class k; 0 disables), each launch is
@@ -300,7 +335,8 @@ enum {
   TG_KT_UPDATE = 5,          /* vector updates (w -= V h, x += Z y, scaling)            */
   TG_KT_SCALAR = 6,          /* reductions and per-problem scalar kernels               */
   TG_KT_SETUP = 7,           /* set_density kernels                                     */
-  TG_KT_COUNT = 8
+  TG_KT_FIDELITY = 8,        /* compliance, sensitivities, gradient comparison          */
+  TG_KT_COUNT = 9
 };
 int tg_timer_enable(int mask);
 int tg_timer_reset(void);

@@ -68,5 +68,6 @@ def gradient_change(g0, g1, solid):
     b = np.asarray(g1, dtype=float)[solid]
     rel_l2 = float(np.linalg.norm(b - a) / np.linalg.norm(a))
     da, db = a - a.mean(), b - b.mean()
-    r = float(np.dot(da, db) / np.sqrt(np.dot(da, da) * np.dot(db, db)))
+    with np.errstate(invalid="ignore", divide="ignore"):   # NaN if either field is constant
+        r = float(np.dot(da, db) / np.sqrt(np.dot(da, da) * np.dot(db, db)))
     return {"n_solid": int(a.size), "rel_l2": rel_l2, "pearson": r}

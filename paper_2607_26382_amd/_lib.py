@@ -54,6 +54,11 @@ class Attempt(C.Structure):
                 ("true_eta", C.c_double)]
 
 
+class GradientChange(C.Structure):
+    _fields_ = [("n_solid", C.c_int64), ("rel_l2", C.c_double), ("pearson", C.c_double),
+                ("norm0", C.c_double), ("norm1", C.c_double)]
+
+
 class PolicyResult(C.Structure):
     _fields_ = [("rung", C.c_int), ("floor", C.c_double), ("k0", C.c_int), ("r50", C.c_double),
                 ("r100", C.c_double), ("probe_iters", C.c_int), ("n_attempts", C.c_int),
@@ -108,12 +113,14 @@ PROTOTYPES = {
     "tg_density_features": (_I, [_P, _P, _D, _D, C.POINTER(_D), _P]),
     "tg_batch_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
     "tg_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
+    "tg_compliance_sensitivity": (_I, [_P, _P, _D, _D, _P, _P, _P, _P, C.POINTER(_D), _P]),
+    "tg_gradient_change": (_I, [_P, _P, _D, _P, _P, C.POINTER(GradientChange), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),
     "tg_timer_read": (_I, [_I, C.POINTER(_D), C.POINTER(C.c_longlong), C.POINTER(_D)]),
     "tg_timer_name": (C.c_char_p, [_I]),
 }
-TG_KT_COUNT = 8
+TG_KT_COUNT = 9
 
 
 def header_symbols(path=HEADER):

@@ -88,7 +88,7 @@ void timer_harvest() {
 using namespace tg;
 
 static const char* kNames[TG_KT_COUNT] = {"apply_f64", "vcycle_fine_op", "vcycle_coarse_op", "transfer",
-                                          "multidot", "vector_update", "scalar", "setup"};
+                                          "multidot", "vector_update", "scalar", "setup", "fidelity"};
 
 extern "C" {
 int tg_timer_enable(int mask) {

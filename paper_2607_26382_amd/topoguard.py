@@ -171,6 +171,27 @@ class Grid:
         check(lib().tg_density_features(self.handle, _ptr(rho), float(p), float(rho0), out, _stream()))
         return list(out)
 
+    def compliance_sensitivity(self, u, f=None, rho=None, p=3.0, rho_min=1e-3, want_energy=False):
+        """dict(compliance=f^T u or None, dc=sensitivities or None, energy=u_e^T K_e u_e or None)
+        for a displacement u (device FP64).  dc needs rho, the compliance needs f."""
+        assert u.dtype == torch.float64 and u.is_cuda and u.numel() == self.n_dof
+        dc = torch.empty(self.n_elem, dtype=torch.float64, device=u.device) if rho is not None else None
+        en = torch.empty(self.n_elem, dtype=torch.float64, device=u.device) if want_energy else None
+        c = C.c_double()
+        check(lib().tg_compliance_sensitivity(
+            self.handle, _ptr(rho) if rho is not None else None, float(p), float(rho_min),
+            _ptr(f) if f is not None else None, _ptr(u), _ptr(en) if en is not None else None,
+            _ptr(dc) if dc is not None else None, C.byref(c) if f is not None else None, _stream()))
+        return {"compliance": c.value if f is not None else None, "dc": dc, "energy": en}
+
+    def gradient_change(self, rho, dc0, dc1, solid_min=0.5):
+        """Relative l2 change and Pearson r of dc1 against dc0 over rho >= solid_min."""
+        out = L.GradientChange()
+        check(lib().tg_gradient_change(self.handle, _ptr(rho), float(solid_min), _ptr(dc0), _ptr(dc1),
+                                       C.byref(out), _stream()))
+        return {"n_solid": out.n_solid, "rel_l2": out.rel_l2, "pearson": out.pearson,
+                "norm0": out.norm0, "norm1": out.norm1}
+
     def autotune(self, prec=F32, force=False):
         zc, us = (C.c_int * 8)(), (C.c_double * 8)()
         check(lib().tg_autotune(self.handle, prec, int(force), zc, us, _stream()))
