@@ -276,11 +276,76 @@ def apply_leg(tg, torch, dev, reps=40):
                      "launches_timed": kt["count"], "us_per_call_wall": t_wall * 1e6}
         log(f"apply_K {name}: {t*1e6:.1f} us, {alg / t / 1e9:.0f} GB/s")
         del us, ys
+    # compliance sensitivities and f^T u (FP64, one z-march): read u and f
+    # (3 DOF per node each) and one density per element, write one
+    # sensitivity per element; buffer sets rotate past the Infinity Cache
+    from paper_2607_26382_amd._lib import lib as _l
+    import ctypes as C
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    nsets = max(3, int(np.ceil(600e6 / (2 * g.n_dof * 8))))
+    sets = [(torch.randn(g.n_dof, dtype=torch.float64, device=dev),
+             torch.randn(g.n_dof, dtype=torch.float64, device=dev),
+             torch.empty(g.n_elem, dtype=torch.float64, device=dev)) for _ in range(nsets)]
+    comp = C.c_double()
+
+    def run_s(i):
+        u, f, dc = sets[i]
+        rc = _l().tg_compliance_sensitivity(g.handle, C.c_void_p(rho.data_ptr()), 3.0, 1e-3,
+                                            C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), None,
+                                            C.c_void_p(dc.data_ptr()), C.byref(comp), st)
+        if rc != 0:
+            raise RuntimeError(_l().tg_last_error().decode())
+    for i in range(nsets):
+        run_s(i)
+    tg.kernel_timer_enable(1 << 8)
+    tg.kernel_timer_reset()
+    for r in range(reps):
+        run_s(r % nsets)
+    kt = tg.kernel_timer_read()["fidelity"]
+    tg.kernel_timer_enable(0)
+    t = kt["avg_us"] * 1e-6
+    alg = 2 * g.n_dof * 8 + 2 * g.n_elem * 8
+    out["sensitivity_f64"] = {"us_per_call": t * 1e6, "alg_bytes": alg, "GB/s": alg / t / 1e9,
+                              "frac_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS, "buffer_sets": nsets,
+                              "launches_timed": kt["count"]}
+    log(f"compliance sensitivities f64: {t*1e6:.1f} us, {alg / t / 1e9:.0f} GB/s")
+    del sets
     out["grid"] = [nx, ny, nz]
     out["n_dof"] = g.n_dof
     del g
     torch.cuda.empty_cache()
     return out
+
+
+def fidelity_stats(grids, rhos, fs, sols, ok, rungs, p, solid_min=0.5):
+    """Tab. perturbation on the states whose original floor (rungs[0]) is
+    admissible: for every raised rung whose solve is also accepted, the
+    absolute relative compliance change and the relative l2 change and Pearson
+    correlation of the compliance sensitivities over the solid elements
+    (rho >= solid_min), all computed by the library's FP64 kernels."""
+    out = {}
+    base = {}
+    for i, g in enumerate(grids):
+        if ok[0][i]:
+            base[i] = g.compliance_sensitivity(sols[0][i], f=fs[i], rho=rhos[i], p=p, rho_min=rungs[0])
+    for k in range(1, len(rungs)):
+        dc, l2, r, decreases = [], [], [], 0
+        for i, b in base.items():
+            if not ok[k][i]:
+                continue
+            o = grids[i].compliance_sensitivity(sols[k][i], f=fs[i], rho=rhos[i], p=p, rho_min=rungs[k])
+            dc.append(abs(o["compliance"] - b["compliance"]) / abs(b["compliance"]))
+            decreases += o["compliance"] < b["compliance"]
+            gc = grids[i].gradient_change(rhos[i], b["dc"], o["dc"], solid_min)
+            l2.append(gc["rel_l2"])
+            r.append(gc["pearson"])
+        if dc:
+            out[f"{rungs[k]:g}"] = {"states": len(dc), "mean_abs_dC_over_C": float(np.mean(dc)),
+                                    "max_abs_dC_over_C": float(np.max(dc)), "compliance_decreases": int(decreases),
+                                    "mean_grad_rel_l2": float(np.mean(l2)), "max_grad_rel_l2": float(np.max(l2)),
+                                    "min_pearson": float(np.min(r))}
+    return {"reference_floor": rungs[0], "reference_admissible_states": len(base), "solid": f"rho >= {solid_min}",
+            "raised": out}
 
 
 B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
@@ -579,14 +644,18 @@ def main():
     # reference labels (untimed): independent guarded solves at every rung
     labels = None
     if not args.no_labels:
-        ok = []
+        ok, sols = [], []
         for r in RUNGS:
             batch.set_density(rhos, 3.0, [r] * n)
-            _, res = batch.solve(fs, tg.solver_opts(restart=30, max_iters=200, prec=mixed_prec,
-                                                    cgs_passes=args.cgs_passes))
+            us_r, res = batch.solve(fs, tg.solver_opts(restart=30, max_iters=200, prec=mixed_prec,
+                                                       cgs_passes=args.cgs_passes))
             ok.append([x["true_eta"] <= 1e-6 for x in res])
+            sols.append(us_r)
         labels = [next((k for k in range(len(RUNGS)) if ok[k][i]), -1) for i in range(n)]
         result["policy"]["stats"] = policy_stats(outs, labels)
+        # what a raised floor changes where the original one was admissible
+        result["fidelity"] = fidelity_stats(grids, rhos, fs, sols, ok, RUNGS, 3.0)
+        del sols
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)

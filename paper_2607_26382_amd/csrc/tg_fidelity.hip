@@ -3,15 +3,14 @@
 // (sensitivity expression of Sec. 3.1; Sec. 4.4.1, Tab. perturbation).
 //
 // k_energy_sens marches element columns in z like the operator kernels: a
-// workgroup owns 16 x 16 columns and a run of element layers, each thread
-// keeps the bottom face of its element in registers and loads only the new
-// top face per layer (coalesced along x, neighbouring columns share lines in
-// L1/L2).  Each face is taken into the per-component Walsh basis once; in
-// that basis the cube's element stiffness has eight distinct coefficients,
-// so u_e^T K_e u_e is a 30-term quadratic form instead of a 24 x 24
-// contraction.  The compliance f^T u rides along: every node is counted by
-// exactly one thread.  All sums use fixed orders, so results are bitwise
-// reproducible.
+// workgroup owns 16 x 16 columns and a run of element layers; each node
+// layer is loaded once (coalesced, one layer ahead) and staged in LDS, and
+// each thread keeps the bottom face of its element from the previous layer.
+// Faces are taken into the per-component Walsh basis once; in that basis the
+// cube's element stiffness has eight distinct coefficients, so u_e^T K_e u_e
+// is a 30-term quadratic form instead of a 24 x 24 contraction.  The
+// compliance f^T u rides along at staging, every node counted by exactly one
+// workgroup.  All sums use fixed orders, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -72,53 +71,107 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// energy[e] = u_e^T K_e u_e, dc[e] = coef rho_e^pm1 energy (coef = -p (1 -
-// rho_min), pm1 = p - 1) for the element layers [z0, z0 + zc) of this tile;
-// part[block] = this block's share of f^T u (f may be NULL).  Clamped nodes
-// (i = 0) read as zero.  Grid: (tiles, z chunks), 256 threads.
+// dc[e] = rho_e^pm1 for exponents that are not whole or half-whole (the
+// energy pass then scales it in place).
+__global__ __launch_bounds__(256) void k_rho_pow(const double* __restrict__ rho, double pm1, long long n,
+                                                 double* __restrict__ dc) {
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256)
+    dc[e] = pow(rho[e], pm1);
+}
+
+// energy[e] = u_e^T K_e u_e, dc[e] = coef rho_e^(p - 1) energy (coef = -p (1 -
+// rho_min)) for the element layers [z0, z0 + zc) of this tile; the power is
+// rho^ipm1 (times sqrt(rho) if half) as a product when ipm1 >= 0, else dc
+// already holds it (k_rho_pow); part[block] = this block's share of f^T u
+// (f may be NULL).
+// Clamped nodes (i = 0) read as zero.  Grid: (tiles, z chunks), 256 threads.
+//
+// Each node layer of the tile (17 x 17 nodes, rows contiguous in memory) is
+// loaded once, coalesced, two nodes per thread, one layer ahead of its use,
+// and staged in LDS; a thread reads its element's four top corners there and
+// keeps the bottom face, already in modes, from the previous layer.  The
+// staging thread of a node also adds its f.u when the tile owns the node
+// (x, y in the tile's half-open range, or the grid's last plane), once per
+// node layer.
 __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ u,
                                                      const double* __restrict__ f,
                                                      const double* __restrict__ rho, int nx, int ny,
-                                                     int nz, int zc, double coef, double pm1, EnCoef c,
-                                                     double* __restrict__ energy,
+                                                     int nz, int zc, double coef, int ipm1, int half,
+                                                     EnCoef c, double* __restrict__ energy,
                                                      double* __restrict__ dc,
                                                      double* __restrict__ part) {
+  constexpr int NT = EN_T + 1;            // nodes per tile edge
+  __shared__ double su[3][NT][NT];
   __shared__ double red[4];
   const int tx = threadIdx.x & (EN_T - 1), ty = threadIdx.x / EN_T;
   const int ntx = (nx + EN_T - 1) / EN_T;
-  const int ex = (int)(blockIdx.x % ntx) * EN_T + tx, ey = (int)(blockIdx.x / ntx) * EN_T + ty;
+  const int x0 = (int)(blockIdx.x % ntx) * EN_T, y0 = (int)(blockIdx.x / ntx) * EN_T;
+  const int ex = x0 + tx, ey = y0 + ty;
   const int z0 = (int)blockIdx.y * zc, z1 = min(nz, z0 + zc);
   const long long NX = nx + 1, NXY = (long long)(nx + 1) * (ny + 1);
+  const bool act = ex < nx && ey < ny;
+  // the two staged nodes of this thread: q = threadIdx.x + 256 s, (lx, ly)
+  int gn[2];                      // node index within a layer, -1 if none
+  bool ownq[2];
+#pragma unroll
+  for (int sI = 0; sI < 2; ++sI) {
+    const int q = threadIdx.x + 256 * sI, lx = q % NT, ly = q / NT;
+    const int i = x0 + lx, j = y0 + ly;
+    const bool in = q < NT * NT && i <= nx && j <= ny;
+    gn[sI] = (in && i > 0) ? (int)(i + NX * j) : -1;   // clamped nodes stay zero
+    ownq[sI] = in && (lx < EN_T || i == nx) && (ly < EN_T || j == ny);
+  }
   double fu = 0.0;
-  if (ex < nx && ey < ny) {
-    // corner (di, dj) of the faces is this thread's node for the compliance
-    // when no other column holds it as its corner (0, 0)
-    bool own[4];
+  double pv[2][3], pf[2][3];
+  auto fetch = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) own[q] = ((q & 1) == 0 || ex == nx - 1) && ((q >> 1) == 0 || ey == ny - 1);
-    auto load_face = [&](int k, double* X, double* Y, double* Z, bool count) {
+    for (int sI = 0; sI < 2; ++sI) {
+      const long long n = gn[sI] >= 0 ? gn[sI] + NXY * k : -1;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = ex + (q & 1);
-        const long long n = i + NX * (ey + (q >> 1)) + NXY * k;
-        if (i == 0) {
-          X[q] = Y[q] = Z[q] = 0.0;
-        } else {
-          X[q] = u[3 * n];
-          Y[q] = u[3 * n + 1];
-          Z[q] = u[3 * n + 2];
-          if (f && count && own[q]) fu += f[3 * n] * X[q] + f[3 * n + 1] * Y[q] + f[3 * n + 2] * Z[q];
-        }
+      for (int cI = 0; cI < 3; ++cI) {
+        pv[sI][cI] = n >= 0 ? u[3 * n + cI] : 0.0;
+        pf[sI][cI] = (f && n >= 0 && ownq[sI]) ? f[3 * n + cI] : 0.0;
       }
-      face_walsh(X);
-      face_walsh(Y);
-      face_walsh(Z);
-    };
-    double bx[4], by[4], bz[4];
-    load_face(z0, bx, by, bz, z0 == 0);
-    for (int k = z0; k < z1; ++k) {
-      double tx4[4], ty4[4], tz4[4];
-      load_face(k + 1, tx4, ty4, tz4, true);
+    }
+  };
+  auto stage = [&](bool count) {
+#pragma unroll
+    for (int sI = 0; sI < 2; ++sI) {
+      const int q = threadIdx.x + 256 * sI;
+      if (q < NT * NT) {
+#pragma unroll
+        for (int cI = 0; cI < 3; ++cI) su[cI][q / NT][q % NT] = pv[sI][cI];
+        if (count) fu += pf[sI][0] * pv[sI][0] + pf[sI][1] * pv[sI][1] + pf[sI][2] * pv[sI][2];
+      }
+    }
+  };
+  auto read_face = [&](double* X, double* Y, double* Z) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      X[q] = su[0][ty + (q >> 1)][tx + (q & 1)];
+      Y[q] = su[1][ty + (q >> 1)][tx + (q & 1)];
+      Z[q] = su[2][ty + (q >> 1)][tx + (q & 1)];
+    }
+    face_walsh(X);
+    face_walsh(Y);
+    face_walsh(Z);
+  };
+  double bx[4], by[4], bz[4];
+  fetch(z0);
+  stage(z0 == 0);
+  fetch(z0 + 1);
+  __syncthreads();
+  read_face(bx, by, bz);
+  for (int k = z0; k < z1; ++k) {
+    const long long ek = ex + (long long)nx * (ey + (long long)ny * k);
+    const double rk = (act && dc) ? (ipm1 >= 0 ? rho[ek] : dc[ek]) : 0.0;
+    __syncthreads();            // every read of the previous layer is done
+    stage(true);                // node layer k + 1
+    if (k + 1 < z1) fetch(k + 2);
+    __syncthreads();
+    double tx4[4], ty4[4], tz4[4];
+    read_face(tx4, ty4, tz4);
+    if (act) {
       double X[8], Y[8], Z[8];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -132,17 +185,25 @@ __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ 
       const double en = energy_form(X, Y, Z, c);
       const long long e = ex + (long long)nx * (ey + (long long)ny * k);
       if (energy) energy[e] = en;
-      if (dc) dc[e] = coef * pow(rho[e], pm1) * en;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bx[m] = tx4[m];
-        by[m] = ty4[m];
-        bz[m] = tz4[m];
+      if (dc) {
+        double rp = rk;
+        if (ipm1 >= 0) {
+          rp = 1.0;
+          for (int t = 0; t < ipm1; ++t) rp *= rk;
+          if (half) rp *= sqrt(rk);
+        }
+        dc[e] = coef * rp * en;
       }
     }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      bx[m] = tx4[m];
+      by[m] = ty4[m];
+      bz[m] = tz4[m];
+    }
   }
-  const double s = block_sum(fu, red);
-  if (part && threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  const double sum = block_sum(fu, red);
+  if (part && threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sum;
 }
 
 // Moments of two gradient fields over the elements with rho >= solid_min,
@@ -207,16 +268,28 @@ int tg_compliance_sensitivity(const tg_grid* g, const double* rho_d, double p, d
   const long long nblk = (long long)tiles * nzc;
   if (nblk > (long long)TG_PART_W * g->lv[0].n_chunks || nzc > 65535)
     return fail(TG_EINVAL, "grid too large for the partial-sum buffer");
+  // whole and half-whole exponents p - 1 <= 8 as products (times a square
+  // root), others by a separate power pass into dc
+  const double pm1 = p - 1.0;
+  const bool prod = pm1 >= 0 && pm1 <= 8 && 2 * pm1 == std::floor(2 * pm1);
+  const int ipm1 = prod ? (int)std::floor(pm1) : -1, half = prod && pm1 != std::floor(pm1);
   const ModeCoef<double>& m = g->mc64;
   const EnCoef c = {m.d, m.o, m.s, m.p, m.q, m.r, m.t, m.w};
   double* part = g->desc.part;
   const double nodes = (double)g->lv[0].n_nodes, elems = (double)nx * ny * nz;
   const double bytes = 24.0 * nodes * (1.0 + (compliance_h ? 1.0 : 0.0)) +
                        elems * ((dc_d ? 16.0 : 0.0) + (energy_d ? 8.0 : 0.0));
+  if (dc_d && !prod) {
+    const long long ne = (long long)nx * ny * nz;
+    void* tp = timer_begin(TG_KT_FIDELITY, s);
+    k_rho_pow<<<(int)std::min<long long>(4096, (ne + 255) / 256), 256, 0, s>>>(rho_d, pm1, ne, dc_d);
+    if (tp) timer_end(tp, 16.0 * (double)ne, s);
+    TG_HIP(hipGetLastError());
+  }
   void* th = timer_begin(TG_KT_FIDELITY, s);
   k_energy_sens<<<dim3((unsigned)tiles, (unsigned)nzc), 256, 0, s>>>(
-      u_d, compliance_h ? f_d : nullptr, rho_d, nx, ny, nz, zc, -p * (1.0 - rho_min), p - 1.0, c,
-      energy_d, dc_d, part);
+      u_d, compliance_h ? f_d : nullptr, dc_d ? rho_d : nullptr, nx, ny, nz, zc, -p * (1.0 - rho_min), ipm1,
+      half, c, energy_d, dc_d, part);
   if (th) timer_end(th, bytes, s);
   TG_HIP(hipGetLastError());
   if (compliance_h) {

@@ -48,7 +48,7 @@ def _check_energy_dc(og, u, rho, p, rmin, en, dc):
 
 CASES = [((1, 1, 1), 3.0, 1e-3), ((3, 2, 2), 4.5, 1e-9), ((16, 8, 8), 3.0, 1e-3), ((17, 9, 7), 3.0, 1e-6),
          ((24, 12, 12), 4.5, 1e-2), ((33, 17, 5), 3.0, 1e-3), ((16, 16, 40), 3.0, 1e-3),
-         ((130, 120, 41), 3.0, 1e-3)]
+         ((130, 120, 41), 3.0, 1e-3), ((9, 5, 3), 3.3, 1e-3), ((7, 20, 3), 1.0, 0.0)]
 
 
 @pytest.mark.parametrize("dims,p,rmin", CASES)
