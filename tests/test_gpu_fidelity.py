@@ -76,11 +76,12 @@ def test_outputs_are_optional_and_errors_are_reported():
     dims = (5, 3, 2)
     og = mesh.Grid(*dims)
     rng = np.random.default_rng(3)
-    u = _t(rng.standard_normal(og.n_dof))
+    un = rng.standard_normal(og.n_dof)
+    u = _t(un)
     g = tg.Grid(*dims, max_restart=4, device=DEV)
     only_c = g.compliance_sensitivity(u, f=u)
     assert only_c["dc"] is None and only_c["energy"] is None
-    assert only_c["compliance"] == pytest.approx(fd.compliance(og, u.cpu().numpy(), u.cpu().numpy()), rel=1e-13)
+    assert only_c["compliance"] == pytest.approx(fd.compliance(og, un, un), rel=1e-13)
     with pytest.raises(TopoguardError):
         g.compliance_sensitivity(u)                       # nothing requested
     with pytest.raises(TopoguardError):
