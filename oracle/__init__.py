@@ -26,6 +26,10 @@ What it computes (citations are to arXiv 2607.26382):
 * ``fidelity``   - compliance, element energies and the compliance sensitivity
                    of Sec. 3.1, and the raised-floor perturbation metrics of
                    Sec. 4.4.1 / Tab. perturbation.
+* ``topopt``     - linear-hat density filter and its adjoint, the smoothed
+                   Heaviside projection (Eq. projection) and the optimality-
+                   criteria step with volume bisection (Sec. 3.1, Eq.
+                   to_problem; Tab. trajectory-settings).
 
 Every function is pinned by tests under ``tests/`` against facts the paper or
 mathematics fix (closed forms, invariants, printed values, library routines on
