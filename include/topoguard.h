@@ -319,6 +319,90 @@ typedef struct {
 int tg_gradient_change(const tg_grid* g, const double* rho_d, double solid_min, const double* dc0_d,
                        const double* dc1_d, tg_gradient_change_result* out, void* stream);
 
+/* ---- the optimizer around the solve (Sec. 3.1 Eq. to_problem, Eq. projection;
+ *      Sec. 4.1.2; Tab. trajectory-settings) ------------------------------- */
+/* Element fields are n_elem doubles on the device (x fastest).  r_min is the
+ * linear-hat filter radius in element widths, 0 < r_min < 4: weights
+ * w_ej = max(0, r_min - |c_e - c_j|) over the elements j of the grid,
+ * normalized per element.  None of these calls synchronizes except
+ * tg_oc_update and tg_topopt_run. */
+/* xt_d = H x_d (the density filter). */
+int tg_density_filter(const tg_grid* g, const double* x_d, double r_min, double* xt_d, void* stream);
+/* y_d = H^T (a_d .* b_d) (b_d may be NULL: ones): the chain rule through the
+ * filter.  y_d must not alias a_d or b_d. */
+int tg_density_filter_adjoint(const tg_grid* g, const double* a_d, const double* b_d, double r_min, double* y_d,
+                              void* stream);
+/* xbar_d = project(H x_d) with the smoothed Heaviside of Eq. projection
+ * (beta > 0, 0 < eta < 1); xt_d (may be NULL) receives H x_d, dxbar_d (may be
+ * NULL) d xbar / d xt. */
+int tg_filter_project(const tg_grid* g, const double* x_d, double r_min, double beta, double eta, double* xt_d,
+                      double* xbar_d, double* dxbar_d, void* stream);
+/* One optimality-criteria step: x_new = clip(x sqrt(max(0, -dc) / (lam dv)),
+ * max(0, x - move), min(1, x + move)), with lam halving the bracket [0, 1e9]
+ * while (l2 - l1) / (l1 + l2) > 1e-9 (at most 200 halvings) so that the
+ * physical volume sum_e project(H x_new)_e meets volfrac * n_elem.  dc_d and
+ * dv_d are the gradients of the compliance and of that volume with respect
+ * to x.  lambda_h (may be NULL) receives the last multiplier.  Synchronizes
+ * `stream` once per halving; uses the grid's reduction scratch. */
+int tg_oc_update(const tg_grid* g, const double* x_d, const double* dc_d, const double* dv_d, double volfrac,
+                 double move, double r_min, double beta, double eta, double* x_new_d, double* lambda_h,
+                 void* stream);
+
+enum {
+  TG_LOOP_GUARDED = 0,  /* Alg. floor_policy at every outer iteration          */
+  TG_LOOP_REUSE = 1,    /* the previous iteration's accepted floor is solved
+                           first and kept if the guard accepts it; otherwise
+                           (and at the first iteration) the full policy runs  */
+  TG_LOOP_FIXED = 2     /* one fixed floor, no acceptance test (the paper's
+                           unguarded controls)                                */
+};
+
+typedef struct {
+  int max_iters, min_iters;  /* 40, 20                                         */
+  double tol;                /* stop after min_iters once max |x_new - x| < tol (0.01) */
+  double volfrac;            /* 0.30                                           */
+  double r_min, eta;         /* 1.5, 0.5                                       */
+  int n_stages;              /* continuation stages (1..4), stage q applies
+                                from outer iteration stages[q].first_iter on;
+                                stages[0].first_iter must be 1               */
+  struct {
+    int first_iter;
+    double p, beta, move;
+  } stages[4];               /* defaults: (1, 1.5, 1, 0.20), (16, 3.5, 4, 0.15) */
+  int mode;                  /* TG_LOOP_*                                      */
+  double fixed_floor;        /* TG_LOOP_FIXED                                  */
+  tg_policy policy;          /* rungs (default 1e-12, 1e-3, 1e-2), rule, solves;
+                                its p is replaced by the stage's p            */
+} tg_topopt_opts;
+
+typedef struct {
+  int iter;
+  double p, beta;
+  double compliance;         /* f^T u of the iteration's solve                 */
+  double volume;             /* mean physical density it solved with           */
+  double change;             /* max |x_new - x| of its OC step                 */
+  int rung;                  /* accepted rung (-1: fixed mode or none)         */
+  double floor;              /* floor of the solve used                        */
+  int probed;                /* the full policy (probe) ran                    */
+  int solve_iters;           /* FGMRES iterations of the iteration, all attempts */
+  double true_eta;           /* FP64 guard value of the solve used             */
+  int accepted;              /* 1 guard passed, 0 nothing admissible (the loop
+                                stops), -1 not tested (fixed mode)            */
+  double ms;                 /* wall time of the iteration                      */
+} tg_topopt_record;
+
+void tg_default_topopt(tg_topopt_opts* o);
+/* Device workspace of tg_topopt_run for this grid (7 element fields and one
+ * displacement vector, 256-byte aligned). */
+int tg_topopt_workspace_bytes(const tg_grid* g, size_t* bytes);
+/* Runs the loop from the design x_d (in: initial design, out: final design)
+ * with load f_d.  rec must hold max_iters records; *n_rec receives the number
+ * written.  The loop ends early after min_iters once the change is below tol,
+ * or (guarded modes) at an iteration where no floor is admissible (its record
+ * has accepted = 0).  Synchronizes `stream` repeatedly. */
+int tg_topopt_run(tg_grid* g, const double* f_d, const tg_topopt_opts* o, void* ws_d, size_t ws_bytes,
+                  double* x_d, tg_topopt_record* rec, int* n_rec, void* stream);
+
 /* ---- instrumentation ----------------------------------------------------- */
 /* Kernel-class timer (process-wide): for every class whose bit is set in the
  * mask given to tg_timer_enable (bit k = class k; 0 disables), each launch is

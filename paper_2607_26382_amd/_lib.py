@@ -15,6 +15,7 @@ TG_F64, TG_F32, TG_BF16MFMA, TG_BF16X3MFMA = 0, 1, 2, 3
 TG_PROJ_CONVERGED, TG_MAXIT, TG_BREAKDOWN, TG_NONFINITE = 0, 1, 2, 3
 TG_SELECT_RULE, TG_SELECT_MLP, TG_SELECT_FIXED = 0, 1, 2
 TG_MAX_RUNGS = 8
+TG_LOOP_GUARDED, TG_LOOP_REUSE, TG_LOOP_FIXED = 0, 1, 2
 
 
 class MgOpts(C.Structure):
@@ -57,6 +58,24 @@ class Attempt(C.Structure):
 class GradientChange(C.Structure):
     _fields_ = [("n_solid", C.c_int64), ("rel_l2", C.c_double), ("pearson", C.c_double),
                 ("norm0", C.c_double), ("norm1", C.c_double)]
+
+
+class Stage(C.Structure):
+    _fields_ = [("first_iter", C.c_int), ("p", C.c_double), ("beta", C.c_double), ("move", C.c_double)]
+
+
+class TopoptOpts(C.Structure):
+    _fields_ = [("max_iters", C.c_int), ("min_iters", C.c_int), ("tol", C.c_double),
+                ("volfrac", C.c_double), ("r_min", C.c_double), ("eta", C.c_double),
+                ("n_stages", C.c_int), ("stages", Stage * 4), ("mode", C.c_int),
+                ("fixed_floor", C.c_double), ("policy", Policy)]
+
+
+class TopoptRecord(C.Structure):
+    _fields_ = [("iter", C.c_int), ("p", C.c_double), ("beta", C.c_double), ("compliance", C.c_double),
+                ("volume", C.c_double), ("change", C.c_double), ("rung", C.c_int), ("floor", C.c_double),
+                ("probed", C.c_int), ("solve_iters", C.c_int), ("true_eta", C.c_double),
+                ("accepted", C.c_int), ("ms", C.c_double)]
 
 
 class PolicyResult(C.Structure):
@@ -115,6 +134,14 @@ PROTOTYPES = {
     "tg_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
     "tg_compliance_sensitivity": (_I, [_P, _P, _D, _D, _P, _P, _P, _P, C.POINTER(_D), _P]),
     "tg_gradient_change": (_I, [_P, _P, _D, _P, _P, C.POINTER(GradientChange), _P]),
+    "tg_density_filter": (_I, [_P, _P, _D, _P, _P]),
+    "tg_density_filter_adjoint": (_I, [_P, _P, _P, _D, _P, _P]),
+    "tg_filter_project": (_I, [_P, _P, _D, _D, _D, _P, _P, _P, _P]),
+    "tg_oc_update": (_I, [_P, _P, _P, _P, _D, _D, _D, _D, _D, _P, C.POINTER(_D), _P]),
+    "tg_default_topopt": (None, [C.POINTER(TopoptOpts)]),
+    "tg_topopt_workspace_bytes": (_I, [_P, C.POINTER(_SZ)]),
+    "tg_topopt_run": (_I, [_P, _P, C.POINTER(TopoptOpts), _P, _SZ, _P, C.POINTER(TopoptRecord),
+                           C.POINTER(_I), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),
     "tg_timer_read": (_I, [_I, C.POINTER(_D), C.POINTER(C.c_longlong), C.POINTER(_D)]),

@@ -192,6 +192,53 @@ class Grid:
         return {"n_solid": out.n_solid, "rel_l2": out.rel_l2, "pearson": out.pearson,
                 "norm0": out.norm0, "norm1": out.norm1}
 
+    # ---- the optimizer around the solve
+    def _efield(self, t):
+        assert t.dtype == torch.float64 and t.is_cuda and t.numel() == self.n_elem
+        return _ptr(t)
+
+    def density_filter(self, x, r_min=1.5):
+        y = torch.empty_like(x)
+        check(lib().tg_density_filter(self.handle, self._efield(x), float(r_min), _ptr(y), _stream()))
+        return y
+
+    def density_filter_adjoint(self, a, b=None, r_min=1.5):
+        y = torch.empty_like(a)
+        check(lib().tg_density_filter_adjoint(self.handle, self._efield(a),
+                                              self._efield(b) if b is not None else None, float(r_min),
+                                              _ptr(y), _stream()))
+        return y
+
+    def filter_project(self, x, r_min=1.5, beta=1.0, eta=0.5):
+        """(xt, xbar, dxbar) = (H x, project(H x), d project / d xt)."""
+        xt, xb, dx = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+        check(lib().tg_filter_project(self.handle, self._efield(x), float(r_min), float(beta), float(eta),
+                                      _ptr(xt), _ptr(xb), _ptr(dx), _stream()))
+        return xt, xb, dx
+
+    def oc_update(self, x, dc, dv, volfrac, move, r_min=1.5, beta=1.0, eta=0.5):
+        xn = torch.empty_like(x)
+        lam = C.c_double()
+        check(lib().tg_oc_update(self.handle, self._efield(x), self._efield(dc), self._efield(dv), float(volfrac),
+                                 float(move), float(r_min), float(beta), float(eta), _ptr(xn), C.byref(lam),
+                                 _stream()))
+        return xn, lam.value
+
+    def topopt_run(self, x0, f, opts):
+        """Runs the optimization loop from design x0 (copied); returns the
+        final design and one dict per outer iteration."""
+        nb = C.c_size_t()
+        check(lib().tg_topopt_workspace_bytes(self.handle, C.byref(nb)))
+        ws, wptr = _alloc_ws(nb.value, x0.device)
+        x = x0.clone()
+        rec = (L.TopoptRecord * opts.max_iters)()
+        n = C.c_int()
+        check(lib().tg_topopt_run(self.handle, _ptr(f), C.byref(opts), C.c_void_p(wptr), nb.value,
+                                  self._efield(x), rec, C.byref(n), _stream()))
+        del ws
+        keys = [k for k, _ in L.TopoptRecord._fields_]
+        return x, [{k: getattr(rec[i], k) for k in keys} for i in range(n.value)]
+
     def autotune(self, prec=F32, force=False):
         zc, us = (C.c_int * 8)(), (C.c_double * 8)()
         check(lib().tg_autotune(self.handle, prec, int(force), zc, us, _stream()))
@@ -257,6 +304,23 @@ class Batch:
 
 
 SELECT_RULE, SELECT_MLP, SELECT_FIXED = L.TG_SELECT_RULE, L.TG_SELECT_MLP, L.TG_SELECT_FIXED
+LOOP_GUARDED, LOOP_REUSE, LOOP_FIXED = L.TG_LOOP_GUARDED, L.TG_LOOP_REUSE, L.TG_LOOP_FIXED
+
+
+def topopt_opts(mode=LOOP_GUARDED, max_iters=40, min_iters=20, tol=0.01, volfrac=0.30, r_min=1.5,
+                stages=((1, 1.5, 1.0, 0.20), (16, 3.5, 4.0, 0.15)), fixed_floor=1e-3, policy=None):
+    """Loop options (defaults: Tab. trajectory-settings); policy defaults to
+    the library's with rungs 1e-12, 1e-3, 1e-2."""
+    o = L.TopoptOpts()
+    lib().tg_default_topopt(C.byref(o))
+    o.mode, o.max_iters, o.min_iters, o.tol = mode, max_iters, min_iters, tol
+    o.volfrac, o.r_min, o.fixed_floor = volfrac, r_min, fixed_floor
+    o.n_stages = len(stages)
+    for q, (it, p, beta, move) in enumerate(stages):
+        o.stages[q].first_iter, o.stages[q].p, o.stages[q].beta, o.stages[q].move = it, p, beta, move
+    if policy is not None:
+        o.policy = policy
+    return o
 N_PARAMS = 4996
 
 

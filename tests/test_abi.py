@@ -102,3 +102,16 @@ def test_default_structs():
     L.lib().tg_default_policy(C.byref(p))
     assert p.n_rungs == 4 and list(p.rungs[:4]) == [1e-9, 1e-6, 1e-4, 1e-3]
     assert (p.t_high, p.t_plateau, p.t_ratio, p.probe_iters) == (1e-2, 1e-4, 0.6, 100)
+
+
+def test_default_topopt_struct():
+    # Tab. trajectory-settings; the nested policy sits at the end of the struct,
+    # so a layout mismatch would garble it
+    o = L.TopoptOpts()
+    L.lib().tg_default_topopt(C.byref(o))
+    assert (o.max_iters, o.min_iters, o.tol, o.volfrac, o.r_min, o.eta) == (40, 20, 0.01, 0.30, 1.5, 0.5)
+    assert o.n_stages == 2 and o.mode == L.TG_LOOP_GUARDED
+    assert [(s.first_iter, s.p, s.beta, s.move) for s in o.stages[:2]] == [(1, 1.5, 1.0, 0.20), (16, 3.5, 4.0, 0.15)]
+    assert o.policy.n_rungs == 3 and list(o.policy.rungs[:3]) == [1e-12, 1e-3, 1e-2]
+    assert (o.policy.t_high, o.policy.probe_iters, o.policy.solve.restart) == (1e-2, 100, 30)
+    assert C.sizeof(L.TopoptRecord) == 96
