@@ -108,6 +108,9 @@ def parse():
                     help="skip the mixed-precision run with the two-feature rule")
     ap.add_argument("--no-labels", action="store_true",
                     help="skip the reference labels (independent solves at every rung) and the policy statistics")
+    ap.add_argument("--no-trajectory", action="store_true",
+                    help="skip the optimization-loop runs (guarded, decision reuse, fixed floors)")
+    ap.add_argument("--trajectory-only", action="store_true", help="run only the optimization-loop leg")
     ap.add_argument("--no-fixed-legs", action="store_true",
                     help="skip the fixed-first-rung baselines (original floor first; always the top rung)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -348,6 +351,50 @@ def fidelity_stats(grids, rhos, fs, sols, ok, rungs, p, solid_min=0.5):
             "raised": out}
 
 
+def trajectory_leg(tg, torch, dev, mixed_prec):
+    """The optimization-loop runs of Sec. 4.1.2 on the 64x32x32 cantilever
+    (volume fraction 0.30, filter radius 1.5, continuation p 1.5 -> 3.5,
+    beta 1 -> 4, move 0.20 -> 0.15 after outer iteration 15, 40 iterations,
+    rungs 1e-12, 1e-3, 1e-2): the guarded policy at every iteration, the
+    same with the previous decision reused until the guard rejects it, and
+    the unguarded fixed-floor controls 1e-12 and 1e-3.  Every run starts from
+    the uniform design; each is timed as a whole (wall clock, synchronized)."""
+    g = tg.Grid(64, 32, 32, max_restart=100, device=dev)
+    f = torch.tensor(g.edge_load(), device=dev)
+    x0 = torch.full((g.n_elem,), 0.30, dtype=torch.float64, device=dev)
+    out = {"grid": [64, 32, 32], "volfrac": 0.30, "r_min": 1.5, "outer_iters": 40,
+           "stages": [[1, 1.5, 1.0, 0.20], [16, 3.5, 4.0, 0.15]], "rungs": [1e-12, 1e-3, 1e-2],
+           "solve": "FGMRES(30), cap 200, split-BF16 V-cycle, FP64 guard"}
+    runs = (("guarded", tg.LOOP_GUARDED, None), ("guarded_reuse", tg.LOOP_REUSE, None),
+            ("fixed_1e-12_unguarded", tg.LOOP_FIXED, 1e-12), ("fixed_1e-3_unguarded", tg.LOOP_FIXED, 1e-3))
+    for name, mode, ff in runs:
+        o = tg.topopt_opts(mode=mode, fixed_floor=ff if ff else 1e-3)
+        o.policy.solve.prec = mixed_prec
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rec = g.topopt_run(x0, f, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = [r for r in rec if r["accepted"] == 1]
+        switch = next((r["iter"] for r in rec if r["rung"] > 0), None)
+        out[name] = {
+            "seconds": dt, "outer_iterations": len(rec), "fgmres_iterations": int(sum(r["solve_iters"] for r in rec)),
+            "probes": int(sum(r["probed"] for r in rec)), "final_compliance": rec[-1]["compliance"],
+            "compliance": [r["compliance"] for r in rec], "floors": [r["floor"] for r in rec],
+            "solve_iters": [r["solve_iters"] for r in rec], "true_eta": [r["true_eta"] for r in rec],
+            "first_raised_floor_iter": switch,
+            "accepted": len(acc), "max_accepted_true_eta": max((r["true_eta"] for r in acc), default=None),
+            "solves_at_cap": int(sum(1 for r in rec if mode == tg.LOOP_FIXED and r["solve_iters"] >= 200)),
+            "solves_above_tau": int(sum(1 for r in rec if r["true_eta"] > 1e-6)),
+        }
+        log(f"trajectory {name}: {dt:.1f} s, {len(rec)} outer its, final C {rec[-1]['compliance']:.4g}, "
+            f"first raised floor at {switch}")
+    out["reuse_speedup"] = out["guarded"]["seconds"] / out["guarded_reuse"]["seconds"]
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
 
 
@@ -526,6 +573,11 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
                           "copies": 4, "GB/s": 2 * a.numel() * 4 / dt / 1e9}), flush=True)
         return
+    if args.trajectory_only:
+        print(json.dumps({"trajectory": trajectory_leg(tg, torch, dev, {"f32": tg.F32, "bf16": tg.BF16MFMA,
+                                                                          "bf16x3": tg.BF16X3MFMA}[args.mixed])}),
+              flush=True)
+        return
     apply_res = None
     if not args.no_apply:
         apply_res = apply_leg(tg, torch, dev)
@@ -693,6 +745,10 @@ def main():
         batch = grids = None
         torch.cuda.empty_cache()
         result["batch_uneven"] = batch4_leg(tg, torch, dev, mixed_prec)
+    if not args.no_trajectory:
+        batch = grids = None
+        torch.cuda.empty_cache()
+        result["trajectory"] = trajectory_leg(tg, torch, dev, mixed_prec)
     if not args.no_cpu:
         setups = float(np.mean([1 + len(o["attempts"]) for o in outs]))
         iters = float(np.mean([o["iters_probe"] + o["iters_selected"] + o["iters_rejected"] for o in outs]))
