@@ -30,6 +30,8 @@ What it computes (citations are to arXiv 2607.26382):
                    Heaviside projection (Eq. projection) and the optimality-
                    criteria step with volume bisection (Sec. 3.1, Eq.
                    to_problem; Tab. trajectory-settings).
+* ``spectrum``   - extreme eigenvalues and condition number of K(rho_min) and
+                   the floor screen of Eq. screen (Sec. 4.2).
 
 Every function is pinned by tests under ``tests/`` against facts the paper or
 mathematics fix (closed forms, invariants, printed values, library routines on
