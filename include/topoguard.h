@@ -319,6 +319,29 @@ typedef struct {
 int tg_gradient_change(const tg_grid* g, const double* rho_d, double solid_min, const double* dc0_d,
                        const double* dc1_d, tg_gradient_change_result* out, void* stream);
 
+/* ---- conditioning (Sec. 4.2, Eq. screen) ------------------------------------ */
+typedef struct {
+  double lambda_min, lambda_max;  /* extreme eigenvalues of K(rho_min), free DOFs   */
+  double kappa;                   /* lambda_max / lambda_min                        */
+  double resid_min;               /* ||K x - lambda_min x|| / ||K x|| at the end     */
+  int iters_min, iters_max;       /* LOBPCG and Lanczos steps taken                 */
+  int converged;                  /* resid_min <= tol reached                        */
+} tg_spectrum_result;
+
+/* Device workspace of tg_extreme_eigenvalues (7 FP64 and 2 FP32 DOF vectors). */
+int tg_spectrum_workspace_bytes(const tg_grid* g, size_t* bytes);
+/* Extreme eigenvalues of the operator of the last set_density: lambda_max by
+ * Lanczos on K (at most max_iters steps, stopped when the largest Ritz value
+ * is stable to 1e-12), lambda_min by LOBPCG preconditioned by one V-cycle at
+ * precision prec per step, stopped when ||K x - lambda x|| <= tol ||K x|| or
+ * after max_iters steps (converged = 0; lambda_min is then an upper bound).
+ * Both start from a fixed hashed vector (deterministic).  The condition
+ * number gives the indicator kappa * eps and the screen c eps / tau with
+ * c = kappa * rho_min.  Synchronizes `stream` every step; uses the grid's
+ * reduction scratch.  TG_ESTATE before set_density. */
+int tg_extreme_eigenvalues(tg_grid* g, int prec, int max_iters, double tol, void* ws_d, size_t ws_bytes,
+                           tg_spectrum_result* out, void* stream);
+
 /* ---- the optimizer around the solve (Sec. 3.1 Eq. to_problem, Eq. projection;
  *      Sec. 4.1.2; Tab. trajectory-settings) ------------------------------- */
 /* Element fields are n_elem doubles on the device (x fastest).  r_min is the

@@ -60,6 +60,12 @@ class GradientChange(C.Structure):
                 ("norm0", C.c_double), ("norm1", C.c_double)]
 
 
+class SpectrumResult(C.Structure):
+    _fields_ = [("lambda_min", C.c_double), ("lambda_max", C.c_double), ("kappa", C.c_double),
+                ("resid_min", C.c_double), ("iters_min", C.c_int), ("iters_max", C.c_int),
+                ("converged", C.c_int)]
+
+
 class Stage(C.Structure):
     _fields_ = [("first_iter", C.c_int), ("p", C.c_double), ("beta", C.c_double), ("move", C.c_double)]
 
@@ -142,6 +148,8 @@ PROTOTYPES = {
     "tg_topopt_workspace_bytes": (_I, [_P, C.POINTER(_SZ)]),
     "tg_topopt_run": (_I, [_P, _P, C.POINTER(TopoptOpts), _P, _SZ, _P, C.POINTER(TopoptRecord),
                            C.POINTER(_I), _P]),
+    "tg_spectrum_workspace_bytes": (_I, [_P, C.POINTER(_SZ)]),
+    "tg_extreme_eigenvalues": (_I, [_P, _I, _I, _D, _P, _SZ, C.POINTER(SpectrumResult), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),
     "tg_timer_read": (_I, [_I, C.POINTER(_D), C.POINTER(C.c_longlong), C.POINTER(_D)]),

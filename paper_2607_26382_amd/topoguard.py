@@ -192,6 +192,18 @@ class Grid:
         return {"n_solid": out.n_solid, "rel_l2": out.rel_l2, "pearson": out.pearson,
                 "norm0": out.norm0, "norm1": out.norm1}
 
+    def extreme_eigenvalues(self, prec=F64, max_iters=300, tol=1e-8):
+        """dict(lambda_min, lambda_max, kappa, resid_min, iters_min, iters_max,
+        converged) of the operator of the last set_density."""
+        nb = C.c_size_t()
+        check(lib().tg_spectrum_workspace_bytes(self.handle, C.byref(nb)))
+        ws, wptr = _alloc_ws(nb.value, self.device)
+        out = L.SpectrumResult()
+        check(lib().tg_extreme_eigenvalues(self.handle, prec, int(max_iters), float(tol), C.c_void_p(wptr),
+                                           nb.value, C.byref(out), _stream()))
+        del ws
+        return {k: getattr(out, k) for k, _ in L.SpectrumResult._fields_}
+
     # ---- the optimizer around the solve
     def _efield(self, t):
         assert t.dtype == torch.float64 and t.is_cuda and t.numel() == self.n_elem
