@@ -320,6 +320,44 @@ def apply_leg(tg, torch, dev, reps=40):
     return out
 
 
+def screen_stats(tg, torch, grids, rhos, labels, rungs, p, prec, tau=1e-6):
+    """Sec. 4.2 on the solver's own operator: per state kappa of K(rho_0) from
+    the library's Lanczos / LOBPCG, c = kappa rho_0 and the screen
+    c eps / tau of Eq. screen, set against the lowest admissible rung of the
+    reference labels."""
+    eps = float(np.finfo(float).eps)
+    rows = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, rho, lab in zip(grids, rhos, labels):
+        g.set_density(rho, p, rungs[0])
+        r = g.extreme_eigenvalues(prec=prec, max_iters=600, tol=1e-6)
+        c = r["kappa"] * rungs[0]
+        rows.append(dict(c=c, screen=c * eps / tau, kappa=r["kappa"], conv=r["converged"], lab=lab,
+                         iters=r["iters_min"]))
+    dt = time.perf_counter() - t0
+    scr = np.array([x["screen"] for x in rows])
+    lab = [x["lab"] for x in rows]
+    adm = [x for x in rows if x["lab"] >= 0]
+    # the first rung at or above the screen, and whether it certifies
+    first = [next((k for k, fl in enumerate(rungs) if fl >= x["screen"]), None) for x in adm]
+    return {
+        "floor": rungs[0], "states": len(rows), "lobpcg_converged": int(sum(x["conv"] for x in rows)),
+        "seconds": dt, "mean_lobpcg_iters": float(np.mean([x["iters"] for x in rows])),
+        "kappa_eps_min": float(min(x["kappa"] for x in rows) * eps),
+        "kappa_eps_max": float(max(x["kappa"] for x in rows) * eps),
+        "c_min": float(min(x["c"] for x in rows)), "c_median": float(np.median([x["c"] for x in rows])),
+        "c_max": float(max(x["c"] for x in rows)),
+        "screen_min": float(scr.min()), "screen_max": float(scr.max()),
+        "admissible_states": len(adm),
+        "certified_below_screen": int(sum(1 for x in adm if rungs[x["lab"]] < x["screen"])),
+        "first_rung_above_screen_admissible": int(sum(1 for x, k in zip(adm, first)
+                                                      if k is not None and k >= x["lab"])),
+        "rungs_skipped_by_screen": int(sum(sum(1 for fl in rungs if fl < x["screen"]) for x in rows)),
+        "none_admissible": int(sum(1 for v in lab if v < 0)),
+    }
+
+
 def fidelity_stats(grids, rhos, fs, sols, ok, rungs, p, solid_min=0.5):
     """Tab. perturbation on the states whose original floor (rungs[0]) is
     admissible: for every raised rung whose solve is also accepted, the
@@ -708,6 +746,7 @@ def main():
         # what a raised floor changes where the original one was admissible
         result["fidelity"] = fidelity_stats(grids, rhos, fs, sols, ok, RUNGS, 3.0)
         del sols
+        result["screen"] = screen_stats(tg, torch, grids, rhos, labels, RUNGS, 3.0, mixed_prec)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)
