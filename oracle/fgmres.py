@@ -21,16 +21,33 @@ PROJ_CONVERGED, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 
 
 class Result:
-    def __init__(self, x, hist, outcome, iters):
+    def __init__(self, x, hist, outcome, iters, checkpoints=()):
         self.x = x
         self.hist = np.asarray(hist)
         self.outcome = outcome
         self.iters = iters
         self.proj_eta = float(self.hist[-1])
+        self.checkpoints = list(checkpoints)
 
 
-def fgmres(A, M, b, restart=30, max_iters=200, tol=1e-6, cgs_passes=2, breakdown=1e-14):
-    """A, M: callables on vectors.  Returns Result."""
+def _lsq(H, g, jdone):
+    """y = R^-1 g over the first jdone columns of the rotated Hessenberg."""
+    y = np.zeros(jdone)
+    for i in range(jdone - 1, -1, -1):
+        y[i] = (g[i] - H[i, i + 1:jdone] @ y[i + 1:jdone]) / H[i, i]
+    return y
+
+
+def fgmres(A, M, b, restart=30, max_iters=200, tol=1e-6, cgs_passes=2, breakdown=1e-14, checkpoint_every=0):
+    """A, M: callables on vectors.  Returns Result.
+
+    checkpoint_every > 0 records, after every such number of iterations, the
+    recomputed true residual ||b - A x_k|| / ||b|| of the current iterate
+    x_k = x + Z y_k (y_k the least-squares solution over the columns so far)
+    as (k, eta) in Result.checkpoints, without changing the iteration: the
+    periodic true-residual checkpoints of the probe that Sec. 4.1.1 leaves
+    untested."""
+    cps = []
     n = b.shape[0]
     bnorm = np.linalg.norm(b)
     x = np.zeros(n)
@@ -44,11 +61,11 @@ def fgmres(A, M, b, restart=30, max_iters=200, tol=1e-6, cgs_passes=2, breakdown
         if k > 0:
             hist[k] = beta / bnorm           # cycle-start true residual
         if not np.isfinite(beta):
-            return Result(x, hist, NONFINITE, k)
+            return Result(x, hist, NONFINITE, k, cps)
         if beta / bnorm <= tol:
-            return Result(x, hist, PROJ_CONVERGED, k)
+            return Result(x, hist, PROJ_CONVERGED, k, cps)
         if k >= max_iters:
-            return Result(x, hist, MAXIT, k)
+            return Result(x, hist, MAXIT, k, cps)
         m = restart
         V = np.zeros((m + 1, n))
         Z = np.zeros((m, n))
@@ -91,6 +108,9 @@ def fgmres(A, M, b, restart=30, max_iters=200, tol=1e-6, cgs_passes=2, breakdown
             jdone = j + 1
             est = abs(g[j + 1]) / bnorm
             hist.append(est)
+            if checkpoint_every and k % checkpoint_every == 0:
+                xk = x + Z[:jdone].T @ _lsq(H, g, jdone)
+                cps.append((k, float(np.linalg.norm(b - A(xk)) / bnorm)))
             if est <= tol:
                 stop = PROJ_CONVERGED
             elif hn <= breakdown * wnorm0:
@@ -101,9 +121,6 @@ def fgmres(A, M, b, restart=30, max_iters=200, tol=1e-6, cgs_passes=2, breakdown
                 break
             V[j + 1] = w / hn
         if jdone > 0:
-            y = np.zeros(jdone)
-            for i in range(jdone - 1, -1, -1):
-                y[i] = (g[i] - H[i, i + 1:jdone] @ y[i + 1:jdone]) / H[i, i]
-            x = x + Z[:jdone].T @ y
+            x = x + Z[:jdone].T @ _lsq(H, g, jdone)
         if stop is not None:
-            return Result(x, hist, stop, k)
+            return Result(x, hist, stop, k, cps)

@@ -79,3 +79,26 @@ def test_solution_approaches_direct_solve():
     u = op.solve_direct(H[0].K, f)
     res = fg.fgmres(lambda v: H[0].K @ v, lambda v: mg.vcycle(H, v), f, 30, 200, 1e-11)
     assert np.linalg.norm(res.x - u) <= 1e-7 * np.linalg.norm(u)
+
+
+def test_checkpoints_equal_the_projected_estimates():
+    """In exact arithmetic the projected estimate |g_{k+1}| / ||b|| is the
+    residual norm of the iterate x + Z y_k, so checkpoints of the true
+    residual repeat the history where the recurrence is accurate; at a
+    restart boundary the checkpoint is that cycle's recomputed residual.
+    The checkpoints change nothing in the iteration itself."""
+    g, E, K, b = _system(seed=2)
+    H = mg.build_hierarchy(g, E, ke.ke())
+    A = lambda v: H[0].K @ v
+    M = lambda v: mg.vcycle(H, v)
+    plain = fg.fgmres(A, M, b, restart=6, max_iters=18, tol=1e-12)
+    cp = fg.fgmres(A, M, b, restart=6, max_iters=18, tol=1e-12, checkpoint_every=3)
+    assert np.array_equal(plain.hist, cp.hist) and np.array_equal(plain.x, cp.x)
+    assert [k for k, _ in cp.checkpoints] == [3, 6, 9, 12, 15, 18][:len(cp.checkpoints)] and len(cp.checkpoints) >= 5
+    for k, eta in cp.checkpoints:
+        assert eta == pytest.approx(cp.hist[k], rel=1e-6)
+    # unpreconditioned GMRES on the small test matrix: the same identity
+    u = fg.fgmres(lambda v: K @ v, lambda v: v, b, restart=40, max_iters=40, tol=1e-14, checkpoint_every=5)
+    assert len(u.checkpoints) == 8
+    for k, eta in u.checkpoints:
+        assert eta == pytest.approx(u.hist[k], rel=1e-8)
