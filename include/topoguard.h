@@ -176,6 +176,18 @@ int tg_true_residual(const tg_grid* g, const double* f_d, const double* u_d,
 int tg_probe_features(tg_grid* g, const double* f_d, const tg_solver_opts* o, int iters,
                       double* r50_h, double* r100_h, int* k_stop_h, void* stream);
 
+/* The probe with periodic true-residual checkpoints (the detector variant
+ * Sec. 4.1.1 leaves untested): the same FGMRES as tg_probe_features, and
+ * after every `every` iterations the FP64 relative residual of the current
+ * iterate x_k = x_0 + Z_k y_k (y_k the least-squares solution over the
+ * columns so far) is recomputed without changing the iteration.  For the
+ * first min(cap, count) checkpoints: k_h[i] = k, true_h[i] = that residual,
+ * proj_h[i] = the history value at k (the projected estimate, or the
+ * cycle-start true residual at a restart boundary).  *n_h = number written.
+ * Not with o->graphs.  Synchronizes `stream`. */
+int tg_probe_checkpoints(tg_grid* g, const double* f_d, const tg_solver_opts* o, int iters, int every, int cap,
+                         int* k_h, double* proj_h, double* true_h, int* n_h, int* k_stop_h, void* stream);
+
 /* ---- policy (Alg. floor_policy) ------------------------------------------ */
 enum { TG_SELECT_RULE = 0, TG_SELECT_MLP = 1, TG_SELECT_FIXED = 2 };
 #define TG_MAX_RUNGS 8

@@ -116,6 +116,8 @@ PROTOTYPES = {
     "tg_true_residual": (_I, [_P, _P, _P, C.POINTER(_D), _P]),
     "tg_probe_features": (_I, [_P, _P, C.POINTER(SolverOpts), _I, C.POINTER(_D), C.POINTER(_D),
                                C.POINTER(_I), _P]),
+    "tg_probe_checkpoints": (_I, [_P, _P, C.POINTER(SolverOpts), _I, _I, _I, C.POINTER(_I), C.POINTER(_D),
+                                  C.POINTER(_D), C.POINTER(_I), C.POINTER(_I), _P]),
     "tg_default_policy": (None, [C.POINTER(Policy)]),
     "tg_select_floor": (_I, [_P, _P, _P, C.POINTER(Policy), _P, C.POINTER(PolicyResult), _P]),
     "tg_batch_create": (_I, [_I, C.POINTER(_P), C.POINTER(_P)]),

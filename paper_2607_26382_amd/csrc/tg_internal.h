@@ -248,7 +248,8 @@ int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s);
 int k_cycle_start(Batch* b, int k, int cap, double tol, hipStream_t s);
 int k_arnoldi(Batch* b, int j, int k, int cap, double tol, double brk, hipStream_t s);
 int k_lsq_update(Batch* b, int mmax, int jmax, hipStream_t s);
-int k_true_eta(Batch* b, hipStream_t s);       // small[SC_TRUE] from R and F dots
+// small[SC_TRUE] from R and F dots; to_status: also into the status gather
+int k_true_eta(Batch* b, hipStream_t s, bool to_status = true);
 int k_init_small(Batch* b, hipStream_t s);
 
 // kernel-class timer (tg_timer.hip)

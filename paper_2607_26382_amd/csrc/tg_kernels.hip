@@ -1237,7 +1237,7 @@ __global__ void k_true_eta_(const ProbDesc* __restrict__ probs, const int2* __re
   const double rr = P.small[o.tmp], ff = P.small[o.tmp + 1];
   const double eta = ff > 0.0 ? sqrt(rr / ff) : 0.0;
   P.small[o.scal + SC_TRUE] = eta;
-  out[wi.x] = eta;
+  if (out) out[wi.x] = eta;
 }
 
 // ===========================================================================
@@ -1581,9 +1581,10 @@ int k_lsq_update(Batch* b, int mmax, int jmax, hipStream_t s) {
              k_xupdate_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, o, slot_Z(mmax, 0)));
   return check_launch("lsq_update");
 }
-int k_true_eta(Batch* b, hipStream_t s) {
+int k_true_eta(Batch* b, hipStream_t s, bool to_status) {
   if (b->prob.n)
-    TG_TIMED(TG_KT_SCALAR, 0, k_true_eta_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), b->sc_d));
+    TG_TIMED(TG_KT_SCALAR, 0, k_true_eta_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b),
+                                                                        to_status ? b->sc_d : nullptr));
   return check_launch("true_eta");
 }
 int k_init_small(Batch* b, hipStream_t s) {

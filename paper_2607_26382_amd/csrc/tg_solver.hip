@@ -103,7 +103,42 @@ static int graph_step(Batch* b, F&& step, const tg_solver_opts* o, int j, hipStr
 
 // Right-preconditioned FGMRES on every problem in `which` (Sec. 3.5), x0 = 0,
 // rhs in slot S_F, solution in slot S_X, history in small + hist.
-int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s) {
+// Periodic true-residual checkpoints of a running FGMRES: after every
+// `every` iterations, ||f - K x_k|| / ||f|| in FP64 for the iterate
+// x_k = x + Z y_k of each problem that made iteration k (y_k: the least
+// squares over the columns so far).  x is saved in S_T and restored; S_R,
+// the dot scratch and y are free between steps and rewritten later, and the
+// value goes to small[SC_TRUE] only, so the iteration is unchanged.
+struct Checkpoints {
+  int every = 0;
+  std::vector<std::vector<std::pair<int, double>>> rec;   // per problem of the batch
+};
+
+static int checkpoint(Batch* b, const std::vector<int>& act, int mmax, int jmax, int k, Checkpoints* cp,
+                      hipStream_t s) {
+  int rc;
+  if ((rc = batch_set_active(b, act, s))) return rc;
+  if ((rc = k_copy0(b, S_X, S_T, s))) return rc;
+  if ((rc = k_lsq_update(b, mmax, jmax, s))) return rc;
+  if ((rc = k_residual64(b, S_F, S_X, S_R, s))) return rc;
+  if ((rc = k_multidot(b, 0, 0, S_R, 1, s))) return rc;
+  if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
+  if ((rc = k_multidot(b, 0, 0, S_F, 1, s))) return rc;
+  if ((rc = k_reduce(b, 1, 2, 1, -1, s))) return rc;
+  if ((rc = k_true_eta(b, s, false))) return rc;
+  if ((rc = k_copy0(b, S_T, S_X, s))) return rc;
+  std::vector<double> v(act.size());
+  for (size_t i = 0; i < act.size(); ++i) {
+    const tg_grid* g = b->grids[act[i]];
+    TG_HIP(hipMemcpyAsync(&v[i], g->desc.small + g->sl.scal + SC_TRUE, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  TG_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < act.size(); ++i) cp->rec[act[i]].push_back({k, v[i]});
+  return TG_OK;
+}
+
+int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s,
+                 Checkpoints* cp = nullptr) {
   const int m = o->restart, cap = o->max_iters;
   const int mmax = b->grids[0]->mmax;
   if (m < 1 || m > mmax) return fail(TG_EINVAL, "restart must be in [1, bound max_restart]");
@@ -113,6 +148,8 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
   if (o->prec < TG_F64 || o->prec > TG_BF16X3MFMA)
     return fail(TG_EINVAL, "unknown preconditioner precision");
   const double tol = o->tol, brk = o->breakdown;
+  if (cp && o->graphs) return fail(TG_EINVAL, "checkpoints are not taken under graph replay");
+  if (cp) cp->rec.assign(b->n, {});
   int rc = check_ready(b, which, true);
   if (rc) return rc;
   rc = batch_set_active(b, which, s);
@@ -166,6 +203,8 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
         }
         ++k;
         if ((rc = batch_read_status(b, s))) return rc;
+        if (cp && cp->every > 0 && k % cp->every == 0 && (rc = checkpoint(b, running, mmax, jmax, k, cp, s)))
+          return rc;
         std::vector<int> still;
         for (int i : running)
           if (b->sc_h[i] == TG_RUNNING) still.push_back(i);
@@ -195,6 +234,8 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
       if ((rc = k_scale_to(b, S_W, slot_V(j + 1), SC_INV, s))) return rc;
       ++k;
       if ((rc = batch_read_status(b, s))) return rc;
+      if (cp && cp->every > 0 && k % cp->every == 0 && (rc = checkpoint(b, running, mmax, jmax, k, cp, s)))
+        return rc;
       std::vector<int> still;
       for (int i : running)
         if (b->sc_h[i] == TG_RUNNING) still.push_back(i);
@@ -493,6 +534,38 @@ int tg_probe_features(tg_grid* g, const double* f_d, const tg_solver_opts* o, in
   std::vector<double> h(kstop + 1);
   if ((rc = read_hist(b, 0, kstop + 1, h.data(), s))) return rc;
   probe_feats(h.data(), kstop, r50_h, r100_h);
+  if (k_stop_h) *k_stop_h = kstop;
+  return TG_OK;
+}
+
+int tg_probe_checkpoints(tg_grid* g, const double* f_d, const tg_solver_opts* o, int iters, int every, int cap,
+                         int* k_h, double* proj_h, double* true_h, int* n_h, int* k_stop_h, void* stream) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!f_d || !o || !k_h || !proj_h || !true_h || !n_h) return fail(TG_EINVAL, "NULL argument");
+  if (every < 1 || cap < 0) return fail(TG_EINVAL, "need every >= 1 and cap >= 0");
+  Batch* b = g->self;
+  hipStream_t s = S(stream);
+  int rc = check_ready(b, {0});
+  if (rc) return rc;
+  tg_solver_opts po = *o;
+  po.max_iters = iters;
+  Checkpoints cp;
+  cp.every = every;
+  if ((rc = copy_in_batch(b, {0}, &f_d, S_F, s))) return rc;
+  if ((rc = fgmres_batch(b, {0}, &po, s, &cp))) return rc;
+  ScalRead sr;
+  if ((rc = read_scal(b, 0, sr, s))) return rc;
+  const int kstop = (int)sr.v[SC_ITERS];
+  std::vector<double> h(kstop + 1);
+  if ((rc = read_hist(b, 0, kstop + 1, h.data(), s))) return rc;
+  const auto& r = cp.rec[0];
+  const int n = std::min<int>(cap, (int)r.size());
+  for (int i = 0; i < n; ++i) {
+    k_h[i] = r[i].first;
+    true_h[i] = r[i].second;
+    proj_h[i] = r[i].first <= kstop ? h[r[i].first] : -1.0;
+  }
+  *n_h = n;
   if (k_stop_h) *k_stop_h = kstop;
   return TG_OK;
 }

@@ -165,6 +165,17 @@ class Grid:
                                       C.byref(r100), C.byref(ks), _stream()))
         return r50.value, r100.value, ks.value
 
+    def probe_checkpoints(self, f, iters=100, restart=100, every=10, prec=F64):
+        """The probe with true-residual checkpoints: (list of (k, projected,
+        true), k_stop)."""
+        o = solver_opts(restart=restart, max_iters=iters, prec=prec)
+        cap = iters // max(int(every), 1) + 1
+        ks, pj, tr = (C.c_int * cap)(), (C.c_double * cap)(), (C.c_double * cap)()
+        n, kst = C.c_int(), C.c_int()
+        check(lib().tg_probe_checkpoints(self.handle, _ptr(f), C.byref(o), iters, every, cap, ks, pj, tr,
+                                         C.byref(n), C.byref(kst), _stream()))
+        return [(ks[i], pj[i], tr[i]) for i in range(n.value)], kst.value
+
     def density_features(self, rho, p=3.0, rho0=1e-9):
         """Six density statistics of rho (device FP64) at probe floor rho0."""
         out = (C.c_double * 6)()
