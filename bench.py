@@ -358,6 +358,30 @@ def screen_stats(tg, torch, grids, rhos, labels, rungs, p, prec, tau=1e-6):
     }
 
 
+def checkpoint_stats(tg, torch, grids, rhos, fs, rungs, p, prec, every=10, t_high=1e-2, t_plateau=1e-4,
+                     t_ratio=0.6):
+    """The probe at rho_0 with true-residual checkpoints every `every`
+    iterations (Sec. 4.1.1's untested detector variant): the largest ratio of
+    recomputed to projected residual, and whether the two-feature rule (Eq.
+    trigger) decides differently on recomputed features r50, r100."""
+    ratios, flips, both, t0 = [], 0, 0, time.perf_counter()
+    rule = lambda a, b: a >= t_high or (b >= t_plateau and b / a >= t_ratio)
+    for g, rho, f in zip(grids, rhos, fs):
+        g.set_density(rho, p, rungs[0])
+        cps, kstop = g.probe_checkpoints(f, iters=100, restart=100, every=every, prec=prec)
+        ratios += [tr / pj for _, pj, tr in cps if pj > 0]
+        d = {k: (pj, tr) for k, pj, tr in cps}
+        if 50 in d and 100 in d:
+            both += 1
+            flips += rule(d[50][0], d[100][0]) != rule(d[50][1], d[100][1])
+    return {"floor": rungs[0], "every": every, "states": len(grids), "checkpoints": len(ratios),
+            "seconds": time.perf_counter() - t0,
+            "max_true_over_projected": float(max(ratios)) if ratios else None,
+            "min_true_over_projected": float(min(ratios)) if ratios else None,
+            "median_true_over_projected": float(np.median(ratios)) if ratios else None,
+            "states_with_50_and_100": both, "rule_decisions_changed": int(flips)}
+
+
 def fidelity_stats(grids, rhos, fs, sols, ok, rungs, p, solid_min=0.5):
     """Tab. perturbation on the states whose original floor (rungs[0]) is
     admissible: for every raised rung whose solve is also accepted, the
@@ -747,6 +771,7 @@ def main():
         result["fidelity"] = fidelity_stats(grids, rhos, fs, sols, ok, RUNGS, 3.0)
         del sols
         result["screen"] = screen_stats(tg, torch, grids, rhos, labels, RUNGS, 3.0, mixed_prec)
+        result["probe_checkpoints"] = checkpoint_stats(tg, torch, grids, rhos, fs, RUNGS, 3.0, mixed_prec)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)
