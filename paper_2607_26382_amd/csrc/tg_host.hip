@@ -186,7 +186,6 @@ static void grid_layout(tg_grid* g, Bump& bp, int mmax) {
     L.vec32 = bp.take<float>((size_t)C_NSLOTS * H.stride);
     if (l >= 1) {
       L.Kel64 = bp.take<double>((size_t)H.n_elem * 576);
-      L.Kel32 = bp.take<float>((size_t)H.n_elem * 576);
     }
     if (l > TG_MF_LEVELS) {
       L.Km64 = bp.take<double>((size_t)H.n_elem * TG_GM_STRIDE);

@@ -66,7 +66,6 @@ struct LevelDesc {
   double* vec64;
   float* vec32;
   double* Kel64;            // levels >= 1: 576 values per element (row-major 24x24)
-  float* Kel32;
   double* Km64;             // levels > TG_MF_LEVELS: the element matrix in the mode
   float* Km32;              // basis, TG_GM_NU values padded to TG_GM_STRIDE per element
   double* Dinv64;           // 9 values per node (3x3 inverse of the node block)

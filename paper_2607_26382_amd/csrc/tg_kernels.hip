@@ -119,16 +119,18 @@ __global__ __launch_bounds__(256) void k_galerkin1(const ProbDesc* __restrict__ 
 #pragma unroll
     for (int c = 0; c < 8; ++c) s += Ec[c] * P.G64[c * 576 + q];
     Lc.Kel64[C * 576 + q] = s;
-    Lc.Kel32[C * 576 + q] = (float)s;
   }
 }
 
 // Level l -> l+1 (l >= 1): Kel_{l+1}[C] = sum_c P_c^T Kel_l[child c] P_c.
+// Each P_c is a scalar trilinear weight matrix W_c (child node a, parent node
+// A) times I_3, so both products sum over the 8 nodes of a component, not
+// over 24 DOFs: T = Kel_child (W_c x I3), out += (W_c^T x I3) T.
 __global__ __launch_bounds__(256) void k_galerkin_up(const ProbDesc* __restrict__ probs,
                                                      const int2* __restrict__ work, int lc) {
   __shared__ double sK[576];
   __shared__ double sT[576];
-  __shared__ double Pc[576];
+  __shared__ double sW[64];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   const LevelDesc& Lf = P.lv[lc - 1];
@@ -141,35 +143,35 @@ __global__ __launch_bounds__(256) void k_galerkin_up(const ProbDesc* __restrict_
   for (int c = 0; c < 8; ++c) {
     const int fx = 2 * cx + (c & 1), fy = 2 * cy + ((c >> 1) & 1), fz = 2 * cz + ((c >> 2) & 1);
     const long long fe = fx + (long long)Lf.ex * (fy + (long long)Lf.ey * fz);
-    // child matrix and prolongation staged in LDS
-    for (int q = threadIdx.x; q < 576; q += 256) {
-      sK[q] = Lf.Kel64[fe * 576 + q];
-      Pc[q] = P.Pc64[c * 576 + q];
+    // child matrix and its node weights (the x-component entries of P_c)
+    for (int q = threadIdx.x; q < 576; q += 256) sK[q] = Lf.Kel64[fe * 576 + q];
+    if (threadIdx.x < 64) {
+      const int a = threadIdx.x >> 3, A = threadIdx.x & 7;
+      sW[threadIdx.x] = P.Pc64[c * 576 + (3 * a) * 24 + 3 * A];
     }
     __syncthreads();
-    // T = Kel_child * P_c   (24 x 24)
+    // T[r][3A + j] = sum_a Kel[r][3a + j] W[a][A]
     for (int q = threadIdx.x; q < 576; q += 256) {
-      const int r = q / 24, s = q % 24;
+      const int r = q / 24, col = q % 24, A = col / 3, j = col % 3;
       double t = 0.0;
-      for (int a = 0; a < 24; ++a) t += sK[r * 24 + a] * Pc[a * 24 + s];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) t += sK[r * 24 + 3 * a + j] * sW[a * 8 + A];
       sT[q] = t;
     }
     __syncthreads();
-    // out += P_c^T T
+    // out[3B + i][col] += sum_b W[b][B] T[3b + i][col]
     int qq = 0;
     for (int q = threadIdx.x; q < 576; q += 256, ++qq) {
-      const int r = q / 24, s = q % 24;
+      const int row = q / 24, col = q % 24, B = row / 3, i = row % 3;
       double t = 0.0;
-      for (int a = 0; a < 24; ++a) t += Pc[a * 24 + r] * sT[a * 24 + s];
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb) t += sW[bb * 8 + B] * sT[(3 * bb + i) * 24 + col];
       acc[qq] += t;
     }
     __syncthreads();
   }
   int qq = 0;
-  for (int q = threadIdx.x; q < 576; q += 256, ++qq) {
-    Lc.Kel64[C * 576 + q] = acc[qq];
-    Lc.Kel32[C * 576 + q] = (float)acc[qq];
-  }
+  for (int q = threadIdx.x; q < 576; q += 256, ++qq) Lc.Kel64[C * 576 + q] = acc[qq];
 }
 
 // Mode-basis form of the level-l Galerkin element matrices (l > TG_MF_LEVELS):
