@@ -36,9 +36,9 @@ sys.path.insert(0, ROOT)
 # the listed kernel definitions within a file), else the traffic is reported
 # as null.
 MEASURED_TRAFFIC = {
-    "vcycle_fine_op": {"bytes_per_launch": 192.9e6, "sources": {"tg_fine.hip": "89396403ba2d182e"},
+    "vcycle_fine_op": {"bytes_per_launch": 193.4e6, "sources": {"tg_fine.hip": "89396403ba2d182e"},
                        "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
-    "multidot": {"bytes_per_launch": 1818.3e6, "sources": {"tg_kernels.hip:k_dots2_": "413b15d1d0705f54"},
+    "multidot": {"bytes_per_launch": 1818.4e6, "sources": {"tg_kernels.hip:k_dots2_": "413b15d1d0705f54"},
                  "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
     "vector_update": {"bytes_per_launch": 1938.0e6, "sources": {"tg_kernels.hip:k_update2_": "e3884c42c4c540bf"},
                       "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
