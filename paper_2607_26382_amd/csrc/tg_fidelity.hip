@@ -262,8 +262,8 @@ int tg_compliance_sensitivity(const tg_grid* g, const double* rho_d, double p, d
   hipStream_t s = (hipStream_t)stream;
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int tiles = ((nx + EN_T - 1) / EN_T) * ((ny + EN_T - 1) / EN_T);
-  // enough z chunks for about 2048 workgroups; each chunk re-reads one face
-  const int want = std::max(1, std::min(nz, (2048 + tiles - 1) / tiles));
+  // enough z chunks for about 1024 workgroups; each chunk re-reads one face
+  const int want = std::max(1, std::min(nz, (1024 + tiles - 1) / tiles));
   const int zc = (nz + want - 1) / want, nzc = (nz + zc - 1) / zc;
   const long long nblk = (long long)tiles * nzc;
   if (nblk > (long long)TG_PART_W * g->lv[0].n_chunks || nzc > 65535)
