@@ -32,6 +32,9 @@ What it computes (citations are to arXiv 2607.26382):
                    to_problem; Tab. trajectory-settings).
 * ``spectrum``   - extreme eigenvalues and condition number of K(rho_min) and
                    the floor screen of Eq. screen (Sec. 4.2).
+* ``adaptive``   - the fine-level adaptive correction of the paper's
+                   preconditioner (Tab. solver-config): V-cycle, then inner
+                   GMRES(20) with node-block Jacobi, kept if it lowers ||r||.
 
 Every function is pinned by tests under ``tests/`` against facts the paper or
 mathematics fix (closed forms, invariants, printed values, library routines on
