@@ -110,6 +110,9 @@ def parse():
                     help="skip the reference labels (independent solves at every rung) and the policy statistics")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the optimization-loop runs (guarded, decision reuse, fixed floors)")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-preconditioner leg (fine-level correction)")
+    ap.add_argument("--adaptive-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--trajectory-only", action="store_true", help="run only the optimization-loop leg")
     ap.add_argument("--no-fixed-legs", action="store_true",
                     help="skip the fixed-first-rung baselines (original floor first; always the top rung)")
@@ -457,6 +460,44 @@ def trajectory_leg(tg, torch, dev, mixed_prec):
     return out
 
 
+def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=12, floor=1e-9):
+    """The fine-level adaptive correction of the preconditioner (Tab.
+    solver-config) on the first n_states severe states at the original floor:
+    FGMRES(30), cap 200, V-cycle at `prec`, with the correction (20 inner
+    node-block-Jacobi GMRES steps, kept only if they lower the residual) and
+    without it.  Per variant: outer iterations, certified solves (FP64 guard
+    <= 1e-6), solves whose projected estimate converged while the guard
+    rejects them, kept corrections, seconds per solve (synchronized wall
+    clock of the solve alone)."""
+    g = tg.Grid(*GRID, max_restart=30, device=dev)
+    out = {"states": n_states, "floor": floor, "solve": "FGMRES(30), cap 200, FP64 operator and guard",
+           "inner_steps": 20}
+    for name, inner in (("adaptive", 20), ("plain_vcycle", 0)):
+        its, cert, false_acc, kept, applied, secs, etas = 0, 0, 0, 0, 0, 0.0, []
+        for i in range(n_states):
+            g.set_density(rhos[i], 3.0, floor)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, res, hist, acc = g.adaptive_solve(fs[i], tg.solver_opts(restart=30, max_iters=200, prec=prec), inner)
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            eta = g.true_residual(fs[i], u)
+            etas.append(eta)
+            its += res["iterations"]
+            cert += eta <= 1e-6
+            false_acc += res["outcome"] == "PROJ_CONVERGED" and eta > 1e-6
+            kept += sum(acc)
+            applied += len(acc)
+        out[name] = {"mean_iters": its / n_states, "certified": int(cert), "proj_converged_guard_rejects": int(false_acc),
+                     "corrections_kept": int(kept), "preconditioner_applications": int(applied),
+                     "seconds_per_solve": secs / n_states, "true_eta": etas}
+        log(f"adaptive leg {name}: mean its {its / n_states:.1f}, certified {cert}/{n_states}, "
+            f"false acceptances caught {false_acc}, {secs / n_states:.3f} s/solve")
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
 
 
@@ -640,6 +681,14 @@ def main():
                                                                           "bf16x3": tg.BF16X3MFMA}[args.mixed])}),
               flush=True)
         return
+    if args.adaptive_only:
+        n_ad = min(args.states, 12)
+        rhos = [torch.tensor(synth.severe(SEED0 + i)[1], device=dev) for i in range(n_ad)]
+        f0 = torch.tensor(tg.Grid(*GRID, max_restart=1, device=dev).edge_load(), device=dev)
+        print(json.dumps({"adaptive_preconditioner": adaptive_leg(
+            tg, torch, dev, rhos, [f0] * n_ad, {"f32": tg.F32, "bf16": tg.BF16MFMA, "bf16x3": tg.BF16X3MFMA}[args.mixed],
+            n_states=n_ad)}), flush=True)
+        return
     apply_res = None
     if not args.no_apply:
         apply_res = apply_leg(tg, torch, dev)
@@ -772,6 +821,8 @@ def main():
         del sols
         result["screen"] = screen_stats(tg, torch, grids, rhos, labels, RUNGS, 3.0, mixed_prec)
         result["probe_checkpoints"] = checkpoint_stats(tg, torch, grids, rhos, fs, RUNGS, 3.0, mixed_prec)
+    if not args.no_adaptive:
+        result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)

@@ -188,6 +188,39 @@ int tg_probe_features(tg_grid* g, const double* f_d, const tg_solver_opts* o, in
 int tg_probe_checkpoints(tg_grid* g, const double* f_d, const tg_solver_opts* o, int iters, int every, int cap,
                          int* k_h, double* proj_h, double* true_h, int* n_h, int* k_stop_h, void* stream);
 
+/* ---- adaptive preconditioner (Tab. solver-config, fine-level correction) -- */
+/* One application z = M(v): one V-cycle at precision `prec` (z = V(v)), then
+ * the fine-level correction: with s = v - K z, `inner_steps` steps of
+ * right-preconditioned GMRES (restart = inner_steps, CGS2, no tolerance stop)
+ * on K d = s from d = 0, preconditioned by the 3 x 3 node-block Jacobi
+ * operator (the inverses of K's diagonal node blocks); z + d replaces z only
+ * if ||s - K d||_2 < ||s||_2.  inner_steps = 0 is the plain V-cycle.  K is
+ * the FP64 operator in every precision.  The outer method must be flexible
+ * (Sec. 3.5): M is nonlinear in v.
+ * Single grid, host-orchestrated (every Arnoldi step reads its column back),
+ * FP64 vectors of n_dof entries (device), clamped DOFs read as 0 and written
+ * as 0.  The caller allocates the workspace (tg_adaptive_workspace_bytes with
+ * the outer restart, 0 for tg_adaptive_precondition) and keeps ownership.
+ * Errors: TG_ESTATE before tg_set_density, TG_EINVAL for a NULL vector, a
+ * precision outside TG_F64..TG_BF16X3MFMA or restart / inner_steps outside
+ * [0, TG_AD_MAX_RESTART], TG_EWORKSPACE for a short workspace.  Both calls
+ * synchronize `stream`. */
+#define TG_AD_MAX_RESTART 256
+int tg_adaptive_workspace_bytes(const tg_grid* g, int restart, int inner_steps, size_t* bytes);
+/* *accepted_h (may be NULL) = 1 if the correction was kept. */
+int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int prec, int inner_steps, void* ws_d,
+                             size_t ws_bytes, int* accepted_h, void* stream);
+/* FGMRES (o->restart >= 1, o->max_iters, o->tol, o->breakdown; cgs_passes 1
+ * = CGS, otherwise CGS2 in place; o->graphs ignored) preconditioned by M,
+ * with the history semantics of tg_fgmres_solve: hist_h (may be NULL, room
+ * for max_iters + 1) receives iterations + 1 values.  accepted_h (may be NULL,
+ * room for max_iters + 1) receives, per application of M in order, 1 if its
+ * correction was kept; *n_applied_h (may be NULL) = the number of
+ * applications.  x0 = 0; res->true_eta = -1 (the guard is tg_true_residual). */
+int tg_adaptive_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
+                      void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, int* accepted_h,
+                      int* n_applied_h, void* stream);
+
 /* ---- policy (Alg. floor_policy) ------------------------------------------ */
 enum { TG_SELECT_RULE = 0, TG_SELECT_MLP = 1, TG_SELECT_FIXED = 2 };
 #define TG_MAX_RUNGS 8

@@ -151,6 +151,10 @@ PROTOTYPES = {
     "tg_topopt_run": (_I, [_P, _P, C.POINTER(TopoptOpts), _P, _SZ, _P, C.POINTER(TopoptRecord),
                            C.POINTER(_I), _P]),
     "tg_spectrum_workspace_bytes": (_I, [_P, C.POINTER(_SZ)]),
+    "tg_adaptive_workspace_bytes": (_I, [_P, _I, _I, C.POINTER(_SZ)]),
+    "tg_adaptive_precondition": (_I, [_P, _P, _P, _I, _I, _P, _SZ, C.POINTER(_I), _P]),
+    "tg_adaptive_solve": (_I, [_P, _P, _P, C.POINTER(SolverOpts), _I, _P, _SZ, C.POINTER(SolveResult),
+                               C.POINTER(_D), C.POINTER(_I), C.POINTER(_I), _P]),
     "tg_extreme_eigenvalues": (_I, [_P, _I, _I, _D, _P, _SZ, C.POINTER(SpectrumResult), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),
@@ -158,6 +162,7 @@ PROTOTYPES = {
     "tg_timer_name": (C.c_char_p, [_I]),
 }
 TG_KT_COUNT = 9
+TG_AD_MAX_RESTART = 256
 
 
 def header_symbols(path=HEADER):

@@ -1,0 +1,463 @@
+// The fine-level adaptive correction of the paper's preconditioner (Tab.
+// solver-config) and the flexible GMRES around it (Sec. 3.5).
+//
+// One application z = M(v): z = V-cycle(v); with s = v - K z, an inner
+// right-preconditioned GMRES (restart = steps = q, stopping only on breakdown
+// or a non-finite value) solves K d = s from d = 0 with the 3 x 3 node-block
+// Jacobi operator as its preconditioner; z + d replaces z only if
+// ||s - K d|| < ||s||.  M depends on v nonlinearly (the accept test, the inner
+// Krylov polynomial), so the outer method stores the preconditioned vectors
+// Z and forms x = x0 + Z y (flexible GMRES, Saad 1993).
+//
+// The path is single-grid and host-orchestrated: every Arnoldi step reads its
+// Hessenberg column back to the host (the accept decision needs two norms on
+// the host anyway).  K is the library's FP64 operator, the V-cycle runs at the
+// requested precision (FP32 forms through float copies), the node-block
+// inverses are the smoother's.  Sums run in a fixed order (block partials,
+// then one wavefront per sum), so results are reproducible run to run.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "tg_internal.h"
+
+namespace tg {
+namespace {
+
+constexpr int AD_BLOCK = 256;
+constexpr int AD_QG = 8;            // basis vectors per workgroup of the multi-dot
+constexpr int AD_MAXB = 1024;       // workgroups of the vector kernels
+constexpr int AD_MAXV = TG_AD_MAX_RESTART + 1;
+
+int nblk(long long n) { return (int)std::max<long long>(1, std::min<long long>(AD_MAXB, (n + AD_BLOCK - 1) / AD_BLOCK)); }
+// multi-dot workgroups: at least four elements per thread, so the partials
+// stay few (one wavefront sums them)
+int nblk_dots(long long n) {
+  return (int)std::max<long long>(1, std::min<long long>(AD_MAXB, (n + 4 * AD_BLOCK - 1) / (4 * AD_BLOCK)));
+}
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+long long ld_of(long long n) { return (n + 31) & ~31LL; }   // doubles per basis vector (256-byte rows)
+
+// part[q * gridDim.x + block] = sum over the block's strided range of V_q[i] w[i]
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_dots(const double* __restrict__ V, long long ld, int nv,
+                                                      const double* __restrict__ w, long long n,
+                                                      double* __restrict__ part) {
+  __shared__ double red[AD_BLOCK / 64][AD_QG];
+  const int q0 = blockIdx.y * AD_QG;
+  double acc[AD_QG];
+#pragma unroll
+  for (int t = 0; t < AD_QG; ++t) acc[t] = 0.0;
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK) {
+    const double wi = w[i];
+#pragma unroll
+    for (int t = 0; t < AD_QG; ++t)
+      if (q0 + t < nv) acc[t] += V[(long long)(q0 + t) * ld + i] * wi;
+  }
+#pragma unroll
+  for (int t = 0; t < AD_QG; ++t) {
+    double s = acc[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][t] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < AD_QG && q0 + (int)threadIdx.x < nv) {
+    double s = 0.0;
+    for (int w8 = 0; w8 < AD_BLOCK / 64; ++w8) s += red[w8][threadIdx.x];
+    part[(long long)(q0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out[q] = sum_b part[q nb + b], one wavefront per q (lane-strided partial
+// sums, then a butterfly; a fixed order for a given block count); h[q] =
+// out[q] (acc = 0) or h[q] + out[q] (acc = 1)
+__global__ __launch_bounds__(64) void k_ad_sum(const double* __restrict__ part, int nb, int nv,
+                                               double* __restrict__ out, double* __restrict__ h, int acc) {
+  const int q = blockIdx.x;
+  if (q >= nv) return;
+  double s = 0.0;
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nb; b += 64) s += part[(long long)q * nb + b];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) {
+    out[q] = s;
+    if (h) h[q] = acc ? h[q] + s : s;
+  }
+}
+
+// w += sgn * sum_q c[q] V_q
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_update(const double* __restrict__ V, long long ld, int nv,
+                                                        const double* __restrict__ c, double sgn,
+                                                        double* __restrict__ w, long long n) {
+  __shared__ double sc[AD_MAXV];
+  for (int q = threadIdx.x; q < nv; q += AD_BLOCK) sc[q] = c[q];
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK) {
+    double s = 0.0;
+    for (int q = 0; q < nv; ++q) s += sc[q] * V[(long long)q * ld + i];
+    w[i] += sgn * s;
+  }
+}
+
+// out = a x + b y (y may be NULL: out = a x); out may alias x or y
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_axpby(double a, const double* x, double b, const double* y,
+                                                       double* out, long long n) {
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+// z = D^-1 r node by node (D the 3 x 3 diagonal block of K at the node); the
+// clamped x = 0 nodes get 0
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_jacobi(const double* __restrict__ Dinv, const double* __restrict__ r,
+                                                        double* __restrict__ z, long long n_nodes, int NX) {
+  for (long long v = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; v < n_nodes;
+       v += (long long)gridDim.x * AD_BLOCK) {
+    const double r0 = r[3 * v], r1 = r[3 * v + 1], r2 = r[3 * v + 2];
+    const double* D = Dinv + 9 * v;
+    const bool fixed = (v % NX) == 0;
+    z[3 * v] = fixed ? 0.0 : D[0] * r0 + D[1] * r1 + D[2] * r2;
+    z[3 * v + 1] = fixed ? 0.0 : D[3] * r0 + D[4] * r1 + D[5] * r2;
+    z[3 * v + 2] = fixed ? 0.0 : D[6] * r0 + D[7] * r1 + D[8] * r2;
+  }
+}
+
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_to32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    b[i] = (float)a[i];
+}
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_to64(const float* __restrict__ a, double* __restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    b[i] = (double)a[i];
+}
+
+// Workspace of one call: outer basis (m + 1) + m vectors, inner basis
+// (q + 1) + q vectors, five work vectors, two float vectors, partials and
+// small device arrays.
+struct Layout {
+  long long n = 0, ld = 0;
+  int m = 0, q = 0, nb = 0;
+  size_t oV = 0, oZ = 0, iV = 0, iZ = 0, wv = 0, f32 = 0, part = 0, small = 0, total = 0;
+  void init(const tg_grid* g, int restart, int inner) {
+    n = g->lv[0].n_dof;
+    ld = ld_of(n);
+    m = restart;
+    q = inner;
+    nb = nblk_dots(n);
+    const size_t vb = (size_t)ld * sizeof(double);
+    size_t o = 0;
+    oV = o; o += (size_t)(m > 0 ? m + 1 : 0) * vb;
+    oZ = o; o += (size_t)m * vb;
+    iV = o; o += (size_t)(q > 0 ? q + 1 : 0) * vb;
+    iZ = o; o += (size_t)q * vb;
+    wv = o; o += 5 * vb;
+    f32 = o; o += 2 * al((size_t)n * sizeof(float));
+    part = o; o += al((size_t)nb * AD_MAXV * sizeof(double));
+    small = o; o += al(4 * AD_MAXV * sizeof(double));
+    total = o;
+  }
+};
+
+struct Ctx {
+  tg_grid* g;
+  hipStream_t s;
+  int prec;
+  Layout L;
+  char* base;
+  double* vec(size_t off, int j) const { return (double*)(base + off) + (long long)j * L.ld; }
+  double* W(int i) const { return vec(L.wv, i); }   // 0: w, 1: r/s, 2: t, 3: d, 4: s kept
+  float* r32() const { return (float*)(base + L.f32); }
+  float* z32() const { return (float*)(base + L.f32 + al((size_t)L.n * sizeof(float))); }
+  double* part() const { return (double*)(base + L.part); }
+  double* tmp() const { return (double*)(base + L.small); }
+  double* h() const { return tmp() + AD_MAXV; }
+  double* coef() const { return tmp() + 2 * AD_MAXV; }
+  double* scal() const { return tmp() + 3 * AD_MAXV; }   // ||w||^2 before and after orthogonalization
+  std::vector<int> accepted;
+};
+
+// out (default tmp) = V^T w over nv basis vectors; h = out or h += out (h
+// may be NULL)
+int dots(Ctx& c, const double* V, int nv, const double* w, double* h, int acc, double* out = nullptr) {
+  dim3 grid(c.L.nb, (nv + AD_QG - 1) / AD_QG);
+  k_ad_dots<<<grid, AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, w, c.L.n, c.part());
+  TG_HIP(hipGetLastError());
+  k_ad_sum<<<nv, 64, 0, c.s>>>(c.part(), c.L.nb, nv, out ? out : c.tmp(), h, acc);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int norm(Ctx& c, const double* w, double* out) {
+  int rc = dots(c, w, 1, w, nullptr, 0);
+  if (rc) return rc;
+  double v = 0.0;
+  TG_HIP(hipMemcpyAsync(&v, c.tmp(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  TG_HIP(hipStreamSynchronize(c.s));
+  *out = std::sqrt(v);
+  return TG_OK;
+}
+
+int axpby(Ctx& c, double a, const double* x, double b, const double* y, double* out) {
+  k_ad_axpby<<<nblk(c.L.n), AD_BLOCK, 0, c.s>>>(a, x, b, y, out, c.L.n);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int update(Ctx& c, const double* V, int nv, const double* coef_d, double sgn, double* w) {
+  k_ad_update<<<nblk(c.L.n), AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, coef_d, sgn, w, c.L.n);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int applyK(Ctx& c, const double* x, double* y) { return tg_apply_K(c.g, x, y, TG_F64, c.s); }
+
+int jacobi(Ctx& c, const double* r, double* z) {
+  k_ad_jacobi<<<nblk(c.g->lv[0].n_nodes), AD_BLOCK, 0, c.s>>>(c.g->desc.lv[0].Dinv64, r, z, c.g->lv[0].n_nodes,
+                                                             c.g->nx + 1);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int vcycle(Ctx& c, const double* r, double* z) {
+  if (c.prec == TG_F64) return tg_vcycle(c.g, r, z, TG_F64, c.s);
+  k_ad_to32<<<nblk(c.L.n), AD_BLOCK, 0, c.s>>>(r, c.r32(), c.L.n);
+  TG_HIP(hipGetLastError());
+  const int rc = tg_vcycle(c.g, c.r32(), c.z32(), c.prec, c.s);
+  if (rc) return rc;
+  k_ad_to64<<<nblk(c.L.n), AD_BLOCK, 0, c.s>>>(c.z32(), z, c.L.n);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+struct Krylov {
+  double* V;
+  double* Z;
+  int m;
+};
+
+struct Outcome {
+  std::vector<double> hist;
+  int outcome = TG_PROJ_CONVERGED;
+  int iters = 0;
+};
+
+// y = R^-1 g over the first jdone columns of the rotated Hessenberg
+std::vector<double> lsq(const std::vector<double>& H, int ldh, const std::vector<double>& g, int jdone) {
+  std::vector<double> y(jdone, 0.0);
+  for (int i = jdone - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int k = i + 1; k < jdone; ++k) s -= H[i + (size_t)ldh * k] * y[k];
+    y[i] = s / H[i + (size_t)ldh * i];
+  }
+  return y;
+}
+
+// Right-preconditioned flexible GMRES on K x = b from x = 0 (Sec. 3.5) with
+// the history semantics of the library's solver: hist[0] = 1, the true
+// residual at every restart, the Givens estimate |g_{j+1}| / ||b|| inside a
+// cycle; stop on estimate <= tol, breakdown, the iteration cap or a
+// non-finite value.  CGS with `passes` sweeps (2 = CGS2 in place).
+int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, double tol, int passes, double brk,
+           const std::function<int(const double*, double*)>& M, Outcome& out) {
+  int rc;
+  double* w = c.W(0);
+  double* r = c.W(1);
+  out = Outcome();
+  TG_HIP(hipMemsetAsync(x, 0, sizeof(double) * c.L.n, c.s));
+  double bnorm;
+  if ((rc = norm(c, b, &bnorm))) return rc;
+  out.hist.push_back(1.0);
+  if (bnorm == 0.0) {
+    out.hist[0] = 0.0;
+    return TG_OK;
+  }
+  const int m = K.m, ldh = m + 1;
+  std::vector<double> H((size_t)ldh * m), cs(m), sn(m), g(m + 1), hcol(AD_MAXV + 1);
+  int k = 0;
+  for (;;) {
+    if (k > 0) {
+      if ((rc = applyK(c, x, w))) return rc;
+      if ((rc = axpby(c, 1.0, b, -1.0, w, r))) return rc;
+    } else {
+      TG_HIP(hipMemcpyAsync(r, b, sizeof(double) * c.L.n, hipMemcpyDeviceToDevice, c.s));
+    }
+    double beta;
+    if ((rc = norm(c, r, &beta))) return rc;
+    if (k > 0) out.hist[k] = beta / bnorm;
+    out.iters = k;
+    if (!std::isfinite(beta)) { out.outcome = TG_NONFINITE; return TG_OK; }
+    if (beta / bnorm <= tol) { out.outcome = TG_PROJ_CONVERGED; return TG_OK; }
+    if (k >= max_iters) { out.outcome = TG_MAXIT; return TG_OK; }
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    if ((rc = axpby(c, 1.0 / beta, r, 0.0, nullptr, K.V))) return rc;
+    g[0] = beta;
+    int stop = -1, jdone = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = K.V + (long long)j * c.L.ld;
+      double* zj = K.Z + (long long)j * c.L.ld;
+      if ((rc = M(vj, zj))) return rc;
+      if ((rc = applyK(c, zj, w))) return rc;
+      if ((rc = dots(c, w, 1, w, nullptr, 0, c.scal()))) return rc;
+      for (int pass = 0; pass < passes; ++pass) {
+        if ((rc = dots(c, K.V, j + 1, w, c.h(), pass > 0))) return rc;
+        if ((rc = update(c, K.V, j + 1, c.tmp(), -1.0, w))) return rc;
+      }
+      if ((rc = dots(c, w, 1, w, nullptr, 0, c.scal() + 1))) return rc;
+      double sq[2];
+      TG_HIP(hipMemcpyAsync(hcol.data(), c.h(), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.s));
+      TG_HIP(hipMemcpyAsync(sq, c.scal(), sizeof(sq), hipMemcpyDeviceToHost, c.s));
+      TG_HIP(hipStreamSynchronize(c.s));
+      const double wnorm0 = std::sqrt(sq[0]), hn = std::sqrt(sq[1]);
+      bool finite_h = true;
+      for (int i = 0; i <= j; ++i) {
+        H[i + (size_t)ldh * j] = hcol[i];
+        finite_h = finite_h && std::isfinite(hcol[i]);
+      }
+      H[j + 1 + (size_t)ldh * j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i + (size_t)ldh * j], bb = H[i + 1 + (size_t)ldh * j];
+        H[i + 1 + (size_t)ldh * j] = -sn[i] * a + cs[i] * bb;
+        H[i + (size_t)ldh * j] = cs[i] * a + sn[i] * bb;
+      }
+      const double a = H[j + (size_t)ldh * j], bb = H[j + 1 + (size_t)ldh * j];
+      const double d = std::hypot(a, bb);
+      if (d == 0.0 || !std::isfinite(d) || !finite_h) {
+        stop = TG_NONFINITE;
+        jdone = j;
+        break;
+      }
+      cs[j] = a / d;
+      sn[j] = bb / d;
+      H[j + (size_t)ldh * j] = d;
+      H[j + 1 + (size_t)ldh * j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++k;
+      jdone = j + 1;
+      const double est = std::fabs(g[j + 1]) / bnorm;
+      out.hist.push_back(est);
+      if (est <= tol) stop = TG_PROJ_CONVERGED;
+      else if (hn <= brk * wnorm0) stop = TG_BREAKDOWN;
+      else if (k >= max_iters) stop = TG_MAXIT;
+      if (stop >= 0) break;
+      if ((rc = axpby(c, 1.0 / hn, w, 0.0, nullptr, K.V + (long long)(j + 1) * c.L.ld))) return rc;
+    }
+    if (jdone > 0) {
+      const std::vector<double> y = lsq(H, ldh, g, jdone);
+      TG_HIP(hipMemcpyAsync(c.coef(), y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, c.s));
+      if ((rc = update(c, K.Z, jdone, c.coef(), 1.0, x))) return rc;
+      TG_HIP(hipStreamSynchronize(c.s));   // y lives on the host stack
+    }
+    if (stop >= 0) {
+      out.outcome = stop;
+      out.iters = k;
+      return TG_OK;
+    }
+  }
+}
+
+// z = M(v): the V-cycle, then the accepted-or-rejected fine-level correction
+int adaptive_apply(Ctx& c, const double* v, double* z) {
+  int rc;
+  if ((rc = vcycle(c, v, z))) return rc;
+  if (c.L.q <= 0) {
+    c.accepted.push_back(0);
+    return TG_OK;
+  }
+  double* s = c.W(1);
+  double* t = c.W(2);
+  double* d = c.W(3);
+  if ((rc = applyK(c, z, t))) return rc;
+  if ((rc = axpby(c, 1.0, v, -1.0, t, s))) return rc;
+  double r0, r1;
+  if ((rc = norm(c, s, &r0))) return rc;
+  // the inner iteration writes its residuals into W(1); keep s in W(4)
+  double* s_keep = c.W(4);
+  TG_HIP(hipMemcpyAsync(s_keep, s, sizeof(double) * c.L.n, hipMemcpyDeviceToDevice, c.s));
+  Krylov inner{c.vec(c.L.iV, 0), c.vec(c.L.iZ, 0), c.L.q};
+  Outcome o;
+  auto jac = [&c](const double* r, double* zz) { return jacobi(c, r, zz); };
+  if ((rc = fgmres(c, inner, s_keep, d, c.L.q, 0.0, 2, 1e-14, jac, o))) return rc;
+  if ((rc = applyK(c, d, t))) return rc;
+  if ((rc = axpby(c, 1.0, s_keep, -1.0, t, t))) return rc;
+  if ((rc = norm(c, t, &r1))) return rc;
+  const bool ok = r1 < r0;
+  c.accepted.push_back(ok ? 1 : 0);
+  if (ok && (rc = axpby(c, 1.0, z, 1.0, d, z))) return rc;
+  return TG_OK;
+}
+
+int check_common(tg_grid* g, int prec, int restart, int inner, void* ws_d, size_t ws_bytes, Layout& L) {
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!g->density_set) return fail(TG_ESTATE, "set_density first");
+  if (!ws_d) return fail(TG_EINVAL, "NULL workspace");
+  if (prec < TG_F64 || prec > TG_BF16X3MFMA) return fail(TG_EINVAL, "unknown precision");
+  if (restart < 0 || restart > TG_AD_MAX_RESTART || inner < 0 || inner > TG_AD_MAX_RESTART)
+    return fail(TG_EINVAL, "restart and inner steps must lie in [0, TG_AD_MAX_RESTART]");
+  L.init(g, restart, inner);
+  if (ws_bytes < L.total) return fail(TG_EWORKSPACE, "adaptive workspace too small");
+  return TG_OK;
+}
+
+}  // namespace
+}  // namespace tg
+
+using namespace tg;
+
+extern "C" {
+
+int tg_adaptive_workspace_bytes(const tg_grid* g, int restart, int inner_steps, size_t* bytes) {
+  if (!g || !bytes) return fail(TG_EINVAL, "NULL argument");
+  if (restart < 0 || restart > TG_AD_MAX_RESTART || inner_steps < 0 || inner_steps > TG_AD_MAX_RESTART)
+    return fail(TG_EINVAL, "restart and inner steps must lie in [0, TG_AD_MAX_RESTART]");
+  Layout L;
+  L.init(g, restart, inner_steps);
+  *bytes = L.total;
+  return TG_OK;
+}
+
+int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int prec, int inner_steps, void* ws_d,
+                             size_t ws_bytes, int* accepted_h, void* stream) {
+  if (!v_d || !z_d) return fail(TG_EINVAL, "NULL vector");
+  Layout L;
+  int rc = check_common(g, prec, 0, inner_steps, ws_d, ws_bytes, L);
+  if (rc) return rc;
+  Ctx c{g, (hipStream_t)stream, prec, L, (char*)ws_d, {}};
+  if ((rc = adaptive_apply(c, v_d, z_d))) return rc;
+  TG_HIP(hipStreamSynchronize(c.s));
+  if (accepted_h) *accepted_h = c.accepted.empty() ? 0 : c.accepted.back();
+  return TG_OK;
+}
+
+int tg_adaptive_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
+                      void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, int* accepted_h,
+                      int* n_applied_h, void* stream) {
+  if (!f_d || !u_d || !o || !res) return fail(TG_EINVAL, "NULL argument");
+  if (o->restart < 1) return fail(TG_EINVAL, "restart must be >= 1");
+  if (o->max_iters < 0 || !(o->tol >= 0.0)) return fail(TG_EINVAL, "need max_iters >= 0 and tol >= 0");
+  if (o->cgs_passes < 1 || o->cgs_passes > 3) return fail(TG_EINVAL, "cgs_passes must be 1, 2 or 3");
+  Layout L;
+  int rc = check_common(g, o->prec, o->restart, inner_steps, ws_d, ws_bytes, L);
+  if (rc) return rc;
+  Ctx c{g, (hipStream_t)stream, o->prec, L, (char*)ws_d, {}};
+  Krylov outer{c.vec(L.oV, 0), c.vec(L.oZ, 0), L.m};
+  Outcome out;
+  auto M = [&c](const double* v, double* z) { return adaptive_apply(c, v, z); };
+  if ((rc = fgmres(c, outer, f_d, u_d, o->max_iters, o->tol, o->cgs_passes == 1 ? 1 : 2, o->breakdown, M, out)))
+    return rc;
+  TG_HIP(hipStreamSynchronize(c.s));
+  res->iterations = out.iters;
+  res->outcome = out.outcome;
+  res->proj_eta = out.hist.back();
+  res->true_eta = -1.0;
+  if (hist_h) std::memcpy(hist_h, out.hist.data(), sizeof(double) * out.hist.size());
+  const int na = (int)std::min<size_t>(c.accepted.size(), (size_t)o->max_iters + 1);
+  if (accepted_h) std::copy(c.accepted.begin(), c.accepted.begin() + na, accepted_h);
+  if (n_applied_h) *n_applied_h = (int)c.accepted.size();
+  return TG_OK;
+}
+
+}  // extern "C"

@@ -176,6 +176,39 @@ class Grid:
                                          C.byref(n), C.byref(kst), _stream()))
         return [(ks[i], pj[i], tr[i]) for i in range(n.value)], kst.value
 
+    def adaptive_precondition(self, v, prec=F64, inner_steps=20):
+        """(z, accepted): one V-cycle plus the fine-level correction, kept if
+        it lowers the residual norm (v, z device FP64)."""
+        assert v.dtype == torch.float64 and v.is_cuda and v.numel() == self.n_dof
+        nb = C.c_size_t()
+        check(lib().tg_adaptive_workspace_bytes(self.handle, 0, int(inner_steps), C.byref(nb)))
+        ws, wptr = _alloc_ws(nb.value, self.device)
+        z = torch.empty_like(v)
+        acc = C.c_int()
+        check(lib().tg_adaptive_precondition(self.handle, _ptr(v), _ptr(z), prec, int(inner_steps),
+                                             C.c_void_p(wptr), nb.value, C.byref(acc), _stream()))
+        del ws
+        return z, bool(acc.value)
+
+    def adaptive_solve(self, f, opts=None, inner_steps=20):
+        """(u, result dict, history, accepted flags per preconditioner
+        application): FGMRES with the adaptive preconditioner."""
+        opts = opts or solver_opts()
+        nb = C.c_size_t()
+        check(lib().tg_adaptive_workspace_bytes(self.handle, opts.restart, int(inner_steps), C.byref(nb)))
+        ws, wptr = _alloc_ws(nb.value, self.device)
+        u = torch.empty_like(f)
+        res = L.SolveResult()
+        hist = np.zeros(opts.max_iters + 1)
+        acc = (C.c_int * (opts.max_iters + 1))()
+        na = C.c_int()
+        check(lib().tg_adaptive_solve(self.handle, _ptr(f), _ptr(u), C.byref(opts), int(inner_steps),
+                                      C.c_void_p(wptr), nb.value, C.byref(res),
+                                      hist.ctypes.data_as(C.POINTER(C.c_double)), acc, C.byref(na), _stream()))
+        del ws
+        n = min(na.value, opts.max_iters + 1)
+        return u, result_dict(res), hist[:res.iterations + 1].copy(), [bool(acc[i]) for i in range(n)]
+
     def density_features(self, rho, p=3.0, rho0=1e-9):
         """Six density statistics of rho (device FP64) at probe floor rho0."""
         out = (C.c_double * 6)()
