@@ -198,6 +198,26 @@ def cpu_cores():
     return max(1, min(16, n))
 
 
+def host_info():
+    """CPU model, library versions and BLAS threads of the host that timed
+    the CPU baseline."""
+    import scipy
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = sorted({d.get("internal_api") for d in threadpool_info()} - {None})
+    except Exception:  # threadpoolctl missing or unable to inspect: report nothing
+        blas = None
+    return {"cpu_model": model, "processes": cpu_cores(), "numpy": np.__version__, "scipy": scipy.__version__,
+            "blas": blas, "blas_threads_per_process": 1}
+
+
 def run_cpu_baseline(setups_per_state, iters_per_state):
     """One oracle process per host core (one BLAS thread each), each timing the
     sample on its own state concurrently; the rate is the sum of the per-process
@@ -716,8 +736,11 @@ def main():
             return tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_MLP, mlp=mlp)
         return tg.policy(rungs=RUNGS, p=3.0, solve=solve)
 
+    step_times = []   # wall seconds of every timed step of the last run (select_floor syncs)
+
     def run(prec, steps, warmup, timer_mask, use_mlp, pol=None):
         pol = pol if pol is not None else policy(prec, use_mlp)
+        step_times.clear()
         for w in range(warmup):
             t = time.perf_counter()
             batch.select_floor(rhos, fs, pol)
@@ -730,6 +753,7 @@ def main():
         for st in range(steps):
             t = time.perf_counter()
             _, outs = batch.select_floor(rhos, fs, pol)
+            step_times.append(time.perf_counter() - t)
             log(f"step {st} prec={prec} {time.perf_counter() - t:.2f}s "
                 f"certified={sum(1 for o in outs if o['rung'] >= 0)}")
         torch.cuda.synchronize()
@@ -751,6 +775,7 @@ def main():
     dom = tg.dominant_kernel(probe_timers)
     dom_mask = 1 << probe_timers[dom]["kind"]
     dt, outs, timers = run(mixed_prec, args.steps, args.warmup, dom_mask, use_mlp)
+    steps_s = list(step_times)
     certified = sum(1 for o in outs if o["rung"] >= 0)
     value = certified * args.steps / dt
     result = {
@@ -759,7 +784,11 @@ def main():
         "selector": args.selector,
         "orthogonalization": {1: "CGS", 2: "CGS2, delayed reorthogonalization", 3: "CGS2 in place"}[args.cgs_passes],
         "value": value, "unit": "certified solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "step_ms": {"median": 1e3 * float(np.median(steps_s)),
+                    "iqr": [1e3 * float(np.percentile(steps_s, 25)), 1e3 * float(np.percentile(steps_s, 75))],
+                    "all": [1e3 * t for t in steps_s]},
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "102 severe random states, 64x32x32 cantilever, guarded floor ladder",
@@ -868,6 +897,7 @@ def main():
         setups = float(np.mean([1 + len(o["attempts"]) for o in outs]))
         iters = float(np.mean([o["iters_probe"] + o["iters_selected"] + o["iters_rejected"] for o in outs]))
         result["cpu_baseline"] = run_cpu_baseline(setups, iters)
+        result["cpu_host"] = host_info()
     print(json.dumps(result), flush=True)
 
 
