@@ -480,9 +480,9 @@ def trajectory_leg(tg, torch, dev, mixed_prec):
     return out
 
 
-def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=12, floor=1e-9):
+def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9):
     """The fine-level adaptive correction of the preconditioner (Tab.
-    solver-config) on the first n_states severe states at the original floor:
+    solver-config) on the severe states at the original floor:
     FGMRES(30), cap 200, V-cycle at `prec`, with the correction (20 inner
     node-block-Jacobi GMRES steps, kept only if they lower the residual) and
     without it.  Per variant: outer iterations, certified solves (FP64 guard
@@ -702,7 +702,7 @@ def main():
               flush=True)
         return
     if args.adaptive_only:
-        n_ad = min(args.states, 12)
+        n_ad = args.states
         rhos = [torch.tensor(synth.severe(SEED0 + i)[1], device=dev) for i in range(n_ad)]
         f0 = torch.tensor(tg.Grid(*GRID, max_restart=1, device=dev).edge_load(), device=dev)
         print(json.dumps({"adaptive_preconditioner": adaptive_leg(
@@ -851,7 +851,7 @@ def main():
         result["screen"] = screen_stats(tg, torch, grids, rhos, labels, RUNGS, 3.0, mixed_prec)
         result["probe_checkpoints"] = checkpoint_stats(tg, torch, grids, rhos, fs, RUNGS, 3.0, mixed_prec)
     if not args.no_adaptive:
-        result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec)
+        result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec, n_states=n)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)
