@@ -197,7 +197,8 @@ int tg_probe_checkpoints(tg_grid* g, const double* f_d, const tg_solver_opts* o,
  * if ||s - K d||_2 < ||s||_2.  inner_steps = 0 is the plain V-cycle.  K is
  * the FP64 operator in every precision.  The outer method must be flexible
  * (Sec. 3.5): M is nonlinear in v.
- * Single grid, host-orchestrated (every Arnoldi step reads its column back),
+ * Single grid; the outer iteration reads each Arnoldi column back to the host,
+ * one application of M needs no host synchronization;
  * FP64 vectors of n_dof entries (device), clamped DOFs read as 0 and written
  * as 0.  The caller allocates the workspace (tg_adaptive_workspace_bytes with
  * the outer restart, 0 for tg_adaptive_precondition) and keeps ownership.

@@ -9,9 +9,11 @@
 // Krylov polynomial), so the outer method stores the preconditioned vectors
 // Z and forms x = x0 + Z y (flexible GMRES, Saad 1993).
 //
-// The path is single-grid and host-orchestrated: every Arnoldi step reads its
-// Hessenberg column back to the host (the accept decision needs two norms on
-// the host anyway).  K is the library's FP64 operator, the V-cycle runs at the
+// The path is single-grid.  The outer iteration reads each Hessenberg column
+// back to the host; the inner iteration of the correction keeps its scalar
+// work (rotations, least squares, accept test) on the device, so one
+// application of M needs no host synchronization.  K is the library's FP64
+// operator, the V-cycle runs at the
 // requested precision (FP32 forms through float copies), the node-block
 // inverses are the smoother's.  Sums run in a fixed order (block partials,
 // then one wavefront per sum), so results are reproducible run to run.
@@ -124,6 +126,118 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_jacobi(const double* __restrict
   }
 }
 
+// ---- the inner iteration's scalar work on the device (one lane), so one
+// application of the preconditioner needs no host synchronization
+
+// inner state: scalars (IS_*), control ints (stop code, columns done)
+enum { IS_R0SQ = 0, IS_INVB = 1, IS_WN0 = 2, IS_HN = 3, IS_INV = 4, IS_R1SQ = 5, IS_ACC = 6, IS_BNORM = 7,
+       IS_N = 8 };
+enum { IC_STOP = 0, IC_JDONE = 1, IC_N = 4 };
+
+// start of the inner solve on s: beta = ||s|| (from sc[IS_R0SQ]), g = beta e1
+__global__ void k_ad_inner_init(double* __restrict__ sc, int* __restrict__ ctl, double* __restrict__ g) {
+  const double r0 = sqrt(sc[IS_R0SQ]);
+  sc[IS_BNORM] = r0;
+  ctl[IC_JDONE] = 0;
+  if (r0 == 0.0 || !isfinite(r0)) {   // nothing to solve (or nothing finite): d = 0
+    ctl[IC_STOP] = 1;
+    sc[IS_INVB] = 0.0;
+    return;
+  }
+  ctl[IC_STOP] = 0;
+  g[0] = r0;
+  sc[IS_INVB] = 1.0 / r0;
+}
+
+// Arnoldi column j: h (projection coefficients), ||w|| before and after the
+// sweeps; earlier rotations, the new one, the estimate and the stop test
+// (no tolerance: estimate exactly 0, breakdown, or the last step)
+__global__ void k_ad_givens(int j, int q, double brk, const double* __restrict__ h, double* __restrict__ H,
+                            double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn,
+                            double* __restrict__ sc, int* __restrict__ ctl) {
+  if (ctl[IC_STOP]) return;
+  const int ldh = q + 1;
+  double* col = H + (long long)ldh * j;
+  const double wn0 = sqrt(sc[IS_WN0]), hn = sqrt(sc[IS_HN]);
+  bool finite_h = true;
+  for (int i = 0; i <= j; ++i) {
+    col[i] = h[i];
+    finite_h = finite_h && isfinite(h[i]);
+  }
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+    col[i] = cs[i] * a + sn[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double d = hypot(a, b);
+  if (d == 0.0 || !isfinite(d) || !finite_h) {
+    ctl[IC_STOP] = 1 + TG_NONFINITE;   // column j unusable
+    return;
+  }
+  cs[j] = a / d;
+  sn[j] = b / d;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  ctl[IC_JDONE] = j + 1;
+  const double est = fabs(g[j + 1]) / sc[IS_BNORM];
+  if (est <= 0.0) ctl[IC_STOP] = 1 + TG_PROJ_CONVERGED;
+  else if (hn <= brk * wn0) ctl[IC_STOP] = 1 + TG_BREAKDOWN;
+  else if (j + 1 >= q) ctl[IC_STOP] = 1 + TG_MAXIT;
+  sc[IS_INV] = 1.0 / hn;
+}
+
+// y = R^-1 g over the columns done
+__global__ void k_ad_lsq(const double* __restrict__ H, int q, const double* __restrict__ g,
+                         const int* __restrict__ ctl, double* __restrict__ y) {
+  const int ldh = q + 1, jd = ctl[IC_JDONE];
+  for (int i = jd - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int k = i + 1; k < jd; ++k) s -= H[i + (long long)ldh * k] * y[k];
+    y[i] = s / H[i + (long long)ldh * i];
+  }
+}
+
+// out = *alpha * x, skipped once the inner iteration stopped
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_scale_dev(const double* __restrict__ x, const double* __restrict__ alpha,
+                                                           const int* __restrict__ ctl, double* __restrict__ out,
+                                                           long long n) {
+  if (ctl[IC_STOP]) return;
+  const double a = *alpha;
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    out[i] = a * x[i];
+}
+
+// w = sum_{q < ctl[IC_JDONE]} c[q] V_q
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_combine_dev(const double* __restrict__ V, long long ld,
+                                                             const int* __restrict__ ctl,
+                                                             const double* __restrict__ c, double* __restrict__ w,
+                                                             long long n) {
+  __shared__ double sc[AD_MAXV];
+  const int nv = ctl[IC_JDONE];
+  for (int q = threadIdx.x; q < nv; q += AD_BLOCK) sc[q] = c[q];
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK) {
+    double s = 0.0;
+    for (int q = 0; q < nv; ++q) s += sc[q] * V[(long long)q * ld + i];
+    w[i] = s;
+  }
+}
+
+// keep the correction iff ||s - K d|| < ||s||: z += d, and the decision in
+// sc[IS_ACC]
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_accept(double* __restrict__ z, const double* __restrict__ d,
+                                                        double* __restrict__ sc, long long n) {
+  const bool ok = sqrt(sc[IS_R1SQ]) < sqrt(sc[IS_R0SQ]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[IS_ACC] = ok ? 1.0 : 0.0;
+  if (!ok) return;
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    z[i] += d[i];
+}
+
 __global__ __launch_bounds__(AD_BLOCK) void k_ad_to32(const double* __restrict__ a, float* __restrict__ b, long long n) {
   for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
     b[i] = (float)a[i];
@@ -139,7 +253,7 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_to64(const float* __restrict__ 
 struct Layout {
   long long n = 0, ld = 0;
   int m = 0, q = 0, nb = 0;
-  size_t oV = 0, oZ = 0, iV = 0, iZ = 0, wv = 0, f32 = 0, part = 0, small = 0, total = 0;
+  size_t oV = 0, oZ = 0, iV = 0, iZ = 0, wv = 0, f32 = 0, part = 0, small = 0, ist = 0, total = 0;
   void init(const tg_grid* g, int restart, int inner) {
     n = g->lv[0].n_dof;
     ld = ld_of(n);
@@ -156,6 +270,8 @@ struct Layout {
     f32 = o; o += 2 * al((size_t)n * sizeof(float));
     part = o; o += al((size_t)nb * AD_MAXV * sizeof(double));
     small = o; o += al(4 * AD_MAXV * sizeof(double));
+    // inner state: Hessenberg (q + 1) x q, g, cs, sn, scalars, control ints
+    ist = o; o += al(((size_t)(q + 1) * q + (q + 1) + 2 * q + IS_N) * sizeof(double) + IC_N * sizeof(int));
     total = o;
   }
 };
@@ -175,6 +291,14 @@ struct Ctx {
   double* h() const { return tmp() + AD_MAXV; }
   double* coef() const { return tmp() + 2 * AD_MAXV; }
   double* scal() const { return tmp() + 3 * AD_MAXV; }   // ||w||^2 before and after orthogonalization
+  // inner state
+  double* iH() const { return (double*)(base + L.ist); }
+  double* ig() const { return iH() + (size_t)(L.q + 1) * L.q; }
+  double* ics() const { return ig() + L.q + 1; }
+  double* isn() const { return ics() + L.q; }
+  double* isc() const { return isn() + L.q; }
+  int* ictl() const { return (int*)(isc() + IS_N); }
+  bool flag_pending = false;   // a decision of M waits in isc()[IS_ACC]
   std::vector<int> accepted;
 };
 
@@ -306,10 +430,15 @@ int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, d
         if ((rc = update(c, K.V, j + 1, c.tmp(), -1.0, w))) return rc;
       }
       if ((rc = dots(c, w, 1, w, nullptr, 0, c.scal() + 1))) return rc;
-      double sq[2];
+      double sq[2], acc = 0.0;
       TG_HIP(hipMemcpyAsync(hcol.data(), c.h(), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.s));
       TG_HIP(hipMemcpyAsync(sq, c.scal(), sizeof(sq), hipMemcpyDeviceToHost, c.s));
+      if (c.flag_pending) TG_HIP(hipMemcpyAsync(&acc, c.isc() + IS_ACC, sizeof(double), hipMemcpyDeviceToHost, c.s));
       TG_HIP(hipStreamSynchronize(c.s));
+      if (c.flag_pending) {
+        c.accepted.push_back(acc != 0.0 ? 1 : 0);
+        c.flag_pending = false;
+      }
       const double wnorm0 = std::sqrt(sq[0]), hn = std::sqrt(sq[1]);
       bool finite_h = true;
       for (int i = 0; i <= j; ++i) {
@@ -359,34 +488,65 @@ int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, d
   }
 }
 
-// z = M(v): the V-cycle, then the accepted-or-rejected fine-level correction
+// z = M(v): the V-cycle, then the accepted-or-rejected fine-level correction.
+// The inner GMRES (restart = steps = q, CGS2, no tolerance) runs a fixed
+// launch sequence whose scalar work and stop test live on the device; steps
+// after a stop compute into columns that are never combined.  The decision
+// is left in isc()[IS_ACC] (flag_pending), read with the caller's next
+// synchronization.
 int adaptive_apply(Ctx& c, const double* v, double* z) {
   int rc;
   if ((rc = vcycle(c, v, z))) return rc;
+  c.flag_pending = true;
   if (c.L.q <= 0) {
-    c.accepted.push_back(0);
+    TG_HIP(hipMemsetAsync(c.isc() + IS_ACC, 0, sizeof(double), c.s));   // 0.0: nothing to keep
     return TG_OK;
   }
+  const int q = c.L.q;
+  const long long n = c.L.n;
+  double* w = c.W(0);
   double* s = c.W(1);
   double* t = c.W(2);
   double* d = c.W(3);
+  double* Vi = c.vec(c.L.iV, 0);
+  double* Zi = c.vec(c.L.iZ, 0);
+  double* sc = c.isc();
+  int* ctl = c.ictl();
+  const int nb = nblk(n);
   if ((rc = applyK(c, z, t))) return rc;
   if ((rc = axpby(c, 1.0, v, -1.0, t, s))) return rc;
-  double r0, r1;
-  if ((rc = norm(c, s, &r0))) return rc;
-  // the inner iteration writes its residuals into W(1); keep s in W(4)
-  double* s_keep = c.W(4);
-  TG_HIP(hipMemcpyAsync(s_keep, s, sizeof(double) * c.L.n, hipMemcpyDeviceToDevice, c.s));
-  Krylov inner{c.vec(c.L.iV, 0), c.vec(c.L.iZ, 0), c.L.q};
-  Outcome o;
-  auto jac = [&c](const double* r, double* zz) { return jacobi(c, r, zz); };
-  if ((rc = fgmres(c, inner, s_keep, d, c.L.q, 0.0, 2, 1e-14, jac, o))) return rc;
+  if ((rc = dots(c, s, 1, s, nullptr, 0, sc + IS_R0SQ))) return rc;
+  k_ad_inner_init<<<1, 1, 0, c.s>>>(sc, ctl, c.ig());
+  TG_HIP(hipGetLastError());
+  k_ad_scale_dev<<<nb, AD_BLOCK, 0, c.s>>>(s, sc + IS_INVB, ctl, Vi, n);
+  TG_HIP(hipGetLastError());
+  for (int j = 0; j < q; ++j) {
+    double* vj = Vi + (long long)j * c.L.ld;
+    double* zj = Zi + (long long)j * c.L.ld;
+    if ((rc = jacobi(c, vj, zj))) return rc;
+    if ((rc = applyK(c, zj, w))) return rc;
+    if ((rc = dots(c, w, 1, w, nullptr, 0, sc + IS_WN0))) return rc;
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((rc = dots(c, Vi, j + 1, w, c.h(), pass > 0))) return rc;
+      if ((rc = update(c, Vi, j + 1, c.tmp(), -1.0, w))) return rc;
+    }
+    if ((rc = dots(c, w, 1, w, nullptr, 0, sc + IS_HN))) return rc;
+    k_ad_givens<<<1, 1, 0, c.s>>>(j, q, 1e-14, c.h(), c.iH(), c.ig(), c.ics(), c.isn(), sc, ctl);
+    TG_HIP(hipGetLastError());
+    if (j + 1 < q) {
+      k_ad_scale_dev<<<nb, AD_BLOCK, 0, c.s>>>(w, sc + IS_INV, ctl, Vi + (long long)(j + 1) * c.L.ld, n);
+      TG_HIP(hipGetLastError());
+    }
+  }
+  k_ad_lsq<<<1, 1, 0, c.s>>>(c.iH(), q, c.ig(), ctl, c.coef());
+  TG_HIP(hipGetLastError());
+  k_ad_combine_dev<<<nb, AD_BLOCK, 0, c.s>>>(Zi, c.L.ld, ctl, c.coef(), d, n);
+  TG_HIP(hipGetLastError());
   if ((rc = applyK(c, d, t))) return rc;
-  if ((rc = axpby(c, 1.0, s_keep, -1.0, t, t))) return rc;
-  if ((rc = norm(c, t, &r1))) return rc;
-  const bool ok = r1 < r0;
-  c.accepted.push_back(ok ? 1 : 0);
-  if (ok && (rc = axpby(c, 1.0, z, 1.0, d, z))) return rc;
+  if ((rc = axpby(c, 1.0, s, -1.0, t, t))) return rc;
+  if ((rc = dots(c, t, 1, t, nullptr, 0, sc + IS_R1SQ))) return rc;
+  k_ad_accept<<<nb, AD_BLOCK, 0, c.s>>>(z, d, sc, n);
+  TG_HIP(hipGetLastError());
   return TG_OK;
 }
 
@@ -427,8 +587,10 @@ int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int pre
   if (rc) return rc;
   Ctx c{g, (hipStream_t)stream, prec, L, (char*)ws_d, {}};
   if ((rc = adaptive_apply(c, v_d, z_d))) return rc;
+  double acc = 0.0;
+  TG_HIP(hipMemcpyAsync(&acc, c.isc() + IS_ACC, sizeof(double), hipMemcpyDeviceToHost, c.s));
   TG_HIP(hipStreamSynchronize(c.s));
-  if (accepted_h) *accepted_h = c.accepted.empty() ? 0 : c.accepted.back();
+  if (accepted_h) *accepted_h = acc != 0.0 ? 1 : 0;
   return TG_OK;
 }
 
