@@ -480,39 +480,65 @@ def trajectory_leg(tg, torch, dev, mixed_prec):
     return out
 
 
-def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9):
+def adaptive_runs(tg, torch, g, rhos, fs, p, floor, opts, inner, tau=1e-6):
+    """Solve each state with tg_adaptive_solve; counts and per-state results."""
+    its, cert, false_acc, maxit, kept, applied, secs, rows = 0, 0, 0, 0, 0, 0, 0.0, []
+    for rho, f in zip(rhos, fs):
+        g.set_density(rho, p, floor)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, res, hist, acc = g.adaptive_solve(f, opts, inner)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        eta = g.true_residual(f, u)
+        rows.append([res["iterations"], res["outcome"], res["proj_eta"], eta])
+        its += res["iterations"]
+        cert += eta <= tau
+        false_acc += res["outcome"] == "PROJ_CONVERGED" and eta > tau
+        maxit += res["outcome"] == "MAXIT"
+        kept += sum(acc)
+        applied += len(acc)
+    n = len(rhos)
+    ratio = [row[3] / row[2] for row in rows if row[1] == "PROJ_CONVERGED" and row[2] > 0]
+    return {"mean_iters": its / n, "certified": int(cert), "proj_converged_guard_rejects": int(false_acc),
+            "true_over_projected_at_stop": [min(ratio), max(ratio)] if ratio else None,
+            "maxit": int(maxit), "corrections_kept": int(kept), "preconditioner_applications": int(applied),
+            "seconds_per_solve": secs / n, "per_state": rows}
+
+
+def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_paper=24):
     """The fine-level adaptive correction of the preconditioner (Tab.
-    solver-config) on the severe states at the original floor:
-    FGMRES(30), cap 200, V-cycle at `prec`, with the correction (20 inner
-    node-block-Jacobi GMRES steps, kept only if they lower the residual) and
-    without it.  Per variant: outer iterations, certified solves (FP64 guard
-    <= 1e-6), solves whose projected estimate converged while the guard
-    rejects them, kept corrections, seconds per solve (synchronized wall
-    clock of the solve alone)."""
+    solver-config), with it (20 inner node-block-Jacobi GMRES steps, kept only
+    if they lower the residual) and without it (inner_steps = 0).  Per
+    variant: outer iterations, certified solves (FP64 guard <= 1e-6), solves
+    whose projected estimate converged while the guard rejects them, kept
+    corrections, seconds per solve (synchronized wall clock of the solve).
+    workload: the severe states at the original floor, p = 3, FGMRES(30),
+    cap 200, V-cycle at `prec`.  paper_setting: the first n_paper states under
+    the adaptive stack's own settings (Tab. solver-config: p = 4.5,
+    rho_0 = 1e-12, restart = cap = 300, FP64 fine path)."""
     g = tg.Grid(*GRID, max_restart=30, device=dev)
-    out = {"states": n_states, "floor": floor, "solve": "FGMRES(30), cap 200, FP64 operator and guard",
-           "inner_steps": 20}
+    out = {"states": n_states, "floor": floor, "p": 3.0, "inner_steps": 20,
+           "solve": "FGMRES(30), cap 200, FP64 operator and guard"}
+    o = tg.solver_opts(restart=30, max_iters=200, prec=prec)
     for name, inner in (("adaptive", 20), ("plain_vcycle", 0)):
-        its, cert, false_acc, kept, applied, secs, etas = 0, 0, 0, 0, 0, 0.0, []
-        for i in range(n_states):
-            g.set_density(rhos[i], 3.0, floor)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            u, res, hist, acc = g.adaptive_solve(fs[i], tg.solver_opts(restart=30, max_iters=200, prec=prec), inner)
-            torch.cuda.synchronize()
-            secs += time.perf_counter() - t0
-            eta = g.true_residual(fs[i], u)
-            etas.append(eta)
-            its += res["iterations"]
-            cert += eta <= 1e-6
-            false_acc += res["outcome"] == "PROJ_CONVERGED" and eta > 1e-6
-            kept += sum(acc)
-            applied += len(acc)
-        out[name] = {"mean_iters": its / n_states, "certified": int(cert), "proj_converged_guard_rejects": int(false_acc),
-                     "corrections_kept": int(kept), "preconditioner_applications": int(applied),
-                     "seconds_per_solve": secs / n_states, "true_eta": etas}
-        log(f"adaptive leg {name}: mean its {its / n_states:.1f}, certified {cert}/{n_states}, "
-            f"false acceptances caught {false_acc}, {secs / n_states:.3f} s/solve")
+        r = adaptive_runs(tg, torch, g, rhos[:n_states], fs[:n_states], 3.0, floor, o, inner)
+        out[name] = {k: v for k, v in r.items() if k != "per_state"}
+        out[name]["true_eta"] = [row[3] for row in r["per_state"]]
+        log(f"adaptive leg {name}: mean its {r['mean_iters']:.1f}, certified {r['certified']}/{n_states}, "
+            f"false acceptances caught {r['proj_converged_guard_rejects']}, {r['seconds_per_solve']:.3f} s/solve")
+    n_paper = min(n_paper, len(rhos))
+    ps = {"states": n_paper, "p": 4.5, "floor": 1e-12, "solve": "FGMRES(300), cap 300, FP64 throughout, CGS2",
+          "adaptive_cgs1": "the same with one Gram-Schmidt sweep per step"}
+    for name, inner, passes in (("adaptive", 20, 2), ("plain_vcycle", 0, 2), ("adaptive_cgs1", 20, 1)):
+        o = tg.solver_opts(restart=300, max_iters=300, prec=tg.F64, cgs_passes=passes)
+        ps[name] = adaptive_runs(tg, torch, g, rhos[:n_paper], fs[:n_paper], 4.5, 1e-12, o, inner)
+        r = ps[name]
+        log(f"adaptive leg, paper setting, {name}: mean its {r['mean_iters']:.1f}, certified "
+            f"{r['certified']}/{n_paper}, false acceptances caught {r['proj_converged_guard_rejects']}, "
+            f"MAXIT {r['maxit']}, true/projected at stop {r['true_over_projected_at_stop']}, "
+            f"{r['seconds_per_solve']:.3f} s/solve")
+    out["paper_setting"] = ps
     del g
     torch.cuda.empty_cache()
     return out

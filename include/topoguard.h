@@ -206,7 +206,7 @@ int tg_probe_checkpoints(tg_grid* g, const double* f_d, const tg_solver_opts* o,
  * precision outside TG_F64..TG_BF16X3MFMA or restart / inner_steps outside
  * [0, TG_AD_MAX_RESTART], TG_EWORKSPACE for a short workspace.  Both calls
  * synchronize `stream`. */
-#define TG_AD_MAX_RESTART 256
+#define TG_AD_MAX_RESTART 512
 int tg_adaptive_workspace_bytes(const tg_grid* g, int restart, int inner_steps, size_t* bytes);
 /* *accepted_h (may be NULL) = 1 if the correction was kept. */
 int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int prec, int inner_steps, void* ws_d,

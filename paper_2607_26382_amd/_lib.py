@@ -162,7 +162,7 @@ PROTOTYPES = {
     "tg_timer_name": (C.c_char_p, [_I]),
 }
 TG_KT_COUNT = 9
-TG_AD_MAX_RESTART = 256
+TG_AD_MAX_RESTART = 512
 
 
 def header_symbols(path=HEADER):

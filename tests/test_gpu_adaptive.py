@@ -95,6 +95,21 @@ def test_solve_matches_oracle(dims, kind, rmin, restart):
     assert np.linalg.norm(uf - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
 
 
+def test_single_sweep_gram_schmidt_matches_oracle():
+    dims = (16, 8, 8)
+    rho = _field("blob", dims, 1001)
+    og, free, H, g = _setup(dims, rho, 1e-6, max_restart=30)
+    K = H[0].K
+    M = oad.adaptive_preconditioner(H, 20)
+    ref = ofg.fgmres(lambda v: K @ v, M, og.edge_load()[free], 30, 200, 1e-6, cgs_passes=1)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist, acc = g.adaptive_solve(f, tg.solver_opts(restart=30, max_iters=200, cgs_passes=1), 20)
+    n = min(len(hist), len(ref.hist), 25)
+    assert np.allclose(hist[:n], ref.hist[:n], rtol=1e-7, atol=0)
+    assert abs(res["iterations"] - ref.iters) <= 1
+    assert acc[:10] == M.log[:10]
+
+
 def test_fewer_outer_iterations_than_the_plain_cycle():
     # on this state the correction is kept and cuts the outer iterations
     dims = (32, 16, 16)
@@ -133,7 +148,7 @@ def test_errors():
     assert lib().tg_adaptive_precondition(*args, tg.F64, 20, C.c_void_p(ptr), nb.value - 8, C.byref(acc),
                                           None) != 0
     assert lib().tg_adaptive_precondition(*args, 9, 20, C.c_void_p(ptr), nb.value, C.byref(acc), None) != 0
-    assert lib().tg_adaptive_workspace_bytes(g.handle, 257, 20, C.byref(nb)) != 0
+    assert lib().tg_adaptive_workspace_bytes(g.handle, 513, 20, C.byref(nb)) != 0
     with pytest.raises(TopoguardError):
         g.adaptive_solve(torch.tensor(g.edge_load(), device=DEV), tg.solver_opts(restart=0), 20)
     # zero right-hand side: nothing to do, zero solution
