@@ -529,8 +529,9 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
             f"false acceptances caught {r['proj_converged_guard_rejects']}, {r['seconds_per_solve']:.3f} s/solve")
     n_paper = min(n_paper, len(rhos))
     ps = {"states": n_paper, "p": 4.5, "floor": 1e-12, "solve": "FGMRES(300), cap 300, FP64 throughout, CGS2",
-          "adaptive_cgs1": "the same with one Gram-Schmidt sweep per step"}
-    for name, inner, passes in (("adaptive", 20, 2), ("plain_vcycle", 0, 2), ("adaptive_cgs1", 20, 1)):
+          "cgs1": "variants *_cgs1: one Gram-Schmidt sweep per step"}
+    for name, inner, passes in (("adaptive", 20, 2), ("plain_vcycle", 0, 2), ("adaptive_cgs1", 20, 1),
+                                ("plain_vcycle_cgs1", 0, 1)):
         o = tg.solver_opts(restart=300, max_iters=300, prec=tg.F64, cgs_passes=passes)
         ps[name] = adaptive_runs(tg, torch, g, rhos[:n_paper], fs[:n_paper], 4.5, 1e-12, o, inner)
         r = ps[name]
