@@ -208,7 +208,8 @@ int tg_probe_checkpoints(tg_grid* g, const double* f_d, const tg_solver_opts* o,
  * synchronize `stream`. */
 #define TG_AD_MAX_RESTART 512
 int tg_adaptive_workspace_bytes(const tg_grid* g, int restart, int inner_steps, size_t* bytes);
-/* *accepted_h (may be NULL) = 1 if the correction was kept. */
+/* v_d and z_d must not overlap; *accepted_h (may be NULL) = 1 if the correction
+ * was kept. */
 int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int prec, int inner_steps, void* ws_d,
                              size_t ws_bytes, int* accepted_h, void* stream);
 /* FGMRES (o->restart >= 1, o->max_iters, o->tol, o->breakdown; cgs_passes 1
@@ -217,7 +218,8 @@ int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int pre
  * for max_iters + 1) receives iterations + 1 values.  accepted_h (may be NULL,
  * room for max_iters + 1) receives, per application of M in order, 1 if its
  * correction was kept; *n_applied_h (may be NULL) = the number of
- * applications.  x0 = 0; res->true_eta = -1 (the guard is tg_true_residual). */
+ * applications.  x0 = 0; f_d and u_d must not overlap; res->true_eta = -1 (the
+ * guard is tg_true_residual). */
 int tg_adaptive_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
                       void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, int* accepted_h,
                       int* n_applied_h, void* stream);
