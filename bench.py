@@ -539,6 +539,22 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
             f"{r['certified']}/{n_paper}, false acceptances caught {r['proj_converged_guard_rejects']}, "
             f"MAXIT {r['maxit']}, true/projected at stop {r['true_over_projected_at_stop']}, "
             f"{r['seconds_per_solve']:.3f} s/solve")
+    # periodic true-residual checkpoints (every 10 iterations) on the states
+    # whose one-sweep solve stopped on a drifted estimate: the first
+    # checkpoint where the recomputed residual exceeds the estimate twofold
+    drift = []
+    o = tg.solver_opts(restart=300, max_iters=300, prec=tg.F64, cgs_passes=1)
+    for i, row in enumerate(ps["adaptive_cgs1"]["per_state"]):
+        if row[1] != "PROJ_CONVERGED" or row[3] <= 1e-6:
+            continue
+        g.set_density(rhos[i], 4.5, 1e-12)
+        _, res, cps = g.adaptive_checkpoints(fs[i], o, 20, every=10)
+        first = next((k for k, pj, tr in cps if tr > 2 * pj), None)
+        drift.append({"state": SEED0 + i, "stop_iteration": res["iterations"], "first_flagged_checkpoint": first,
+                      "checkpoints": cps})
+        log(f"adaptive leg, checkpoints on state {SEED0 + i}: stop at {res['iterations']}, "
+            f"first checkpoint with true > 2 x projected at {first}")
+    ps["adaptive_cgs1_checkpoints"] = drift
     out["paper_setting"] = ps
     del g
     torch.cuda.empty_cache()

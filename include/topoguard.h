@@ -223,6 +223,16 @@ int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int pre
 int tg_adaptive_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
                       void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, int* accepted_h,
                       int* n_applied_h, void* stream);
+/* tg_adaptive_solve with periodic true-residual checkpoints (the detector
+ * variant Sec. 4.1.1 leaves untested, here under the adaptive preconditioner):
+ * after every `every` (>= 1) iterations the FP64 relative residual of the
+ * current iterate x_k = x_0 + Z_k y_k is recomputed without changing the
+ * iteration.  For the first min(cap, count) checkpoints: k_h[i] = k,
+ * proj_h[i] = the history value at k, true_h[i] = that residual; *n_h = number
+ * written.  u_d receives the solution as in tg_adaptive_solve. */
+int tg_adaptive_checkpoints(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
+                            int every, int cap, void* ws_d, size_t ws_bytes, tg_solve_result* res, int* k_h,
+                            double* proj_h, double* true_h, int* n_h, void* stream);
 
 /* ---- policy (Alg. floor_policy) ------------------------------------------ */
 enum { TG_SELECT_RULE = 0, TG_SELECT_MLP = 1, TG_SELECT_FIXED = 2 };

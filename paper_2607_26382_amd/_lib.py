@@ -155,6 +155,9 @@ PROTOTYPES = {
     "tg_adaptive_precondition": (_I, [_P, _P, _P, _I, _I, _P, _SZ, C.POINTER(_I), _P]),
     "tg_adaptive_solve": (_I, [_P, _P, _P, C.POINTER(SolverOpts), _I, _P, _SZ, C.POINTER(SolveResult),
                                C.POINTER(_D), C.POINTER(_I), C.POINTER(_I), _P]),
+    "tg_adaptive_checkpoints": (_I, [_P, _P, _P, C.POINTER(SolverOpts), _I, _I, _I, _P, _SZ,
+                                     C.POINTER(SolveResult), C.POINTER(_I), C.POINTER(_D), C.POINTER(_D),
+                                     C.POINTER(_I), _P]),
     "tg_extreme_eigenvalues": (_I, [_P, _I, _I, _D, _P, _SZ, C.POINTER(SpectrumResult), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),

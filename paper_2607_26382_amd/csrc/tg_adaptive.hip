@@ -300,6 +300,13 @@ struct Ctx {
   int* ictl() const { return (int*)(isc() + IS_N); }
   bool flag_pending = false;   // a decision of M waits in isc()[IS_ACC]
   std::vector<int> accepted;
+  // true-residual checkpoints of the outer iteration (every cp_every steps)
+  struct Checkpoint {
+    int k;
+    double proj, eta;
+  };
+  int cp_every = 0;
+  std::vector<Checkpoint> cps;
 };
 
 // out (default tmp) = V^T w over nv basis vectors; h = out or h += out (h
@@ -468,6 +475,22 @@ int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, d
       jdone = j + 1;
       const double est = std::fabs(g[j + 1]) / bnorm;
       out.hist.push_back(est);
+      if (c.cp_every > 0 && k % c.cp_every == 0) {
+        // recomputed residual of x_k = x + Z y_k, y_k over the columns so far;
+        // the iteration itself is unchanged (W(2), W(3) are free between
+        // applications of M)
+        const std::vector<double> y = lsq(H, ldh, g, jdone);
+        double* xk = c.W(3);
+        double* t = c.W(2);
+        TG_HIP(hipMemcpyAsync(c.coef(), y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, c.s));
+        TG_HIP(hipMemcpyAsync(xk, x, sizeof(double) * c.L.n, hipMemcpyDeviceToDevice, c.s));
+        if ((rc = update(c, K.Z, jdone, c.coef(), 1.0, xk))) return rc;
+        if ((rc = applyK(c, xk, t))) return rc;
+        if ((rc = axpby(c, 1.0, b, -1.0, t, t))) return rc;
+        double rn;
+        if ((rc = norm(c, t, &rn))) return rc;   // synchronizes: y is no longer read
+        c.cps.push_back({k, est, rn / bnorm});
+      }
       if (est <= tol) stop = TG_PROJ_CONVERGED;
       else if (hn <= brk * wnorm0) stop = TG_BREAKDOWN;
       else if (k >= max_iters) stop = TG_MAXIT;
@@ -563,6 +586,46 @@ int check_common(tg_grid* g, int prec, int restart, int inner, void* ws_d, size_
 }
 
 }  // namespace
+
+static int adaptive_solve_impl(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
+                        int every, int cap, void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h,
+                        int* accepted_h, int* n_applied_h, int* k_h, double* proj_h, double* true_h, int* n_h,
+                        void* stream) {
+  if (!f_d || !u_d || !o || !res) return fail(TG_EINVAL, "NULL argument");
+  if (o->restart < 1) return fail(TG_EINVAL, "restart must be >= 1");
+  if (o->max_iters < 0 || !(o->tol >= 0.0)) return fail(TG_EINVAL, "need max_iters >= 0 and tol >= 0");
+  if (o->cgs_passes < 1 || o->cgs_passes > 3) return fail(TG_EINVAL, "cgs_passes must be 1, 2 or 3");
+  Layout L;
+  int rc = check_common(g, o->prec, o->restart, inner_steps, ws_d, ws_bytes, L);
+  if (rc) return rc;
+  Ctx c{g, (hipStream_t)stream, o->prec, L, (char*)ws_d, {}};
+  c.cp_every = every;
+  Krylov outer{c.vec(L.oV, 0), c.vec(L.oZ, 0), L.m};
+  Outcome out;
+  auto M = [&c](const double* v, double* z) { return adaptive_apply(c, v, z); };
+  if ((rc = fgmres(c, outer, f_d, u_d, o->max_iters, o->tol, o->cgs_passes == 1 ? 1 : 2, o->breakdown, M, out)))
+    return rc;
+  TG_HIP(hipStreamSynchronize(c.s));
+  res->iterations = out.iters;
+  res->outcome = out.outcome;
+  res->proj_eta = out.hist.back();
+  res->true_eta = -1.0;
+  if (hist_h) std::memcpy(hist_h, out.hist.data(), sizeof(double) * out.hist.size());
+  const int na = (int)std::min<size_t>(c.accepted.size(), (size_t)o->max_iters + 1);
+  if (accepted_h) std::copy(c.accepted.begin(), c.accepted.begin() + na, accepted_h);
+  if (n_applied_h) *n_applied_h = (int)c.accepted.size();
+  if (n_h) {
+    const int nc = (int)std::min<size_t>(c.cps.size(), (size_t)cap);
+    for (int i = 0; i < nc; ++i) {
+      k_h[i] = c.cps[i].k;
+      proj_h[i] = c.cps[i].proj;
+      true_h[i] = c.cps[i].eta;
+    }
+    *n_h = nc;
+  }
+  return TG_OK;
+}
+
 }  // namespace tg
 
 using namespace tg;
@@ -597,29 +660,18 @@ int tg_adaptive_precondition(tg_grid* g, const double* v_d, double* z_d, int pre
 int tg_adaptive_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
                       void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, int* accepted_h,
                       int* n_applied_h, void* stream) {
-  if (!f_d || !u_d || !o || !res) return fail(TG_EINVAL, "NULL argument");
-  if (o->restart < 1) return fail(TG_EINVAL, "restart must be >= 1");
-  if (o->max_iters < 0 || !(o->tol >= 0.0)) return fail(TG_EINVAL, "need max_iters >= 0 and tol >= 0");
-  if (o->cgs_passes < 1 || o->cgs_passes > 3) return fail(TG_EINVAL, "cgs_passes must be 1, 2 or 3");
-  Layout L;
-  int rc = check_common(g, o->prec, o->restart, inner_steps, ws_d, ws_bytes, L);
-  if (rc) return rc;
-  Ctx c{g, (hipStream_t)stream, o->prec, L, (char*)ws_d, {}};
-  Krylov outer{c.vec(L.oV, 0), c.vec(L.oZ, 0), L.m};
-  Outcome out;
-  auto M = [&c](const double* v, double* z) { return adaptive_apply(c, v, z); };
-  if ((rc = fgmres(c, outer, f_d, u_d, o->max_iters, o->tol, o->cgs_passes == 1 ? 1 : 2, o->breakdown, M, out)))
-    return rc;
-  TG_HIP(hipStreamSynchronize(c.s));
-  res->iterations = out.iters;
-  res->outcome = out.outcome;
-  res->proj_eta = out.hist.back();
-  res->true_eta = -1.0;
-  if (hist_h) std::memcpy(hist_h, out.hist.data(), sizeof(double) * out.hist.size());
-  const int na = (int)std::min<size_t>(c.accepted.size(), (size_t)o->max_iters + 1);
-  if (accepted_h) std::copy(c.accepted.begin(), c.accepted.begin() + na, accepted_h);
-  if (n_applied_h) *n_applied_h = (int)c.accepted.size();
-  return TG_OK;
+  return tg::adaptive_solve_impl(g, f_d, u_d, o, inner_steps, 0, 0, ws_d, ws_bytes, res, hist_h, accepted_h,
+                                 n_applied_h, nullptr, nullptr, nullptr, nullptr, stream);
+}
+
+int tg_adaptive_checkpoints(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, int inner_steps,
+                            int every, int cap, void* ws_d, size_t ws_bytes, tg_solve_result* res, int* k_h,
+                            double* proj_h, double* true_h, int* n_h, void* stream) {
+  if (every < 1 || cap < 0) return fail(TG_EINVAL, "need every >= 1 and cap >= 0");
+  if (cap > 0 && (!k_h || !proj_h || !true_h)) return fail(TG_EINVAL, "NULL checkpoint array");
+  if (!n_h) return fail(TG_EINVAL, "NULL argument");
+  return tg::adaptive_solve_impl(g, f_d, u_d, o, inner_steps, every, cap, ws_d, ws_bytes, res, nullptr, nullptr,
+                                 nullptr, k_h, proj_h, true_h, n_h, stream);
 }
 
 }  // extern "C"

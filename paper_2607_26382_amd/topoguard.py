@@ -209,6 +209,23 @@ class Grid:
         n = min(na.value, opts.max_iters + 1)
         return u, result_dict(res), hist[:res.iterations + 1].copy(), [bool(acc[i]) for i in range(n)]
 
+    def adaptive_checkpoints(self, f, opts=None, inner_steps=20, every=10):
+        """(u, result dict, [(k, projected, true)]): the adaptive solve with a
+        recomputed residual of the iterate every `every` iterations."""
+        opts = opts or solver_opts()
+        nb = C.c_size_t()
+        check(lib().tg_adaptive_workspace_bytes(self.handle, opts.restart, int(inner_steps), C.byref(nb)))
+        ws, wptr = _alloc_ws(nb.value, self.device)
+        u = torch.empty_like(f)
+        res = L.SolveResult()
+        cap = opts.max_iters // max(int(every), 1) + 1
+        ks, pj, tr, n = (C.c_int * cap)(), (C.c_double * cap)(), (C.c_double * cap)(), C.c_int()
+        check(lib().tg_adaptive_checkpoints(self.handle, _ptr(f), _ptr(u), C.byref(opts), int(inner_steps),
+                                            int(every), cap, C.c_void_p(wptr), nb.value, C.byref(res), ks, pj, tr,
+                                            C.byref(n), _stream()))
+        del ws
+        return u, result_dict(res), [(ks[i], pj[i], tr[i]) for i in range(n.value)]
+
     def density_features(self, rho, p=3.0, rho0=1e-9):
         """Six density statistics of rho (device FP64) at probe floor rho0."""
         out = (C.c_double * 6)()

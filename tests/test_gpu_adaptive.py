@@ -110,6 +110,25 @@ def test_single_sweep_gram_schmidt_matches_oracle():
     assert acc[:10] == M.log[:10]
 
 
+def test_checkpoints_match_oracle_and_leave_the_iteration_unchanged():
+    dims = (16, 8, 8)
+    rho = _field("blob", dims, 1001)
+    og, free, H, g = _setup(dims, rho, 1e-6)
+    K = H[0].K
+    M = oad.adaptive_preconditioner(H, 20)
+    ref = ofg.fgmres(lambda v: K @ v, M, og.edge_load()[free], 30, 200, 1e-6, checkpoint_every=4)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    o = tg.solver_opts(restart=30, max_iters=200)
+    u, res, cps = g.adaptive_checkpoints(f, o, 20, every=4)
+    u2, res2, hist, acc = g.adaptive_solve(f, o, 20)
+    assert torch.equal(u, u2) and res == res2
+    assert len(cps) == res["iterations"] // 4 and len(cps) >= 2
+    n = min(len(cps), len(ref.checkpoints))
+    for (k, pj, tr), (kr, er) in zip(cps[:n], ref.checkpoints[:n]):
+        assert k == kr and abs(tr - er) <= 1e-6 * er
+        assert pj == hist[k]
+
+
 def test_fewer_outer_iterations_than_the_plain_cycle():
     # on this state the correction is kept and cuts the outer iterations
     dims = (32, 16, 16)
