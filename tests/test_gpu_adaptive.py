@@ -70,6 +70,7 @@ def test_zero_inner_steps_is_the_vcycle():
 
 
 @pytest.mark.parametrize("dims,kind,rmin,restart", [((16, 8, 8), "uniform", 1e-3, 30),
+                                                    ((16, 8, 8), "uniform", 1e-3, 1),
                                                     ((16, 8, 8), "blob", 1e-9, 7),
                                                     ((32, 16, 16), "blob", 1e-3, 30)])
 def test_solve_matches_oracle(dims, kind, rmin, restart):
