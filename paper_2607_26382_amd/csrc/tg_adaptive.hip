@@ -248,7 +248,7 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_to64(const float* __restrict__ 
 }
 
 // Workspace of one call: outer basis (m + 1) + m vectors, inner basis
-// (q + 1) + q vectors, five work vectors, two float vectors, partials and
+// (q + 1) + q vectors, four work vectors, two float vectors, partials and
 // small device arrays.
 struct Layout {
   long long n = 0, ld = 0;
@@ -266,7 +266,7 @@ struct Layout {
     oZ = o; o += (size_t)m * vb;
     iV = o; o += (size_t)(q > 0 ? q + 1 : 0) * vb;
     iZ = o; o += (size_t)q * vb;
-    wv = o; o += 5 * vb;
+    wv = o; o += 4 * vb;
     f32 = o; o += 2 * al((size_t)n * sizeof(float));
     part = o; o += al((size_t)nb * AD_MAXV * sizeof(double));
     small = o; o += al(4 * AD_MAXV * sizeof(double));
@@ -283,7 +283,7 @@ struct Ctx {
   Layout L;
   char* base;
   double* vec(size_t off, int j) const { return (double*)(base + off) + (long long)j * L.ld; }
-  double* W(int i) const { return vec(L.wv, i); }   // 0: w, 1: r/s, 2: t, 3: d, 4: s kept
+  double* W(int i) const { return vec(L.wv, i); }   // 0: w, 1: r / s, 2: t, 3: d
   float* r32() const { return (float*)(base + L.f32); }
   float* z32() const { return (float*)(base + L.f32 + al((size_t)L.n * sizeof(float))); }
   double* part() const { return (double*)(base + L.part); }
