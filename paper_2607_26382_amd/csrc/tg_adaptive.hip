@@ -43,9 +43,11 @@ size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 long long ld_of(long long n) { return (n + 31) & ~31LL; }   // doubles per basis vector (256-byte rows)
 
 // part[q * gridDim.x + block] = sum over the block's strided range of V_q[i] w[i]
+// for q < nv, and (with_self) of w[i]^2 for q = nv
 __global__ __launch_bounds__(AD_BLOCK) void k_ad_dots(const double* __restrict__ V, long long ld, int nv,
-                                                      const double* __restrict__ w, long long n,
+                                                      int with_self, const double* __restrict__ w, long long n,
                                                       double* __restrict__ part) {
+  const int nt = nv + with_self;
   __shared__ double red[AD_BLOCK / 64][AD_QG];
   const int q0 = blockIdx.y * AD_QG;
   double acc[AD_QG];
@@ -54,8 +56,10 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_dots(const double* __restrict__
   for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK) {
     const double wi = w[i];
 #pragma unroll
-    for (int t = 0; t < AD_QG; ++t)
+    for (int t = 0; t < AD_QG; ++t) {
       if (q0 + t < nv) acc[t] += V[(long long)(q0 + t) * ld + i] * wi;
+      else if (q0 + t == nv && with_self) acc[t] += wi * wi;
+    }
   }
 #pragma unroll
   for (int t = 0; t < AD_QG; ++t) {
@@ -65,7 +69,7 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_dots(const double* __restrict__
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][t] = s;
   }
   __syncthreads();
-  if (threadIdx.x < AD_QG && q0 + (int)threadIdx.x < nv) {
+  if (threadIdx.x < AD_QG && q0 + (int)threadIdx.x < nt) {
     double s = 0.0;
     for (int w8 = 0; w8 < AD_BLOCK / 64; ++w8) s += red[w8][threadIdx.x];
     part[(long long)(q0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
@@ -74,17 +78,22 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_dots(const double* __restrict__
 
 // out[q] = sum_b part[q nb + b], one wavefront per q (lane-strided partial
 // sums, then a butterfly; a fixed order for a given block count); h[q] =
-// out[q] (acc = 0) or h[q] + out[q] (acc = 1)
+// out[q] (acc = 0) or h[q] + out[q] (acc = 1); the sum q = nv (if the grid
+// has it) goes to *self_out
 __global__ __launch_bounds__(64) void k_ad_sum(const double* __restrict__ part, int nb, int nv,
-                                               double* __restrict__ out, double* __restrict__ h, int acc) {
+                                               double* __restrict__ out, double* __restrict__ h, int acc,
+                                               double* __restrict__ self_out) {
   const int q = blockIdx.x;
-  if (q >= nv) return;
   double s = 0.0;
 #pragma unroll 4
   for (int b = threadIdx.x; b < nb; b += 64) s += part[(long long)q * nb + b];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (threadIdx.x == 0) {
+    if (q == nv) {
+      *self_out = s;
+      return;
+    }
     out[q] = s;
     if (h) h[q] = acc ? h[q] + s : s;
   }
@@ -101,6 +110,34 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_update(const double* __restrict
     double s = 0.0;
     for (int q = 0; q < nv; ++q) s += sc[q] * V[(long long)q * ld + i];
     w[i] += sgn * s;
+  }
+}
+
+// w -= sum_q c[q] V_q, and part[block] = the block's sum of the updated
+// w[i]^2 (the norm after the last sweep without another pass over w)
+__global__ __launch_bounds__(AD_BLOCK) void k_ad_update_norm(const double* __restrict__ V, long long ld, int nv,
+                                                             const double* __restrict__ c, double* __restrict__ w,
+                                                             long long n, double* __restrict__ part) {
+  __shared__ double sc[AD_MAXV];
+  __shared__ double red[AD_BLOCK / 64];
+  for (int q = threadIdx.x; q < nv; q += AD_BLOCK) sc[q] = c[q];
+  __syncthreads();
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK) {
+    double s = 0.0;
+    for (int q = 0; q < nv; ++q) s += sc[q] * V[(long long)q * ld + i];
+    const double wn = w[i] - s;
+    w[i] = wn;
+    acc += wn * wn;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w8 = 0; w8 < AD_BLOCK / 64; ++w8) s += red[w8];
+    part[blockIdx.x] = s;
   }
 }
 
@@ -310,12 +347,24 @@ struct Ctx {
 };
 
 // out (default tmp) = V^T w over nv basis vectors; h = out or h += out (h
-// may be NULL)
-int dots(Ctx& c, const double* V, int nv, const double* w, double* h, int acc, double* out = nullptr) {
-  dim3 grid(c.L.nb, (nv + AD_QG - 1) / AD_QG);
-  k_ad_dots<<<grid, AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, w, c.L.n, c.part());
+// may be NULL); self_out (may be NULL) = w^T w from the same pass
+int dots(Ctx& c, const double* V, int nv, const double* w, double* h, int acc, double* out = nullptr,
+         double* self_out = nullptr) {
+  const int ws = self_out ? 1 : 0;
+  dim3 grid(c.L.nb, (nv + ws + AD_QG - 1) / AD_QG);
+  k_ad_dots<<<grid, AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, ws, w, c.L.n, c.part());
   TG_HIP(hipGetLastError());
-  k_ad_sum<<<nv, 64, 0, c.s>>>(c.part(), c.L.nb, nv, out ? out : c.tmp(), h, acc);
+  k_ad_sum<<<nv + ws, 64, 0, c.s>>>(c.part(), c.L.nb, nv, out ? out : c.tmp(), h, acc, self_out);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+// w -= V coef (nv vectors), then *norm2_out = w^T w
+int update_norm(Ctx& c, const double* V, int nv, const double* coef_d, double* w, double* norm2_out) {
+  const int nb = nblk(c.L.n);
+  k_ad_update_norm<<<nb, AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, coef_d, w, c.L.n, c.part());
+  TG_HIP(hipGetLastError());
+  k_ad_sum<<<1, 64, 0, c.s>>>(c.part(), nb, 0, nullptr, nullptr, 0, norm2_out);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -431,12 +480,16 @@ int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, d
       double* zj = K.Z + (long long)j * c.L.ld;
       if ((rc = M(vj, zj))) return rc;
       if ((rc = applyK(c, zj, w))) return rc;
-      if ((rc = dots(c, w, 1, w, nullptr, 0, c.scal()))) return rc;
+      // ||w||^2 rides on the first sweep's dots, ||w||^2 after the last
+      // sweep on its update
       for (int pass = 0; pass < passes; ++pass) {
-        if ((rc = dots(c, K.V, j + 1, w, c.h(), pass > 0))) return rc;
-        if ((rc = update(c, K.V, j + 1, c.tmp(), -1.0, w))) return rc;
+        if ((rc = dots(c, K.V, j + 1, w, c.h(), pass > 0, nullptr, pass == 0 ? c.scal() : nullptr))) return rc;
+        if (pass + 1 < passes) {
+          if ((rc = update(c, K.V, j + 1, c.tmp(), -1.0, w))) return rc;
+        } else if ((rc = update_norm(c, K.V, j + 1, c.tmp(), w, c.scal() + 1))) {
+          return rc;
+        }
       }
-      if ((rc = dots(c, w, 1, w, nullptr, 0, c.scal() + 1))) return rc;
       double sq[2], acc = 0.0;
       TG_HIP(hipMemcpyAsync(hcol.data(), c.h(), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.s));
       TG_HIP(hipMemcpyAsync(sq, c.scal(), sizeof(sq), hipMemcpyDeviceToHost, c.s));
@@ -548,12 +601,10 @@ int adaptive_apply(Ctx& c, const double* v, double* z) {
     double* zj = Zi + (long long)j * c.L.ld;
     if ((rc = jacobi(c, vj, zj))) return rc;
     if ((rc = applyK(c, zj, w))) return rc;
-    if ((rc = dots(c, w, 1, w, nullptr, 0, sc + IS_WN0))) return rc;
-    for (int pass = 0; pass < 2; ++pass) {
-      if ((rc = dots(c, Vi, j + 1, w, c.h(), pass > 0))) return rc;
-      if ((rc = update(c, Vi, j + 1, c.tmp(), -1.0, w))) return rc;
-    }
-    if ((rc = dots(c, w, 1, w, nullptr, 0, sc + IS_HN))) return rc;
+    if ((rc = dots(c, Vi, j + 1, w, c.h(), 0, nullptr, sc + IS_WN0))) return rc;
+    if ((rc = update(c, Vi, j + 1, c.tmp(), -1.0, w))) return rc;
+    if ((rc = dots(c, Vi, j + 1, w, c.h(), 1))) return rc;
+    if ((rc = update_norm(c, Vi, j + 1, c.tmp(), w, sc + IS_HN))) return rc;
     k_ad_givens<<<1, 1, 0, c.s>>>(j, q, 1e-14, c.h(), c.iH(), c.ig(), c.ics(), c.isn(), sc, ctl);
     TG_HIP(hipGetLastError());
     if (j + 1 < q) {
