@@ -212,3 +212,33 @@ def test_full_size_against_the_oracle_operator(prec):
     assert res["iterations"] == 12 and res["outcome"] == "MAXIT" and len(acc) == 12
     eta = np.linalg.norm((f - op.apply_full(og, E, KE, u.cpu().numpy()))[free]) / np.linalg.norm(f[free])
     assert abs(eta - hist[-1]) <= 1e-6 * eta
+
+
+def test_largest_restart():
+    """restart = TG_AD_MAX_RESTART with no tolerance: one cycle runs until the
+    estimate underflows to 0 (about 350 Arnoldi steps, so the multi-dot and
+    the sweeps reach bases of over 256 vectors), following the oracle."""
+    dims = (16, 8, 8)
+    rho = _field("blob", dims, 7)
+    og, free, H, g = _setup(dims, rho, 1e-9)
+    K = H[0].K
+    ref = ofg.fgmres(lambda v: K @ v, lambda v: omg.vcycle(H, v), og.edge_load()[free], 512, 512, 0.0)
+    print(f"restart 512: oracle {ref.iters} iterations, outcome {ref.outcome}", flush=True)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist, acc = g.adaptive_solve(f, tg.solver_opts(restart=512, max_iters=512, tol=0.0), 0)
+    assert len(hist) == res["iterations"] + 1 and np.all(np.isfinite(hist))
+    # at rho_min = 1e-9 the cycle's explicit coarsest inverse and the oracle's
+    # Cholesky solve differ by about kappa_c eps (1e-8 relative), which the
+    # early history carries at the 1e-7 level
+    n = min(len(hist), len(ref.hist), 25)
+    assert np.allclose(hist[:n], ref.hist[:n], rtol=1e-6, atol=0)
+    assert res["outcome"] == "PROJ_CONVERGED" and ref.outcome == ofg.PROJ_CONVERGED
+    assert res["iterations"] > 256 and abs(res["iterations"] - ref.iters) <= 32
+    # the estimate underflows to 0 while the recomputed residual stays at this
+    # operator's attainable accuracy in FP64 (about 2.6e-7 on both sides)
+    ff = og.edge_load()[free]
+    eta_ref = np.linalg.norm(ff - K @ ref.x) / np.linalg.norm(ff)
+    eta = g.true_residual(f, u)
+    assert hist[-1] == 0.0 and 0.25 * eta_ref <= eta <= 4 * eta_ref
+    with pytest.raises(TopoguardError):
+        g.adaptive_solve(f, tg.solver_opts(restart=513, max_iters=10), 0)
