@@ -18,7 +18,8 @@ from . import multigrid as mg
 
 def adaptive_preconditioner(levels, inner_steps=20):
     """v -> z: one V-cycle followed by the accepted-or-rejected fine-level
-    correction.  Also returns a callable's log of acceptances."""
+    correction.  The returned callable keeps one keep/reject flag per call in
+    its attribute ``log``."""
     K = levels[0].K
     Binv = levels[0].Binv
     log = []

@@ -115,3 +115,28 @@ def test_default_topopt_struct():
     assert o.policy.n_rungs == 3 and list(o.policy.rungs[:3]) == [1e-12, 1e-3, 1e-2]
     assert (o.policy.t_high, o.policy.probe_iters, o.policy.solve.restart) == (1e-2, 100, 30)
     assert C.sizeof(L.TopoptRecord) == 96
+
+
+def test_adaptive_workspace_sizing():
+    """Host-only: the adaptive path's workspace holds the outer basis (2m + 1
+    vectors), the inner basis (2q + 1), four work vectors, two float vectors
+    and a Hessenberg of the inner iteration; restart and inner steps outside
+    [0, TG_AD_MAX_RESTART] are errors."""
+    h = _grid((16, 8, 8))
+    info = L.GridInfo()
+    L.check(L.lib().tg_get_grid_info(h, C.byref(info)))
+    vb = ((info.n_dof + 31) // 32 * 32) * 8
+    nb = C.c_size_t()
+
+    def size(m, q):
+        L.check(L.lib().tg_adaptive_workspace_bytes(h, m, q, C.byref(nb)))
+        return nb.value
+
+    base = size(0, 0)
+    assert base >= 4 * vb + 2 * info.n_dof * 4
+    assert size(30, 0) - base == 61 * vb
+    assert size(0, 20) - base >= 41 * vb + 21 * 20 * 8
+    assert size(L.TG_AD_MAX_RESTART, 20) > size(30, 20)
+    for m, q in ((L.TG_AD_MAX_RESTART + 1, 20), (30, L.TG_AD_MAX_RESTART + 1), (-1, 0), (0, -1)):
+        assert L.lib().tg_adaptive_workspace_bytes(h, m, q, C.byref(nb)) == L.TG_EINVAL
+    L.lib().tg_destroy(h)
