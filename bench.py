@@ -113,6 +113,8 @@ def parse():
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive-preconditioner leg (fine-level correction)")
     ap.add_argument("--adaptive-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--paper-states", type=int, default=24,
+                    help="states of the adaptive leg's paper-setting part (p = 4.5, rho_0 = 1e-12, FGMRES(300))")
     ap.add_argument("--trajectory-only", action="store_true", help="run only the optimization-loop leg")
     ap.add_argument("--no-fixed-legs", action="store_true",
                     help="skip the fixed-first-rung baselines (original floor first; always the top rung)")
@@ -752,7 +754,7 @@ def main():
         f0 = torch.tensor(tg.Grid(*GRID, max_restart=1, device=dev).edge_load(), device=dev)
         print(json.dumps({"adaptive_preconditioner": adaptive_leg(
             tg, torch, dev, rhos, [f0] * n_ad, {"f32": tg.F32, "bf16": tg.BF16MFMA, "bf16x3": tg.BF16X3MFMA}[args.mixed],
-            n_states=n_ad)}), flush=True)
+            n_states=n_ad, n_paper=args.paper_states)}), flush=True)
         return
     apply_res = None
     if not args.no_apply:
@@ -896,7 +898,8 @@ def main():
         result["screen"] = screen_stats(tg, torch, grids, rhos, labels, RUNGS, 3.0, mixed_prec)
         result["probe_checkpoints"] = checkpoint_stats(tg, torch, grids, rhos, fs, RUNGS, 3.0, mixed_prec)
     if not args.no_adaptive:
-        result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec, n_states=n)
+        result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec, n_states=n,
+                                                         n_paper=args.paper_states)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)
