@@ -113,7 +113,7 @@ def parse():
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive-preconditioner leg (fine-level correction)")
     ap.add_argument("--adaptive-only", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--paper-states", type=int, default=24,
+    ap.add_argument("--paper-states", type=int, default=102,
                     help="states of the adaptive leg's paper-setting part (p = 4.5, rho_0 = 1e-12, FGMRES(300))")
     ap.add_argument("--trajectory-only", action="store_true", help="run only the optimization-loop leg")
     ap.add_argument("--no-fixed-legs", action="store_true",
@@ -509,7 +509,7 @@ def adaptive_runs(tg, torch, g, rhos, fs, p, floor, opts, inner, tau=1e-6):
             "seconds_per_solve": secs / n, "per_state": rows}
 
 
-def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_paper=24):
+def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_paper=102):
     """The fine-level adaptive correction of the preconditioner (Tab.
     solver-config), with it (20 inner node-block-Jacobi GMRES steps, kept only
     if they lower the residual) and without it (inner_steps = 0).  Per
