@@ -527,7 +527,6 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
     for name, inner in (("adaptive", 20), ("plain_vcycle", 0)):
         r = adaptive_runs(tg, torch, g, rhos[:n_states], fs[:n_states], 3.0, floor, o, inner)
         out[name] = {k: v for k, v in r.items() if k != "per_state"}
-        out[name]["true_eta"] = [row[3] for row in r["per_state"]]
         log(f"adaptive leg {name}: mean its {r['mean_iters']:.1f}, certified {r['certified']}/{n_states}, "
             f"false acceptances caught {r['proj_converged_guard_rejects']}, {r['seconds_per_solve']:.3f} s/solve")
     n_paper = min(n_paper, len(rhos))
@@ -555,10 +554,15 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
         _, res, cps = g.adaptive_checkpoints(fs[i], o, 20, every=10)
         first = next((k for k, pj, tr in cps if tr > 2 * pj), None)
         drift.append({"state": SEED0 + i, "stop_iteration": res["iterations"], "first_flagged_checkpoint": first,
-                      "checkpoints": cps})
+                      "true_over_projected": [round(tr / pj, 4) for k, pj, tr in cps if pj > 0]})
         log(f"adaptive leg, checkpoints on state {SEED0 + i}: stop at {res['iterations']}, "
             f"first checkpoint with true > 2 x projected at {first}")
     ps["adaptive_cgs1_checkpoints"] = drift
+    # per-state rows only where the estimate converged but the guard rejects
+    for name in ("adaptive", "plain_vcycle", "adaptive_cgs1", "plain_vcycle_cgs1"):
+        rows = ps[name].pop("per_state")
+        ps[name]["false_acceptances"] = [[SEED0 + i, row[0], row[2], row[3]] for i, row in enumerate(rows)
+                                         if row[1] == "PROJ_CONVERGED" and row[3] > 1e-6]
     out["paper_setting"] = ps
     del g
     torch.cuda.empty_cache()
