@@ -36,9 +36,19 @@ What it computes (citations are to arXiv 2607.26382):
                    preconditioner (Tab. solver-config): V-cycle, then inner
                    GMRES(20) with node-block Jacobi, kept if it lowers ||r||.
 
-Every function is pinned by tests under ``tests/`` against facts the paper or
-mathematics fix (closed forms, invariants, printed values, library routines on
-special cases).  A function without such a pin would say "parity unpinned"
-here; at present every function has one (Adam by its closed forms: first
-step, constant-gradient steps, geometric moment averages).
+Every function is pinned by tests under ``tests/test_oracle_*.py`` against
+facts the paper or mathematics fix (closed forms, invariants, printed values,
+library routines on special cases, exact rational evaluation).  Private
+helpers (``ke.grad_products_exact``, ``ke.elasticity_D``, ``ke.hadamard8``,
+``fgmres._lsq``, ``topopt.filter_weight_sums``, ``policy.first_rung``) are
+pinned through the functions built on them.  Among the pins: the screen
+against the values printed in Sec. 4.2; the guard's FP64 value and its
+rounding bound against exact rational evaluation; FGMRES's breakdown exit in
+an invariant subspace and its non-finite exits; the reference label and the
+selector's feature layout by scripted cases; Adam by its closed forms.  A
+function without such a pin would say "parity unpinned" here; none does.
+
+Reading of Eq. relative_residual where the paper leaves it undefined: for
+f = 0, eta = 0 when r = 0 too (u = 0 solves it exactly); any other f whose
+norm is not a finite positive number gives NaN, which no acceptance passes.
 """

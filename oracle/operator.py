@@ -87,9 +87,28 @@ def solve_direct(K_ff, f_f):
     return spla.splu(sp.csc_matrix(K_ff)).solve(f_f)
 
 
+def _ratio(nr, nf):
+    """||r|| / ||f||.  Eq. (relative_residual) is undefined for f = 0; the
+    reading taken: 0 when r = 0 as well (u = 0 solves f = 0 exactly), NaN for
+    every other case where ||f|| is not a finite positive number."""
+    if nr == 0.0 and nf == 0.0:
+        return 0.0
+    if not (nf > 0.0 and np.isfinite(nf)):
+        return float("nan")
+    return float(nr / nf)
+
+
 def relative_residual(K_ff, f_f, u_f):
     """Eq. (relative_residual) on free DOFs."""
-    return float(np.linalg.norm(f_f - K_ff @ u_f) / np.linalg.norm(f_f))
+    return _ratio(np.linalg.norm(f_f - K_ff @ u_f), np.linalg.norm(f_f))
+
+
+def relative_residual_full(grid, E, Ke, f, u):
+    """Eq. (relative_residual) with the matrix-free operator, for grids too
+    large to assemble: f, u are full-length vectors, norms over free DOFs."""
+    free = grid.free_dofs()
+    r = np.where(free, f, 0.0) - apply_full(grid, E, Ke, u)
+    return _ratio(np.linalg.norm(r[free]), np.linalg.norm(f[free]))
 
 
 def residual_bound(K_ff, f_f, u_f):
@@ -99,6 +118,16 @@ def residual_bound(K_ff, f_f, u_f):
     nnz_row = int(np.diff(sp.csr_matrix(K_ff).indptr).max())
     eps = np.finfo(float).eps
     return float(nnz_row * eps * np.linalg.norm(absK @ np.abs(u_f) + np.abs(f_f)) / np.linalg.norm(f_f))
+
+
+def residual_bound_full(grid, E, Ke, f, u):
+    """The bound of residual_bound without assembling K: |K| |u| <= sum_e E_e
+    |K_e| |u_e| entrywise (E_e > 0), and a free row of the hex8 operator has
+    at most 81 nonzeros (27 nodes x 3 components)."""
+    free = grid.free_dofs()
+    a = apply_full(grid, E, np.abs(Ke), np.abs(u))
+    eps = np.finfo(float).eps
+    return float(81 * eps * np.linalg.norm((a + np.abs(f))[free]) / np.linalg.norm(f[free]))
 
 
 def compliance(f_f, u_f):

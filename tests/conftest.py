@@ -23,5 +23,6 @@ def read_table(name):
             line = line.strip()
             if not line or line.startswith("#"):
                 continue
-            rows.append(line.split(None, 4) if name == "rule_cases.txt" else line.split(None, 5))
+            n = {"rule_cases.txt": 4, "screen_cases.txt": 4}.get(name, 5)
+            rows.append(line.split(None, n))
     return rows

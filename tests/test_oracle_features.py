@@ -40,3 +40,13 @@ def test_density_statistics_closed_values():
     E = 1e-9 + (1 - 1e-9) * np.array([0.5, 1.0, 0.25, 0.75, 1.0]) ** 3
     assert abs(contrast - np.log10(E.max() / E.min())) < 1e-14
     assert abs(size - np.log10(81)) < 1e-15
+
+
+def test_selector_features_layout():
+    """Network input: log10 r50, log10 r100, then the six density statistics
+    in order; a zero residual (probe converged exactly) is clamped, not -inf."""
+    st = features.density_stats(np.ones(8), 2, 2, 2, 3.0, 1e-9)
+    x = features.selector_features(1e-2, 1e-5, st)
+    assert x[:2] == [-2.0, -5.0] and x[2:] == st and len(x) == 8
+    assert features.selector_features(0.0, 1.0, st)[:2] == [-300.0, 0.0]
+    assert all(np.isfinite(features.selector_features(0.0, 0.0, st)))

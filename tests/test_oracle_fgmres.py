@@ -102,3 +102,47 @@ def test_checkpoints_equal_the_projected_estimates():
     assert len(u.checkpoints) == 8
     for k, eta in u.checkpoints:
         assert eta == pytest.approx(u.hist[k], rel=1e-8)
+
+
+def test_breakdown_in_an_invariant_subspace_gives_the_exact_solution():
+    """A right-hand side inside a 2-dimensional invariant subspace of A: the
+    Krylov space stops growing at the second step (the subdiagonal falls to
+    rounding level), the oracle exits with BREAKDOWN after 2 iterations, and
+    its iterate is the exact solution (a lucky breakdown)."""
+    rng = np.random.default_rng(11)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.linspace(1.0, 50.0, n)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = 3.0 * Q[:, 4] - 2.0 * Q[:, 17]
+    res = fg.fgmres(lambda v: A @ v, lambda v: v, b, restart=30, max_iters=200, tol=0.0)
+    assert res.outcome == fg.BREAKDOWN and res.iters == 2
+    x = 3.0 / lam[4] * Q[:, 4] - 2.0 / lam[17] * Q[:, 17]
+    assert np.linalg.norm(res.x - x) <= 1e-12 * np.linalg.norm(x)
+    # with a positive tolerance the same system converges on its estimate
+    res2 = fg.fgmres(lambda v: A @ v, lambda v: v, b, restart=30, max_iters=200, tol=1e-10)
+    assert res2.outcome == fg.PROJ_CONVERGED and res2.iters == 2
+
+
+def test_nonfinite_exits():
+    """A non-finite right-hand side stops before the first step; a
+    preconditioner that returns a non-finite vector stops at that step with
+    the column left out, so the iterate stays the finite one of the steps
+    before."""
+    g, E, K, f = _system(seed=5)
+    bad = f.copy()
+    bad[7] = np.inf
+    r = fg.fgmres(lambda v: K @ v, lambda v: v, bad, restart=10, max_iters=50, tol=1e-8)
+    assert r.outcome == fg.NONFINITE and r.iters == 0 and np.all(r.x == 0)
+    calls = []
+
+    def M(v):
+        calls.append(1)
+        return v * np.nan if len(calls) == 4 else v
+    r = fg.fgmres(lambda v: K @ v, M, f, restart=10, max_iters=50, tol=1e-12)
+    ref = fg.fgmres(lambda v: K @ v, lambda v: v, f, restart=3, max_iters=3, tol=1e-12)
+    assert r.outcome == fg.NONFINITE and r.iters == 3 and np.all(np.isfinite(r.x))
+    # the first three steps are plain GMRES steps: same iterate as a 3-step solve
+    assert np.allclose(r.x, ref.x, rtol=0, atol=1e-12 * np.abs(ref.x).max())
+    assert np.array_equal(r.hist, ref.hist)

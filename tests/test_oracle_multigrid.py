@@ -95,3 +95,9 @@ def test_vcycle_matches_error_propagation_form(dims, rmin, nlev):
     K = H[0].K.toarray()
     rho = np.max(np.abs(np.linalg.eigvals(np.eye(K.shape[0]) - M @ K)))
     assert rho < 1.0
+
+
+def test_free_dof_count_equals_the_grid_mask():
+    from oracle import mesh
+    for dims in ((1, 1, 1), (4, 2, 2), (16, 8, 8), (17, 9, 7), (64, 32, 32)):
+        assert mg.free_dof_count(*dims) == int(mesh.Grid(*dims).free_dofs().sum())

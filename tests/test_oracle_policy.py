@@ -104,3 +104,31 @@ def test_confusion_counts_of_heldout_test():
     pred = [1] * 74 + [0] * 24 + [0] * 4
     ref = [1] * 74 + [0] * 24 + [1] * 4
     assert stats.confusion(pred, ref) == (74, 24, 0, 4)
+
+
+def test_reference_label_is_lowest_rung_passing_the_guard():
+    """Reference label (Sec. 4.3.1 held-out reference): independent solves
+    from the lowest rung up; the first one whose recomputed residual passes
+    is the label, and no rung above it is solved."""
+    m = Mock({1e-9: (200, 1, 3e-4, 3e-4), 1e-6: (85, 0, 8e-7, 2e-6),     # cap; projected-only pass
+              1e-4: (40, 0, 9e-7, 9.9e-7), 1e-3: (20, 0, 5e-7, 4e-7)})
+    assert policy.reference_label(RUNGS, m.solve, m.true_eta) == 2
+    assert m.calls == [1e-9, 1e-6, 1e-4]
+
+
+def test_reference_label_none_and_inclusive():
+    m = Mock({f: (200, 1, 1e-3, 1e-3) for f in RUNGS})
+    assert policy.reference_label(RUNGS, m.solve, m.true_eta) == -1 and m.calls == RUNGS
+    m = Mock({f: (10, 0, 1e-6, 1e-6) for f in RUNGS})
+    assert policy.reference_label(RUNGS, m.solve, m.true_eta, tau=1e-6) == 0
+
+
+@pytest.mark.parametrize("passing", [[], [3], [2, 3], [1, 2, 3], [0, 1, 2, 3], [0, 3], [1, 3]])
+def test_reference_label_equals_ladder_from_the_original_floor(passing):
+    """The label is the rung the guarded ladder reaches from k0 = 0 (the rule
+    quiet), so a rule that never escalates wrongly costs iterations only."""
+    table = {f: (10, 0, 5e-7, 5e-7 if k in passing else 5e-6) for k, f in enumerate(RUNGS)}
+    lab = policy.reference_label(RUNGS, Mock(table).solve, Mock(table).true_eta)
+    m = Mock(table)
+    rung, _, _ = policy.guarded_ladder(RUNGS, 0, m.solve, m.true_eta)
+    assert lab == rung == (min(passing) if passing else -1)

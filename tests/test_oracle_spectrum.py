@@ -8,6 +8,7 @@ import pytest
 from oracle import ke, mesh
 from oracle import operator as op
 from oracle import spectrum as sp
+from conftest import read_table
 
 Ke = ke.ke()
 
@@ -48,3 +49,29 @@ def test_kappa_times_floor_is_fixed_by_the_field():
     c = [sp.condition_number(_K(dims, rho, 3.0, rm)) * rm for rm in (1e-8, 1e-7, 1e-6)]
     assert max(c) / min(c) < 1.01
     assert sp.screen_floor(c[0] / 1e-8, 1e-8) == pytest.approx(c[0] * np.finfo(float).eps / 1e-6)
+
+
+SCREEN_ROWS = read_table("screen_cases.txt")
+
+
+@pytest.mark.parametrize("row", SCREEN_ROWS, ids=[r[4][:40] for r in SCREEN_ROWS])
+def test_screen_on_printed_values(row):
+    """Sec. 4.2 prints kappa up to 1.6e16 at rho_0 = 1e-12 and 3.6e-6 as the
+    hardest field's screen: the oracle's screen reproduces the printed value,
+    and the same pair rules out half the machine epsilon and c = kappa /
+    rho_min."""
+    kappa, rmin, tau, want = (float(x) for x in row[:4])
+    got = sp.screen_floor(kappa, rmin, tau)
+    assert float(f"{got:.1e}") == want
+    assert float(f"{sp.screen_floor(kappa, rmin, tau, eps=2.0 ** -53):.1e}") != want
+    assert float(f"{kappa / rmin * sp.EPS / tau:.1e}") != want
+
+
+def test_screen_is_where_kappa_eps_meets_tau():
+    """With kappa(rho) = c / rho, the screen is the floor at which the
+    indicator kappa eps equals tau (Eq. screen's derivation); floors above it
+    have kappa eps < tau."""
+    c, tau = 125.0, 1e-6
+    s = sp.screen_floor(c / 1e-9, 1e-9, tau)
+    assert (c / s) * sp.EPS == pytest.approx(tau, rel=1e-14)
+    assert (c / (2 * s)) * sp.EPS < tau < (c / (0.5 * s)) * sp.EPS
