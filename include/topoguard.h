@@ -289,6 +289,12 @@ int tg_batch_set_density(tg_batch* b, const double* const* rho_d, double p,
 /* f_d[i] -> u_d[i]; res[i] gets the outcome and (guard) true_eta. */
 int tg_batch_solve(tg_batch* b, const double* const* f_d, double* const* u_d,
                    const tg_solver_opts* o, tg_solve_result* res, void* stream);
+/* History of problem i of the last tg_batch_solve on this batch (the same
+ * values tg_fgmres_solve returns in hist_h: cycle-start true residuals and
+ * in-cycle projected estimates, Tab. residual-semantics): `count` doubles,
+ * count <= res[i].iterations + 1 is meaningful, count <= 4096 accepted.
+ * Synchronizes `stream`.  TG_EINVAL for i or count out of range. */
+int tg_batch_history(const tg_batch* b, int i, int count, double* hist_h, void* stream);
 /* Alg. floor_policy for every problem at once (probe, first rung, ladder). */
 int tg_batch_select_floor(tg_batch* b, const double* const* rho_d, const double* const* f_d,
                           const tg_policy* pol, double* const* u_d, tg_policy_result* out,

@@ -127,6 +127,7 @@ PROTOTYPES = {
     "tg_batch_set_density": (_I, [_P, C.POINTER(_P), _D, C.POINTER(_D), _P]),
     "tg_batch_solve": (_I, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolverOpts),
                             C.POINTER(SolveResult), _P]),
+    "tg_batch_history": (_I, [_P, _I, _I, C.POINTER(_D), _P]),
     "tg_batch_select_floor": (_I, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(Policy),
                                    C.POINTER(_P), C.POINTER(PolicyResult), _P]),
     "tg_mlp_workspace_bytes": (_I, [_I, C.POINTER(_SZ)]),

@@ -1230,14 +1230,23 @@ __global__ __launch_bounds__(256) void k_xupdate_(const ProbDesc* __restrict__ p
   }
 }
 
-// eta = sqrt(r.r / f.f) with tmp[0] = r.r, tmp[1] = f.f
+// eta = sqrt(r.r / f.f) with tmp[0] = r.r, tmp[1] = f.f.  A zero right-hand
+// side solved exactly (r.r = f.f = 0) gives 0; any other f.f that is not a
+// finite positive number (a non-finite entry in f, or f.f = 0 with r != 0)
+// gives NaN, which no acceptance test passes.
 __global__ void k_true_eta_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
                             SmallOffs o, double* out) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   if (threadIdx.x != 0) return;
   const double rr = P.small[o.tmp], ff = P.small[o.tmp + 1];
-  const double eta = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+  double eta;
+  if (rr == 0.0 && ff == 0.0)
+    eta = 0.0;
+  else if (ff > 0.0 && isfinite(ff))
+    eta = sqrt(rr / ff);   // NaN when r.r is NaN, +inf when it overflows
+  else
+    eta = __builtin_nan("");
   P.small[o.scal + SC_TRUE] = eta;
   if (out) out[wi.x] = eta;
 }

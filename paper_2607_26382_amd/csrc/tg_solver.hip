@@ -652,6 +652,14 @@ int tg_batch_solve(tg_batch* tb, const double* const* f_d, double* const* u_d, c
   }
   return copy_out_batch(b, all, u_d, S_X, s);
 }
+int tg_batch_history(const tg_batch* tb, int i, int count, double* hist_h, void* stream) {
+  if (!tb || !hist_h) return fail(TG_EINVAL, "NULL argument");
+  if (!tb->b.ws) return fail(TG_EWORKSPACE, "batch workspace not bound");
+  if (i < 0 || i >= tb->b.n) return fail(TG_EINVAL, "problem index out of range");
+  if (count < 0 || count > TG_HIST_CAP) return fail(TG_EINVAL, "count out of range");
+  if (count == 0) return TG_OK;
+  return read_hist(const_cast<Batch*>(&tb->b), i, count, hist_h, S(stream));
+}
 int tg_batch_autotune(tg_batch* tb, int prec, int force, int* zc_out, double* us_out, void* stream) {
   if (!tb) return fail(TG_EINVAL, "NULL batch");
   if (!tb->b.ws) return fail(TG_EWORKSPACE, "batch workspace not bound");

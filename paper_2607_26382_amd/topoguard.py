@@ -361,7 +361,15 @@ class Batch:
         res = (L.SolveResult * len(fs))()
         check(lib().tg_batch_solve(self.handle, self._ptrs(fs), self._ptrs(us), C.byref(opts), res,
                                    _stream()))
+        self._iters = [r.iterations for r in res]
         return us, [result_dict(r) for r in res]
+
+    def history(self, i):
+        """Residual history of problem i of the last solve (iterations + 1 values)."""
+        n = self._iters[i] + 1
+        h = (C.c_double * n)()
+        check(lib().tg_batch_history(self.handle, i, n, h, _stream()))
+        return np.array(h[:])
 
     def autotune(self, prec=F32, force=False):
         zc, us = (C.c_int * 8)(), (C.c_double * 8)()
