@@ -14,15 +14,20 @@ squares / guard) with the learned selector; the same mixed form with the
 rule, and the plain FP64 form with the rule (the published method), are timed
 beside it.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.
+The last line on stdout is one compact JSON object (under 4 KB) with the
+headline, the roofline of the dominant kernel, the CPU oracle baseline and
+the oracle's recheck of the accepted solutions; every leg's full record goes
+to --full-out (default gpurun_out/bench_full.json).
 """
 import argparse
 import json
 import math
 import os
+import multiprocessing
 import subprocess
 import sys
 import time
+from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -74,6 +79,9 @@ def measured_traffic(cls):
 
 
 GRID = (64, 32, 32)
+# arithmetic of the mixed form: the fine V-cycle operator's contraction, the
+# FP32 V-cycle vectors, FP64 outer operator / Gram-Schmidt / least squares / guard
+DTYPES = {"bf16x3": "bf16x3-mfma+f32+f64", "bf16": "bf16-mfma+f32+f64", "f32": "f32+f64"}
 RUNGS = (1e-9, 1e-6, 1e-4, 1e-3)
 SEED0 = 1000
 HBM_PEAK_GBS = 8000.0
@@ -120,6 +128,10 @@ def parse():
                     help="skip the fixed-first-rung baselines (original floor first; always the top rung)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--no-recheck", action="store_true",
+                    help="skip the oracle's recomputation of the accepted solutions' residuals")
+    ap.add_argument("--full-out", default=os.path.join("gpurun_out", "bench_full.json"),
+                    help="file for the full record of every leg (the stdout line is the compact summary)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-seed", type=int, default=1000, help=argparse.SUPPRESS)
     return ap.parse_args()
@@ -144,6 +156,160 @@ def cpu_baseline_child(seed):
     ofg.fgmres(lambda v: H[0].K @ v, lambda v: omg.vcycle(H, v), f, 30, n_it, 1e-30)
     t2 = time.perf_counter()
     print(json.dumps({"t_setup": t1 - t0, "t_iter": (t2 - t1) / n_it}), flush=True)
+
+
+def _get(d, *keys):
+    for k in keys:
+        if not isinstance(d, dict) or k not in d:
+            return None
+        d = d[k]
+    return d
+
+
+def _r(x, n=4):
+    """Round floats to n significant digits (the summary line stays short)."""
+    if isinstance(x, float) and math.isfinite(x):
+        return float(f"{x:.{n}g}")
+    if isinstance(x, (list, tuple)):
+        return [_r(v, n) for v in x]
+    if isinstance(x, dict):
+        return {k: _r(v, n) for k, v in x.items()}
+    return x
+
+
+def compact(result, full_path=None):
+    """The summary line printed last on stdout (kept under 4 KB): headline,
+    roofline of the dominant kernel, CPU oracle baseline, the FP64 method,
+    apply_K per precision, guard and oracle-recheck figures, and one or two
+    numbers per further leg; `full_path` holds the full record."""
+    r = result
+    c = {k: r.get(k) for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                               "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    cfg = r.get("config") or {}
+    c["config"] = {k: cfg.get(k) for k in ("workload", "states", "grid", "rungs", "p", "probe", "solve",
+                                            "preconditioner")}
+    c["config"]["mixed_form"] = r.get("mixed_form")
+    c["config"]["selector"] = r.get("selector")
+    rf = r.get("roofline")
+    if rf:
+        c["roofline"] = {k: rf.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                                                "avg_launch_us", "alg_bytes_per_launch", "launches")}
+    cb = r.get("cpu_baseline")
+    if cb:
+        c["cpu_baseline"] = {k: cb.get(k) for k in ("value", "unit", "cores", "kind")}
+        c["cpu_baseline"]["sample"] = (cb.get("sample") or "")[:240]
+    c["step_ms"] = {k: _get(r, "step_ms", k) for k in ("median", "iqr")}
+    pol = r.get("policy") or {}
+    c["guard"] = {"certified": pol.get("certified"), "states": pol.get("states"),
+                  "max_accepted_true_eta": pol.get("max_accepted_true_eta"),
+                  "accepted_above_tolerance": pol.get("accepted_above_tolerance"),
+                  "first_attempt_accepted": pol.get("first_attempt_accepted"),
+                  "mean_attempts": pol.get("mean_attempts")}
+    orc = r.get("oracle_recheck")
+    if orc:
+        c["oracle_recheck"] = {k: orc.get(k) for k in ("checked", "false_acceptances_oracle", "above_tau_oracle",
+                                                       "boundary_ambiguous", "max_eta_oracle",
+                                                       "max_abs_gpu_minus_oracle_over_delta")}
+    if "fp64" in r:
+        c["fp64"] = {k: r["fp64"].get(k) for k in ("value", "ms_per_step", "certified", "mean_iters")}
+        c["mixed_over_fp64"] = r.get("mixed_over_fp64")
+    if "mixed_rule" in r:
+        c["mixed_rule"] = {k: r["mixed_rule"].get(k) for k in ("value", "ms_per_step", "certified")}
+        c["selector_gain"] = r.get("selector_gain")
+    st = _get(pol, "stats")
+    if st:
+        c["selector_stats"] = {"sensitivity": _get(st, "sensitivity", "k"), "escalate": _get(st, "sensitivity", "n"),
+                               "specificity": _get(st, "specificity", "k"), "preserve": _get(st, "specificity", "n"),
+                               "guard_fallbacks": st.get("guard_fallbacks"),
+                               "lowest_admissible_selected": st.get("lowest_admissible_selected")}
+    ak = r.get("apply_K")
+    if ak:
+        c["apply_K_256x128x128"] = {}
+        for k in ("f32", "f64", "bf16_mfma", "bf16x3_mfma"):
+            if isinstance(ak.get(k), dict) and "us_per_apply" in ak[k]:
+                c["apply_K_256x128x128"][k] = {"us": ak[k]["us_per_apply"], "GB/s": ak[k]["GB/s"],
+                                               "frac": ak[k]["frac_hbm_peak"]}
+        se = ak.get("sensitivity_f64")
+        if isinstance(se, dict):
+            c["apply_K_256x128x128"]["sensitivity_f64"] = {"us": se["us_per_call"], "GB/s": se["GB/s"],
+                                                           "frac": se["frac_hbm_peak"]}
+    sp_ = r.get("small_plain")
+    if sp_:
+        c["small_plain_16x8x8"] = {"solves_per_s": _get(sp_, "direct_launches", "value"),
+                                   "us_per_iteration": _get(sp_, "direct_launches", "us_per_iteration"),
+                                   "graph_us_per_iteration": _get(sp_, "graph_replay", "us_per_iteration")}
+    bu = r.get("batch_uneven")
+    if bu:
+        c["batch_uneven_192"] = {"mixed": _get(bu, "mixed_batched", "value"),
+                                 "mixed_graphs": _get(bu, "mixed_batched_graphs", "value"),
+                                 "serial": _get(bu, "mixed_serial", "value"), "fp64": _get(bu, "fp64_batched", "value"),
+                                 "guard_passing": _get(bu, "mixed_batched", "guard_passing"),
+                                 "oracle_false_acceptances": _get(bu, "oracle_recheck", "false_acceptances_oracle")}
+    ms = r.get("mixed_at_scale")
+    if ms:
+        c["mixed_at_scale_256x128x128"] = {
+            "iterations": [_get(ms, "mixed", "iterations"), _get(ms, "fp64", "iterations")],
+            "seconds": [_get(ms, "mixed", "seconds"), _get(ms, "fp64", "seconds")],
+            "true_eta": [_get(ms, "mixed", "true_eta"), _get(ms, "fp64", "true_eta")],
+            "rel_error_vs_fp64": ms.get("rel_error_vs_fp64"),
+            "oracle_max_eta": _get(ms, "oracle_recheck", "max_eta_oracle"),
+            "oracle_false_acceptances": _get(ms, "oracle_recheck", "false_acceptances_oracle")}
+    tr = r.get("trajectory")
+    if tr:
+        c["trajectory_s"] = {k: _get(tr, k, "seconds") for k in ("guarded", "guarded_reuse")}
+    ad = r.get("adaptive_preconditioner")
+    if ad:
+        c["adaptive"] = {"certified": [_get(ad, "adaptive", "certified"), _get(ad, "plain_vcycle", "certified")],
+                         "s_per_solve": [_get(ad, "adaptive", "seconds_per_solve"),
+                                         _get(ad, "plain_vcycle", "seconds_per_solve")]}
+    if full_path:
+        c["full_record"] = full_path
+    return _r(c)
+
+
+def recheck_task(item):
+    """The oracle's recomputed residual of one GPU solution (runs in a worker
+    process): eta = ||f - K u|| / ||f|| over free DOFs with the matrix-free
+    FP64 operator of the floor the solution was accepted at, and the rounding
+    bound delta of that evaluation."""
+    dims, rho, p, floor, f, u = item
+    from oracle import ke, mesh
+    from oracle import operator as op
+    g = mesh.Grid(*dims)
+    E = op.young(rho, p, floor)
+    Ke = ke.ke()
+    return op.relative_residual_full(g, E, Ke, f, u), op.residual_bound_full(g, E, Ke, f, u)
+
+
+def oracle_recheck(items, gpu_etas, tau=1e-6, workers=None):
+    """Recheck accepted GPU solutions with the oracle in a pool of host
+    processes.  A false acceptance is an oracle eta above tau by more than
+    the evaluation bound delta; |eta - tau| < delta is boundary-ambiguous."""
+    if not items:
+        return {"checked": 0}
+    env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_keep:
+        os.environ[k] = "1"
+    t0 = time.perf_counter()
+    try:
+        with ProcessPoolExecutor(workers or cpu_cores(), mp_context=multiprocessing.get_context("spawn")) as ex:
+            res = list(ex.map(recheck_task, items))
+    finally:
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    eta = np.array([r[0] for r in res])
+    dlt = np.array([r[1] for r in res])
+    gpu = np.asarray(gpu_etas, dtype=float)
+    return {"checked": len(items), "seconds": time.perf_counter() - t0,
+            "false_acceptances_oracle": int(np.sum(eta > tau + dlt)),
+            "above_tau_oracle": int(np.sum(~(eta <= tau))),
+            "boundary_ambiguous": int(np.sum(np.abs(eta - tau) < dlt)),
+            "max_eta_oracle": float(np.max(eta)), "max_delta": float(np.max(dlt)),
+            "max_abs_gpu_minus_oracle": float(np.max(np.abs(gpu - eta))),
+            "max_abs_gpu_minus_oracle_over_delta": float(np.max(np.abs(gpu - eta) / dlt))}
 
 
 def wilson(k, n, z=1.959963984540054):
@@ -572,7 +738,7 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
 B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
 
 
-def batch4_leg(tg, torch, dev, mixed_prec):
+def batch4_leg(tg, torch, dev, mixed_prec, recheck=True):
     """Batched uneven solves: 48 blob states (seeds 4000-4047, grid
     B4_GRIDS[i % 4], the severe-state generator at that size) x 4 ladder
     floors = 192 independent solves in one batch (FP32 V-cycle, FP64 guard),
@@ -597,20 +763,38 @@ def batch4_leg(tg, torch, dev, mixed_prec):
     batch.set_density(rhos, 3.0, floors)
     zc, _ = batch.autotune(mixed_prec)
 
+    last = {}
+
     def batched(prec, graphs=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch.set_density(rhos, 3.0, floors)
-        _, res = batch.solve(fs, tg.solver_opts(prec=prec, graphs=graphs))
+        us, res = batch.solve(fs, tg.solver_opts(prec=prec, graphs=graphs))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        last["us"], last["res"] = us, res
         ok = sum(1 for r in res if r["true_eta"] <= 1e-6)
         return {"value": ok / dt, "seconds": dt, "guard_passing": ok,
                 "mean_iters": float(np.mean([r["iterations"] for r in res]))}
 
     batched(mixed_prec)   # warm-up
     out = {"solves": len(grids), "grids": [list(d) for d in B4_GRIDS], "autotuned_zc": zc[:2],
-           "mixed_batched": batched(mixed_prec), "fp64_batched": batched(tg.F64)}
+           "mixed_batched": batched(mixed_prec)}
+    if recheck:
+        # the oracle's eta of every guard-passing solution of the mixed batch
+        items, etas = [], []
+        for q, r in enumerate(last["res"]):
+            if r["true_eta"] <= 1e-6:
+                g = grids[q]
+                items.append(((g.nx, g.ny, g.nz), rhos[q].cpu().numpy(), 3.0, floors[q], fs[q].cpu().numpy(),
+                              last["us"][q].cpu().numpy()))
+                etas.append(r["true_eta"])
+        out["oracle_recheck"] = oracle_recheck(items, etas)
+        del items
+        log(f"uneven batch oracle recheck: {out['oracle_recheck']['checked']} solutions, "
+            f"{out['oracle_recheck']['false_acceptances_oracle']} false acceptances")
+    last.clear()
+    out["fp64_batched"] = batched(tg.F64)
     # the same batch with every FGMRES step (V-cycle, operator, Gram-Schmidt)
     # replayed from a captured HIP graph; the first pass captures one graph
     # per (active set, step) and is not timed
@@ -639,7 +823,7 @@ def batch4_leg(tg, torch, dev, mixed_prec):
     return out
 
 
-def scale_leg(tg, torch, dev, mixed_prec):
+def scale_leg(tg, torch, dev, mixed_prec, recheck=True):
     """Mixed precision at scale: one solve on 256x128x128 (12.8M DOF), the
     8-strut optimized-like field (seed 3000), p = 3, rho_min = 1e-3,
     FGMRES(30) cap 200, in the mixed form and in FP64; error of the mixed
@@ -668,6 +852,16 @@ def scale_leg(tg, torch, dev, mixed_prec):
                      "ms_per_iteration": 1e3 * dt / max(res["iterations"], 1)}
     d = sols["mixed"] - sols["fp64"]
     out["rel_error_vs_fp64"] = float((d.norm() / sols["fp64"].norm()).item())
+    if recheck:
+        # the oracle's eta of both solutions (matrix-free FP64, host processes)
+        rho_np, f_np = rho.cpu().numpy(), f.cpu().numpy()
+        names = ("mixed", "fp64")
+        items = [((nx, ny, nz), rho_np, 3.0, 1e-3, f_np, sols[k].cpu().numpy()) for k in names]
+        rc = oracle_recheck(items, [out[k]["true_eta"] for k in names], workers=2)
+        out["oracle_recheck"] = rc
+        del items
+        log(f"256x128x128 oracle recheck: max eta {rc['max_eta_oracle']:.3e}, "
+            f"{rc['false_acceptances_oracle']} false acceptances")
     out["compliance_rel_diff"] = abs(out["mixed"]["compliance"] - out["fp64"]["compliance"]) / abs(
         out["fp64"]["compliance"])
     out["mixed_speedup"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
@@ -788,6 +982,7 @@ def main():
         return tg.policy(rungs=RUNGS, p=3.0, solve=solve)
 
     step_times = []   # wall seconds of every timed step of the last run (select_floor syncs)
+    last_us = []      # solutions of the last timed step
 
     def run(prec, steps, warmup, timer_mask, use_mlp, pol=None):
         pol = pol if pol is not None else policy(prec, use_mlp)
@@ -801,9 +996,10 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         outs = None
+        us = None
         for st in range(steps):
             t = time.perf_counter()
-            _, outs = batch.select_floor(rhos, fs, pol)
+            us, outs = batch.select_floor(rhos, fs, pol)
             step_times.append(time.perf_counter() - t)
             log(f"step {st} prec={prec} {time.perf_counter() - t:.2f}s "
                 f"certified={sum(1 for o in outs if o['rung'] >= 0)}")
@@ -811,6 +1007,7 @@ def main():
         dt = time.perf_counter() - t0
         timers = tg.kernel_timer_read()
         tg.kernel_timer_enable(0)
+        last_us[:] = us if us is not None else []
         return dt, outs, timers
 
     MIXED = {"f32": tg.F32, "bf16": tg.BF16MFMA, "bf16x3": tg.BF16X3MFMA}
@@ -827,6 +1024,7 @@ def main():
     dom_mask = 1 << probe_timers[dom]["kind"]
     dt, outs, timers = run(mixed_prec, args.steps, args.warmup, dom_mask, use_mlp)
     steps_s = list(step_times)
+    head_us = list(last_us)
     certified = sum(1 for o in outs if o["rung"] >= 0)
     value = certified * args.steps / dt
     result = {
@@ -840,7 +1038,7 @@ def main():
                     "iqr": [1e3 * float(np.percentile(steps_s, 25)), 1e3 * float(np.percentile(steps_s, 75))],
                     "all": [1e3 * t for t in steps_s]},
         "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.mixed],
         "data": "synthetic",
         "config": {"workload": "102 severe random states, 64x32x32 cantilever, guarded floor ladder",
                    "states": n, "grid": list(GRID), "rungs": list(RUNGS), "p": 3.0,
@@ -884,6 +1082,22 @@ def main():
                 "mean_attempts": float(np.mean([len(x["attempts"]) for x in o]))}
 
     result["policy"]["mean_attempts"] = float(np.mean([len(o["attempts"]) for o in outs]))
+    result["policy"]["accepted_above_tolerance"] = sum(
+        1 for o in outs for a in o["attempts"] if a["accepted"] and not a["true_eta"] <= 1e-6)
+    if not args.no_recheck:
+        # the oracle recomputes eta of every accepted solution of the last
+        # timed step (matrix-free FP64 operator at the accepted floor), untimed
+        f_np = f0.cpu().numpy()
+        items, etas = [], []
+        for i, o in enumerate(outs):
+            if o["rung"] >= 0:
+                items.append((GRID, rhos[i].cpu().numpy(), 3.0, RUNGS[o["rung"]], f_np, head_us[i].cpu().numpy()))
+                etas.append(o["attempts"][-1]["true_eta"])
+        result["oracle_recheck"] = oracle_recheck(items, etas)
+        log(f"oracle recheck of {len(items)} accepted solutions: "
+            f"{result['oracle_recheck'].get('false_acceptances_oracle')} false acceptances, "
+            f"{result['oracle_recheck'].get('boundary_ambiguous')} boundary-ambiguous")
+    del head_us
     # reference labels (untimed): independent guarded solves at every rung
     labels = None
     if not args.no_labels:
@@ -936,11 +1150,11 @@ def main():
     if not args.no_scale:
         del batch, grids
         torch.cuda.empty_cache()
-        result["mixed_at_scale"] = scale_leg(tg, torch, dev, mixed_prec)
+        result["mixed_at_scale"] = scale_leg(tg, torch, dev, mixed_prec, recheck=not args.no_recheck)
     if not args.no_batch4:
         batch = grids = None
         torch.cuda.empty_cache()
-        result["batch_uneven"] = batch4_leg(tg, torch, dev, mixed_prec)
+        result["batch_uneven"] = batch4_leg(tg, torch, dev, mixed_prec, recheck=not args.no_recheck)
     if not args.no_trajectory:
         batch = grids = None
         torch.cuda.empty_cache()
@@ -950,7 +1164,18 @@ def main():
         iters = float(np.mean([o["iters_probe"] + o["iters_selected"] + o["iters_rejected"] for o in outs]))
         result["cpu_baseline"] = run_cpu_baseline(setups, iters)
         result["cpu_host"] = host_info()
-    print(json.dumps(result), flush=True)
+    full = None
+    try:
+        d = os.path.dirname(args.full_out)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.full_out, "w") as fh:
+            json.dump(result, fh)
+        full = args.full_out
+    except OSError as exc:
+        log(f"full record not written: {exc}")
+    # nothing is printed after this line: it is the run's summary
+    print(json.dumps(compact(result, full)), flush=True)
 
 
 if __name__ == "__main__":
