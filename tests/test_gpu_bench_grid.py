@@ -98,9 +98,10 @@ def test_vcycle_at_bench_grid_autotuned(severe, seed):
         zc = zc + [zcm[0]]
     print(f"seed {seed}: tile heights {zc}, V-cycle max error / max |z|: {err}", flush=True)
     assert err["f64"] <= 1e-9
-    # the FP32 cycle (vector or split-BF16 fine operator) carries ~1e-7 and
-    # ~1e-4 relative operator errors through the contrast of the 1e-9 floor
-    assert err["f32"] <= 2e-3 and err["bf16x3"] <= 2e-2
+    # the FP32 cycle carries FP32 rounding (unit 6e-8) through five levels
+    # (measured 6e-8 .. 8e-8 here); the split-BF16 fine operator keeps about
+    # 16 significant bits (2^-16 = 1.5e-5 per product; measured 5e-6)
+    assert err["f32"] <= 1e-6 and err["bf16x3"] <= 1e-4
 
 
 @pytest.mark.parametrize("seed", SEEDS)
@@ -222,7 +223,7 @@ def test_guard_on_degenerate_right_hand_sides():
     rung); a NaN entry in f makes eta NaN, so no rung is accepted."""
     dims = (16, 8, 8)
     rho = synth.uniform(*dims, 0)
-    g = tg.Grid(*dims, max_restart=30, device=DEV)
+    g = tg.Grid(*dims, max_restart=100, device=DEV)    # the probe runs one 100-step cycle
     g.set_density(torch.tensor(rho, device=DEV), 3.0, 1e-3)
     zero = torch.zeros(g.n_dof, dtype=torch.float64, device=DEV)
     assert g.true_residual(zero, zero) == 0.0
