@@ -383,6 +383,28 @@ typedef struct {
 int tg_gradient_change(const tg_grid* g, const double* rho_d, double solid_min, const double* dc0_d,
                        const double* dc1_d, tg_gradient_change_result* out, void* stream);
 
+/* ---- allocation-free entry point ------------------------------------------
+ * For callers that cannot allocate device memory or bind a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same comparison as tg_gradient_change (same kernels, same
+ * summation order, so bitwise the same result) on n_elem elements, with no
+ * grid: rho_d, dc0_d, dc1_d are device arrays of n_elem doubles, `out` a host
+ * struct.  The reduction partials live in a fixed array inside the library,
+ * TG_NOALLOC_SCRATCH_BYTES per GPU, taken when the library is loaded and held
+ * until the process ends; the call allocates nothing (no hipMalloc, no host
+ * heap).  Every call on one GPU shares that GPU's array and rewrites every
+ * value it reads, so calls in sequence are independent, but calls that
+ * overlap on one GPU (two host threads, or two streams without ordering)
+ * race and give undefined results.  Any n_elem in [1, TG_NOALLOC_MAX_ELEMS]
+ * fits the array (the partial sums come from at most 1024 workgroups);
+ * larger or smaller counts, NULL pointers and a non-finite solid_min are
+ * TG_EINVAL, as is no element with rho >= solid_min.  Synchronizes
+ * `stream`. */
+#define TG_NOALLOC_SCRATCH_BYTES 49264
+#define TG_NOALLOC_MAX_ELEMS 2147483647LL
+int tg_gradient_change_noalloc(int64_t n_elem, const double* rho_d, double solid_min, const double* dc0_d,
+                               const double* dc1_d, tg_gradient_change_result* out, void* stream);
+
 /* ---- conditioning (Sec. 4.2, Eq. screen) ------------------------------------ */
 typedef struct {
   double lambda_min, lambda_max;  /* extreme eigenvalues of K(rho_min), free DOFs   */

@@ -143,6 +143,7 @@ PROTOTYPES = {
     "tg_autotune": (_I, [_P, _I, _I, C.POINTER(_I), C.POINTER(_D), _P]),
     "tg_compliance_sensitivity": (_I, [_P, _P, _D, _D, _P, _P, _P, _P, C.POINTER(_D), _P]),
     "tg_gradient_change": (_I, [_P, _P, _D, _P, _P, C.POINTER(GradientChange), _P]),
+    "tg_gradient_change_noalloc": (_I, [C.c_int64, _P, _D, _P, _P, C.POINTER(GradientChange), _P]),
     "tg_density_filter": (_I, [_P, _P, _D, _P, _P]),
     "tg_density_filter_adjoint": (_I, [_P, _P, _P, _D, _P, _P]),
     "tg_filter_project": (_I, [_P, _P, _D, _D, _D, _P, _P, _P, _P]),
@@ -167,6 +168,7 @@ PROTOTYPES = {
 }
 TG_KT_COUNT = 9
 TG_AD_MAX_RESTART = 512
+TG_NOALLOC_SCRATCH_BYTES, TG_NOALLOC_MAX_ELEMS = 49264, 2147483647
 
 
 def header_symbols(path=HEADER):

@@ -13,6 +13,7 @@
 // workgroup.  All sums use fixed orders, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "tg_internal.h"
@@ -211,12 +212,19 @@ __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ 
 // pass 0: count, sum g0, sum g1.  pass 1 (means m0, m1 given): centred
 // sum (g0 - m0)^2, sum (g1 - m1)^2, sum (g0 - m0)(g1 - m1), sum (g1 - g0)^2,
 // and the plain sums g0^2, g1^2.
+// mean_d (may be null): the two means read from device memory instead of
+// m0, m1 (the allocation-free path keeps them on the device between passes).
 __global__ __launch_bounds__(256) void k_grad_moments(const double* __restrict__ rho, double solid_min,
                                                       const double* __restrict__ g0,
                                                       const double* __restrict__ g1, long long n,
                                                       int pass, double m0, double m1,
+                                                      const double* __restrict__ mean_d,
                                                       double* __restrict__ part) {
   __shared__ double red[4];
+  if (mean_d) {
+    m0 = mean_d[0];
+    m1 = mean_d[1];
+  }
   double a[GM_VALS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
     if (!(rho[e] >= solid_min)) continue;
@@ -240,6 +248,55 @@ __global__ __launch_bounds__(256) void k_grad_moments(const double* __restrict__
     const double s = block_sum(a[q], red);
     if (threadIdx.x == 0) part[(long long)blockIdx.x * GM_VALS + q] = s;
   }
+}
+
+// One lane sums the nblk x GM_VALS partials of a moment pass in block order
+// (the order the host-side sum of tg_gradient_change uses) into
+// tot[GM_VALS * pass + q]; after pass 0 the two means follow in
+// tot[2 * GM_VALS], tot[2 * GM_VALS + 1] (0 when no element is solid).
+__global__ void k_grad_finish(const double* __restrict__ part, int nblk, int pass, double* __restrict__ tot) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc[GM_VALS];
+  for (int q = 0; q < GM_VALS; ++q) {
+    acc[q] = 0.0;
+    for (int b = 0; b < nblk; ++b) acc[q] += part[(long long)b * GM_VALS + q];
+    tot[GM_VALS * pass + q] = acc[q];
+  }
+  if (pass == 0) {
+    const double cnt = acc[0];
+    tot[2 * GM_VALS] = cnt >= 1 ? acc[1] / cnt : 0.0;
+    tot[2 * GM_VALS + 1] = cnt >= 1 ? acc[2] / cnt : 0.0;
+  }
+}
+
+// Reduction scratch of the allocation-free comparison: the per-workgroup
+// partials of one pass, then the totals of both passes and the two means.
+// One copy per GPU, held until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr int NA_PART = GM_BLOCKS * GM_VALS;
+constexpr int NA_DOUBLES = NA_PART + 2 * GM_VALS + 2;
+static_assert(NA_DOUBLES * sizeof(double) == TG_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+__device__ __align__(256) double scratch[NA_DOUBLES];
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mu;
+double* na_ptr[NA_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+int noalloc_scratch(double** out) {
+  int dev = -1;
+  TG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NA_MAX_DEVICES) return fail(TG_EINVAL, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lk(na_mu);
+  if (!na_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    na_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = na_ptr[dev];
+  return TG_OK;
 }
 
 }  // namespace
@@ -318,7 +375,7 @@ int tg_gradient_change(const tg_grid* g, const double* rho_d, double solid_min, 
   double acc[GM_VALS];
   auto sweep = [&](int pass, double m0, double m1) -> int {
     void* th = timer_begin(TG_KT_FIDELITY, s);
-    k_grad_moments<<<nblk, 256, 0, s>>>(rho_d, solid_min, dc0_d, dc1_d, n, pass, m0, m1, part);
+    k_grad_moments<<<nblk, 256, 0, s>>>(rho_d, solid_min, dc0_d, dc1_d, n, pass, m0, m1, nullptr, part);
     if (th) timer_end(th, 24.0 * (double)n, s);
     TG_HIP(hipGetLastError());
     TG_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
@@ -340,6 +397,45 @@ int tg_gradient_change(const tg_grid* g, const double* rho_d, double solid_min, 
   out->norm1 = std::sqrt(acc[5]);
   out->rel_l2 = std::sqrt(acc[3]) / out->norm0;
   out->pearson = acc[2] / std::sqrt(acc[0] * acc[1]);
+  return TG_OK;
+}
+
+int tg_gradient_change_noalloc(int64_t n_elem, const double* rho_d, double solid_min, const double* dc0_d,
+                               const double* dc1_d, tg_gradient_change_result* out, void* stream) {
+  if (!rho_d || !dc0_d || !dc1_d || !out) return fail(TG_EINVAL, "NULL argument");
+  if (n_elem < 1 || n_elem > TG_NOALLOC_MAX_ELEMS)
+    return fail(TG_EINVAL, "n_elem must be in [1, TG_NOALLOC_MAX_ELEMS]");
+  if (!std::isfinite(solid_min)) return fail(TG_EINVAL, "solid_min must be finite");
+  double* sc = nullptr;
+  int rc = noalloc_scratch(&sc);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const long long n = (long long)n_elem;
+  const int nblk = (int)std::min<long long>(GM_BLOCKS, (n + 255) / 256);
+  double* part = sc;
+  double* tot = sc + NA_PART;
+  // every partial and total read below is written earlier in the same call
+  // (k_grad_moments writes all nblk x GM_VALS partials it is launched with)
+  for (int pass = 0; pass < 2; ++pass) {
+    void* th = timer_begin(TG_KT_FIDELITY, s);
+    k_grad_moments<<<nblk, 256, 0, s>>>(rho_d, solid_min, dc0_d, dc1_d, n, pass, 0.0, 0.0,
+                                        pass ? tot + 2 * GM_VALS : nullptr, part);
+    if (th) timer_end(th, 24.0 * (double)n, s);
+    TG_HIP(hipGetLastError());
+    k_grad_finish<<<1, 64, 0, s>>>(part, nblk, pass, tot);
+    TG_HIP(hipGetLastError());
+  }
+  double acc[2 * GM_VALS];
+  TG_HIP(hipMemcpyAsync(acc, tot, sizeof(acc), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  const double cnt = acc[0];
+  if (cnt < 1) return fail(TG_EINVAL, "no element has rho >= solid_min");
+  const double* c = acc + GM_VALS;
+  out->n_solid = (int64_t)cnt;
+  out->norm0 = std::sqrt(c[4]);
+  out->norm1 = std::sqrt(c[5]);
+  out->rel_l2 = std::sqrt(c[3]) / out->norm0;
+  out->pearson = c[2] / std::sqrt(c[0] * c[1]);
   return TG_OK;
 }
 

@@ -325,6 +325,16 @@ class Grid:
         return u, policy_dict(out)
 
 
+def gradient_change_noalloc(rho, dc0, dc1, solid_min=0.5):
+    """tg_gradient_change_noalloc: the comparison of Grid.gradient_change on
+    n = rho.numel() elements, with no grid and no device allocation."""
+    out = L.GradientChange()
+    check(lib().tg_gradient_change_noalloc(rho.numel(), _ptr(rho), float(solid_min), _ptr(dc0), _ptr(dc1),
+                                           C.byref(out), _stream()))
+    return {"n_solid": out.n_solid, "rel_l2": out.rel_l2, "pearson": out.pearson,
+            "norm0": out.norm0, "norm1": out.norm1}
+
+
 class Batch:
     """Independent problems of possibly different grid sizes solved together."""
 
