@@ -245,18 +245,24 @@ __device__ __forceinline__ void elem_galerkin1(T* ux, T* uy, T* uz, const T TG_G
 
 // ---------------------------------------------------------------------------
 // BF16 matrix-core form of the fine element contraction v = Ke u (FP32
-// accumulate; the caller scales by E).  A wave's 64 elements form the columns
-// of U (24 DOFs padded to K = 32); Ke (24 rows padded to 32, two 16-row
-// tiles) is the A operand of v_mfma_f32_16x16x32_bf16, held in registers for
-// the whole kernel.  Lane layout of that instruction (measured on gfx950):
-// A[i][k] at lane i % 16 + 16 (k / 8), element k % 8; B[k][n] at lane
-// n + 16 (k / 8), element k % 8; D[m][n] at lane n + 16 (m / 4), element
-// m % 4.  Inputs reach the B layout and results leave the D layout by
-// lane-row transposes in registers.  SPLIT adds the low halves
-// u_lo = bf16(u - u_hi), Ke_lo = bf16(Ke - Ke_hi): Ke_hi u_hi + Ke_hi u_lo +
-// Ke_lo u_hi, about 16 significant bits.
+// accumulate, the element modulus applied to the FP32 result).  A wave's 64
+// elements (4 rows of 16 element columns) are the columns N of four
+// v_mfma_f32_16x16x32_bf16 products, one per element row; Ke (24 rows padded
+// to 32, two 16-row tiles: bottom-face outputs, top-face outputs) is the A
+// operand, held in registers for the whole kernel.  Lane layout of that
+// instruction (measured on gfx950): A[i][k] at lane i % 16 + 16 (k / 8),
+// element k % 8; B[k][n] at lane n + 16 (k / 8), element k % 8; D[m][n] at
+// lane n + 16 (m / 4), element m % 4.  The K slots are laid out so that B
+// comes straight from LDS: slot group g = k / 8 holds corners 2 g (s < 4) and
+// 2 g + 1 (s >= 4), s = k % 8, component s % 4 (s % 4 = 3 is a zero pad), so
+// lane n + 16 g reads two adjacent nodes of one node row: the (dj, dk) =
+// (g & 1, g >> 1) row of element n's faces.  Node values are rounded to BF16
+// once, when their layer is staged (hi = bf16(u); SPLIT adds
+// lo = bf16(u - hi) and Ke_lo = bf16(Ke - Ke_hi):
+// Ke_hi u_hi + Ke_hi u_lo + Ke_lo u_hi, about 16 significant bits).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 struct MfmaA {
   bf16x8 hi[2], lo[2];   // two 16-row tiles of Ke
@@ -264,37 +270,20 @@ struct MfmaA {
 
 __device__ __forceinline__ void mfma_load_ke(const float TG_GLOBAL* Ke, MfmaA& A) {
   const int lane = threadIdx.x & 63;
+  const int i = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int s = 0; s < 8; ++s) {
       // tile mt holds Ke rows 12 mt .. 12 mt + 11 (bottom, then top face) and
-      // four zero rows; K slot 8 g + j is DOF 6 g + j (j < 6), slots 6, 7 of
-      // each group are zero
-      const int i = lane & 15, row = 12 * mt + i, g = lane >> 4;
-      const float v = (i < 12 && j < 6) ? Ke[row * 24 + 6 * g + j] : 0.f;
+      // four zero rows; K slot 8 g + s is DOF 3 (2 g + s / 4) + s % 4
+      const int row = 12 * mt + i, comp = s & 3, col = 3 * (2 * g + (s >> 2)) + comp;
+      const float v = (i < 12 && comp < 3) ? Ke[row * 24 + col] : 0.f;
       const __bf16 h = (__bf16)v;
-      A.hi[mt][j] = h;
-      A.lo[mt][j] = (__bf16)(v - (float)h);
+      A.hi[mt][s] = h;
+      A.lo[mt][s] = (__bf16)(v - (float)h);
     }
 }
-
-// 4 x 4 transpose of 16-lane rows across four registers: afterwards register
-// q, row r holds what register r, row q held.  Two cross-half swaps
-// (v_permlane32_swap: rows 2, 3 of the first operand <-> rows 0, 1 of the
-// second) then two odd/even row swaps (v_permlane16_swap: rows 1, 3 of the
-// first <-> rows 0, 2 of the second), all in registers.
-__device__ __forceinline__ void xpose_rows4(unsigned& r0, unsigned& r1, unsigned& r2, unsigned& r3) {
-  const auto a = __builtin_amdgcn_permlane32_swap(r0, r2, false, false);
-  const auto b = __builtin_amdgcn_permlane32_swap(r1, r3, false, false);
-  const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
-  const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
-  r0 = c[0];
-  r1 = c[1];
-  r2 = d[0];
-  r3 = d[1];
-}
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -303,66 +292,19 @@ __device__ __forceinline__ unsigned pack_bf16(float x0, float x1) {
   return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){x0, x1}, bf16x2));
 }
 
-// x = E u for this lane's element (the wave's 64 elements are its 4 rows of
-// 16 lanes; DOF 3 a + c).  Lane row r holds DOF groups q = 0..3 (DOFs
-// 6 q .. 6 q + 5, K slots 8 q .. 8 q + 5; slots 8 q + 6, 8 q + 7 are zero) of
-// its element; the B operand of the product for element row nb needs group g
-// of that row's elements in lane row g: the row/register transpose of the
-// groups, three registers per group (the fourth is zero throughout).  With
-// Ke's rows ordered bottom face (tile 0) then top face (tile 1), the results
-// stay where the matrix cores leave them: lane n + 16 g, component w of
-// D0[nb] / D1[nb] is face DOF 4 g + w (g < 3) of the bottom / top face of
-// element (row nb, column n).
+// One node's three components as B-operand words, (x, y) and (z, 0): the
+// BF16 high parts into hi, and (SPLIT) the low parts into lo.
 template <bool SPLIT>
-__device__ __forceinline__ void elem_mfma(const float* ux, const float* uy, const float* uz, float E,
-                                          const MfmaA& A, f32x4* D0, f32x4* D1) {
-  float x[24];
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    x[3 * a + 0] = E * ux[a];
-    x[3 * a + 1] = E * uy[a];
-    x[3 * a + 2] = E * uz[a];
-  }
-  // packed pairs: dword w of group q holds DOFs 6 q + 2 w, 6 q + 2 w + 1
-  unsigned hp[4][3], lp[4][3];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      const int d = 6 * q + 2 * w;
-      const unsigned h = pack_bf16(x[d], x[d + 1]);
-      hp[q][w] = h;
-      if (SPLIT) {
-        // the low parts: exact remainders x - bf16(x), rounded to BF16
-        const float h0 = __builtin_bit_cast(float, h << 16);
-        const float h1 = __builtin_bit_cast(float, h & 0xffff0000u);
-        lp[q][w] = pack_bf16(x[d] - h0, x[d + 1] - h1);
-      }
-    }
-#pragma unroll
-  for (int w = 0; w < 3; ++w) {
-    xpose_rows4(hp[0][w], hp[1][w], hp[2][w], hp[3][w]);
-    if (SPLIT) xpose_rows4(lp[0][w], lp[1][w], lp[2][w], lp[3][w]);
-  }
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const u32x4 th = {hp[nb][0], hp[nb][1], hp[nb][2], 0u};
-    const bf16x8 bh = __builtin_bit_cast(bf16x8, th);
-    bf16x8 bl;
-    if (SPLIT) {
-      const u32x4 tl = {lp[nb][0], lp[nb][1], lp[nb][2], 0u};
-      bl = __builtin_bit_cast(bf16x8, tl);
-    }
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bh, c, 0, 0, 0);
-      if (SPLIT) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi[mt], bl, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo[mt], bh, c, 0, 0, 0);
-      }
-      (mt == 0 ? D0 : D1)[nb] = c;
-    }
+__device__ __forceinline__ void split_node(float a0, float a1, float a2, uint2& hi, uint2& lo) {
+  hi.x = pack_bf16(a0, a1);
+  hi.y = pack_bf16(a2, 0.f);
+  if (SPLIT) {
+    // the exact remainders u - bf16(u), rounded to BF16
+    const float h0 = __builtin_bit_cast(float, hi.x << 16);
+    const float h1 = __builtin_bit_cast(float, hi.x & 0xffff0000u);
+    const float h2 = __builtin_bit_cast(float, hi.y << 16);
+    lo.x = pack_bf16(a0 - h0, a1 - h1);
+    lo.y = pack_bf16(a2 - h2, 0.f);
   }
 }
 
@@ -420,12 +362,24 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
                                                  void* ey_, int sy2, T omega, ModeCoef<T> mc) {
   // Single buffers suffice: every read of a layer's values happens between the
   // two barriers of its step, every write of the next layer after them.
-  __shared__ T su[3][17][17];           // node values of the current top layer
   constexpr bool MF = (KIND == 2 || KIND == 3);   // matrix-core forms
+  // node values of the current top layer; FP32 rows padded to 48 words so
+  // that the two tile rows a half-wave touches fall in disjoint LDS banks
+  // (17 columns of 16 consecutive reads per row)
+  __shared__ T su[MF ? 1 : 3][17][sizeof(T) == 4 ? 48 : 17];
+  // matrix-core forms: the BF16 high and low parts of two node layers (slot =
+  // layer & 1: the bottom and the top face of the current element layer) and
+  // the moduli of the current element layer
+  __shared__ uint2 sbh[MF ? 2 : 1][17][17], sbl[KIND == 3 ? 2 : 1][17][17];
+  __shared__ float sE[MF ? FZ_TX : 1][FZ_TX];
   // per element: 4 corners x 3 comps, layer sum (the matrix-core forms also
   // write four planes that are never read, from the padding rows of their
   // products)
-  __shared__ T ss[MF ? 16 : 12][FZ_TX][FZ_TX];
+  // (planes of 16 x 16; the matrix-core forms write lane groups g = 0..3 to
+  // planes 4 g .. 4 g + 3, so their planes are padded to 260 words: the two
+  // lane groups of a half-wave then use disjoint banks)
+  constexpr int SSP = MF ? 260 : FZ_TX * FZ_TX;
+  __shared__ T ss[MF ? 16 : 12][SSP];
   MfmaA mfA;
   const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
@@ -495,14 +449,20 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     }
     return r;
   };
-  auto stage = [&](const Pre& r) {
-    su[0][ty + 1][tx + 1] = r.a0;
-    su[1][ty + 1][tx + 1] = r.a1;
-    su[2][ty + 1][tx + 1] = r.a2;
-    if (xt < 33) {
-      su[0][ety][etx] = r.e0;
-      su[1][ety][etx] = r.e1;
-      su[2][ety][etx] = r.e2;
+  auto stage = [&](const Pre& r, int k) {
+    if constexpr (MF) {
+      constexpr bool SPL = KIND == 3;
+      split_node<SPL>(r.a0, r.a1, r.a2, sbh[k & 1][ty + 1][tx + 1], sbl[SPL ? k & 1 : 0][ty + 1][tx + 1]);
+      if (xt < 33) split_node<SPL>(r.e0, r.e1, r.e2, sbh[k & 1][ety][etx], sbl[SPL ? k & 1 : 0][ety][etx]);
+    } else {
+      su[0][ty + 1][tx + 1] = r.a0;
+      su[1][ty + 1][tx + 1] = r.a1;
+      su[2][ty + 1][tx + 1] = r.a2;
+      if (xt < 33) {
+        su[0][ety][etx] = r.e0;
+        su[1][ety][etx] = r.e1;
+        su[2][ety][etx] = r.e2;
+      }
     }
   };
   // State carried from one element layer to the next: the shared face in the
@@ -524,20 +484,26 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
 #pragma unroll
   for (int q = 0; q < 16; ++q) s0.cr[q] = T(0);
   Pre pre = fetch(z0 - 1);
-  stage(pre);
+  stage(pre, z0 - 1);
+  if constexpr (MF) {
+    // node (ni, nj, z0 - 1) of this thread; the face stays in LDS
+    s0.own[0] = pre.a0;
+    s0.own[1] = pre.a1;
+    s0.own[2] = pre.a2;
+  }
   pre = fetch(z0);           // in flight while the prologue reads LDS
   lds_barrier();
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int di = c & 1, dj = c >> 1;
-    s0.bx[c] = su[0][ty + dj][tx + di];
-    s0.by[c] = su[1][ty + dj][tx + di];
-    s0.bz[c] = su[2][ty + dj][tx + di];
-  }
-  s0.own[0] = s0.bx[3];
-  s0.own[1] = s0.by[3];
-  s0.own[2] = s0.bz[3];
   if constexpr (!MF) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int di = c & 1, dj = c >> 1;
+      s0.bx[c] = su[0][ty + dj][tx + di];
+      s0.by[c] = su[1][ty + dj][tx + di];
+      s0.bz[c] = su[2][ty + dj][tx + di];
+    }
+    s0.own[0] = s0.bx[3];
+    s0.own[1] = s0.by[3];
+    s0.own[2] = s0.bz[3];
     face_fwd(s0.bx);
     face_fwd(s0.by);
     face_fwd(s0.bz);
@@ -555,9 +521,15 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   // for layer k + 1
   auto step = [&](const int k, St& A, St& B) {
     const T own0 = A.own[0], own1 = A.own[1], own2 = A.own[2];   // node (ni, nj, k)
-    stage(pre);              // node layer k + 1 (fetched one step ahead)
+    if constexpr (MF) {
+      B.own[0] = pre.a0;     // node (ni, nj, k + 1)
+      B.own[1] = pre.a1;
+      B.own[2] = pre.a2;
+    }
+    stage(pre, k + 1);       // node layer k + 1 (fetched one step ahead)
     pre = fetch(k + 2);      // next layer in flight during this step
     const T Ecur = A.E;      // modulus of element layer k (0 outside the grid)
+    if constexpr (MF) sE[ty][tx] = (float)Ecur;
     B.E = modulus(k + 1);
     // output-side operands of node (ni, nj, k), loaded before the barrier
     T rb0 = T(0), rb1 = T(0), rb2 = T(0);
@@ -632,43 +604,43 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       face_inv(fz);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        ss[3 * c + 0][ty][tx] = fx[c];
-        ss[3 * c + 1][ty][tx] = fy[c];
-        ss[3 * c + 2][ty][tx] = fz[c];
+        ss[3 * c + 0][ty * FZ_TX + tx] = fx[c];
+        ss[3 * c + 1][ty * FZ_TX + tx] = fy[c];
+        ss[3 * c + 2][ty * FZ_TX + tx] = fz[c];
       }
     } else {
+      // lane n + 16 g of wave w works on element (n, 4 w + nb) of the tile for
+      // nb = 0..3: its B operand is node row (dj, dk) = (g & 1, g >> 1) of that
+      // element's faces, two adjacent nodes, read as staged
+      const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, r0 = 4 * (threadIdx.x >> 6);
+      const int dj = g & 1, sl = (k + (g >> 1)) & 1;
+      float Ev[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int di = c & 1, dj = c >> 1;
-        ux[c] = A.bx[c];
-        uy[c] = A.by[c];
-        uz[c] = A.bz[c];
-        ux[c + 4] = su[0][ty + dj][tx + di];
-        uy[c + 4] = su[1][ty + dj][tx + di];
-        uz[c + 4] = su[2][ty + dj][tx + di];
-      }
-      B.own[0] = ux[7];
-      B.own[1] = uy[7];
-      B.own[2] = uz[7];
+      for (int nb = 0; nb < 4; ++nb) Ev[nb] = sE[r0 + nb][n];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        B.bx[c] = ux[c + 4];
-        B.by[c] = uy[c + 4];
-        B.bz[c] = uz[c + 4];
-      }
-      f32x4 D0[4], D1[4];
-      elem_mfma<KIND == 3>((const float*)ux, (const float*)uy, (const float*)uz, (float)Ecur, mfA, D0, D1);
-      // layer-k node contributions: bottom of this element + top of the
-      // previous one, face DOF j = 3 corner + component of element row nb
-      const int lg = (threadIdx.x >> 4) & 3, row0 = 4 * (threadIdx.x >> 6);
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
+      for (int nb = 0; nb < 4; ++nb) {
+        const uint2 h0 = sbh[sl][r0 + nb + dj][n], h1 = sbh[sl][r0 + nb + dj][n + 1];
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, (u32x4){h0.x, h0.y, h1.x, h1.y});
+        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mfA.hi[0], bh, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mfA.hi[1], bh, c1, 0, 0, 0);
+        if constexpr (KIND == 3) {
+          const uint2 l0 = sbl[sl][r0 + nb + dj][n], l1 = sbl[sl][r0 + nb + dj][n + 1];
+          const bf16x8 bl = __builtin_bit_cast(bf16x8, (u32x4){l0.x, l0.y, l1.x, l1.y});
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mfA.hi[0], bl, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mfA.hi[1], bl, c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mfA.lo[0], bh, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mfA.lo[1], bh, c1, 0, 0, 0);
+        }
+        // lane n + 16 g, component w: face DOF 4 g + w (g < 3) of element
+        // (n, r0 + nb); layer-k nodes get this element's bottom face plus the
+        // previous element layer's top face, scaled by the moduli
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          const T v = T(D0[nb][w]) + A.cr[4 * nb + w];
-          ss[4 * lg + w][row0 + nb][tx] = v;
-          B.cr[4 * nb + w] = T(D1[nb][w]);
+          ss[4 * g + w][(r0 + nb) * FZ_TX + n] = mad_(Ev[nb], c0[w], (float)A.cr[4 * nb + w]);
+          B.cr[4 * nb + w] = T(Ev[nb] * c1[w]);
         }
+      }
     }
     lds_barrier();
     // (the restriction needs every fine column of its tile, zero outside the grid)
@@ -678,8 +650,8 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       T a[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        a[q] = (ss[9 + q][ty][tx] + ss[6 + q][ty][tx + 1]) +
-               (ss[3 + q][ty + 1][tx] + ss[0 + q][ty + 1][tx + 1]);
+        a[q] = (ss[9 + q][ty * FZ_TX + tx] + ss[6 + q][ty * FZ_TX + tx + 1]) +
+               (ss[3 + q][(ty + 1) * FZ_TX + tx] + ss[0 + q][(ty + 1) * FZ_TX + tx + 1]);
       if constexpr (RST) {
         // free-DOF residual; zero at clamped nodes and outside the grid
 #pragma unroll

@@ -286,7 +286,9 @@ def test_full_size_apply_sampled(dims, gen):
     rng = np.random.default_rng(2)
     u = rng.standard_normal(og.n_dof)
     y = g.apply_K(torch.tensor(u, device=DEV), tg.F64).cpu().numpy()
-    y32 = g.apply_K(torch.tensor(u, dtype=torch.float32, device=DEV), tg.F32).cpu().numpy()
+    u32 = torch.tensor(u, dtype=torch.float32, device=DEV)
+    y32 = g.apply_K(u32, tg.F32).cpu().numpy()
+    y3 = g.apply_K(u32, tg.BF16X3MFMA).cpu().numpy()
     nodes = np.concatenate([rng.integers(0, og.n_nodes, 150),
                             [0, og.n_nodes - 1, og.node(og.nx, og.ny, 0), og.node(1, 0, og.nz)]])
     Ka = np.abs(KE)
@@ -295,6 +297,7 @@ def test_full_size_apply_sampled(dims, gen):
         bnd = op.apply_at_node(og, E, Ka, np.abs(u), int(n))
         assert np.all(np.abs(y[3 * n:3 * n + 3] - ref) <= 64 * 2.2e-16 * bnd + 1e-300)
         assert np.all(np.abs(y32[3 * n:3 * n + 3] - ref) <= 3e-5 * bnd + 1e-30)
+        assert np.all(np.abs(y3[3 * n:3 * n + 3] - ref) <= 2.0 ** -13 * bnd + 1e-30)
 
 
 @pytest.mark.parametrize("dims,kind,rmin", [((16, 8, 8), "uniform", 1e-3), ((32, 16, 16), "blob", 1e-4),
