@@ -235,13 +235,14 @@ def compact(result, full_path=None):
                                                            "frac": se["frac_hbm_peak"]}
     sp_ = r.get("small_plain")
     if sp_:
-        c["small_plain_16x8x8"] = {"solves_per_s": _get(sp_, "direct_launches", "value"),
-                                   "us_per_iteration": _get(sp_, "direct_launches", "us_per_iteration"),
-                                   "graph_us_per_iteration": _get(sp_, "graph_replay", "us_per_iteration")}
+        c["small_plain_16x8x8"] = {"solves_per_s": _get(sp_, "graph_replay", "value"),
+                                   "us_per_iteration": {k: _get(sp_, k, "us_per_iteration") for k in
+                                                        ("direct_launches_sync1", "direct_launches", "graph_replay")}}
     bu = r.get("batch_uneven")
     if bu:
         c["batch_uneven_192"] = {"mixed": _get(bu, "mixed_batched", "value"),
                                  "mixed_graphs": _get(bu, "mixed_batched_graphs", "value"),
+                                 "mixed_sync1": _get(bu, "mixed_batched_sync1", "value"),
                                  "serial": _get(bu, "mixed_serial", "value"), "fp64": _get(bu, "fp64_batched", "value"),
                                  "guard_passing": _get(bu, "mixed_batched", "guard_passing"),
                                  "oracle_false_acceptances": _get(bu, "oracle_recheck", "false_acceptances_oracle")}
@@ -765,11 +766,11 @@ def batch4_leg(tg, torch, dev, mixed_prec, recheck=True):
 
     last = {}
 
-    def batched(prec, graphs=False):
+    def batched(prec, graphs=False, sync_every=8):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch.set_density(rhos, 3.0, floors)
-        us, res = batch.solve(fs, tg.solver_opts(prec=prec, graphs=graphs))
+        us, res = batch.solve(fs, tg.solver_opts(prec=prec, graphs=graphs, sync_every=sync_every))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         last["us"], last["res"] = us, res
@@ -802,6 +803,8 @@ def batch4_leg(tg, torch, dev, mixed_prec, recheck=True):
     batched(mixed_prec, graphs=True)
     out["graph_capture_pass_s"] = time.perf_counter() - t0
     out["mixed_batched_graphs"] = batched(mixed_prec, graphs=True)
+    out["mixed_batched_sync1"] = batched(mixed_prec, sync_every=1)
+    out["tile_heights_per_size"] = {"x".join(map(str, B4_GRIDS[q])): batch.tile_heights(4 * q) for q in range(4)}
     # the same solves one at a time (each grid alone)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -884,8 +887,8 @@ def small_leg(tg, torch, dev, reps=3):
     rhos = [torch.tensor(synth.uniform(16, 8, 8, sd), device=dev) for sd in range(10)]
     out = {"grid": [16, 8, 8], "states": len(rhos), "dtype": "f64", "levels": g.n_levels}
 
-    def run(graphs):
-        o = tg.solver_opts(prec=tg.F64, graphs=graphs)
+    def run(graphs, sync_every=8):
+        o = tg.solver_opts(prec=tg.F64, graphs=graphs, sync_every=sync_every)
         ok = its = 0
         for r in rhos:   # warm-up (and graph capture)
             g.set_density(r, 3.0, 1e-3)
@@ -903,11 +906,16 @@ def small_leg(tg, torch, dev, reps=3):
         return {"value": ok / dt, "certified": ok, "solves": reps * len(rhos),
                 "mean_iters": its / (reps * len(rhos)), "us_per_iteration": 1e6 * dt / its}
 
+    # status read after every Arnoldi step (host round trip per step), then
+    # runs of 8 steps per read with device-side gating, launched directly or
+    # replayed as captured graphs
+    out["direct_launches_sync1"] = run(False, 1)
     out["direct_launches"] = run(False)
     out["graph_replay"] = run(True)
     out["graph_speedup"] = out["graph_replay"]["value"] / out["direct_launches"]["value"]
-    log(f"small cantilever: {out['direct_launches']['value']:.0f} solves/s direct, "
-        f"{out['graph_replay']['value']:.0f} with graph replay")
+    log(f"small cantilever: {out['direct_launches_sync1']['us_per_iteration']:.0f} us/iteration with a read per "
+        f"step, {out['direct_launches']['us_per_iteration']:.0f} with runs of 8, "
+        f"{out['graph_replay']['us_per_iteration']:.0f} with graph replay")
     return out
 
 

@@ -87,11 +87,20 @@ typedef struct {
                           over the basis per step); 3 = CGS2 in place
                           (three sweeps per step)                        */
   double breakdown;    /* subdiagonal <= breakdown * ||w|| -> BREAKDOWN, 1e-14 */
-  int graphs;          /* nonzero (with cgs_passes = 2): each Arnoldi step
-                          (V-cycle, K z, both sweeps, scalar kernels) is
-                          captured once as a HIP graph per work-list state
-                          and step index and replayed; results are bitwise
-                          those of direct launches.  Default 0.          */
+  int graphs;          /* nonzero: each run of Arnoldi steps between two
+                          status reads (V-cycle, K z, Gram-Schmidt sweeps,
+                          scalar kernels) is captured once as a HIP graph
+                          per work-list state and step range and replayed;
+                          results are bitwise those of direct launches.
+                          Default 0.                                     */
+  int sync_every;      /* Arnoldi steps between host reads of the per-
+                          problem status, >= 1 (default 8).  The kernels of
+                          a step skip problems whose status on the device is
+                          no longer running, so a problem that stops inside
+                          a run of steps is left exactly as if the run had
+                          ended there: results are bitwise the same for
+                          every value.  Checkpointed solves read after every
+                          step.                                          */
 } tg_solver_opts;
 
 typedef struct {
@@ -315,6 +324,12 @@ int tg_batch_select_floor(tg_batch* b, const double* const* rho_d, const double*
  * change only the work decomposition: results agree with untuned runs to
  * rounding.  Synchronises the stream; TG_ESTATE before set_density. */
 int tg_batch_autotune(tg_batch* b, int prec, int force, int* zc_out, double* us_out, void* stream);
+/* The z-tile heights (node layers per tile) problem i of the batch uses at
+ * each of its levels (zc_out: 8 ints, 0 beyond its levels).  In a batch of
+ * several grid sizes the autotuner picks them per size: after the level-wide
+ * choice it revisits each size in turn, the others fixed, timing the sweep
+ * over the whole batch.  TG_EINVAL for i out of range. */
+int tg_batch_tile_heights(const tg_batch* b, int i, int* zc_out);
 int tg_autotune(tg_grid* g, int prec, int force, int* zc_out, double* us_out, void* stream);
 
 /* ---- learned first-floor selector (addition (4)) ------------------------- */

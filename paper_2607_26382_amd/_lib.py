@@ -26,7 +26,7 @@ class MgOpts(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("tol", C.c_double),
                 ("prec", C.c_int), ("cgs_passes", C.c_int), ("breakdown", C.c_double),
-                ("graphs", C.c_int)]
+                ("graphs", C.c_int), ("sync_every", C.c_int)]
 
 
 class SolveResult(C.Structure):
@@ -128,6 +128,7 @@ PROTOTYPES = {
     "tg_batch_solve": (_I, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolverOpts),
                             C.POINTER(SolveResult), _P]),
     "tg_batch_history": (_I, [_P, _I, _I, C.POINTER(_D), _P]),
+    "tg_batch_tile_heights": (_I, [_P, _I, C.POINTER(_I)]),
     "tg_batch_select_floor": (_I, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(Policy),
                                    C.POINTER(_P), C.POINTER(PolicyResult), _P]),
     "tg_mlp_workspace_bytes": (_I, [_I, C.POINTER(_SZ)]),

@@ -1,8 +1,12 @@
 // Autotuner for the z-march kernels: per level, time the V-cycle smoothing
 // sweep of the actual batch for each candidate z-tile height and keep the
-// fastest.  Results are cached per batch signature (grid dimensions of every
+// fastest; in a batch of several grid sizes, then choose each size's height
+// in turn (the other sizes fixed), again timing the sweep over the whole
+// batch.  Results are cached per batch signature (grid dimensions of every
 // problem and the working precision) for the life of the process, and
-// optionally in a text file named by TG_AUTOTUNE_CACHE.
+// optionally in a text file named by TG_AUTOTUNE_CACHE (one line per
+// signature: the key, the count of values, the level-wide heights, then the
+// heights of each size in order of first appearance).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -28,9 +32,11 @@ void load_file() {
   if (!f) return;
   char key[4096];
   while (std::fscanf(f, "%4095s", key) == 1) {
-    std::vector<int> v(TG_MAXLEV);
-    for (int l = 0; l < TG_MAXLEV; ++l)
-      if (std::fscanf(f, "%d", &v[l]) != 1) v[l] = 0;
+    int cnt = 0;
+    if (std::fscanf(f, "%d", &cnt) != 1 || cnt < TG_MAXLEV || cnt > 64 * TG_MAXLEV) break;
+    std::vector<int> v(cnt);
+    for (int q = 0; q < cnt; ++q)
+      if (std::fscanf(f, "%d", &v[q]) != 1) v[q] = 0;
     g_cache[key] = v;
   }
   std::fclose(f);
@@ -42,7 +48,7 @@ void save_file() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_cache) {
-    std::fprintf(f, "%s", kv.first.c_str());
+    std::fprintf(f, "%s %d", kv.first.c_str(), (int)kv.second.size());
     for (int x : kv.second) std::fprintf(f, " %d", x);
     std::fprintf(f, "\n");
   }
@@ -65,14 +71,30 @@ std::string batch_signature(const Batch* b, int prec) {
   return o.str();
 }
 
+// Grid sizes of the batch in order of first appearance.
+static std::vector<std::array<int, 3>> batch_sizes(const Batch* b) {
+  std::vector<std::array<int, 3>> v;
+  for (auto* g : b->grids) {
+    const std::array<int, 3> d = {g->nx, g->ny, g->nz};
+    if (std::find(v.begin(), v.end(), d) == v.end()) v.push_back(d);
+  }
+  return v;
+}
+
 // Applies cached tile heights if this batch has been tuned before.
 bool autotune_lookup(Batch* b, int prec) {
   std::lock_guard<std::mutex> lk(g_mu);
   load_file();
   auto it = g_cache.find(batch_signature(b, prec));
   if (it == g_cache.end()) return false;
+  const std::vector<int>& v = it->second;
   for (int l = 0; l < TG_MAXLEV; ++l)
-    if (it->second[l] > 0) b->zc[l] = it->second[l];
+    if (v[l] > 0) b->zc[l] = v[l];
+  b->zc_size.clear();
+  const auto sizes = batch_sizes(b);
+  if (sizes.size() > 1 && v.size() == (sizes.size() + 1) * TG_MAXLEV)
+    for (size_t q = 0; q < sizes.size(); ++q)
+      for (int l = 0; l < TG_MAXLEV; ++l) b->zc_size[sizes[q]][l] = v[(q + 1) * TG_MAXLEV + l];
   return true;
 }
 
@@ -89,6 +111,35 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
   TG_HIP(hipEventCreate(&e0));
   TG_HIP(hipEventCreate(&e1));
   int rc = TG_OK;
+  b->zc_size.clear();
+  const int mf = prec == TG_BF16MFMA ? 1 : prec == TG_BF16X3MFMA ? 2 : 0;
+  // time of the level-l smoothing sweep over the whole batch with the
+  // current heights (microseconds, mean of 3 after one untimed sweep)
+  auto timed = [&](int l, double& us) -> int {
+    int r;
+    if ((r = batch_upload_desc(b, s)) || (r = batch_set_active(b, all, s))) return r;
+    auto sweep = [&]() {
+      // damped Jacobi sweep on the level's scratch vectors (values irrelevant)
+      if (prec == TG_F64)
+        return launch_fine<double>(b, b->zm_s[l], l, 2, l == 0 ? S_VXA : C_XA, nullptr,
+                                   l == 0 ? S_VB : C_B, nullptr, l == 0 ? S_VXB : C_XB, nullptr, 0.6, s);
+      if (l == 0 && mf)
+        return launch_fine_mfma(b, b->zm_s[0], 2, mf == 2, C_XA, nullptr, C_B, nullptr, C_XB, nullptr, 0.6,
+                                false, s);
+      return launch_fine<float>(b, b->zm_s[l], l, 2, C_XA, nullptr, C_B, nullptr, C_XB, nullptr, 0.6, s);
+    };
+    if ((r = sweep())) return r;
+    TG_HIP(hipEventRecord(e0, s));
+    const int reps = 3;
+    for (int q = 0; q < reps; ++q)
+      if ((r = sweep())) return r;
+    TG_HIP(hipEventRecord(e1, s));
+    TG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    us = 1e3 * ms / reps;
+    return TG_OK;
+  };
   for (int l = 0; l < TG_MAXLEV && rc == TG_OK; ++l) {
     bool any = false;
     for (auto* g : b->grids) any = any || (l < g->nlev - 1);
@@ -108,28 +159,8 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
     int pick = b->zc[l];
     for (int c : cand) {
       b->zc[l] = c;
-      if ((rc = batch_upload_desc(b, s)) || (rc = batch_set_active(b, all, s))) break;
-      const int mf = prec == TG_BF16MFMA ? 1 : prec == TG_BF16X3MFMA ? 2 : 0;
-      auto sweep = [&]() {
-        // damped Jacobi sweep on the level's scratch vectors (values irrelevant)
-        if (prec == TG_F64)
-          return launch_fine<double>(b, b->zm_s[l], l, 2, l == 0 ? S_VXA : C_XA, nullptr,
-                                     l == 0 ? S_VB : C_B, nullptr, l == 0 ? S_VXB : C_XB, nullptr, 0.6, s);
-        if (l == 0 && mf)
-          return launch_fine_mfma(b, b->zm_s[0], 2, mf == 2, C_XA, nullptr, C_B, nullptr, C_XB, nullptr, 0.6,
-                                  false, s);
-        return launch_fine<float>(b, b->zm_s[l], l, 2, C_XA, nullptr, C_B, nullptr, C_XB, nullptr, 0.6, s);
-      };
-      if ((rc = sweep())) break;
-      TG_HIP(hipEventRecord(e0, s));
-      const int reps = 3;
-      for (int r = 0; r < reps; ++r)
-        if ((rc = sweep())) break;
-      TG_HIP(hipEventRecord(e1, s));
-      TG_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      TG_HIP(hipEventElapsedTime(&ms, e0, e1));
-      const double us = 1e3 * ms / reps;
+      double us = 0.0;
+      if ((rc = timed(l, us))) break;
       if (us < best) {
         best = us;
         pick = c;
@@ -138,13 +169,48 @@ int autotune_batch(Batch* b, int prec, hipStream_t s, double* best_us, bool forc
     b->zc[l] = pick;
     if (best_us) best_us[l] = best;
   }
+  // several grid sizes: each size's height in turn, the others fixed
+  const auto sizes = batch_sizes(b);
+  if (rc == TG_OK && sizes.size() > 1) {
+    for (const auto& d : sizes) b->zc_size[d].fill(0);
+    for (int l = 0; l < TG_MAXLEV && rc == TG_OK; ++l) {
+      for (const auto& d : sizes) {
+        const tg_grid* g = nullptr;
+        for (auto* gg : b->grids)
+          if (gg->nx == d[0] && gg->ny == d[1] && gg->nz == d[2]) g = gg;
+        if (l >= g->nlev - 1) continue;
+        const int NZ = g->lv[l].ez + 1;
+        std::vector<int> cand = {2, 3, 4, 6, 8, b->zc[l]};
+        for (int t = 1; t <= std::min(NZ, 64); ++t) cand.push_back((NZ + t - 1) / t);
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        double best = 1e30;
+        int pick = b->zc[l];
+        for (int c : cand) {
+          b->zc_size[d][l] = c;
+          double us = 0.0;
+          if ((rc = timed(l, us))) break;
+          if (us < best) {
+            best = us;
+            pick = c;
+          }
+        }
+        b->zc_size[d][l] = pick;
+        if (rc) break;
+        if (best_us && best < best_us[l]) best_us[l] = best;
+      }
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
   if ((rc = batch_upload_desc(b, s))) return rc;
+  std::vector<int> v(b->zc, b->zc + TG_MAXLEV);
+  if (sizes.size() > 1)
+    for (const auto& d : sizes) v.insert(v.end(), b->zc_size[d].begin(), b->zc_size[d].end());
   std::lock_guard<std::mutex> lk(g_mu);
   load_file();
-  g_cache[batch_signature(b, prec)] = std::vector<int>(b->zc, b->zc + TG_MAXLEV);
+  g_cache[batch_signature(b, prec)] = v;
   save_file();
   return TG_OK;
 }

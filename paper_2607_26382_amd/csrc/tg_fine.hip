@@ -383,6 +383,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   MfmaA mfA;
   const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[l];
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
   const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;

@@ -252,19 +252,45 @@ int batch_bind(Batch* b, void* ws, size_t bytes) {
   return TG_OK;
 }
 
+int batch_zc(const Batch* b, int p, int l) {
+  const tg_grid* g = b->grids[p];
+  if (!b->zc_size.empty()) {
+    const auto it = b->zc_size.find({g->nx, g->ny, g->nz});
+    if (it != b->zc_size.end() && it->second[l] > 0) return it->second[l];
+  }
+  return b->zc[l];
+}
+
+unsigned long long batch_zc_hash(const Batch* b) {
+  unsigned long long h = 1469598103934665603ull;
+  auto mix = [&](long long v) {
+    for (int q = 0; q < 8; ++q) {
+      h ^= (unsigned long long)((v >> (8 * q)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (int l = 0; l < TG_MAXLEV; ++l) mix(b->zc[l]);
+  for (const auto& kv : b->zc_size) {
+    for (int d : kv.first) mix(d);
+    for (int z : kv.second) mix(z);
+  }
+  return h;
+}
+
 int batch_upload_desc(Batch* b, hipStream_t s) {
   for (int p = 0; p < b->n; ++p) {
     b->host_desc[p] = b->grids[p]->desc;
+    b->host_desc[p].gate = b->gated ? b->sc_d + p : nullptr;
     for (int l = 0; l < b->grids[p]->nlev; ++l)
-      b->host_desc[p].lv[l].zc = zm_height(b->grids[p]->lv[l].ez + 1, b->zc[l]);
+      b->host_desc[p].lv[l].zc = zm_height(b->grids[p]->lv[l].ez + 1, batch_zc(b, p, l));
   }
   TG_HIP(hipMemcpyAsync(b->desc_d, b->host_desc.data(), sizeof(ProbDesc) * b->n, hipMemcpyHostToDevice, s));
   return TG_OK;
 }
 
 int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bool with_elem) {
-  if (b->lists_valid && b->lists_active == active && (b->lists_elem || !with_elem) &&
-      std::memcmp(b->lists_zc, b->zc, sizeof(b->zc)) == 0) {
+  const unsigned long long zh = batch_zc_hash(b);
+  if (b->lists_valid && b->lists_active == active && (b->lists_elem || !with_elem) && b->lists_zc_hash == zh) {
     b->active = active;
     return TG_OK;   // the lists on the device already describe this set
   }
@@ -324,18 +350,18 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   finish(b->prob, o);
   o = begin();
   for (int p : active)
-    for (int t = 0, nt = zm_tiles(b->grids[p], 0, b->zc[0]); t < nt; ++t) H.push_back(make_int2(p, t));
+    for (int t = 0, nt = zm_tiles(b->grids[p], 0, batch_zc(b, p, 0)); t < nt; ++t) H.push_back(make_int2(p, t));
   finish(b->fine, o);
   for (int l = 0; l < TG_MAXLEV; ++l) {
     o = begin();
     for (int p : active)
       if (l < b->grids[p]->nlev - 1)
-        for (int t = 0, nt = zm_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
+        for (int t = 0, nt = zm_tiles(b->grids[p], l, batch_zc(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_s[l], o);
     o = begin();
     for (int p : active)
       if (l < b->grids[p]->nlev - 1)
-        for (int t = 0, nt = rz_tiles(b->grids[p], l, b->zc[l]); t < nt; ++t) H.push_back(make_int2(p, t));
+        for (int t = 0, nt = rz_tiles(b->grids[p], l, batch_zc(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_r[l], o);
   }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");
@@ -344,7 +370,7 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   b->lists_valid = true;
   b->lists_elem = with_elem;
   b->lists_active = active;
-  std::memcpy(b->lists_zc, b->zc, sizeof(b->zc));
+  b->lists_zc_hash = zh;
   // the list layout is a function of (active set, zc, elem flag): equal
   // signatures mean identical device lists at identical addresses
   unsigned long long h = 1469598103934665603ull;
@@ -356,7 +382,7 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   };
   mix((long long)active.size());
   for (int p : active) mix(p);
-  for (int l = 0; l < TG_MAXLEV; ++l) mix(b->zc[l]);
+  mix((long long)zh);
   mix(with_elem ? 1 : 0);
   b->lists_sig = h;
   return TG_OK;
@@ -517,6 +543,7 @@ void tg_default_solver_opts(tg_solver_opts* o) {
   o->cgs_passes = 2;
   o->graphs = 0;
   o->breakdown = 1e-14;
+  o->sync_every = 8;
 }
 
 int tg_setup_grid(int nx, int ny, int nz, double E0, double nu, const tg_mg_opts* mg, tg_grid** out) {

@@ -92,8 +92,18 @@ struct ProbDesc {
   const double* ext0;       // per-call external vectors (batched copy in/out)
   double* ext1;
   int* cc;                  // 2 x n_elem: component labels, clamped-face flags
+  // Inside FGMRES: this problem's entry of the status gather.  The kernels
+  // of an Arnoldi step return at once (whole workgroups) when it is no
+  // longer TG_RUNNING, so several steps run between host reads of the
+  // status.  Null elsewhere.
+  const double* gate;
   LevelDesc lv[TG_MAXLEV];
 };
+// Workgroup-uniform early exit of a step kernel for a problem that stopped.
+#define TG_GATE(P)                                       \
+  do {                                                   \
+    if ((P).gate && *(P).gate != TG_RUNNING) return;     \
+  } while (0)
 
 // Level-0 FP64 slots.
 enum { S_F = 0, S_X = 1, S_R = 2, S_W = 3, S_T = 4, S_VB = 5, S_VXA = 6, S_VXB = 7, S_VR = 8, S_V0 = 9 };
@@ -204,11 +214,15 @@ struct Batch {
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
   int zc[TG_MAXLEV] = {};         // z-tile height per level for this batch
+  // z-tile heights per grid size (nx, ny, nz) and level where the autotuner
+  // chose one for that size (0: zc[l])
+  std::map<std::array<int, 3>, std::array<int, TG_MAXLEV>> zc_size;
+  bool gated = false;             // descriptors carry the step gate (FGMRES)
   // key of the work lists currently on the device (rebuilt only when it changes)
   bool lists_valid = false;
   bool lists_elem = false;
   std::vector<int> lists_active;
-  int lists_zc[TG_MAXLEV] = {};
+  unsigned long long lists_zc_hash = 0;
   unsigned long long lists_sig = 0;     // hash of what the device lists encode (set, zc, elem)
   // captured FGMRES steps (graph replay), keyed by lists epoch and step shape
   hipStream_t cap_stream = nullptr;
@@ -222,6 +236,8 @@ int batch_bind(Batch* b, void* ws, size_t bytes);
 int batch_upload_desc(Batch* b, hipStream_t s);
 int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bool with_elem = false);
 int batch_read_status(Batch* b, hipStream_t s);   // fills sc_h from small[SC_STATUS]
+int batch_zc(const Batch* b, int p, int l);       // z-tile height of problem p at level l
+unsigned long long batch_zc_hash(const Batch* b); // of zc and every per-size choice
 
 // launch wrappers (tg_kernels.hip)
 int k_set_density(Batch* b, hipStream_t s);

@@ -355,6 +355,7 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict
                                                       int scale_off) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[l];
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
   if (n >= L.n_nodes) return;
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ pr
                                                  int se) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& Lf = P.lv[l];
   const LevelDesc& Lc = P.lv[l + 1];
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
@@ -418,6 +420,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const ProbDesc* __restrict
   __shared__ T sb_[TG_MAX_COARSE];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[l];
   const int n = P.ncoarse;
   const auto* b = vslot<TB>(L, sb, eb_);
@@ -452,6 +455,7 @@ __global__ __launch_bounds__(256) void k_copy_level(const ProbDesc* __restrict__
                                                     const void* ea, int sb, void* eb, int scale_off) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[l];
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
   if (n >= L.n_nodes) return;
@@ -519,6 +523,7 @@ __global__ __launch_bounds__(256) void k_multidot_(const ProbDesc* __restrict__ 
   __shared__ double sh[8][4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -569,6 +574,7 @@ __global__ __launch_bounds__(256) void k_reduce_(const ProbDesc* __restrict__ pr
   __shared__ double sh[4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const int nc = P.lv[0].n_chunks;
   const int k = blockIdx.y;
   double s = 0.0;
@@ -591,6 +597,7 @@ __global__ __launch_bounds__(256) void k_update_(const ProbDesc* __restrict__ pr
                                                  int sw, int coef_off) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -625,6 +632,7 @@ __global__ __launch_bounds__(256) void k_update_dots_(const ProbDesc* __restrict
   __shared__ double sh[8][4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -702,6 +710,7 @@ __global__ __launch_bounds__(256) void k_update_dots_reg_(const ProbDesc* __rest
   __shared__ double sh[NVR + 1][4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -762,6 +771,7 @@ __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ pro
   __shared__ double sh[16][4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -843,6 +853,7 @@ __global__ __launch_bounds__(256) void k_update2_(const ProbDesc* __restrict__ p
   __shared__ double sh[4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -886,6 +897,7 @@ __global__ __launch_bounds__(256) void k_scale_(const ProbDesc* __restrict__ pro
                                                 int sidx) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const LevelDesc& L = P.lv[0];
   long long lo, hi;
   chunk_range(L, wi.y, lo, hi);
@@ -946,6 +958,7 @@ __global__ void k_arnoldi_(const ProbDesc* __restrict__ probs, const int2* __res
                            double* status_out) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   if (threadIdx.x != 0) return;
   double* S = P.small;
   double* sc = S + o.scal;
@@ -987,7 +1000,8 @@ __global__ void k_arnoldi_(const ProbDesc* __restrict__ probs, const int2* __res
   const double gj = S[o.g + j];
   S[o.g + j + 1] = -s * gj;
   S[o.g + j] = c * gj;
-  const int kk = k + 1;
+  const int kk = (int)sc[SC_ITERS] + 1;   // iterations so far live on the device (k: the host's count)
+  (void)k;
   const double est = fabs(S[o.g + j + 1]) / sc[SC_BNORM];
   S[o.hist + kk] = est;
   sc[SC_EST] = est;
@@ -1020,6 +1034,7 @@ __global__ __launch_bounds__(64) void k_dcgs_a_(const ProbDesc* __restrict__ pro
   __shared__ int bad;
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const int lane = threadIdx.x;
   double* S = P.small;
   double* sc = S + o.scal;
@@ -1112,6 +1127,7 @@ __global__ __launch_bounds__(64) void k_dcgs_b_(const ProbDesc* __restrict__ pro
   __shared__ int bad;
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
   const int lane = threadIdx.x;
   double* S = P.small;
   double* sc = S + o.scal;

@@ -62,17 +62,18 @@ static int check_ready(Batch* b, const std::vector<int>& which, bool need_mg = f
   return TG_OK;
 }
 
-// One FGMRES step as a captured graph.  The step's kernels depend only on the
-// device work lists (their signature), the step index j and the options, never on
-// host values that change between replays (the iteration count lives on the
-// device), so a graph is captured once per key and replayed on the caller's
-// stream.  Capture runs on a private stream (default priority); nothing
-// executes during capture and the timer records no events.
+// A run of FGMRES steps as a captured graph.  The steps' kernels depend only
+// on the device work lists (their signature), the step range and the
+// options, never on host values that change between replays (the iteration
+// count and the status live on the device), so a graph is captured once per
+// key and replayed on the caller's stream.  Capture runs on a private stream
+// (default priority); nothing executes during capture and the timer records
+// no events.
 template <class F>
-static int graph_step(Batch* b, F&& step, const tg_solver_opts* o, int j, hipStream_t s) {
-  char key[160];
-  std::snprintf(key, sizeof(key), "%llx|%d|%d|%d|%.17g|%.17g|%d", b->lists_sig, o->prec, j, o->max_iters,
-                o->tol, o->breakdown, b->grids[0]->mmax);
+static int graph_run(Batch* b, F&& steps, const tg_solver_opts* o, int j0, int j1, hipStream_t s) {
+  char key[192];
+  std::snprintf(key, sizeof(key), "%llx|%d|%d|%d|%d|%d|%.17g|%.17g|%d", b->lists_sig, o->prec, o->cgs_passes, j0,
+                j1, o->max_iters, o->tol, o->breakdown, b->grids[0]->mmax);
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
     if (b->graphs.size() >= 1024) {
@@ -82,7 +83,7 @@ static int graph_step(Batch* b, F&& step, const tg_solver_opts* o, int j, hipStr
     if (!b->cap_stream) TG_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     TG_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     timer_suspend(true);
-    const int rc = step(b->cap_stream);
+    const int rc = steps(b->cap_stream);
     timer_suspend(false);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
@@ -114,8 +115,29 @@ struct Checkpoints {
   std::vector<std::vector<std::pair<int, double>>> rec;   // per problem of the batch
 };
 
+static int checkpoint_eval(Batch* b, const std::vector<int>& act, int mmax, int jmax, int k, Checkpoints* cp,
+                           hipStream_t s);
 static int checkpoint(Batch* b, const std::vector<int>& act, int mmax, int jmax, int k, Checkpoints* cp,
                       hipStream_t s) {
+  int rc;
+  // a problem that stopped at this very step is still checked: the step
+  // gate is off while the checkpoint runs
+  const bool was_gated = b->gated;
+  if (was_gated) {
+    b->gated = false;
+    if ((rc = batch_upload_desc(b, s))) return rc;
+  }
+  rc = checkpoint_eval(b, act, mmax, jmax, k, cp, s);
+  if (was_gated) {
+    b->gated = true;
+    const int r2 = batch_upload_desc(b, s);
+    if (!rc) rc = r2;
+  }
+  return rc;
+}
+
+static int checkpoint_eval(Batch* b, const std::vector<int>& act, int mmax, int jmax, int k, Checkpoints* cp,
+                           hipStream_t s) {
   int rc;
   if ((rc = batch_set_active(b, act, s))) return rc;
   if ((rc = k_copy0(b, S_X, S_T, s))) return rc;
@@ -137,8 +159,29 @@ static int checkpoint(Batch* b, const std::vector<int>& act, int mmax, int jmax,
   return TG_OK;
 }
 
+// Turns the step gate off again on every way out of fgmres_batch.
+struct GateOff {
+  Batch* b;
+  hipStream_t s;
+  ~GateOff() {
+    if (b->gated) {
+      b->gated = false;
+      batch_upload_desc(b, s);
+    }
+  }
+};
+
+static int fgmres_batch_impl(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s,
+                             Checkpoints* cp);
+
 int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s,
                  Checkpoints* cp = nullptr) {
+  GateOff off{b, s};
+  return fgmres_batch_impl(b, which, o, s, cp);
+}
+
+static int fgmres_batch_impl(Batch* b, const std::vector<int>& which, const tg_solver_opts* o, hipStream_t s,
+                             Checkpoints* cp) {
   const int m = o->restart, cap = o->max_iters;
   const int mmax = b->grids[0]->mmax;
   if (m < 1 || m > mmax) return fail(TG_EINVAL, "restart must be in [1, bound max_restart]");
@@ -149,6 +192,8 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
     return fail(TG_EINVAL, "unknown preconditioner precision");
   const double tol = o->tol, brk = o->breakdown;
   if (cp && o->graphs) return fail(TG_EINVAL, "checkpoints are not taken under graph replay");
+  if (o->sync_every < 1) return fail(TG_EINVAL, "sync_every must be >= 1");
+  const int K = (cp && cp->every > 0) ? 1 : o->sync_every;
   if (cp) cp->rec.assign(b->n, {});
   int rc = check_ready(b, which, true);
   if (rc) return rc;
@@ -168,6 +213,12 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
     if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
     if ((rc = k_cycle_start(b, k, cap, tol, s))) return rc;
     if ((rc = batch_read_status(b, s))) return rc;
+    if (!b->gated) {
+      // the status gather now holds every running problem's state: from here
+      // on the step kernels skip the problems that stop
+      b->gated = true;
+      if ((rc = batch_upload_desc(b, s))) return rc;
+    }
     std::vector<int> nr;
     for (int i : running)
       if (b->sc_h[i] == TG_RUNNING) nr.push_back(i);
@@ -177,15 +228,20 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
     if (!delayed && (rc = k_scale_to(b, S_R, slot_V(0), SC_INV, s))) return rc;
     const std::vector<int> members = running;
     int jmax = 0;
-    for (int j = 0; j < m; ++j) {
-      jmax = j + 1;
-      if (delayed) {
-        // CGS2 with delayed reorthogonalization: V_j holds q~_j (projected
-        // once, first-pass norm rho_j in SC_RHO); z_j = M^-1 (q~_j / rho_j).
-        // Sweep A: dots of [V_0..V_{j-1}, q~_j] with q~_j and w = K z_j;
-        // sweep B: reorthogonalized q_j into V_j and q~_{j+1} into V_{j+1}.
-        auto step = [&](hipStream_t st) -> int {
-          int r;
+    // Runs of up to K Arnoldi steps between host reads of the status: a
+    // problem that stops inside a run is skipped on the device by the rest
+    // of it (the step kernels' gate), so every run leaves each problem
+    // exactly as single steps would.
+    for (int j0 = 0; j0 < m;) {
+      const int j1 = std::min(m, j0 + K);
+      const int k0 = k;
+      auto one_step = [&](int j, int kk, hipStream_t st) -> int {
+        int r;
+        if (delayed) {
+          // CGS2 with delayed reorthogonalization: V_j holds q~_j (projected
+          // once, first-pass norm rho_j in SC_RHO); z_j = M^-1 (q~_j / rho_j).
+          // Sweep A: dots of [V_0..V_{j-1}, q~_j] with q~_j and w = K z_j;
+          // sweep B: reorthogonalized q_j into V_j and q~_{j+1} into V_{j+1}.
           if ((r = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, st, SC_INV)))
             return r;
           if ((r = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, st))) return r;
@@ -195,55 +251,51 @@ int fgmres_batch(Batch* b, const std::vector<int>& which, const tg_solver_opts* 
           if ((r = k_update2(b, slot_V(0), j, slot_V(j), S_W, slot_V(j + 1), st))) return r;
           if ((r = k_reduce(b, 1, 2, 0, -1, st))) return r;
           return k_dcgs_b(b, j, cap, tol, brk, st);
-        };
-        if (o->graphs) {
-          if ((rc = graph_step(b, step, o, j, s))) return rc;
-        } else if ((rc = step(s))) {
-          return rc;
         }
-        ++k;
-        if ((rc = batch_read_status(b, s))) return rc;
-        if (cp && cp->every > 0 && k % cp->every == 0 && (rc = checkpoint(b, running, mmax, jmax, k, cp, s)))
-          return rc;
-        std::vector<int> still;
-        for (int i : running)
-          if (b->sc_h[i] == TG_RUNNING) still.push_back(i);
-        if (still.empty() || j == m - 1) break;
-        if (still.size() != running.size()) {
-          running.swap(still);
-          if ((rc = batch_set_active(b, running, s))) return rc;
+        if ((r = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, st))) return r;
+        if ((r = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, st))) return r;
+        // Classical Gram-Schmidt, each pass h = V^T w then w -= V h, in fused
+        // sweeps: [dots1 (+ w.w before projection -> SC_FLAG, breakdown test)]
+        // [w -= V h1; dots2] [w -= V h2; w.w]  (CGS2), or [dots1] [w -= V h1; w.w].
+        if ((r = k_multidot(b, slot_V(0), j + 1, S_W, 1, st))) return r;
+        if ((r = k_reduce(b, j + 2, 0, 0, j + 1, st))) return r;
+        if (o->cgs_passes == 3) {
+          if ((r = k_update_dots(b, slot_V(0), j + 1, S_W, 0, j + 1, 0, st))) return r;
+          if ((r = k_reduce(b, j + 1, 1, 0, -1, st))) return r;
+          if ((r = k_update_dots(b, slot_V(0), j + 1, S_W, 1, 0, 1, st))) return r;
+        } else {
+          if ((r = k_update_dots(b, slot_V(0), j + 1, S_W, 0, 0, 1, st))) return r;
         }
-        continue;
+        if ((r = k_reduce(b, 1, 2, 0, -1, st))) return r;
+        if ((r = k_arnoldi(b, j, kk, cap, tol, brk, st))) return r;
+        return k_scale_to(b, S_W, slot_V(j + 1), SC_INV, st);
+      };
+      auto run = [&](hipStream_t st) -> int {
+        for (int j = j0; j < j1; ++j) {
+          const int r = one_step(j, k0 + (j - j0), st);
+          if (r) return r;
+        }
+        return TG_OK;
+      };
+      if (o->graphs) {
+        if ((rc = graph_run(b, run, o, j0, j1, s))) return rc;
+      } else if ((rc = run(s))) {
+        return rc;
       }
-      if ((rc = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, s))) return rc;
-      if ((rc = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, s))) return rc;
-      // Classical Gram-Schmidt, each pass h = V^T w then w -= V h, in fused
-      // sweeps: [dots1 (+ w.w before projection -> SC_FLAG, breakdown test)]
-      // [w -= V h1; dots2] [w -= V h2; w.w]  (CGS2), or [dots1] [w -= V h1; w.w].
-      if ((rc = k_multidot(b, slot_V(0), j + 1, S_W, 1, s))) return rc;
-      if ((rc = k_reduce(b, j + 2, 0, 0, j + 1, s))) return rc;
-      if (o->cgs_passes == 3) {
-        if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 0, j + 1, 0, s))) return rc;
-        if ((rc = k_reduce(b, j + 1, 1, 0, -1, s))) return rc;
-        if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 1, 0, 1, s))) return rc;
-      } else {
-        if ((rc = k_update_dots(b, slot_V(0), j + 1, S_W, 0, 0, 1, s))) return rc;
-      }
-      if ((rc = k_reduce(b, 1, 2, 0, -1, s))) return rc;
-      if ((rc = k_arnoldi(b, j, k, cap, tol, brk, s))) return rc;
-      if ((rc = k_scale_to(b, S_W, slot_V(j + 1), SC_INV, s))) return rc;
-      ++k;
+      k += j1 - j0;   // every problem still running made each step of the run
+      jmax = j1;
       if ((rc = batch_read_status(b, s))) return rc;
       if (cp && cp->every > 0 && k % cp->every == 0 && (rc = checkpoint(b, running, mmax, jmax, k, cp, s)))
         return rc;
       std::vector<int> still;
       for (int i : running)
         if (b->sc_h[i] == TG_RUNNING) still.push_back(i);
-      if (still.empty() || j == m - 1) break;
+      if (still.empty() || j1 == m) break;
       if (still.size() != running.size()) {
         running.swap(still);
         if ((rc = batch_set_active(b, running, s))) return rc;
       }
+      j0 = j1;
     }
     // end of cycle: y = R^-1 g, x += Z y for every problem of this cycle
     if ((rc = batch_set_active(b, members, s))) return rc;
@@ -651,6 +703,14 @@ int tg_batch_solve(tg_batch* tb, const double* const* f_d, double* const* u_d, c
     res[i].true_eta = sr.v[SC_TRUE];
   }
   return copy_out_batch(b, all, u_d, S_X, s);
+}
+int tg_batch_tile_heights(const tg_batch* tb, int i, int* zc_out) {
+  if (!tb || !zc_out) return fail(TG_EINVAL, "NULL argument");
+  if (i < 0 || i >= tb->b.n) return fail(TG_EINVAL, "problem index out of range");
+  const tg_grid* g = tb->b.grids[i];
+  for (int l = 0; l < TG_MAXLEV; ++l)
+    zc_out[l] = (l < g->nlev) ? zm_height(g->lv[l].ez + 1, batch_zc(&tb->b, i, l)) : 0;
+  return TG_OK;
 }
 int tg_batch_history(const tg_batch* tb, int i, int count, double* hist_h, void* stream) {
   if (!tb || !hist_h) return fail(TG_EINVAL, "NULL argument");

@@ -35,8 +35,9 @@ def mg_opts(max_levels=0, max_coarse_dof=300, omega=0.6, nu_pre=2, nu_post=2):
     return L.MgOpts(max_levels, max_coarse_dof, omega, nu_pre, nu_post)
 
 
-def solver_opts(restart=30, max_iters=200, tol=1e-6, prec=F64, cgs_passes=2, breakdown=1e-14, graphs=False):
-    return L.SolverOpts(restart, max_iters, tol, prec, cgs_passes, breakdown, int(bool(graphs)))
+def solver_opts(restart=30, max_iters=200, tol=1e-6, prec=F64, cgs_passes=2, breakdown=1e-14, graphs=False,
+                sync_every=8):
+    return L.SolverOpts(restart, max_iters, tol, prec, cgs_passes, breakdown, int(bool(graphs)), sync_every)
 
 
 def policy(rungs=(1e-9, 1e-6, 1e-4, 1e-3), p=3.0, tau=1e-6, probe_iters=100, probe_restart=100,
@@ -373,6 +374,12 @@ class Batch:
                                    _stream()))
         self._iters = [r.iterations for r in res]
         return us, [result_dict(r) for r in res]
+
+    def tile_heights(self, i):
+        """z-tile heights problem i uses at each of its levels."""
+        z = (C.c_int * 8)()
+        check(lib().tg_batch_tile_heights(self.handle, i, z))
+        return [v for v in z if v > 0]
 
     def history(self, i):
         """Residual history of problem i of the last solve (iterations + 1 values)."""
