@@ -272,13 +272,13 @@ __device__ __forceinline__ int coarse_free_index(const LevelDesc& L, int node, i
 }
 
 __global__ __launch_bounds__(256) void k_coarse_factor(const ProbDesc* __restrict__ probs,
-                                                       const int2* __restrict__ work, int* bad) {
+                                                       const int2* __restrict__ work, int* bad, int nmin) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   const int l = P.nlev - 1;
   const LevelDesc& L = P.lv[l];
   const int n = P.ncoarse;
-  if (n == 0) return;              // no direct-solvable coarsest level
+  if (n == 0 || n < nmin) return;  // no direct-solvable coarsest level, or one k_coarse_factor_lds took
   double* A = P.Cwork;             // n x n, row-major; lower triangle -> L
   double* X = P.Cwork + (long long)n * n;
   for (int q = threadIdx.x; q < n * n; q += blockDim.x) A[q] = 0.0;
@@ -334,6 +334,71 @@ __global__ __launch_bounds__(256) void k_coarse_factor(const ProbDesc* __restric
     const int r = q / n, c = q % n;
     // symmetrize the explicit inverse
     const double v = 0.5 * (X[r * n + c] + X[c * n + r]);
+    P.Cinv64[q] = v;
+    P.Cinv32[q] = (float)v;
+  }
+}
+
+// The same coarsest-level set-up held in LDS, for coarsest levels whose
+// matrix fits (n^2 + 2 n doubles): the assembled matrix is inverted in place
+// by Gauss-Jordan elimination without pivoting (its pivots are the diagonal
+// entries of successive Schur complements, positive for an SPD matrix), all
+// n^2 updates of a step in parallel; the explicit inverse is symmetrized as
+// in k_coarse_factor.  A non-positive pivot flags the problem.
+#define CF_THREADS 1024
+__global__ __launch_bounds__(CF_THREADS) void k_coarse_factor_lds(const ProbDesc* __restrict__ probs,
+                                                                  const int2* __restrict__ work, int* bad,
+                                                                  int nmax) {
+  extern __shared__ double smem[];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  const int l = P.nlev - 1;
+  const LevelDesc& L = P.lv[l];
+  const int n = P.ncoarse;
+  if (n == 0 || n > nmax) return;   // larger coarsest levels: k_coarse_factor
+  double* A = smem;                  // n x n, row-major
+  double* rowk = smem + n * n;       // pivot row, scaled
+  double* colk = rowk + n;           // pivot column
+  for (int q = threadIdx.x; q < n * n; q += blockDim.x) A[q] = 0.0;
+  __syncthreads();
+  const int ne = L.ex * L.ey * L.ez;
+  for (int e = 0; e < ne; ++e) {
+    const int ex = e % L.ex, ey = (e / L.ex) % L.ey, ez = e / (L.ex * L.ey);
+    for (int q = threadIdx.x; q < 576; q += blockDim.x) {
+      const int r = q / 24, c = q % 24;
+      const int a = r / 3, b = c / 3;
+      const int na = (ex + (a & 1)) + L.NX * ((ey + ((a >> 1) & 1)) + L.NY * (ez + ((a >> 2) & 1)));
+      const int nb = (ex + (b & 1)) + L.NX * ((ey + ((b >> 1) & 1)) + L.NY * (ez + ((b >> 2) & 1)));
+      const int fr = coarse_free_index(L, na, r % 3), fc = coarse_free_index(L, nb, c % 3);
+      if (fr < 0 || fc < 0) continue;
+      const double v = (l == 0) ? P.E64[e] * P.Ke64[q] : L.Kel64[(long long)e * 576 + q];
+      A[fr * n + fc] += v;         // distinct (fr, fc) within one element
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < n; ++k) {
+    const double p = A[k * n + k];
+    if (threadIdx.x == 0 && !(p > 0.0)) atomicOr(bad + wi.x, 2);
+    const double ip = 1.0 / p;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      colk[j] = A[j * n + k];
+      rowk[j] = A[k * n + j] * ip;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+      const int i = q / n, j = q - (q / n) * n;
+      if (i == k)
+        A[q] = (j == k) ? ip : rowk[j];
+      else if (j == k)
+        A[q] = -colk[i] * ip;
+      else
+        A[q] -= colk[i] * rowk[j];
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+    const int r = q / n, c = q % n;
+    const double v = 0.5 * (A[r * n + c] + A[c * n + r]);
     P.Cinv64[q] = v;
     P.Cinv32[q] = (float)v;
   }
@@ -1321,6 +1386,40 @@ static double dofs0(const Batch* b) {
     if (_th) timer_end(_th, (double)(bytes_expr), s);   \
   } while (0)
 
+// Largest coarsest level (free DOFs) whose two packed triangles fit the
+// dynamic LDS the set-up kernel may take on the current device (the
+// device's per-workgroup limit less the kernel's static LDS), with the
+// kernel's limit raised to it once per device.
+static size_t coarse_lds_limit();
+static int coarse_lds_n() {
+  const size_t lim = coarse_lds_limit();
+  int n = 0;
+  while (sizeof(double) * (size_t)(n + 1) * (n + 3) <= lim) ++n;   // (n + 1)^2 + 2 (n + 1)
+  return n;
+}
+static size_t coarse_lds_limit() {
+  static size_t lim[64] = {};
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!done[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+      (void)hipGetLastError();   // leave no error for the next launch check
+      v = 0;
+    }
+    size_t l = v > 1024 ? (size_t)v - 1024 : 0;
+    if (l && hipFuncSetAttribute((const void*)k_coarse_factor_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)l) != hipSuccess) {
+      (void)hipGetLastError();
+      l = std::min<size_t>(l, 65536 - 1024);
+    }
+    lim[dev] = l;
+    done[dev] = true;
+  }
+  return lim[dev];
+}
+
 int k_set_density(Batch* b, hipStream_t s) {
   int* bad = b->flag_d;
   TG_HIP(hipMemsetAsync(bad, 0, sizeof(int) * b->n, s));
@@ -1333,7 +1432,22 @@ int k_set_density(Batch* b, hipStream_t s) {
       if (b->elem[l].n) k_mode_pack<<<nblk(b->elem[l]), 256, 0, s>>>(b->desc_d, b->elem[l].ptr, l);
     for (int l = 0; l < b->maxlev; ++l)
       if (b->node[l].n) k_nodeblock<<<nblk(b->node[l]), 256, 0, s>>>(b->desc_d, b->node[l].ptr, l);
-    if (b->prob.n) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad);
+    if (b->prob.n) {
+      // which kernel sets up a problem depends only on its own coarsest size
+      // and the device, so a problem gets the same inverse alone or batched
+      const int nlds = coarse_lds_n();
+      int nmax = 0, nmin = INT_MAX;
+      for (int p : b->active) {
+        const int n = b->grids[p]->ncoarse;
+        if (n > 0) nmax = std::max(nmax, n), nmin = std::min(nmin, n);
+      }
+      if (nmin <= nlds) {
+        const int nl = std::min(nmax, nlds);
+        k_coarse_factor_lds<<<nblk(b->prob), CF_THREADS, sizeof(double) * (size_t)nl * (nl + 2), s>>>(
+            b->desc_d, b->prob.ptr, bad, nlds);
+      }
+      if (nmax > nlds) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad, nlds + 1);
+    }
   });
   return check_launch("set_density kernels");
 }
