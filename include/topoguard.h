@@ -243,6 +243,73 @@ int tg_adaptive_checkpoints(tg_grid* g, const double* f_d, double* u_d, const tg
                             int every, int cap, void* ws_d, size_t ws_bytes, tg_solve_result* res, int* k_h,
                             double* proj_h, double* true_h, int* n_h, void* stream);
 
+/* ---- the full adaptive stack (Tab. solver-config; Sec. 3.5) --------------- */
+/* One application z = M(v), every part in FP64 on the device:
+ *   1. Chebyshev smoothing of degree nu_pre on K x = v from x = 0, on the
+ *      interval [lo, hi] * lambda~ of the finest level;
+ *   2. r = v - K x; the coarse problem K_1 e = P^T r (K_1 the Galerkin
+ *      operator of level 1, P the trilinear prolongation) gets coarse_steps
+ *      steps of GMRES (restart = coarse_steps, CGS2, no tolerance stop) from
+ *      e = 0, right-preconditioned by the V-cycle of levels 1.. with
+ *      Chebyshev smoothing (coarse_steps = 0: one such V-cycle; level 1
+ *      coarsest: the direct solve);
+ *   3. line search: with d = P e, alpha = (r . K d) / (K d . K d) (0 if
+ *      K d = 0) minimizes ||r - alpha K d||_2; the correction x += alpha d
+ *      is kept iff ratio = ||r - alpha K d|| / ||r|| <= theta (ratio = 1
+ *      when r = 0);
+ *   4. Chebyshev smoothing of degree nu_post from x;
+ *   5. the fine-level correction of tg_adaptive_precondition (inner_steps
+ *      GMRES steps with the node-block Jacobi preconditioner, kept iff it
+ *      lowers ||v - K z||).
+ * The Chebyshev iteration x_{k+1} = x_k + omega_k D^-1 (b - K x_k) +
+ * beta_k (x_k - x_{k-1}) (D the 3 x 3 node blocks of the level's operator)
+ * targets [lo, hi] * lambda~_l, where lambda~_l = ||D^-1 K v|| after
+ * power_iters normalized power steps from the start vector v_d =
+ * ((d + 1) * 0x9E3779B1 mod 2^32) / 2^32 - 0.5 over the level's free DOFs d
+ * (full numbering: x-fastest nodes, three components).  The outer method
+ * must be flexible: M is nonlinear in v.
+ * Single grid with at least two levels; vectors: FP64, n_dof entries
+ * (device), clamped DOFs read as 0 and written as 0.  The caller allocates
+ * the workspace (tg_stack_workspace_bytes with the outer restart, 0 for
+ * tg_stack_precondition / tg_stack_lambdas) and keeps ownership; the grid's
+ * own level vectors are used as scratch.
+ * Errors: TG_ESTATE before tg_set_density, TG_EINVAL for NULL arguments, a
+ * single-level grid, steps outside [0, TG_AD_MAX_RESTART], degrees outside
+ * [1, 16], power_iters outside [1, 1000], not 0 < lo < hi, or theta < 0;
+ * TG_EWORKSPACE for a short workspace.  Every call synchronizes `stream`. */
+typedef struct {
+  int inner_steps;     /* fine-level correction steps, default 20 (0: none)  */
+  int coarse_steps;    /* level-1 GMRES steps, default 10                     */
+  int nu_pre, nu_post; /* Chebyshev degrees, default 2 / 2                    */
+  int power_iters;     /* power steps for lambda~, default 10                 */
+  double lo, hi;       /* Chebyshev interval factors, default 0.1 / 1.1       */
+  double theta;        /* acceptance ratio of the coarse correction, 0.95     */
+} tg_stack_opts;
+typedef struct {
+  double alpha;        /* line-search step of the coarse correction           */
+  double ratio;        /* ||r - alpha K d|| / ||r||                           */
+  int coarse_accepted; /* ratio <= theta                                      */
+  int fine_kept;       /* the fine-level correction was kept                  */
+} tg_stack_log;
+void tg_default_stack_opts(tg_stack_opts* so);
+int tg_stack_workspace_bytes(const tg_grid* g, int restart, const tg_stack_opts* so, size_t* bytes);
+/* lams_h (room for n_levels - 1): lambda~ of every level above the coarsest. */
+int tg_stack_lambdas(tg_grid* g, const tg_stack_opts* so, void* ws_d, size_t ws_bytes, double* lams_h,
+                     void* stream);
+/* z = M(v); v_d and z_d must not overlap.  lams_h: lambda~ per level (n_levels
+ * - 1 values > 0) or NULL to estimate them first.  *log_h (may be NULL)
+ * receives the application's decisions. */
+int tg_stack_precondition(tg_grid* g, const double* v_d, double* z_d, const tg_stack_opts* so,
+                          const double* lams_h, void* ws_d, size_t ws_bytes, tg_stack_log* log_h, void* stream);
+/* FGMRES preconditioned by M (options and history as in tg_adaptive_solve;
+ * o->prec is not used: the stack runs in FP64).  lambda~ is estimated once
+ * per call.  log_h (may be NULL, room for max_iters + 1) receives one entry
+ * per application of M in order, *n_applied_h (may be NULL) their number,
+ * lams_h (may be NULL, room for n_levels - 1) the estimates used. */
+int tg_stack_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, const tg_stack_opts* so,
+                   void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, tg_stack_log* log_h,
+                   int* n_applied_h, double* lams_h, void* stream);
+
 /* ---- policy (Alg. floor_policy) ------------------------------------------ */
 enum { TG_SELECT_RULE = 0, TG_SELECT_MLP = 1, TG_SELECT_FIXED = 2 };
 #define TG_MAX_RUNGS 8

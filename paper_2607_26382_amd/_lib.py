@@ -49,6 +49,16 @@ class Policy(C.Structure):
                 ("solve", SolverOpts), ("want_features", C.c_int)]
 
 
+class StackOpts(C.Structure):
+    _fields_ = [("inner_steps", C.c_int), ("coarse_steps", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
+                ("power_iters", C.c_int), ("lo", C.c_double), ("hi", C.c_double), ("theta", C.c_double)]
+
+
+class StackLog(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("ratio", C.c_double), ("coarse_accepted", C.c_int),
+                ("fine_kept", C.c_int)]
+
+
 class Attempt(C.Structure):
     _fields_ = [("rung", C.c_int), ("iterations", C.c_int), ("outcome", C.c_int),
                 ("accepted", C.c_int), ("floor", C.c_double), ("proj_eta", C.c_double),
@@ -161,6 +171,14 @@ PROTOTYPES = {
     "tg_adaptive_checkpoints": (_I, [_P, _P, _P, C.POINTER(SolverOpts), _I, _I, _I, _P, _SZ,
                                      C.POINTER(SolveResult), C.POINTER(_I), C.POINTER(_D), C.POINTER(_D),
                                      C.POINTER(_I), _P]),
+    "tg_default_stack_opts": (None, [C.POINTER(StackOpts)]),
+    "tg_stack_workspace_bytes": (_I, [_P, _I, C.POINTER(StackOpts), C.POINTER(_SZ)]),
+    "tg_stack_lambdas": (_I, [_P, C.POINTER(StackOpts), _P, _SZ, C.POINTER(_D), _P]),
+    "tg_stack_precondition": (_I, [_P, _P, _P, C.POINTER(StackOpts), C.POINTER(_D), _P, _SZ, C.POINTER(StackLog),
+                                   _P]),
+    "tg_stack_solve": (_I, [_P, _P, _P, C.POINTER(SolverOpts), C.POINTER(StackOpts), _P, _SZ,
+                            C.POINTER(SolveResult), C.POINTER(_D), C.POINTER(StackLog), C.POINTER(_I),
+                            C.POINTER(_D), _P]),
     "tg_extreme_eigenvalues": (_I, [_P, _I, _I, _D, _P, _SZ, C.POINTER(SpectrumResult), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),

@@ -284,20 +284,151 @@ __global__ __launch_bounds__(AD_BLOCK) void k_ad_to64(const float* __restrict__ 
     b[i] = (double)a[i];
 }
 
+// ---- kernels of the full adaptive stack (Chebyshev smoothing, line-searched
+// coarse correction)
+
+// scalars of the stack: the log of one application first (read by the host)
+enum { ST_ALPHA = 0, ST_RATIO = 1, ST_OK = 2, ST_RKD = 3, ST_KK = 4, ST_TT = 5, ST_RR = 6, ST_PW = 7, ST_N = 16 };
+
+// start vector of the power iteration: DOF d of the level's full numbering
+// (x-fastest nodes, three components) gets ((d + 1) * 0x9E3779B1 mod 2^32) /
+// 2^32 - 0.5, exact in FP64; the clamped nodes get 0
+__global__ __launch_bounds__(AD_BLOCK) void k_st_hash(double* __restrict__ v, long long n_nodes, int NX) {
+  for (long long d = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; d < 3 * n_nodes;
+       d += (long long)gridDim.x * AD_BLOCK) {
+    const unsigned int h = (unsigned int)((unsigned long long)(d + 1) * 0x9E3779B1ull);
+    v[d] = ((d / 3) % NX == 0) ? 0.0 : (double)h / 4294967296.0 - 0.5;
+  }
+}
+
+// out = x / sqrt(*ss)
+__global__ __launch_bounds__(AD_BLOCK) void k_st_div_norm(const double* __restrict__ x, const double* __restrict__ ss,
+                                                          double* __restrict__ out, long long n) {
+  const double nr = sqrt(*ss);
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    out[i] = x[i] / nr;
+}
+
+__global__ void k_st_sqrt(const double* __restrict__ ss, double* __restrict__ out) { *out = sqrt(*ss); }
+
+// x = omega D^-1 b node by node at one level (D the 3 x 3 diagonal block of
+// K at the node); the clamped nodes get 0
+__global__ __launch_bounds__(AD_BLOCK) void k_st_jacobi(const double* __restrict__ Dinv, const double* __restrict__ b,
+                                                        double* __restrict__ x, double omega, long long n_nodes,
+                                                        int NX) {
+  for (long long v = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; v < n_nodes;
+       v += (long long)gridDim.x * AD_BLOCK) {
+    const double b0 = b[3 * v], b1 = b[3 * v + 1], b2 = b[3 * v + 2];
+    const double* D = Dinv + 9 * v;
+    const bool fixed = (v % NX) == 0;
+    x[3 * v] = fixed ? 0.0 : omega * (D[0] * b0 + D[1] * b1 + D[2] * b2);
+    x[3 * v + 1] = fixed ? 0.0 : omega * (D[3] * b0 + D[4] * b1 + D[5] * b2);
+    x[3 * v + 2] = fixed ? 0.0 : omega * (D[6] * b0 + D[7] * b1 + D[8] * b2);
+  }
+}
+
+// the momentum term of a Chebyshev step: y += beta (x - xp) (xp NULL: zero)
+__global__ __launch_bounds__(AD_BLOCK) void k_st_cheb_fix(double* __restrict__ y, const double* __restrict__ x,
+                                                          const double* __restrict__ xp, double beta, long long n) {
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    y[i] += beta * (xp ? x[i] - xp[i] : x[i]);
+}
+
+// bc = P^T rf (full weighting, the transpose of the trilinear prolongation):
+// coarse node (I, J, K) sums the fine nodes (2I + a, 2J + b, 2K + c),
+// a, b, c in {-1, 0, 1}, weighted by 1/2 per nonzero offset; the clamped
+// coarse nodes (I = 0) get 0
+__global__ __launch_bounds__(AD_BLOCK) void k_st_restrict(const double* __restrict__ rf, double* __restrict__ bc,
+                                                          int NXf, int NYf, int NZf, int NXc, int NYc, int NZc) {
+  const long long nc = (long long)NXc * NYc * NZc;
+  for (long long m = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; m < nc; m += (long long)gridDim.x * AD_BLOCK) {
+    const int I = (int)(m % NXc);
+    const long long t = m / NXc;
+    const int J = (int)(t % NYc), K = (int)(t / NYc);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (I > 0) {
+      for (int c = -1; c <= 1; ++c) {
+        const int k = 2 * K + c;
+        if (k < 0 || k >= NZf) continue;
+        for (int b = -1; b <= 1; ++b) {
+          const int j = 2 * J + b;
+          if (j < 0 || j >= NYf) continue;
+          for (int a = -1; a <= 1; ++a) {
+            const int i = 2 * I + a;
+            if (i < 0 || i >= NXf) continue;
+            const double w = 1.0 / (double)(1 << ((a != 0) + (b != 0) + (c != 0)));
+            const long long f = 3 * (i + (long long)NXf * (j + (long long)NYf * k));
+            s0 += w * rf[f];
+            s1 += w * rf[f + 1];
+            s2 += w * rf[f + 2];
+          }
+        }
+      }
+    }
+    bc[3 * m] = s0;
+    bc[3 * m + 1] = s1;
+    bc[3 * m + 2] = s2;
+  }
+}
+
+// line search: alpha = (r . Kd) / (Kd . Kd), 0 when Kd = 0
+__global__ void k_st_alpha(double* __restrict__ st) {
+  st[ST_ALPHA] = st[ST_KK] > 0.0 ? st[ST_RKD] / st[ST_KK] : 0.0;
+}
+
+// t = r - alpha Kd
+__global__ __launch_bounds__(AD_BLOCK) void k_st_axmy(const double* __restrict__ r, const double* __restrict__ Kd,
+                                                      const double* __restrict__ st, double* __restrict__ t,
+                                                      long long n) {
+  const double a = st[ST_ALPHA];
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    t[i] = r[i] - a * Kd[i];
+}
+
+// ratio = ||r - alpha Kd|| / ||r|| (1 when r = 0); the correction is kept,
+// x += alpha d, iff ratio <= theta (the acceptance ratio)
+__global__ __launch_bounds__(AD_BLOCK) void k_st_accept(double* __restrict__ st, double theta, double* __restrict__ x,
+                                                        const double* __restrict__ d, long long n) {
+  const double nr = sqrt(st[ST_RR]);
+  const double ratio = nr > 0.0 ? sqrt(st[ST_TT]) / nr : 1.0;
+  const bool ok = ratio <= theta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[ST_RATIO] = ratio;
+    st[ST_OK] = ok ? 1.0 : 0.0;
+  }
+  if (!ok) return;
+  const double a = st[ST_ALPHA];
+  for (long long i = (long long)blockIdx.x * AD_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * AD_BLOCK)
+    x[i] += a * d[i];
+}
+
+size_t inner_state_bytes(int q) {
+  // Hessenberg (q + 1) x q, g, cs, sn, scalars, control ints
+  return al(((size_t)(q + 1) * q + (q + 1) + 2 * q + IS_N) * sizeof(double) + IC_N * sizeof(int));
+}
+
 // Workspace of one call: outer basis (m + 1) + m vectors, inner basis
 // (q + 1) + q vectors, four work vectors, two float vectors, partials and
-// small device arrays.
+// small device arrays.  The full stack adds six fine vectors, the level-1
+// Krylov basis (cs + 1) + cs vectors and three level-1 work vectors, the
+// level-1 inner state and the stack's scalars.
 struct Layout {
-  long long n = 0, ld = 0;
-  int m = 0, q = 0, nb = 0;
-  size_t oV = 0, oZ = 0, iV = 0, iZ = 0, wv = 0, f32 = 0, part = 0, small = 0, ist = 0, total = 0;
-  void init(const tg_grid* g, int restart, int inner) {
+  long long n = 0, ld = 0, n1 = 0, ld1 = 0;
+  int m = 0, q = 0, nb = 0, cs = 0;
+  bool stack = false;
+  size_t oV = 0, oZ = 0, iV = 0, iZ = 0, wv = 0, f32 = 0, part = 0, small = 0, ist = 0;
+  size_t s0 = 0, c1V = 0, c1Z = 0, c1x = 0, cist = 0, stk = 0, total = 0;
+  void init(const tg_grid* g, int restart, int inner, bool with_stack = false, int coarse = 0) {
     n = g->lv[0].n_dof;
     ld = ld_of(n);
     m = restart;
     q = inner;
     nb = nblk_dots(n);
-    const size_t vb = (size_t)ld * sizeof(double);
+    stack = with_stack;
+    cs = with_stack ? coarse : 0;
+    n1 = (with_stack && g->nlev > 1) ? 3LL * g->lv[1].n_nodes : 0;
+    ld1 = ld_of(n1);
+    const size_t vb = (size_t)ld * sizeof(double), vb1 = (size_t)ld1 * sizeof(double);
     size_t o = 0;
     oV = o; o += (size_t)(m > 0 ? m + 1 : 0) * vb;
     oZ = o; o += (size_t)m * vb;
@@ -307,10 +438,31 @@ struct Layout {
     f32 = o; o += 2 * al((size_t)n * sizeof(float));
     part = o; o += al((size_t)nb * AD_MAXV * sizeof(double));
     small = o; o += al(4 * AD_MAXV * sizeof(double));
-    // inner state: Hessenberg (q + 1) x q, g, cs, sn, scalars, control ints
-    ist = o; o += al(((size_t)(q + 1) * q + (q + 1) + 2 * q + IS_N) * sizeof(double) + IC_N * sizeof(int));
+    ist = o; o += inner_state_bytes(q);
+    if (stack) {
+      s0 = o; o += 6 * vb;
+      c1V = o; o += (size_t)(cs > 0 ? cs + 1 : 0) * vb1;
+      c1Z = o; o += (size_t)cs * vb1;
+      c1x = o; o += 3 * vb1;
+      cist = o; o += inner_state_bytes(cs);
+      stk = o; o += al((ST_N + TG_MAXLEV) * sizeof(double));
+    }
     total = o;
   }
+};
+
+// One inner GMRES: its basis, Hessenberg and device scalars.
+struct Inner {
+  double* V;
+  double* Z;
+  long long ld, n;
+  int q;
+  double* H;
+  double* g;
+  double* cs;
+  double* sn;
+  double* sc;
+  int* ctl;
 };
 
 struct Ctx {
@@ -335,8 +487,38 @@ struct Ctx {
   double* isn() const { return ics() + L.q; }
   double* isc() const { return isn() + L.q; }
   int* ictl() const { return (int*)(isc() + IS_N); }
+  // an inner state at byte offset off with q columns, basis V (q + 1) and Z (q)
+  Inner inner_at(size_t off, int q, double* V, double* Z, long long ld_, long long n_) const {
+    Inner S;
+    S.V = V;
+    S.Z = Z;
+    S.ld = ld_;
+    S.n = n_;
+    S.q = q;
+    S.H = (double*)(base + off);
+    S.g = S.H + (size_t)(q + 1) * q;
+    S.cs = S.g + q + 1;
+    S.sn = S.cs + q;
+    S.sc = S.sn + q;
+    S.ctl = (int*)(S.sc + IS_N);
+    return S;
+  }
+  Inner fine_inner() const { return inner_at(L.ist, L.q, vec(L.iV, 0), vec(L.iZ, 0), L.ld, L.n); }
+  Inner coarse_inner() const {
+    return inner_at(L.cist, L.cs, (double*)(base + L.c1V), (double*)(base + L.c1Z), L.ld1, L.n1);
+  }
+  // stack vectors: fine S0(0..5), level-1 work C1(0..2), scalars, lambdas
+  double* S0(int i) const { return vec(L.s0, i); }
+  double* C1(int i) const { return (double*)(base + L.c1x) + (long long)i * L.ld1; }
+  double* stk() const { return (double*)(base + L.stk); }
+  double* lams_d() const { return stk() + ST_N; }
   bool flag_pending = false;   // a decision of M waits in isc()[IS_ACC]
   std::vector<int> accepted;
+  // the full stack: options, lambda~ per level, one log entry per application
+  bool stack = false;
+  tg_stack_opts so{};
+  double lam[TG_MAXLEV] = {};
+  std::vector<tg_stack_log> slog;
   // true-residual checkpoints of the outer iteration (every cp_every steps)
   struct Checkpoint {
     int k;
@@ -346,27 +528,37 @@ struct Ctx {
   std::vector<Checkpoint> cps;
 };
 
-// out (default tmp) = V^T w over nv basis vectors; h = out or h += out (h
-// may be NULL); self_out (may be NULL) = w^T w from the same pass
-int dots(Ctx& c, const double* V, int nv, const double* w, double* h, int acc, double* out = nullptr,
-         double* self_out = nullptr) {
+// out (default tmp) = V^T w over nv basis vectors of n entries (leading
+// dimension ld); h = out or h += out (h may be NULL); self_out (may be NULL)
+// = w^T w from the same pass
+int dots_n(Ctx& c, long long ld, long long n, const double* V, int nv, const double* w, double* h, int acc,
+           double* out = nullptr, double* self_out = nullptr) {
   const int ws = self_out ? 1 : 0;
-  dim3 grid(c.L.nb, (nv + ws + AD_QG - 1) / AD_QG);
-  k_ad_dots<<<grid, AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, ws, w, c.L.n, c.part());
+  const int nb = nblk_dots(n);
+  dim3 grid(nb, (nv + ws + AD_QG - 1) / AD_QG);
+  k_ad_dots<<<grid, AD_BLOCK, 0, c.s>>>(V, ld, nv, ws, w, n, c.part());
   TG_HIP(hipGetLastError());
-  k_ad_sum<<<nv + ws, 64, 0, c.s>>>(c.part(), c.L.nb, nv, out ? out : c.tmp(), h, acc, self_out);
+  k_ad_sum<<<nv + ws, 64, 0, c.s>>>(c.part(), nb, nv, out ? out : c.tmp(), h, acc, self_out);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
+int dots(Ctx& c, const double* V, int nv, const double* w, double* h, int acc, double* out = nullptr,
+         double* self_out = nullptr) {
+  return dots_n(c, c.L.ld, c.L.n, V, nv, w, h, acc, out, self_out);
+}
 
 // w -= V coef (nv vectors), then *norm2_out = w^T w
-int update_norm(Ctx& c, const double* V, int nv, const double* coef_d, double* w, double* norm2_out) {
-  const int nb = nblk(c.L.n);
-  k_ad_update_norm<<<nb, AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, coef_d, w, c.L.n, c.part());
+int update_norm_n(Ctx& c, long long ld, long long n, const double* V, int nv, const double* coef_d, double* w,
+                  double* norm2_out) {
+  const int nb = nblk(n);
+  k_ad_update_norm<<<nb, AD_BLOCK, 0, c.s>>>(V, ld, nv, coef_d, w, n, c.part());
   TG_HIP(hipGetLastError());
   k_ad_sum<<<1, 64, 0, c.s>>>(c.part(), nb, 0, nullptr, nullptr, 0, norm2_out);
   TG_HIP(hipGetLastError());
   return TG_OK;
+}
+int update_norm(Ctx& c, const double* V, int nv, const double* coef_d, double* w, double* norm2_out) {
+  return update_norm_n(c, c.L.ld, c.L.n, V, nv, coef_d, w, norm2_out);
 }
 
 int norm(Ctx& c, const double* w, double* out) {
@@ -385,10 +577,14 @@ int axpby(Ctx& c, double a, const double* x, double b, const double* y, double* 
   return TG_OK;
 }
 
-int update(Ctx& c, const double* V, int nv, const double* coef_d, double sgn, double* w) {
-  k_ad_update<<<nblk(c.L.n), AD_BLOCK, 0, c.s>>>(V, c.L.ld, nv, coef_d, sgn, w, c.L.n);
+int update_n(Ctx& c, long long ld, long long n, const double* V, int nv, const double* coef_d, double sgn,
+             double* w) {
+  k_ad_update<<<nblk(n), AD_BLOCK, 0, c.s>>>(V, ld, nv, coef_d, sgn, w, n);
   TG_HIP(hipGetLastError());
   return TG_OK;
+}
+int update(Ctx& c, const double* V, int nv, const double* coef_d, double sgn, double* w) {
+  return update_n(c, c.L.ld, c.L.n, V, nv, coef_d, sgn, w);
 }
 
 int applyK(Ctx& c, const double* x, double* y) { return tg_apply_K(c.g, x, y, TG_F64, c.s); }
@@ -490,13 +686,15 @@ int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, d
           return rc;
         }
       }
-      double sq[2], acc = 0.0;
+      double sq[2], acc = 0.0, lg[3] = {0.0, 0.0, 0.0};
       TG_HIP(hipMemcpyAsync(hcol.data(), c.h(), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.s));
       TG_HIP(hipMemcpyAsync(sq, c.scal(), sizeof(sq), hipMemcpyDeviceToHost, c.s));
       if (c.flag_pending) TG_HIP(hipMemcpyAsync(&acc, c.isc() + IS_ACC, sizeof(double), hipMemcpyDeviceToHost, c.s));
+      if (c.flag_pending && c.stack) TG_HIP(hipMemcpyAsync(lg, c.stk(), sizeof(lg), hipMemcpyDeviceToHost, c.s));
       TG_HIP(hipStreamSynchronize(c.s));
       if (c.flag_pending) {
         c.accepted.push_back(acc != 0.0 ? 1 : 0);
+        if (c.stack) c.slog.push_back({lg[ST_ALPHA], lg[ST_RATIO], lg[ST_OK] != 0.0 ? 1 : 0, acc != 0.0 ? 1 : 0});
         c.flag_pending = false;
       }
       const double wnorm0 = std::sqrt(sq[0]), hn = std::sqrt(sq[1]);
@@ -564,64 +762,269 @@ int fgmres(Ctx& c, const Krylov& K, const double* b, double* x, int max_iters, d
   }
 }
 
-// z = M(v): the V-cycle, then the accepted-or-rejected fine-level correction.
-// The inner GMRES (restart = steps = q, CGS2, no tolerance) runs a fixed
-// launch sequence whose scalar work and stop test live on the device; steps
-// after a stop compute into columns that are never combined.  The decision
-// is left in isc()[IS_ACC] (flag_pending), read with the caller's next
-// synchronization.
-int adaptive_apply(Ctx& c, const double* v, double* z) {
+// d = the iterate after S.q steps of right-preconditioned GMRES on A d = rhs
+// from d = 0 (restart = steps = q, CGS2, no tolerance stop): a fixed launch
+// sequence whose scalar work and stop test (breakdown, non-finite, estimate
+// exactly 0) live on the device; steps after a stop compute into columns
+// that are never combined.  w: a work vector of S.n entries.
+template <class AF, class MF>
+int inner_gmres(Ctx& c, const Inner& S, const double* rhs, double* w, double* d, AF&& A, MF&& M) {
   int rc;
-  if ((rc = vcycle(c, v, z))) return rc;
+  const int q = S.q;
+  const long long n = S.n, ld = S.ld;
+  const int nb = nblk(n);
+  if ((rc = dots_n(c, ld, n, rhs, 1, rhs, nullptr, 0, S.sc + IS_R0SQ))) return rc;
+  k_ad_inner_init<<<1, 1, 0, c.s>>>(S.sc, S.ctl, S.g);
+  TG_HIP(hipGetLastError());
+  k_ad_scale_dev<<<nb, AD_BLOCK, 0, c.s>>>(rhs, S.sc + IS_INVB, S.ctl, S.V, n);
+  TG_HIP(hipGetLastError());
+  for (int j = 0; j < q; ++j) {
+    double* vj = S.V + (long long)j * ld;
+    double* zj = S.Z + (long long)j * ld;
+    if ((rc = M(vj, zj))) return rc;
+    if ((rc = A(zj, w))) return rc;
+    if ((rc = dots_n(c, ld, n, S.V, j + 1, w, c.h(), 0, nullptr, S.sc + IS_WN0))) return rc;
+    if ((rc = update_n(c, ld, n, S.V, j + 1, c.tmp(), -1.0, w))) return rc;
+    if ((rc = dots_n(c, ld, n, S.V, j + 1, w, c.h(), 1))) return rc;
+    if ((rc = update_norm_n(c, ld, n, S.V, j + 1, c.tmp(), w, S.sc + IS_HN))) return rc;
+    k_ad_givens<<<1, 1, 0, c.s>>>(j, q, 1e-14, c.h(), S.H, S.g, S.cs, S.sn, S.sc, S.ctl);
+    TG_HIP(hipGetLastError());
+    if (j + 1 < q) {
+      k_ad_scale_dev<<<nb, AD_BLOCK, 0, c.s>>>(w, S.sc + IS_INV, S.ctl, S.V + (long long)(j + 1) * ld, n);
+      TG_HIP(hipGetLastError());
+    }
+  }
+  k_ad_lsq<<<1, 1, 0, c.s>>>(S.H, q, S.g, S.ctl, c.coef());
+  TG_HIP(hipGetLastError());
+  k_ad_combine_dev<<<nb, AD_BLOCK, 0, c.s>>>(S.Z, ld, S.ctl, c.coef(), d, n);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+// The fine-level correction of z (Tab. solver-config): with s = v - K z, q
+// inner GMRES steps on K d = s preconditioned by the node-block Jacobi
+// operator; z += d iff ||s - K d|| < ||s||.  The decision is left in
+// isc()[IS_ACC] (flag_pending), read with the caller's next synchronization.
+int fine_correction(Ctx& c, const double* v, double* z) {
+  int rc;
   c.flag_pending = true;
   if (c.L.q <= 0) {
     TG_HIP(hipMemsetAsync(c.isc() + IS_ACC, 0, sizeof(double), c.s));   // 0.0: nothing to keep
     return TG_OK;
   }
-  const int q = c.L.q;
-  const long long n = c.L.n;
-  double* w = c.W(0);
   double* s = c.W(1);
   double* t = c.W(2);
   double* d = c.W(3);
-  double* Vi = c.vec(c.L.iV, 0);
-  double* Zi = c.vec(c.L.iZ, 0);
   double* sc = c.isc();
-  int* ctl = c.ictl();
-  const int nb = nblk(n);
   if ((rc = applyK(c, z, t))) return rc;
   if ((rc = axpby(c, 1.0, v, -1.0, t, s))) return rc;
-  if ((rc = dots(c, s, 1, s, nullptr, 0, sc + IS_R0SQ))) return rc;
-  k_ad_inner_init<<<1, 1, 0, c.s>>>(sc, ctl, c.ig());
-  TG_HIP(hipGetLastError());
-  k_ad_scale_dev<<<nb, AD_BLOCK, 0, c.s>>>(s, sc + IS_INVB, ctl, Vi, n);
-  TG_HIP(hipGetLastError());
-  for (int j = 0; j < q; ++j) {
-    double* vj = Vi + (long long)j * c.L.ld;
-    double* zj = Zi + (long long)j * c.L.ld;
-    if ((rc = jacobi(c, vj, zj))) return rc;
-    if ((rc = applyK(c, zj, w))) return rc;
-    if ((rc = dots(c, Vi, j + 1, w, c.h(), 0, nullptr, sc + IS_WN0))) return rc;
-    if ((rc = update(c, Vi, j + 1, c.tmp(), -1.0, w))) return rc;
-    if ((rc = dots(c, Vi, j + 1, w, c.h(), 1))) return rc;
-    if ((rc = update_norm(c, Vi, j + 1, c.tmp(), w, sc + IS_HN))) return rc;
-    k_ad_givens<<<1, 1, 0, c.s>>>(j, q, 1e-14, c.h(), c.iH(), c.ig(), c.ics(), c.isn(), sc, ctl);
-    TG_HIP(hipGetLastError());
-    if (j + 1 < q) {
-      k_ad_scale_dev<<<nb, AD_BLOCK, 0, c.s>>>(w, sc + IS_INV, ctl, Vi + (long long)(j + 1) * c.L.ld, n);
-      TG_HIP(hipGetLastError());
-    }
-  }
-  k_ad_lsq<<<1, 1, 0, c.s>>>(c.iH(), q, c.ig(), ctl, c.coef());
-  TG_HIP(hipGetLastError());
-  k_ad_combine_dev<<<nb, AD_BLOCK, 0, c.s>>>(Zi, c.L.ld, ctl, c.coef(), d, n);
-  TG_HIP(hipGetLastError());
+  rc = inner_gmres(c, c.fine_inner(), s, c.W(0), d, [&c](const double* x, double* y) { return applyK(c, x, y); },
+                   [&c](const double* x, double* y) { return jacobi(c, x, y); });
+  if (rc) return rc;
   if ((rc = applyK(c, d, t))) return rc;
   if ((rc = axpby(c, 1.0, s, -1.0, t, t))) return rc;
   if ((rc = dots(c, t, 1, t, nullptr, 0, sc + IS_R1SQ))) return rc;
-  k_ad_accept<<<nb, AD_BLOCK, 0, c.s>>>(z, d, sc, n);
+  k_ad_accept<<<nblk(c.L.n), AD_BLOCK, 0, c.s>>>(z, d, sc, c.L.n);
   TG_HIP(hipGetLastError());
   return TG_OK;
+}
+
+// z = M(v): the V-cycle, then the accepted-or-rejected fine-level correction.
+int adaptive_apply(Ctx& c, const double* v, double* z) {
+  int rc;
+  if ((rc = vcycle(c, v, z))) return rc;
+  return fine_correction(c, v, z);
+}
+
+// ---- the full adaptive stack (Tab. solver-config; Sec. 3.5)
+//
+// One application z = M(v), all in FP64:
+//   x  = Chebyshev iteration of degree nu_pre on K x = v from 0 (finest level);
+//   r  = v - K x, b1 = P^T r;
+//   e  = coarse_steps steps of GMRES (restart = steps) on K_1 e = b1 from 0,
+//        right-preconditioned by the Chebyshev V-cycle of levels 1.. (one such
+//        V-cycle if coarse_steps = 0, the direct solve if level 1 is the
+//        coarsest);
+//   d  = P e; alpha minimizes ||r - alpha K d||; x += alpha d iff
+//        ||r - alpha K d|| <= theta ||r||;
+//   z  = Chebyshev iteration of degree nu_post from x;
+//   then the fine-level correction of z.
+// The Chebyshev iteration at level l runs on [lo, hi] * lambda~_l, lambda~_l
+// from power_iters power steps on D_l^-1 K_l from a hashed start vector.
+// Every decision is taken on the device; the log (alpha, ratio, accepted) is
+// read with the caller's next synchronization.
+
+long long lvl_n(const Ctx& c, int l) { return 3LL * c.g->lv[l].n_nodes; }
+double* pool64(const Ctx& c, int l, int slot) {
+  return c.g->desc.lv[l].vec64 + (long long)slot * c.g->desc.lv[l].stride;
+}
+
+// (omega_k, beta_k), k < deg, of the three-term Chebyshev step
+// x_{k+1} = x_k + omega_k D^-1 (b - K x_k) + beta_k (x_k - x_{k-1}) on the
+// interval [lo lam, hi lam]: centre c, half-width h, sigma = c / h,
+// rho_0 = 1 / sigma, rho_k = 1 / (2 sigma - rho_{k-1}); omega_0 = 1 / c,
+// beta_0 = 0, omega_k = 2 rho_k / h, beta_k = rho_k rho_{k-1}
+void cheb_coefs(double lam, int deg, double lo, double hi, double* om, double* be) {
+  const double a = lo * lam, b = hi * lam;
+  const double c = 0.5 * (a + b), h = 0.5 * (b - a);
+  const double sigma = c / h;
+  om[0] = 1.0 / c;
+  be[0] = 0.0;
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < deg; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    om[k] = 2.0 * rn / h;
+    be[k] = rn * rho;
+    rho = rn;
+  }
+}
+
+int st_jacobi(Ctx& c, int l, const double* b, double* x, double om) {
+  const long long nn = c.g->lv[l].n_nodes;
+  k_st_jacobi<<<nblk(nn), AD_BLOCK, 0, c.s>>>(c.g->desc.lv[l].Dinv64, b, x, om, nn, c.g->desc.lv[l].NX);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+constexpr int ST_MAX_DEGREE = 16;
+
+// Chebyshev iteration of degree deg at level l on K_l x = b from x0 (NULL:
+// from zero).  The iterates rotate through rot[0..2] (distinct from b; x0 may
+// be one of them); the last goes to out if out is non-NULL (distinct from b,
+// x0 and rot), else it stays in rot.  *res = the result.
+int cheb(Ctx& c, int l, const double* b, const double* x0, double* out, int deg, double* const* rot,
+         const double** res) {
+  int rc;
+  double om[ST_MAX_DEGREE], be[ST_MAX_DEGREE];
+  cheb_coefs(c.lam[l], deg, c.so.lo, c.so.hi, om, be);
+  const long long n = lvl_n(c, l);
+  const double* xc = x0;   // x_k
+  const double* xp = x0;   // x_{k-1}
+  for (int k = 0; k < deg; ++k) {
+    double* dst = (k == deg - 1) ? out : nullptr;
+    for (int i = 0; i < 3 && !dst; ++i)
+      if (rot[i] != xc && rot[i] != xp) dst = rot[i];
+    if (!xc) {
+      if ((rc = st_jacobi(c, l, b, dst, om[0]))) return rc;   // x_1 = omega_0 D^-1 b
+    } else {
+      if ((rc = level_op64(c.g->self, l, LV_SMOOTH, xc, b, dst, om[k], c.s))) return rc;
+      if (be[k] != 0.0) {
+        k_st_cheb_fix<<<nblk(n), AD_BLOCK, 0, c.s>>>(dst, xc, xp, be[k], n);
+        TG_HIP(hipGetLastError());
+      }
+    }
+    xp = xc;
+    xc = dst;
+  }
+  *res = xc;
+  return TG_OK;
+}
+
+// The V-cycle with Chebyshev smoothing from level l >= 1 on K_l x = b (b an
+// external vector or level l's slot C_B): result to out if non-NULL (distinct
+// from b and level l's other slots), else left in one of level l's slots
+// C_XA, C_XB, C_R; *res = the result.
+int cheb_vcycle(Ctx& c, int l, const double* b, double* out, const double** res) {
+  int rc;
+  Batch* B = c.g->self;
+  if (l == c.g->nlev - 1) {
+    double* y = out ? out : pool64(c, l, C_XA);
+    if ((rc = level_coarse64(B, l, b, y, c.s))) return rc;
+    *res = y;
+    return TG_OK;
+  }
+  double* rot[3] = {pool64(c, l, C_XA), pool64(c, l, C_XB), pool64(c, l, C_R)};
+  const double* x;
+  const double* e;
+  if ((rc = cheb(c, l, b, nullptr, nullptr, c.so.nu_pre, rot, &x))) return rc;
+  // the residual restricted straight into level l + 1's right-hand side
+  if ((rc = level_restrict64(B, l, x, b, C_B, c.s))) return rc;
+  if ((rc = cheb_vcycle(c, l + 1, pool64(c, l + 1, C_B), nullptr, &e))) return rc;
+  if ((rc = level_prolong64(B, l, e, const_cast<double*>(x), c.s))) return rc;
+  return cheb(c, l, b, x, out, c.so.nu_post, rot, res);
+}
+
+// lambda~ of every level above the coarsest into c.lam (synchronizes)
+int stack_setup(Ctx& c) {
+  int rc;
+  Batch* B = c.g->self;
+  double* st = c.stk();
+  const int nl = c.g->nlev - 1;
+  for (int l = 0; l < nl; ++l) {
+    const long long n = lvl_n(c, l);
+    double* v = l == 0 ? c.S0(0) : pool64(c, l, C_XA);
+    double* t = l == 0 ? c.S0(1) : pool64(c, l, C_XB);
+    double* w = l == 0 ? c.S0(2) : pool64(c, l, C_R);
+    const int nb = nblk(n);
+    k_st_hash<<<nb, AD_BLOCK, 0, c.s>>>(v, c.g->lv[l].n_nodes, c.g->desc.lv[l].NX);
+    TG_HIP(hipGetLastError());
+    if ((rc = dots_n(c, n, n, v, 1, v, nullptr, 0, st + ST_PW))) return rc;
+    k_st_div_norm<<<nb, AD_BLOCK, 0, c.s>>>(v, st + ST_PW, v, n);
+    TG_HIP(hipGetLastError());
+    for (int it = 0; it < c.so.power_iters; ++it) {
+      if ((rc = level_op64(B, l, LV_APPLY, v, nullptr, t, 0.0, c.s))) return rc;
+      if ((rc = st_jacobi(c, l, t, w, 1.0))) return rc;
+      if ((rc = dots_n(c, n, n, w, 1, w, nullptr, 0, st + ST_PW))) return rc;
+      k_st_div_norm<<<nb, AD_BLOCK, 0, c.s>>>(w, st + ST_PW, v, n);
+      TG_HIP(hipGetLastError());
+    }
+    k_st_sqrt<<<1, 1, 0, c.s>>>(st + ST_PW, c.lams_d() + l);
+    TG_HIP(hipGetLastError());
+  }
+  TG_HIP(hipMemcpyAsync(c.lam, c.lams_d(), sizeof(double) * nl, hipMemcpyDeviceToHost, c.s));
+  TG_HIP(hipStreamSynchronize(c.s));
+  return TG_OK;
+}
+
+// z = M(v) of the full stack (v and z distinct, n_dof entries each)
+int stack_apply(Ctx& c, const double* v, double* z) {
+  int rc;
+  Batch* B = c.g->self;
+  const long long n = c.L.n;
+  const int nb = nblk(n);
+  double* rot[3] = {c.S0(0), c.S0(1), c.S0(2)};
+  double* r = c.S0(3);
+  double* dc = c.S0(4);
+  double* Kd = c.S0(5);
+  double* st = c.stk();
+  const double* x;
+  const double* xo;
+  if ((rc = cheb(c, 0, v, nullptr, nullptr, c.so.nu_pre, rot, &x))) return rc;
+  if ((rc = level_op64(B, 0, LV_RESID, x, v, r, 0.0, c.s))) return rc;
+  // coarse right-hand side b1 = P^T r and the coarse correction e
+  double* b1 = c.C1(0);
+  double* e = c.C1(1);
+  const LevelDesc& L0 = c.g->desc.lv[0];
+  const LevelDesc& L1 = c.g->desc.lv[1];
+  k_st_restrict<<<nblk(c.g->lv[1].n_nodes), AD_BLOCK, 0, c.s>>>(r, b1, L0.NX, L0.NY, L0.NZ, L1.NX, L1.NY, L1.NZ);
+  TG_HIP(hipGetLastError());
+  if (c.g->nlev == 2) {
+    if ((rc = level_coarse64(B, 1, b1, e, c.s))) return rc;
+  } else if (c.L.cs == 0) {
+    if ((rc = cheb_vcycle(c, 1, b1, e, &xo))) return rc;
+  } else {
+    auto A1 = [&c, B](const double* a, double* y) { return level_op64(B, 1, LV_APPLY, a, nullptr, y, 0.0, c.s); };
+    auto M1 = [&c](const double* a, double* y) {
+      const double* res;
+      return cheb_vcycle(c, 1, a, y, &res);
+    };
+    if ((rc = inner_gmres(c, c.coarse_inner(), b1, c.C1(2), e, A1, M1))) return rc;
+  }
+  // d = P e, K d, and the line search on the fine residual
+  TG_HIP(hipMemsetAsync(dc, 0, sizeof(double) * n, c.s));
+  if ((rc = level_prolong64(B, 0, e, dc, c.s))) return rc;
+  if ((rc = level_op64(B, 0, LV_APPLY, dc, nullptr, Kd, 0.0, c.s))) return rc;
+  if ((rc = dots(c, r, 1, Kd, nullptr, 0, st + ST_RKD, st + ST_KK))) return rc;
+  k_st_alpha<<<1, 1, 0, c.s>>>(st);
+  TG_HIP(hipGetLastError());
+  k_st_axmy<<<nb, AD_BLOCK, 0, c.s>>>(r, Kd, st, c.W(2), n);
+  TG_HIP(hipGetLastError());
+  if ((rc = dots(c, c.W(2), 1, c.W(2), nullptr, 0, st + ST_TT))) return rc;
+  if ((rc = dots(c, r, 1, r, nullptr, 0, st + ST_RR))) return rc;
+  k_st_accept<<<nb, AD_BLOCK, 0, c.s>>>(st, c.so.theta, const_cast<double*>(x), dc, n);
+  TG_HIP(hipGetLastError());
+  if ((rc = cheb(c, 0, v, x, z, c.so.nu_post, rot, &xo))) return rc;
+  return fine_correction(c, v, z);
 }
 
 int check_common(tg_grid* g, int prec, int restart, int inner, void* ws_d, size_t ws_bytes, Layout& L) {
@@ -633,6 +1036,27 @@ int check_common(tg_grid* g, int prec, int restart, int inner, void* ws_d, size_
     return fail(TG_EINVAL, "restart and inner steps must lie in [0, TG_AD_MAX_RESTART]");
   L.init(g, restart, inner);
   if (ws_bytes < L.total) return fail(TG_EWORKSPACE, "adaptive workspace too small");
+  return TG_OK;
+}
+
+int stack_check(tg_grid* g, const tg_stack_opts* so, int restart, void* ws_d, size_t ws_bytes, Layout& L) {
+  if (!so) return fail(TG_EINVAL, "NULL stack options");
+  if (!g || !g->bound) return fail(TG_ESTATE, "grid has no bound workspace");
+  if (!g->density_set) return fail(TG_ESTATE, "set_density first");
+  if (!g->coarse_ok) return fail(TG_EINVAL, "grid cannot be coarsened to a level with <= 512 free DOFs: no V-cycle");
+  if (g->nlev < 2) return fail(TG_EINVAL, "the adaptive stack needs at least two levels");
+  if (restart < 0 || restart > TG_AD_MAX_RESTART || so->inner_steps < 0 || so->inner_steps > TG_AD_MAX_RESTART ||
+      so->coarse_steps < 0 || so->coarse_steps > TG_AD_MAX_RESTART)
+    return fail(TG_EINVAL, "restart, inner and coarse steps must lie in [0, TG_AD_MAX_RESTART]");
+  if (so->nu_pre < 1 || so->nu_pre > ST_MAX_DEGREE || so->nu_post < 1 || so->nu_post > ST_MAX_DEGREE)
+    return fail(TG_EINVAL, "Chebyshev degrees must lie in [1, 16]");
+  if (so->power_iters < 1 || so->power_iters > 1000) return fail(TG_EINVAL, "power_iters must lie in [1, 1000]");
+  if (!(so->lo > 0.0) || !(so->hi > so->lo) || !std::isfinite(so->hi))
+    return fail(TG_EINVAL, "need 0 < lo < hi, finite");
+  if (!(so->theta >= 0.0) || !std::isfinite(so->theta)) return fail(TG_EINVAL, "theta must be finite and >= 0");
+  L.init(g, restart, so->inner_steps, true, so->coarse_steps);
+  if (!ws_d) return fail(TG_EINVAL, "NULL workspace");
+  if (ws_bytes < L.total) return fail(TG_EWORKSPACE, "stack workspace too small");
   return TG_OK;
 }
 
@@ -723,6 +1147,103 @@ int tg_adaptive_checkpoints(tg_grid* g, const double* f_d, double* u_d, const tg
   if (!n_h) return fail(TG_EINVAL, "NULL argument");
   return tg::adaptive_solve_impl(g, f_d, u_d, o, inner_steps, every, cap, ws_d, ws_bytes, res, nullptr, nullptr,
                                  nullptr, k_h, proj_h, true_h, n_h, stream);
+}
+
+void tg_default_stack_opts(tg_stack_opts* so) {
+  if (!so) return;
+  so->inner_steps = 20;
+  so->coarse_steps = 10;
+  so->nu_pre = 2;
+  so->nu_post = 2;
+  so->power_iters = 10;
+  so->lo = 0.1;
+  so->hi = 1.1;
+  so->theta = 0.95;
+}
+
+int tg_stack_workspace_bytes(const tg_grid* g, int restart, const tg_stack_opts* so, size_t* bytes) {
+  if (!g || !so || !bytes) return fail(TG_EINVAL, "NULL argument");
+  if (restart < 0 || restart > TG_AD_MAX_RESTART || so->inner_steps < 0 || so->inner_steps > TG_AD_MAX_RESTART ||
+      so->coarse_steps < 0 || so->coarse_steps > TG_AD_MAX_RESTART)
+    return fail(TG_EINVAL, "restart, inner and coarse steps must lie in [0, TG_AD_MAX_RESTART]");
+  Layout L;
+  L.init(g, restart, so->inner_steps, true, so->coarse_steps);
+  *bytes = L.total;
+  return TG_OK;
+}
+
+int tg_stack_lambdas(tg_grid* g, const tg_stack_opts* so, void* ws_d, size_t ws_bytes, double* lams_h,
+                     void* stream) {
+  if (!lams_h) return fail(TG_EINVAL, "NULL argument");
+  Layout L;
+  int rc = stack_check(g, so, 0, ws_d, ws_bytes, L);
+  if (rc) return rc;
+  Ctx c{g, (hipStream_t)stream, TG_F64, L, (char*)ws_d, {}};
+  c.stack = true;
+  c.so = *so;
+  if ((rc = batch_set_active(g->self, {0}, c.s))) return rc;
+  if ((rc = stack_setup(c))) return rc;
+  std::copy(c.lam, c.lam + g->nlev - 1, lams_h);
+  return TG_OK;
+}
+
+int tg_stack_precondition(tg_grid* g, const double* v_d, double* z_d, const tg_stack_opts* so,
+                          const double* lams_h, void* ws_d, size_t ws_bytes, tg_stack_log* log_h, void* stream) {
+  if (!v_d || !z_d) return fail(TG_EINVAL, "NULL vector");
+  Layout L;
+  int rc = stack_check(g, so, 0, ws_d, ws_bytes, L);
+  if (rc) return rc;
+  Ctx c{g, (hipStream_t)stream, TG_F64, L, (char*)ws_d, {}};
+  c.stack = true;
+  c.so = *so;
+  if ((rc = batch_set_active(g->self, {0}, c.s))) return rc;
+  if (lams_h) {
+    for (int l = 0; l < g->nlev - 1; ++l)
+      if (!(lams_h[l] > 0.0) || !std::isfinite(lams_h[l])) return fail(TG_EINVAL, "lambda estimates must be > 0");
+    std::copy(lams_h, lams_h + g->nlev - 1, c.lam);
+  } else if ((rc = stack_setup(c))) {
+    return rc;
+  }
+  if ((rc = stack_apply(c, v_d, z_d))) return rc;
+  double lg[3] = {0.0, 0.0, 0.0}, acc = 0.0;
+  TG_HIP(hipMemcpyAsync(lg, c.stk(), sizeof(lg), hipMemcpyDeviceToHost, c.s));
+  TG_HIP(hipMemcpyAsync(&acc, c.isc() + IS_ACC, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  TG_HIP(hipStreamSynchronize(c.s));
+  if (log_h) *log_h = {lg[ST_ALPHA], lg[ST_RATIO], lg[ST_OK] != 0.0 ? 1 : 0, acc != 0.0 ? 1 : 0};
+  return TG_OK;
+}
+
+int tg_stack_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_opts* o, const tg_stack_opts* so,
+                   void* ws_d, size_t ws_bytes, tg_solve_result* res, double* hist_h, tg_stack_log* log_h,
+                   int* n_applied_h, double* lams_h, void* stream) {
+  if (!f_d || !u_d || !o || !res) return fail(TG_EINVAL, "NULL argument");
+  if (o->restart < 1) return fail(TG_EINVAL, "restart must be >= 1");
+  if (o->max_iters < 0 || !(o->tol >= 0.0)) return fail(TG_EINVAL, "need max_iters >= 0 and tol >= 0");
+  if (o->cgs_passes < 1 || o->cgs_passes > 3) return fail(TG_EINVAL, "cgs_passes must be 1, 2 or 3");
+  Layout L;
+  int rc = stack_check(g, so, o->restart, ws_d, ws_bytes, L);
+  if (rc) return rc;
+  Ctx c{g, (hipStream_t)stream, TG_F64, L, (char*)ws_d, {}};
+  c.stack = true;
+  c.so = *so;
+  if ((rc = batch_set_active(g->self, {0}, c.s))) return rc;
+  if ((rc = stack_setup(c))) return rc;
+  Krylov outer{c.vec(L.oV, 0), c.vec(L.oZ, 0), L.m};
+  Outcome out;
+  auto M = [&c](const double* v, double* z) { return stack_apply(c, v, z); };
+  if ((rc = fgmres(c, outer, f_d, u_d, o->max_iters, o->tol, o->cgs_passes == 1 ? 1 : 2, o->breakdown, M, out)))
+    return rc;
+  TG_HIP(hipStreamSynchronize(c.s));
+  res->iterations = out.iters;
+  res->outcome = out.outcome;
+  res->proj_eta = out.hist.back();
+  res->true_eta = -1.0;
+  if (hist_h) std::memcpy(hist_h, out.hist.data(), sizeof(double) * out.hist.size());
+  const int na = (int)std::min<size_t>(c.slog.size(), (size_t)o->max_iters + 1);
+  if (log_h) std::copy(c.slog.begin(), c.slog.begin() + na, log_h);
+  if (n_applied_h) *n_applied_h = (int)c.slog.size();
+  if (lams_h) std::copy(c.lam, c.lam + g->nlev - 1, lams_h);
+  return TG_OK;
 }
 
 }  // extern "C"

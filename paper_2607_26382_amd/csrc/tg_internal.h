@@ -266,6 +266,15 @@ int k_lsq_update(Batch* b, int mmax, int jmax, hipStream_t s);
 // small[SC_TRUE] from R and F dots; to_status: also into the status gather
 int k_true_eta(Batch* b, hipStream_t s, bool to_status = true);
 int k_init_small(Batch* b, hipStream_t s);
+// level primitives of host-stepped cycles (FP64; x, bb, y external vectors
+// of level l): op 0 y = K x, 1 y = bb - K x, 2 y = x + omega D^-1 (bb - K x);
+// the fused residual-restriction into pool slot slot_next of level l + 1;
+// xf += P ec; y = K_c^-1 bb at the coarsest level
+enum { LV_APPLY = 0, LV_RESID = 1, LV_SMOOTH = 2 };
+int level_op64(Batch* b, int l, int op, const double* x, const double* bb, double* y, double omega, hipStream_t s);
+int level_restrict64(Batch* b, int l, const double* x, const double* bb, int slot_next, hipStream_t s);
+int level_prolong64(Batch* b, int l, const double* ec, double* xf, hipStream_t s);
+int level_coarse64(Batch* b, int l, const double* bb, double* y, hipStream_t s);
 
 // kernel-class timer (tg_timer.hip)
 bool timer_on();

@@ -442,11 +442,12 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict
   x[3LL * n + 2] = omega * (D[6] * b0 + D[7] * b1 + D[8] * b2);
 }
 
-// Prolongation and correction x_f += P e_c (trilinear).
+// Prolongation and correction x_f += P e_c (trilinear); slots < 0 take the
+// external vectors ee (coarse) and ex (fine).
 template <class T>
 __global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ probs,
                                                  const int2* __restrict__ work, int l, int sx,
-                                                 int se) {
+                                                 int se, const void* ee, void* ex) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   TG_GATE(P);
@@ -456,8 +457,8 @@ __global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ pr
   if (n >= Lf.n_nodes) return;
   const int i = n % Lf.NX, t = n / Lf.NX, j = t % Lf.NY, k = t / Lf.NY;
   if (i == 0) return;
-  const auto* e = vslot<T>(Lc, se, nullptr);
-  auto* x = vslot<T>(Lf, sx, nullptr);
+  const auto* e = vslot<T>(Lc, se, ee);
+  auto* x = vslot<T>(Lf, sx, ex);
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
   const T wi_ = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
   T s0 = T(0), s1 = T(0), s2 = T(0);
@@ -1579,7 +1580,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     int o = (c == XA) ? XB : XA;
     level_sums(b, l, 1, nodes, elems, c2);
     TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 3.0 * nodes / 8 * sT,
-             k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN));
+             k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN, nullptr, nullptr));
     for (int it = 0; it < mg.nu_post; ++it) {
       if (l == 0 && fast_out && it == mg.nu_post - 1) {
         if (mf)
@@ -1616,6 +1617,42 @@ int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_
   if (prec == TG_F64) return vcycle_t<double>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, 0, in_scale);
   const int mf = prec == TG_BF16MFMA ? 1 : prec == TG_BF16X3MFMA ? 2 : 0;
   return vcycle_t<float>(b, in_is_f32, sb, eb, out_is_f32, sy, ey, s, mf, in_scale);
+}
+
+// ---- level primitives of host-stepped cycles (FP64, external vectors of
+// the level's full length, clamped nodes zero)
+int level_op64(Batch* b, int l, int op, const double* x, const double* bb, double* y, double omega,
+               hipStream_t s) {
+  const bool all = (l == 0 && op == OP_APPLY);
+  const DevList& dl = all ? b->fine : b->zm_s[l];
+  TG_TIMED(l == 0 ? TG_KT_APPLY_F64 : TG_KT_VCYCLE_COARSE, (op_bytes<double>(b, l, all ? 0 : 1, op)),
+           launch_fine<double>(b, dl, l, op, -1, x, -1, bb, -1, y, omega, s));
+  return check_launch("level operator");
+}
+int level_restrict64(Batch* b, int l, const double* x, const double* bb, int slot_next, hipStream_t s) {
+  TG_TIMED(l == 0 ? TG_KT_APPLY_F64 : TG_KT_VCYCLE_COARSE, (op_bytes<double>(b, l, 1, OP_RESTRICT)),
+           launch_fine<double>(b, b->zm_r[l], l, OP_RESTRICT, -1, x, -1, bb, slot_next, nullptr, 0.0, s, -1));
+  return check_launch("level restriction");
+}
+int level_prolong64(Batch* b, int l, const double* ec, double* xf, hipStream_t s) {
+  const DevList& sm = b->smooth[l];
+  if (sm.n) {
+    double nodes, elems, c2;
+    level_sums(b, l, 1, nodes, elems, c2);
+    TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 16.0 + 3.0 * nodes / 8 * 8.0,
+             k_prolong<double><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, -1, -1, ec, xf));
+  }
+  return check_launch("level prolongation");
+}
+int level_coarse64(Batch* b, int l, const double* bb, double* y, hipStream_t s) {
+  const DevList& co = b->coarse[l];
+  if (co.n) {
+    double nodes, elems, c2;
+    level_sums(b, l, 2, nodes, elems, c2);
+    TG_TIMED(TG_KT_TRANSFER, c2 * 8.0 + 6.0 * nodes * 8.0,
+             k_coarse_solve<double, double, double><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, -1, bb, -1, y));
+  }
+  return check_launch("coarsest solve");
 }
 
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s) {

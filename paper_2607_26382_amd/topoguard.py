@@ -58,6 +58,14 @@ def policy(rungs=(1e-9, 1e-6, 1e-4, 1e-3), p=3.0, tau=1e-6, probe_iters=100, pro
     return pol
 
 
+def stack_opts(inner_steps=20, coarse_steps=10, nu_pre=2, nu_post=2, power_iters=10, lo=0.1, hi=1.1, theta=0.95):
+    return L.StackOpts(inner_steps, coarse_steps, nu_pre, nu_post, power_iters, lo, hi, theta)
+
+
+def stack_log_dict(g):
+    return dict(alpha=g.alpha, ratio=g.ratio, coarse_accepted=bool(g.coarse_accepted), fine_kept=bool(g.fine_kept))
+
+
 def result_dict(r):
     return dict(iterations=r.iterations, outcome=OUTCOMES.get(r.outcome, r.outcome),
                 proj_eta=r.proj_eta, true_eta=r.true_eta)
@@ -226,6 +234,57 @@ class Grid:
                                             C.byref(n), _stream()))
         del ws
         return u, result_dict(res), [(ks[i], pj[i], tr[i]) for i in range(n.value)]
+
+    def _stack_ws(self, restart, so):
+        nb = C.c_size_t()
+        check(lib().tg_stack_workspace_bytes(self.handle, int(restart), C.byref(so), C.byref(nb)))
+        ws, wptr = _alloc_ws(nb.value, self.device)
+        return ws, C.c_void_p(wptr), nb.value
+
+    def stack_lambdas(self, so=None):
+        """lambda~ of every level above the coarsest (power estimates of the
+        largest eigenvalue of D^-1 K, the Chebyshev intervals' scale)."""
+        so = so or stack_opts()
+        ws, wptr, nb = self._stack_ws(0, so)
+        out = (C.c_double * 8)()
+        check(lib().tg_stack_lambdas(self.handle, C.byref(so), wptr, nb, out, _stream()))
+        del ws
+        return [out[i] for i in range(self.n_levels - 1)]
+
+    def stack_precondition(self, v, so=None, lams=None):
+        """(z, log dict): one application of the full adaptive stack (v, z
+        device FP64); lams: lambda~ per level, or None to estimate them."""
+        assert v.dtype == torch.float64 and v.is_cuda and v.numel() == self.n_dof
+        so = so or stack_opts()
+        ws, wptr, nb = self._stack_ws(0, so)
+        z = torch.empty_like(v)
+        lg = L.StackLog()
+        lam = None if lams is None else (C.c_double * len(lams))(*[float(x) for x in lams])
+        check(lib().tg_stack_precondition(self.handle, _ptr(v), _ptr(z), C.byref(so), lam, wptr, nb, C.byref(lg),
+                                          _stream()))
+        del ws
+        return z, stack_log_dict(lg)
+
+    def stack_solve(self, f, opts=None, so=None):
+        """(u, result dict, history, per-application logs, lambda~): FGMRES
+        preconditioned by the full adaptive stack."""
+        opts = opts or solver_opts()
+        so = so or stack_opts()
+        ws, wptr, nb = self._stack_ws(opts.restart, so)
+        u = torch.empty_like(f)
+        res = L.SolveResult()
+        hist = np.zeros(opts.max_iters + 1)
+        logs = (L.StackLog * (opts.max_iters + 1))()
+        na = C.c_int()
+        lams = (C.c_double * 8)()
+        check(lib().tg_stack_solve(self.handle, _ptr(f), _ptr(u), C.byref(opts), C.byref(so), wptr, nb,
+                                   C.byref(res), hist.ctypes.data_as(C.POINTER(C.c_double)), logs, C.byref(na),
+                                   lams, _stream()))
+        del ws
+        n = min(na.value, opts.max_iters + 1)
+        nl = self.n_levels - 1
+        return (u, result_dict(res), hist[:res.iterations + 1].copy(), [stack_log_dict(logs[i]) for i in range(n)],
+                [lams[i] for i in range(nl)])
 
     def density_features(self, rho, p=3.0, rho0=1e-9):
         """Six density statistics of rho (device FP64) at probe floor rho0."""

@@ -1,0 +1,216 @@
+"""GPU parity of the full adaptive stack (Tab. solver-config; Sec. 3.5) against
+the oracle, through the C ABI: the power estimates lambda~ per level, one
+application on seeded vectors (the coarse correction's line-search step, its
+residual ratio and accept decision, the fine correction's decision, the
+output element by element), the cases the stack reduces to (level 1
+coarsest, no coarse Krylov steps, every correction rejected), the flexible
+GMRES around it (histories, iteration counts, per-application decisions,
+the solution) and the error paths."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adaptive as oad
+from oracle import fgmres as ofg
+from oracle import ke as oke
+from oracle import mesh
+from oracle import multigrid as omg
+from oracle import operator as op
+from paper_2607_26382_amd import synth
+from paper_2607_26382_amd import topoguard as tg
+from paper_2607_26382_amd._lib import TopoguardError, lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+KE = oke.ke()
+
+
+def _field(kind, dims, seed):
+    if kind == "uniform":
+        return synth.uniform(*dims, seed)
+    return synth.blobs(*dims, seed, blob=2 if kind == "blob2" else 4)
+
+
+def _setup(dims, rho, rmin, max_restart=30):
+    og = mesh.Grid(*dims)
+    H = omg.build_hierarchy(og, op.young(rho, 3.0, rmin), KE)
+    g = tg.Grid(*dims, max_restart=max_restart, device=DEV)
+    g.set_density(torch.tensor(rho, dtype=torch.float64, device=DEV), 3.0, rmin)
+    assert g.n_levels == len(H)
+    return og, og.free_dofs(), H, g
+
+
+def _stack_kw(so):
+    return dict(inner_steps=so.inner_steps, coarse_steps=so.coarse_steps, theta=so.theta, nu_pre=so.nu_pre,
+                nu_post=so.nu_post, lo=so.lo, hi=so.hi)
+
+
+# grids of two (8x4x4), three (16x8x8, 24x12x12) and four (32x16x16) levels
+CASES = [((8, 4, 4), "uniform", 1e-3), ((16, 8, 8), "uniform", 1e-3), ((24, 12, 12), "blob", 1e-6),
+         ((24, 12, 8), "blob2", 1e-9), ((32, 16, 16), "blob", 1e-9)]
+
+
+@pytest.mark.parametrize("dims,kind,rmin", CASES)
+def test_lambdas_match_oracle(dims, kind, rmin):
+    og, free, H, g = _setup(dims, _field(kind, dims, 5), rmin)
+    print(f"stack lambdas {dims} rmin={rmin}", flush=True)
+    lam = np.array(g.stack_lambdas())
+    ref = np.array(oad.level_lambdas(H))
+    assert lam.shape == ref.shape
+    assert np.allclose(lam, ref, rtol=1e-10, atol=0)
+
+
+def _one(og, free, H, g, so, seed, trials=2):
+    M = oad.adaptive_stack(H, **_stack_kw(so))
+    rng = np.random.default_rng(seed)
+    for trial in range(trials):
+        v = np.zeros(og.n_dof)
+        v[free] = rng.standard_normal(int(free.sum()))
+        z_ref = M(v[free])
+        alpha, ratio, ok, kept = M.log[-1]
+        z, lg = g.stack_precondition(torch.tensor(v, device=DEV), so)
+        z = z.cpu().numpy()
+        print(f"  trial {trial}: oracle alpha={alpha:.6g} ratio={ratio:.6g} ok={ok} kept={kept}; "
+              f"gpu alpha={lg['alpha']:.6g} ratio={lg['ratio']:.6g}", flush=True)
+        # the decisions are taken with a margin (no rounding-level ties here)
+        assert abs(ratio - so.theta) > 1e-6
+        assert lg["coarse_accepted"] == ok and lg["fine_kept"] == kept
+        assert lg["alpha"] == pytest.approx(alpha, rel=1e-8, abs=1e-300)
+        assert lg["ratio"] == pytest.approx(ratio, rel=1e-9, abs=1e-14)
+        assert np.all(z[~free] == 0.0)
+        assert np.linalg.norm(z[free] - z_ref) <= 1e-7 * np.linalg.norm(z_ref)
+    return M
+
+
+@pytest.mark.parametrize("dims,kind,rmin", CASES)
+def test_one_application_matches_oracle(dims, kind, rmin):
+    og, free, H, g = _setup(dims, _field(kind, dims, 21), rmin)
+    print(f"stack M(v) {dims} rmin={rmin}", flush=True)
+    _one(og, free, H, g, tg.stack_opts(), 8)
+
+
+@pytest.mark.parametrize("coarse_steps,theta,inner", [(0, 0.95, 20), (3, 0.95, 0), (10, 0.0, 20), (10, 1.0, 5)])
+def test_variants_match_oracle(coarse_steps, theta, inner):
+    """One Chebyshev V-cycle as the coarse correction, no fine correction,
+    every coarse correction rejected (theta = 0), every one kept (theta = 1)."""
+    dims = (24, 12, 12)
+    og, free, H, g = _setup(dims, _field("blob", dims, 33), 1e-6)
+    so = tg.stack_opts(inner_steps=inner, coarse_steps=coarse_steps, theta=theta)
+    print(f"stack variant coarse_steps={coarse_steps} theta={theta} inner={inner}", flush=True)
+    M = _one(og, free, H, g, so, 17)
+    if theta == 0.0:
+        assert not any(e[2] for e in M.log)
+    if theta == 1.0:
+        assert all(e[2] for e in M.log)
+
+
+def test_chebyshev_degrees_and_interval():
+    dims = (16, 8, 8)
+    og, free, H, g = _setup(dims, _field("blob", dims, 3), 1e-3)
+    so = tg.stack_opts(nu_pre=3, nu_post=1, lo=0.2, hi=1.3, power_iters=6)
+    print("stack degrees 3/1 on [0.2, 1.3], 6 power steps", flush=True)
+    lam = np.array(g.stack_lambdas(so))
+    assert np.allclose(lam, oad.level_lambdas(H, iters=6), rtol=1e-10, atol=0)
+    M = oad.adaptive_stack(H, nu_pre=3, nu_post=1, lo=0.2, hi=1.3, lams=oad.level_lambdas(H, iters=6))
+    v = np.zeros(og.n_dof)
+    v[free] = np.random.default_rng(4).standard_normal(int(free.sum()))
+    z_ref = M(v[free])
+    z, lg = g.stack_precondition(torch.tensor(v, device=DEV), so)
+    assert lg["coarse_accepted"] == M.log[-1][2] and lg["fine_kept"] == M.log[-1][3]
+    z = z.cpu().numpy()
+    assert np.linalg.norm(z[free] - z_ref) <= 1e-7 * np.linalg.norm(z_ref)
+
+
+def test_given_lambdas_are_used():
+    """Estimates passed in replace the power iteration: the oracle fed the
+    same values gives the same output."""
+    dims = (16, 8, 8)
+    og, free, H, g = _setup(dims, _field("uniform", dims, 2), 1e-3)
+    lams = [2.5, 3.0]
+    M = oad.adaptive_stack(H, lams=lams)
+    v = np.zeros(og.n_dof)
+    v[free] = np.random.default_rng(6).standard_normal(int(free.sum()))
+    z_ref = M(v[free])
+    z, lg = g.stack_precondition(torch.tensor(v, device=DEV), lams=lams)
+    z = z.cpu().numpy()
+    assert lg["coarse_accepted"] == M.log[-1][2]
+    assert np.linalg.norm(z[free] - z_ref) <= 1e-7 * np.linalg.norm(z_ref)
+
+
+@pytest.mark.parametrize("dims,kind,rmin,restart", [((16, 8, 8), "uniform", 1e-3, 30),
+                                                    ((24, 12, 12), "blob", 1e-6, 30),
+                                                    ((16, 8, 8), "blob", 1e-9, 7),
+                                                    ((32, 16, 16), "blob", 1e-9, 30)])
+def test_solve_matches_oracle(dims, kind, rmin, restart):
+    rho = _field(kind, dims, 1001)
+    og, free, H, g = _setup(dims, rho, rmin, max_restart=restart)
+    K = H[0].K
+    f_free = og.edge_load()[free]
+    M = oad.adaptive_stack(H)
+    ref = ofg.fgmres(lambda v: K @ v, M, f_free, restart, 200, 1e-6)
+    print(f"stack FGMRES {dims} rmin={rmin} restart={restart}: oracle {ref.iters} iterations", flush=True)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    u, res, hist, logs, lams = g.stack_solve(f, tg.solver_opts(restart=restart, max_iters=200))
+    assert np.allclose(lams, M.lams, rtol=1e-10, atol=0)
+    n = min(len(hist), len(ref.hist), 20)
+    assert np.allclose(hist[:n], ref.hist[:n], rtol=1e-6, atol=0)
+    assert abs(res["iterations"] - ref.iters) <= 1
+    assert len(logs) == res["iterations"]
+    m = min(len(logs), len(M.log), 8)
+    for lg, (alpha, ratio, ok, kept) in zip(logs[:m], M.log[:m]):
+        assert lg["coarse_accepted"] == ok and lg["fine_kept"] == kept
+        assert lg["ratio"] == pytest.approx(ratio, rel=1e-6)
+    names = {ofg.PROJ_CONVERGED: "PROJ_CONVERGED", ofg.MAXIT: "MAXIT", ofg.BREAKDOWN: "BREAKDOWN"}
+    assert res["outcome"] == names[ref.outcome]
+    if ref.outcome == ofg.PROJ_CONVERGED:
+        assert g.true_residual(f, u) <= 1e-6
+        uf = u.cpu().numpy()[free]
+        assert np.linalg.norm(uf - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
+    else:
+        # short restarts stall on this state (the oracle's run too): both stop at
+        # the cap above the tolerance.  Over 28 restarts of a nonlinear
+        # preconditioner rounding-level differences grow, so only the start of
+        # the history (above) is compared value by value.
+        assert res["iterations"] == ref.iters == 200
+        assert g.true_residual(f, u) > 1e-6 and op.relative_residual(K, f_free, ref.x) > 1e-6
+
+
+def test_errors():
+    dims = (8, 4, 4)
+    og, free, H, g = _setup(dims, synth.uniform(*dims, 0), 1e-3)
+    v = torch.zeros(g.n_dof, dtype=torch.float64, device=DEV)
+    z = torch.empty_like(v)
+    so = tg.stack_opts()
+    nb = C.c_size_t()
+    assert lib().tg_stack_workspace_bytes(g.handle, 0, C.byref(so), C.byref(nb)) == 0
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=DEV)
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    lg = tg.L.StackLog()
+    args = (g.handle, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr()))
+    assert lib().tg_stack_precondition(*args, C.byref(so), None, C.c_void_p(ptr), nb.value - 8, C.byref(lg),
+                                       None) != 0
+    for bad in (dict(nu_pre=0), dict(nu_post=17), dict(power_iters=0), dict(lo=0.0), dict(hi=0.05),
+                dict(theta=-1.0), dict(coarse_steps=513), dict(inner_steps=-1)):
+        sb = tg.stack_opts(**bad)
+        assert lib().tg_stack_precondition(*args, C.byref(sb), None, C.c_void_p(ptr), nb.value, C.byref(lg),
+                                           None) != 0, bad
+    bad_lams = (C.c_double * 1)(0.0)
+    assert lib().tg_stack_precondition(*args, C.byref(so), bad_lams, C.c_void_p(ptr), nb.value, C.byref(lg),
+                                       None) != 0
+    with pytest.raises(TopoguardError):
+        g.stack_solve(torch.tensor(g.edge_load(), device=DEV), tg.solver_opts(restart=0))
+    # a single-level grid has no coarse level for the stack
+    g1 = tg.Grid(4, 2, 2, mg=tg.mg_opts(max_levels=1), device=DEV)
+    assert g1.n_levels == 1
+    g1.set_density(torch.tensor(synth.uniform(4, 2, 2, 0), device=DEV), 3.0, 1e-3)
+    with pytest.raises(TopoguardError):
+        g1.stack_lambdas()
+    # before set_density
+    g2 = tg.Grid(*dims, device=DEV)
+    with pytest.raises(TopoguardError):
+        g2.stack_lambdas()
+    # zero right-hand side: nothing to do, zero solution
+    u, res, hist, logs, lams = g.stack_solve(torch.zeros_like(v), tg.solver_opts())
+    assert res["iterations"] == 0 and list(hist) == [0.0] and not torch.any(u)
