@@ -121,6 +121,10 @@ def parse():
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive-preconditioner leg (fine-level correction)")
     ap.add_argument("--adaptive-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--stack-states", type=int, default=24,
+                    help="states of the full-adaptive-stack policy leg (paper setting, one at a time)")
+    ap.add_argument("--no-stack", action="store_true", help="skip the full-adaptive-stack policy leg")
+    ap.add_argument("--stack-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--paper-states", type=int, default=102,
                     help="states of the adaptive leg's paper-setting part (p = 4.5, rho_0 = 1e-12, FGMRES(300))")
     ap.add_argument("--trajectory-only", action="store_true", help="run only the optimization-loop leg")
@@ -215,7 +219,13 @@ def compact(result, full_path=None):
         c["mixed_over_fp64"] = r.get("mixed_over_fp64")
     if "mixed_rule" in r:
         c["mixed_rule"] = {k: r["mixed_rule"].get(k) for k in ("value", "ms_per_step", "certified")}
+        c["mixed_rule"]["lowest_admissible_selected"] = _get(r, "mixed_rule", "stats", "lowest_admissible_selected")
         c["selector_gain"] = r.get("selector_gain")
+    if "mixed_rule_tuned" in r:
+        c["mixed_rule_tuned"] = {k: r["mixed_rule_tuned"].get(k) for k in ("value", "ms_per_step", "certified")}
+        c["mixed_rule_tuned"]["lowest_admissible_selected"] = _get(r, "mixed_rule_tuned", "stats",
+                                                                   "lowest_admissible_selected")
+        c["selector_gain_vs_tuned_rule"] = r.get("selector_gain_vs_tuned_rule")
     st = _get(pol, "stats")
     if st:
         c["selector_stats"] = {"sensitivity": _get(st, "sensitivity", "k"), "escalate": _get(st, "sensitivity", "n"),
@@ -263,6 +273,14 @@ def compact(result, full_path=None):
         c["adaptive"] = {"certified": [_get(ad, "adaptive", "certified"), _get(ad, "plain_vcycle", "certified")],
                          "s_per_solve": [_get(ad, "adaptive", "seconds_per_solve"),
                                          _get(ad, "plain_vcycle", "seconds_per_solve")]}
+    sp = r.get("stack_policy")
+    if sp:
+        c["stack_policy_paper_setting"] = {
+            "states": sp.get("states"), "certified": sp.get("certified"),
+            "false_stops_caught": sp.get("false_stops_caught"),
+            "accepted_above_tolerance": sp.get("accepted_above_tolerance"),
+            "oracle_false_acceptances": _get(sp, "oracle_recheck", "false_acceptances_oracle"),
+            "s_per_state": sp.get("seconds_per_state")}
     if full_path:
         c["full_record"] = full_path
     return _r(c)
@@ -736,6 +754,65 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
     return out
 
 
+
+PAPER_RUNGS = (1e-12, 1e-3, 1e-2)
+
+
+def stack_policy_leg(tg, torch, dev, rhos, fs, n_states, recheck=True, tau=1e-6):
+    """Alg. floor_policy with the full adaptive stack (Chebyshev smoothing,
+    line-searched and rejectable coarse correction with 10 level-1 GMRES
+    steps, fine-level correction) preconditioning the probe and every rung,
+    under the paper's settings (Tab. solver-config: p = 4.5, rho_0 = 1e-12,
+    ladder {1e-3, 1e-2}, 100-iteration probe, FGMRES(300) with cap 300, FP64
+    throughout), one state at a time through tg_stack_select_floor.  Reports
+    certified states, the attempts whose projected estimate converged while the
+    recomputed residual is above tau (false stops the guard rejects), first
+    and selected rungs, stage iterations, seconds per state and the oracle's
+    recheck of every accepted solution."""
+    n = min(n_states, len(rhos))
+    g = tg.Grid(*GRID, max_restart=30, device=dev)
+    pol = tg.policy(rungs=PAPER_RUNGS, p=4.5, solve=tg.solver_opts(restart=300, max_iters=300, prec=tg.F64))
+    outs, us, secs = [], [], []
+    for i in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, o = g.stack_select_floor(rhos[i], fs[i], pol)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        outs.append(o)
+        us.append(u.cpu().numpy() if o["rung"] >= 0 else None)
+        log(f"stack policy state {SEED0 + i}: k0={o['k0']} rung={o['rung']} r50={o['r50']:.3g} "
+            f"r100={o['r100']:.3g} attempts={[(a['rung'], a['iterations'], a['outcome'], a['true_eta']) for a in o['attempts']]} "
+            f"{secs[-1]:.2f}s")
+    false_stops = [[SEED0 + i, a["rung"], a["iterations"], a["proj_eta"], a["true_eta"]]
+                   for i, o in enumerate(outs) for a in o["attempts"]
+                   if a["outcome"] == "PROJ_CONVERGED" and not a["true_eta"] <= tau]
+    acc = [o for o in outs if o["rung"] >= 0]
+    res = {"states": n, "p": 4.5, "rungs": list(PAPER_RUNGS), "probe": "100 its, restart 100",
+           "solve": "FGMRES(300), cap 300, adaptive stack, FP64 throughout",
+           "certified": len(acc),
+           "first_rung": {str(r): sum(1 for o in outs if o["k0"] == r) for r in range(len(PAPER_RUNGS))},
+           "selected_rungs": {str(r): sum(1 for o in outs if o["rung"] == r) for r in range(-1, len(PAPER_RUNGS))},
+           "false_stops_caught": len(false_stops), "false_stop_rows": false_stops,
+           "accepted_above_tolerance": sum(1 for o in outs for a in o["attempts"]
+                                           if a["accepted"] and not a["true_eta"] <= tau),
+           "max_accepted_true_eta": max((o["attempts"][-1]["true_eta"] for o in acc), default=None),
+           "mean_attempts": float(np.mean([len(o["attempts"]) for o in outs])) if outs else None,
+           "mean_iters": {k: float(np.mean([o[k] for o in outs])) if outs else None
+                          for k in ("iters_probe", "iters_selected", "iters_rejected")},
+           "seconds_per_state": float(np.mean(secs)) if secs else None}
+    if recheck and acc:
+        f_np = fs[0].cpu().numpy()
+        items = [(GRID, rhos[i].cpu().numpy(), 4.5, PAPER_RUNGS[o["rung"]], f_np, us[i])
+                 for i, o in enumerate(outs) if o["rung"] >= 0]
+        res["oracle_recheck"] = oracle_recheck(items, [o["attempts"][-1]["true_eta"] for o in acc])
+    log(f"stack policy leg: certified {res['certified']}/{n}, false stops caught {res['false_stops_caught']}, "
+        f"{res['seconds_per_state']:.2f} s/state")
+    del g
+    torch.cuda.empty_cache()
+    return res
+
+
 B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
 
 
@@ -962,6 +1039,13 @@ def main():
             tg, torch, dev, rhos, [f0] * n_ad, {"f32": tg.F32, "bf16": tg.BF16MFMA, "bf16x3": tg.BF16X3MFMA}[args.mixed],
             n_states=n_ad, n_paper=args.paper_states)}), flush=True)
         return
+    if args.stack_only:
+        n_st = args.stack_states
+        rhos = [torch.tensor(synth.severe(SEED0 + i)[1], device=dev) for i in range(n_st)]
+        f0 = torch.tensor(tg.Grid(*GRID, max_restart=1, device=dev).edge_load(), device=dev)
+        print(json.dumps({"stack_policy": stack_policy_leg(tg, torch, dev, rhos, [f0] * n_st, n_st,
+                                                           recheck=not args.no_recheck)}), flush=True)
+        return
     apply_res = None
     if not args.no_apply:
         apply_res = apply_leg(tg, torch, dev)
@@ -1126,6 +1210,9 @@ def main():
     if not args.no_adaptive:
         result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec, n_states=n,
                                                          n_paper=args.paper_states)
+    if not args.no_stack and args.stack_states > 0:
+        result["stack_policy"] = stack_policy_leg(tg, torch, dev, rhos, fs, args.stack_states,
+                                                  recheck=not args.no_recheck)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)
@@ -1133,6 +1220,19 @@ def main():
         if labels is not None:
             result["mixed_rule"]["stats"] = policy_stats(o, labels)
         result["selector_gain"] = value / result["mixed_rule"]["value"]
+        # the rule with thresholds re-tuned on the network's training states
+        # (the 288-combination search), so the network's gain is not a
+        # recalibration of Eq. trigger
+        th = model["meta"].get("tuned_rule")
+        if th:
+            solve = tg.solver_opts(restart=30, max_iters=200, prec=mixed_prec, cgs_passes=args.cgs_passes)
+            pol = tg.policy(rungs=RUNGS, p=3.0, solve=solve, t_high=th[0], t_plateau=th[1], t_ratio=th[2])
+            d, o, _ = run(mixed_prec, args.steps, 0, 0, False, pol)
+            result["mixed_rule_tuned"] = brief(o, d, args.steps)
+            result["mixed_rule_tuned"]["thresholds"] = list(th)
+            if labels is not None:
+                result["mixed_rule_tuned"]["stats"] = policy_stats(o, labels)
+            result["selector_gain_vs_tuned_rule"] = value / result["mixed_rule_tuned"]["value"]
     if not args.no_fixed_legs:
         # the two fixed baselines: the original floor first, then the ladder;
         # always the top rung (the conventional floor 1e-3)

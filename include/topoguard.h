@@ -350,6 +350,23 @@ void tg_default_policy(tg_policy* pol);
  * eta > tau. */
 int tg_select_floor(tg_grid* g, const double* rho_d, const double* f_d, const tg_policy* pol,
                     double* u_d, tg_policy_result* out, void* stream);
+/* Alg. floor_policy with the adaptive stack preconditioning every solve
+ * (the paper's own configuration, Tab. solver-config): the probe at
+ * pol->rungs[0] (pol->probe_iters iterations, restart pol->probe_restart,
+ * tolerance pol->solve.tol), the first rung from Eq. trigger, the network or a
+ * fixed rung as in tg_select_floor, then per rung from there an independent
+ * tg_stack_solve with pol->solve's restart, cap and tolerance, followed by the
+ * FP64 guard eta = ||f - K u|| / ||f|| <= pol->tau (Eq. relative_residual);
+ * the first accepted rung ends the climb.  pol->solve.prec is not used (the
+ * stack runs in FP64).  Single grid with at least two levels; rho_d: stored
+ * densities (device, n_elem doubles), f_d and u_d: FP64, n_dof (device).  On
+ * return u_d holds the accepted solution, or zeros when no rung is accepted;
+ * the probe's iterate is never returned.  Workspace: tg_stack_workspace_bytes
+ * with max(probe_restart, solve.restart), caller-owned.  Errors as
+ * tg_stack_solve and tg_select_floor; synchronizes `stream`. */
+int tg_stack_select_floor(tg_grid* g, const double* rho_d, const double* f_d, const tg_policy* pol,
+                          const tg_stack_opts* so, void* ws_d, size_t ws_bytes, double* u_d,
+                          tg_policy_result* out, void* stream);
 
 /* ---- batching (addition (2)) --------------------------------------------- */
 /* A batch solves independent problems of possibly different grid sizes

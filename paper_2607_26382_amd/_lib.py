@@ -179,6 +179,8 @@ PROTOTYPES = {
     "tg_stack_solve": (_I, [_P, _P, _P, C.POINTER(SolverOpts), C.POINTER(StackOpts), _P, _SZ,
                             C.POINTER(SolveResult), C.POINTER(_D), C.POINTER(StackLog), C.POINTER(_I),
                             C.POINTER(_D), _P]),
+    "tg_stack_select_floor": (_I, [_P, _P, _P, C.POINTER(Policy), C.POINTER(StackOpts), _P, _SZ, _P,
+                                   C.POINTER(PolicyResult), _P]),
     "tg_extreme_eigenvalues": (_I, [_P, _I, _I, _D, _P, _SZ, C.POINTER(SpectrumResult), _P]),
     "tg_timer_enable": (_I, [_I]),
     "tg_timer_reset": (_I, []),

@@ -1246,4 +1246,80 @@ int tg_stack_solve(tg_grid* g, const double* f_d, double* u_d, const tg_solver_o
   return TG_OK;
 }
 
+int tg_stack_select_floor(tg_grid* g, const double* rho_d, const double* f_d, const tg_policy* pol,
+                          const tg_stack_opts* so, void* ws_d, size_t ws_bytes, double* u_d,
+                          tg_policy_result* out, void* stream) {
+  if (!g || !rho_d || !f_d || !pol || !so || !u_d || !out) return fail(TG_EINVAL, "NULL argument");
+  if (pol->n_rungs < 1 || pol->n_rungs > TG_MAX_RUNGS) return fail(TG_EINVAL, "bad policy rungs");
+  for (int r = 0; r < pol->n_rungs; ++r)
+    if (!(pol->rungs[r] > 0 && pol->rungs[r] <= 1)) return fail(TG_EINVAL, "rungs must be in (0, 1]");
+  if (pol->probe_iters < 0 || pol->probe_restart < 1) return fail(TG_EINVAL, "bad probe settings");
+  hipStream_t s = (hipStream_t)stream;
+  std::memset(out, 0, sizeof(*out));
+  int rc;
+  // ---- probe at the original floor (its iterate is never returned)
+  if ((rc = tg_set_density(g, rho_d, pol->p, pol->rungs[0], stream))) return rc;
+  tg_solver_opts po = pol->solve;
+  po.restart = pol->probe_restart;
+  po.max_iters = pol->probe_iters;
+  std::vector<double> h((size_t)std::max(po.max_iters, std::max(pol->solve.max_iters, 0)) + 1);
+  tg_solve_result res{};
+  if ((rc = tg_stack_solve(g, f_d, u_d, &po, so, ws_d, ws_bytes, &res, h.data(), nullptr, nullptr, nullptr,
+                           stream)))
+    return rc;
+  probe_feats(h.data(), res.iterations, &out->r50, &out->r100);
+  out->probe_iters = res.iterations;
+  out->iters_probe = res.iterations;
+  // ---- first rung: Eq. trigger, the network or a fixed rung
+  int k0 = rule_fires(pol, out->r50, out->r100) ? std::min(1, pol->n_rungs - 1) : 0;
+  std::vector<std::array<float, 8>> feats(1);
+  feats[0].fill(0.f);
+  feats[0][0] = (float)std::log10(std::max(out->r50, 1e-300));
+  feats[0][1] = (float)std::log10(std::max(out->r100, 1e-300));
+  const bool use_mlp = pol->selector == TG_SELECT_MLP && pol->mlp;
+  if (use_mlp || pol->want_features)
+    if ((rc = density_features(g->self, {0}, &rho_d, pol->p, pol->rungs[0], feats, s))) return rc;
+  if (use_mlp) {
+    std::vector<int> pred;
+    if ((rc = mlp_select(pol->mlp, feats, pred, s))) return rc;
+    k0 = std::min(std::max(pred[0], 0), pol->n_rungs - 1);
+  } else if (pol->selector == TG_SELECT_FIXED) {
+    k0 = std::min(std::max(pol->fixed_rung, 0), pol->n_rungs - 1);
+  }
+  out->k0 = k0;
+  out->rung = -1;
+  out->floor = -1.0;
+  for (int q = 0; q < 8; ++q) out->features[q] = feats[0][q];
+  // ---- guarded ladder: independent solve per rung, recomputed FP64 residual
+  for (int r = k0; r < pol->n_rungs && out->rung < 0; ++r) {
+    if ((rc = tg_set_density(g, rho_d, pol->p, pol->rungs[r], stream))) return rc;
+    if ((rc = tg_stack_solve(g, f_d, u_d, &pol->solve, so, ws_d, ws_bytes, &res, nullptr, nullptr, nullptr,
+                             nullptr, stream)))
+      return rc;
+    double eta = 0.0;
+    if ((rc = tg_true_residual(g, f_d, u_d, &eta, stream))) return rc;
+    auto& A = out->attempts[out->n_attempts++];
+    A.rung = r;
+    A.floor = pol->rungs[r];
+    A.iterations = res.iterations;
+    A.outcome = res.outcome;
+    A.proj_eta = res.proj_eta;
+    A.true_eta = eta;
+    A.accepted = (eta <= pol->tau) && std::isfinite(eta);
+    if (A.accepted) {
+      out->rung = r;
+      out->floor = A.floor;
+      out->iters_selected = A.iterations;
+    } else {
+      out->iters_rejected += A.iterations;
+    }
+  }
+  if (out->rung < 0) {
+    const size_t n_dof = 3ull * (g->nx + 1) * (g->ny + 1) * (g->nz + 1);
+    TG_HIP(hipMemsetAsync(u_d, 0, n_dof * sizeof(double), s));
+  }
+  TG_HIP(hipStreamSynchronize(s));
+  return TG_OK;
+}
+
 }  // extern "C"

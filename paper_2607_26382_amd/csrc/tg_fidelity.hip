@@ -106,9 +106,15 @@ __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ 
   __shared__ double red[4];
   const int tx = threadIdx.x & (EN_T - 1), ty = threadIdx.x / EN_T;
   const int ntx = (nx + EN_T - 1) / EN_T;
-  const int x0 = (int)(blockIdx.x % ntx) * EN_T, y0 = (int)(blockIdx.x / ntx) * EN_T;
+  // logical block (tile, z chunk) = tile + tiles * chunk, dealt so that each
+  // XCD runs a contiguous range: neighbouring tiles share their halo nodes
+  // and partly used cache lines in one L2
+  const int nb = (int)(gridDim.x * gridDim.y);
+  const int lb = xcd_tile((int)(blockIdx.x + gridDim.x * blockIdx.y), nb);
+  const int tile = lb % (int)gridDim.x, chunk = lb / (int)gridDim.x;
+  const int x0 = (tile % ntx) * EN_T, y0 = (tile / ntx) * EN_T;
   const int ex = x0 + tx, ey = y0 + ty;
-  const int z0 = (int)blockIdx.y * zc, z1 = min(nz, z0 + zc);
+  const int z0 = chunk * zc, z1 = min(nz, z0 + zc);
   const long long NX = nx + 1, NXY = (long long)(nx + 1) * (ny + 1);
   const bool act = ex < nx && ey < ny;
   // the two staged nodes of this thread: q = threadIdx.x + 256 s, (lx, ly)
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ 
     }
   }
   const double sum = block_sum(fu, red);
-  if (part && threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+  if (part && threadIdx.x == 0) part[lb] = sum;   // summed on the host in logical order
 }
 
 // Moments of two gradient fields over the elements with rho >= solid_min,

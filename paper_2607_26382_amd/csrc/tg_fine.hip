@@ -338,14 +338,6 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Workgroups are dealt to the 8 XCDs round robin (workgroup i runs on XCD
-// i mod 8) and each XCD has its own L2.  Giving every XCD a contiguous range
-// of the work list keeps neighbouring tiles, which share halo nodes and
-// partly used cache lines, in one L2.  A bijection on [0, n).
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-  const int q = n >> 3, r = n & 7, x = b & 7;
-  return x * q + min(x, r) + (b >> 3);
-}
 
 // z-tiles of height zc node layers
 __host__ __device__ __forceinline__ int fz_tiles(int NX, int NY, int NZ, int zc) {
@@ -359,7 +351,8 @@ template <class T, int OP, int KIND, class TY = T>
 __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ probs,
                                                  const int2* __restrict__ work, int l, int sx,
                                                  const void* ex_, int sb, const void* eb_, int sy,
-                                                 void* ey_, int sy2, T omega, ModeCoef<T> mc) {
+                                                 void* ey_, int sy2, T omega, ModeCoef<T> mc,
+                                                 int vbskip) {
   // Single buffers suffice: every read of a layer's values happens between the
   // two barriers of its step, every write of the next layer after them.
   constexpr bool MF = (KIND == 2 || KIND == 3);   // matrix-core forms
@@ -384,6 +377,8 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   const int2 wi = work[xcd_tile(blockIdx.x, gridDim.x)];
   const ProbDesc& P = probs[wi.x];
   TG_GATE(P);
+  // inside a V-cycle, levels from the problem's bottom level down belong to k_vbottom
+  if (KIND == 4 && vbskip && l >= (sizeof(T) == 8 ? P.vb_lb64 : P.vb_lb32)) return;
   const LevelDesc& L = P.lv[l];
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
   const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;
@@ -937,7 +932,7 @@ template <> ModeCoef<float> mcoef<float>(const tg_grid* g) { return g->mc32; }
 // Every grid of a batch shares one Ke (checked at batch creation).
 template <class T>
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
-                const void* eb, int sy, void* ey, double omega, hipStream_t s, int sy2) {
+                const void* eb, int sy, void* ey, double omega, hipStream_t s, int sy2, int vbskip) {
   if (!dl.n) return TG_OK;
   const ModeCoef<T> mc = mcoef<T>(b->grids[0]);
   const ProbDesc* desc = b->desc_d;
@@ -945,13 +940,13 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
 #define TG_ZM(KV)                                                                                         \
   do {                                                                                                    \
     if (op == FOP_APPLY)                                                                                  \
-      k_fine_zm<T, FOP_APPLY, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc);    \
+      k_fine_zm<T, FOP_APPLY, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip);    \
     else if (op == FOP_RESID)                                                                             \
-      k_fine_zm<T, FOP_RESID, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc);    \
+      k_fine_zm<T, FOP_RESID, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip);    \
     else if (op == FOP_SMOOTH)                                                                            \
-      k_fine_zm<T, FOP_SMOOTH, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc);   \
+      k_fine_zm<T, FOP_SMOOTH, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip);   \
     else                                                                                                  \
-      k_fine_zm<T, FOP_RESTRICT, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc); \
+      k_fine_zm<T, FOP_RESTRICT, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip); \
   } while (0)
   if (l == 0)
     TG_ZM(0);
@@ -963,7 +958,7 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
   return TG_OK;
 }
 template int launch_fine<double>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
-                                 int, void*, double, hipStream_t, int);
+                                 int, void*, double, hipStream_t, int, int);
 
 // Level 0 with the BF16 matrix-core contraction (FP32 vectors): op as above.
 int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,
@@ -973,7 +968,7 @@ int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int 
   const ProbDesc* desc = b->desc_d;
   const float om = float(omega);
 #define TG_MF(OPV, K, TYV) \
-  k_fine_zm<float, OPV, K, TYV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, sy2, om, mc)
+  k_fine_zm<float, OPV, K, TYV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, 0, sx, ex, sb, eb, sy, ey, sy2, om, mc, 0)
   if (out64) {
     if (split) TG_MF(FOP_SMOOTH, 3, double); else TG_MF(FOP_SMOOTH, 2, double);
   } else if (op == FOP_APPLY) {
@@ -996,10 +991,367 @@ int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, 
   if (!dl.n) return TG_OK;
   const ModeCoef<float> mc = mcoef<float>(b->grids[0]);
   k_fine_zm<float, FOP_SMOOTH, 0, double><<<dl.n, 256, 0, s>>>(b->desc_d, dl.ptr, 0, sx, nullptr, sb, nullptr,
-                                                               sy, nullptr, -1, float(omega), mc);
+                                                               sy, nullptr, -1, float(omega), mc, 0);
   return TG_OK;
 }
 template int launch_fine<float>(const Batch*, const DevList&, int, int, int, const void*, int, const void*,
-                                int, void*, double, hipStream_t, int);
+                                int, void*, double, hipStream_t, int, int);
+
+// ---------------------------------------------------------------------------
+// The bottom of the V-cycle in one launch.  From a level lb >= 2 down, every
+// level of a problem is small: one workgroup per problem keeps the level
+// vectors x and b of levels lb..L in LDS and runs that part of the cycle
+// (the remaining pre-sweeps, residual and restriction, the coarsest solve
+// with the explicit inverse, prolongation and post-sweeps) with barriers in
+// place of launches.  The level operators are the stored mode-basis Galerkin
+// elements: an element pass writes each element's 24 outputs to LDS
+// (component-major, one thread per element), a node pass sums the up to
+// eight contributions of each node in a fixed order.  Entry: b and
+// the first sweep x = w D^-1 b of level lb in slots C_B and C_XA (written by
+// the restriction from level lb - 1; b only when lb is the coarsest level);
+// exit: the level-lb result in slot sfin.
+// threads per workgroup: FP32 fits 128 registers (16 waves), FP64 takes 256
+template <class T>
+struct VbThreads {
+  static constexpr int N = sizeof(T) == 8 ? 512 : 1024;
+};
+
+// LDS words (of type T) the bottom needs from level lb of grid g down
+static size_t vb_words(const tg_grid* g, int lb) {
+  const auto& H = g->lv[lb];
+  size_t w = (size_t)24 * H.n_elem;                     // element outputs
+  w += 3 * (size_t)H.n_nodes;                           // residual
+  for (int l = lb; l < g->nlev; ++l) w += 6 * (size_t)g->lv[l].n_nodes;   // x, b
+  return w;
+}
+
+size_t vbottom_lds_bytes(const tg_grid* g, int lb, size_t tsize) { return vb_words(g, lb) * tsize; }
+
+// Algorithmic bytes of one bottom launch over the problems of list tv: per
+// level the stored element matrices once per operator pass and the node-block
+// inverses once per sweep, the coarsest inverse, and level lb's b and x in and
+// result out.
+double vbottom_bytes(const Batch* b, int tv) {
+  const double ts = tv ? 8.0 : 4.0;
+  const tg_mg_opts& mg = b->grids[0]->mg;
+  double bytes = 0.0;
+  for (int p : b->active) {
+    const tg_grid* g = b->grids[p];
+    const int lb = b->host_desc[p].vb_lb32 * (1 - tv) + b->host_desc[p].vb_lb64 * tv;
+    if (lb >= g->nlev) continue;
+    const int Lc = g->nlev - 1;
+    for (int l = lb; l < Lc; ++l) {
+      bytes += (mg.nu_pre + mg.nu_post) * (double)TG_GM_STRIDE * ts * g->lv[l].n_elem;
+      bytes += (mg.nu_pre - 1 + mg.nu_post) * 9.0 * ts * g->lv[l].n_nodes;
+      if (l + 1 < Lc) bytes += 9.0 * ts * g->lv[l + 1].n_nodes;
+    }
+    bytes += (double)g->ncoarse * g->ncoarse * ts;
+    bytes += 3.0 * 3.0 * ts * g->lv[lb].n_nodes;
+  }
+  return bytes;
+}
+
+// First level from which the bottom kernel runs the cycle of g (TG_MAXLEV if
+// none): the smallest lb >= 2 whose levels fit `lds` bytes with elements of
+// `tsize` bytes and a direct coarsest solve.
+int vbottom_level(const tg_grid* g, size_t tsize, size_t lds) {
+  if (g->ncoarse <= 0 || g->nlev < 3) return TG_MAXLEV;
+  for (int lb = 2; lb < g->nlev; ++lb)
+    if (vb_words(g, lb) * tsize <= lds) return lb;
+  return TG_MAXLEV;
+}
+
+template <class T> __device__ __forceinline__ const T* vb_cinv(const ProbDesc& P);
+template <> __device__ __forceinline__ const double* vb_cinv<double>(const ProbDesc& P) { return P.Cinv64; }
+template <> __device__ __forceinline__ const float* vb_cinv<float>(const ProbDesc& P) { return P.Cinv32; }
+
+template <class T>
+struct VbLev {
+  int NX, NY, NZ, ex, ey, ez, nn, ne;
+  T* x;
+  T* b;
+};
+
+template <class T>
+__device__ __forceinline__ VbLev<T> vb_lev(const LevelDesc& L, T* x, T* b) {
+  return {L.NX, L.NY, L.NZ, L.ex, L.ey, L.ez, L.n_nodes, L.ex * L.ey * L.ez, x, b};
+}
+
+// eb[(3 a + c) * ne + e] = (K_e x_e)[3 a + c] for every element e of level l
+template <class T>
+__device__ __forceinline__ void vb_elements(const LevelDesc& L, const VbLev<T>& V, T* eb) {
+  const T TG_GLOBAL* Km = gp(fKm<T>(L));
+  const int NXY = V.NX * V.NY;
+  for (int e = threadIdx.x; e < V.ne; e += VbThreads<T>::N) {
+    const int i = e % V.ex, t = e / V.ex, j = t % V.ey, k = t / V.ey;
+    const int n0 = i + V.NX * j + NXY * k;
+    T ux[8], uy[8], uz[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int na = n0 + (a & 1) + V.NX * ((a >> 1) & 1) + NXY * (a >> 2);
+      ux[a] = V.x[3 * na];
+      uy[a] = V.x[3 * na + 1];
+      uz[a] = V.x[3 * na + 2];
+    }
+    wht_fwd(ux);
+    wht_fwd(uy);
+    wht_fwd(uz);
+    elem_mode_stored<T>(ux, uy, uz, (const T*)Km, e);
+    wht_inv(ux);
+    wht_inv(uy);
+    wht_inv(uz);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      eb[(3 * a + 0) * V.ne + e] = ux[a];
+      eb[(3 * a + 1) * V.ne + e] = uy[a];
+      eb[(3 * a + 2) * V.ne + e] = uz[a];
+    }
+  }
+}
+
+// (K x)_n from the element buffer: the elements around node (i, j, k) in the
+// order dk, dj, di
+template <class T>
+__device__ __forceinline__ void vb_gather(const VbLev<T>& V, const T* eb, int i, int j, int k, T* kx) {
+  kx[0] = kx[1] = kx[2] = T(0);
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int ei = i - 1 + di, ej = j - 1 + dj, ek = k - 1 + dk;
+        if (ei < 0 || ei >= V.ex || ej < 0 || ej >= V.ey || ek < 0 || ek >= V.ez) continue;
+        const int e = ei + V.ex * (ej + V.ey * ek);
+        const int a = (1 - di) + 2 * (1 - dj) + 4 * (1 - dk);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) kx[c] += eb[(3 * a + c) * V.ne + e];
+      }
+}
+
+// One damped node-block Jacobi sweep x <- x + w D^-1 (b - K x) (RESID =
+// false; after the element pass a node's update reads only its own x, so x
+// is updated in place), or r = b - K x into rbuf (RESID = true); clamped
+// nodes 0.
+template <class T, bool RESID>
+__device__ void vb_sweep(const LevelDesc& L, const VbLev<T>& V, T* eb, T* rbuf, T omega) {
+  vb_elements<T>(L, V, eb);
+  __syncthreads();
+  for (int n = threadIdx.x; n < V.nn; n += VbThreads<T>::N) {
+    const int i = n % V.NX, t = n / V.NX, j = t % V.NY, k = t / V.NY;
+    T* dst = RESID ? rbuf : V.x;
+    if (i == 0) {
+      if (RESID) dst[3 * n] = dst[3 * n + 1] = dst[3 * n + 2] = T(0);
+      continue;
+    }
+    T kx[3];
+    vb_gather<T>(V, eb, i, j, k, kx);
+    const T r0 = V.b[3 * n] - kx[0], r1 = V.b[3 * n + 1] - kx[1], r2 = V.b[3 * n + 2] - kx[2];
+    if (RESID) {
+      dst[3 * n] = r0;
+      dst[3 * n + 1] = r1;
+      dst[3 * n + 2] = r2;
+    } else {
+      const T TG_GLOBAL* D = gp(fD<T>(L)) + 9LL * n;
+      T xn[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        xn[c] = mad_(omega, mad_(D[3 * c + 2], r2, mad_(D[3 * c + 1], r1, D[3 * c] * r0)), V.x[3 * n + c]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dst[3 * n + c] = xn[c];
+    }
+  }
+  __syncthreads();
+}
+
+// b_c = P^T r (r = the fine residual in r[3 n + c]; full weighting, coarse
+// x = 0 nodes clamped) and, if first_sweep, x_c = w D_c^-1 b_c
+template <class T>
+__device__ void vb_restrict(const VbLev<T>& F, const T* r, const LevelDesc& Lc, const VbLev<T>& C, T omega,
+                            bool first_sweep) {
+  for (int n = threadIdx.x; n < C.nn; n += VbThreads<T>::N) {
+    const int I = n % C.NX, t = n / C.NX, J = t % C.NY, K = t / C.NY;
+    T s[3] = {T(0), T(0), T(0)};
+    if (I > 0) {
+      for (int dk = -1; dk <= 1; ++dk) {
+        const int k = 2 * K + dk;
+        if (k < 0 || k >= F.NZ) continue;
+        for (int dj = -1; dj <= 1; ++dj) {
+          const int j = 2 * J + dj;
+          if (j < 0 || j >= F.NY) continue;
+          for (int di = -1; di <= 1; ++di) {
+            const int i = 2 * I + di;
+            if (i < 0 || i >= F.NX) continue;
+            const T w = T(1) / T(1 << ((di != 0) + (dj != 0) + (dk != 0)));
+            const int f = i + F.NX * (j + F.NY * k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s[c] = mad_(w, r[3 * f + c], s[c]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) C.b[3 * n + c] = s[c];
+    if (first_sweep) {
+      const T TG_GLOBAL* D = gp(fD<T>(Lc)) + 9LL * n;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        C.x[3 * n + c] = omega * mad_(D[3 * c + 2], s[2], mad_(D[3 * c + 1], s[1], D[3 * c] * s[0]));
+    }
+  }
+  __syncthreads();
+}
+
+// x_f += P x_c (trilinear; clamped fine nodes untouched)
+template <class T>
+__device__ void vb_prolong(const VbLev<T>& F, const VbLev<T>& C) {
+  for (int n = threadIdx.x; n < F.nn; n += VbThreads<T>::N) {
+    const int i = n % F.NX, t = n / F.NX, j = t % F.NY, k = t / F.NY;
+    if (i == 0) continue;
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+    const T w = ((i & 1) ? T(0.5) : T(1)) * ((j & 1) ? T(0.5) : T(1)) * ((k & 1) ? T(0.5) : T(1));
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if ((c & 1) && !(i & 1)) continue;
+      if ((c & 2) && !(j & 1)) continue;
+      if ((c & 4) && !(k & 1)) continue;
+      const int I = (c & 1) ? i1 : i0, J = (c & 2) ? j1 : j0, K = (c & 4) ? k1 : k0;
+      const int m = I + C.NX * (J + C.NY * K);
+      s0 = mad_(w, C.x[3 * m], s0);
+      s1 = mad_(w, C.x[3 * m + 1], s1);
+      s2 = mad_(w, C.x[3 * m + 2], s2);
+    }
+    F.x[3 * n] += s0;
+    F.x[3 * n + 1] += s1;
+    F.x[3 * n + 2] += s2;
+  }
+  __syncthreads();
+}
+
+// x = K_c^-1 b on the free DOFs of the coarsest level (free index
+// 3 ((NX - 1) t + i - 1) + c of node i + NX t): eight lanes per row, each
+// summing every eighth column, then a fixed butterfly over the eight
+template <class T>
+__device__ void vb_coarse(const ProbDesc& P, const VbLev<T>& C) {
+  const int n = P.ncoarse;
+  const T TG_GLOBAL* Ci = gp(vb_cinv<T>(P));
+  const int part = threadIdx.x & 7, row0 = threadIdx.x >> 3;
+  const int NXm = C.NX - 1;
+  for (int q0 = 0; q0 < n; q0 += VbThreads<T>::N / 8) {
+    const int q = q0 + row0;
+    T s = T(0);
+    if (q < n)
+      for (int c = part; c < n; c += 8) {
+        const int fn = c / 3, node = fn % NXm + 1 + C.NX * (fn / NXm);
+        s = mad_(Ci[(long long)q * n + c], C.b[3 * node + c % 3], s);
+      }
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    if (q < n && part == 0) {
+      const int fn = q / 3, node = fn % NXm + 1 + C.NX * (fn / NXm);
+      C.x[3 * node + q % 3] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(VbThreads<T>::N) void k_vbottom(const ProbDesc* __restrict__ probs,
+                                                        const int2* __restrict__ work, int sfin, T omega,
+                                                        int nu_pre, int nu_post) {
+  extern __shared__ __align__(16) unsigned char vb_smem[];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
+  const int lb = sizeof(T) == 8 ? P.vb_lb64 : P.vb_lb32;
+  const int Lc = P.nlev - 1;
+  T* eb = (T*)vb_smem;
+  T* rbuf = eb + 24 * (P.lv[lb].ex * P.lv[lb].ey * P.lv[lb].ez);
+  // level l's x and b follow the element and residual buffers, level by level
+  auto V = [&](int l) -> VbLev<T> {
+    T* o = rbuf + 3 * P.lv[lb].n_nodes;
+    for (int m = lb; m < l; ++m) o += 6 * P.lv[m].n_nodes;
+    return vb_lev<T>(P.lv[l], o, o + 3 * P.lv[l].n_nodes);
+  };
+  // level-lb right-hand side and first sweep from the pools; deeper levels'
+  // x start at zero (the coarsest keeps its clamped nodes at zero)
+  {
+    const LevelDesc& L = P.lv[lb];
+    const T TG_GLOBAL* bg = gp(fpool<T>(L) + (long long)C_B * L.stride);
+    const T TG_GLOBAL* xg = gp(fpool<T>(L) + (long long)C_XA * L.stride);
+    const bool first = lb < Lc;
+    const VbLev<T> Vb = V(lb);
+    for (int q = threadIdx.x; q < 3 * Vb.nn; q += VbThreads<T>::N) {
+      Vb.b[q] = bg[q];
+      Vb.x[q] = first ? xg[q] : T(0);
+    }
+    for (int l = lb + 1; l <= Lc; ++l) {
+      const VbLev<T> Vl = V(l);
+      for (int q = threadIdx.x; q < 3 * Vl.nn; q += VbThreads<T>::N) Vl.x[q] = T(0);
+    }
+  }
+  __syncthreads();
+  // descend
+  for (int l = lb; l < Lc; ++l) {
+    const VbLev<T> Vl = V(l);
+    for (int it = 1; it < nu_pre; ++it) vb_sweep<T, false>(P.lv[l], Vl, eb, rbuf, omega);
+    vb_sweep<T, true>(P.lv[l], Vl, eb, rbuf, omega);
+    vb_restrict<T>(Vl, rbuf, P.lv[l + 1], V(l + 1), omega, l + 1 < Lc);
+  }
+  vb_coarse<T>(P, V(Lc));
+  // ascend
+  for (int l = Lc - 1; l >= lb; --l) {
+    const VbLev<T> Vl = V(l);
+    vb_prolong<T>(Vl, V(l + 1));
+    for (int it = 0; it < nu_post; ++it) vb_sweep<T, false>(P.lv[l], Vl, eb, rbuf, omega);
+  }
+  const LevelDesc& L = P.lv[lb];
+  const VbLev<T> Vb = V(lb);
+  T TG_GLOBAL* yg = gp(fpool<T>(L) + (long long)sfin * L.stride);
+  for (int q = threadIdx.x; q < 3 * Vb.nn; q += VbThreads<T>::N) yg[q] = Vb.x[q];
+}
+
+// Dynamic LDS the bottom kernel may take on the current device (the
+// per-workgroup limit less a margin), with both kernels' limits raised to it
+// once per device.
+size_t vbottom_lds_limit() {
+  static size_t lim[64] = {};
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (!done[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      v = 0;
+    }
+    size_t l = v > 1024 ? (size_t)v - 1024 : 0;
+    if (l && (hipFuncSetAttribute((const void*)k_vbottom<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)l) != hipSuccess ||
+              hipFuncSetAttribute((const void*)k_vbottom<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)l) != hipSuccess)) {
+      (void)hipGetLastError();
+      l = std::min<size_t>(l, 65536 - 1024);
+    }
+    lim[dev] = l;
+    done[dev] = true;
+  }
+  return lim[dev];
+}
+
+template <class T>
+int launch_vbottom(const Batch* b, const DevList& dl, size_t lds_bytes, int sfin, double omega, int nu_pre,
+                   int nu_post, hipStream_t s) {
+  if (!dl.n) return TG_OK;
+  k_vbottom<T><<<dl.n, VbThreads<T>::N, lds_bytes, s>>>(b->desc_d, dl.ptr, sfin, T(omega), nu_pre, nu_post);
+  return TG_OK;
+}
+template int launch_vbottom<float>(const Batch*, const DevList&, size_t, int, double, int, int, hipStream_t);
+template int launch_vbottom<double>(const Batch*, const DevList&, size_t, int, double, int, int, hipStream_t);
 
 }  // namespace tg

@@ -139,6 +139,7 @@ static size_t list_capacity(const std::vector<tg_grid*>& gs) {
       c += (l == 0) ? (g->lv[0].n_elem + 255) / 256 : g->lv[l].n_elem;
     }
     c += g->lv[0].n_chunks + 1;
+    c += 2;   // the V-cycle bottom lists
     for (int l = 0; l < g->nlev; ++l) c += zm_tiles(g, l, 1);
     for (int l = 0; l + 1 < g->nlev; ++l) c += rz_tiles(g, l, 1);
     c += zm_tiles(g, 0, 1);
@@ -281,6 +282,9 @@ int batch_upload_desc(Batch* b, hipStream_t s) {
   for (int p = 0; p < b->n; ++p) {
     b->host_desc[p] = b->grids[p]->desc;
     b->host_desc[p].gate = b->gated ? b->sc_d + p : nullptr;
+    const size_t lim = vbottom_lds_limit();
+    b->host_desc[p].vb_lb32 = vbottom_level(b->grids[p], sizeof(float), lim);
+    b->host_desc[p].vb_lb64 = vbottom_level(b->grids[p], sizeof(double), lim);
     for (int l = 0; l < b->grids[p]->nlev; ++l)
       b->host_desc[p].lv[l].zc = zm_height(b->grids[p]->lv[l].ez + 1, batch_zc(b, p, l));
   }
@@ -363,6 +367,28 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
       if (l < b->grids[p]->nlev - 1)
         for (int t = 0, nt = rz_tiles(b->grids[p], l, batch_zc(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_r[l], o);
+  }
+  // the one-launch V-cycle bottom (per vector type): its problems, its LDS,
+  // and the levels that still need level-by-level launches
+  {
+    const size_t lim = vbottom_lds_limit();
+    for (int t = 0; t < 2; ++t) {
+      const size_t ts = t ? sizeof(double) : sizeof(float);
+      o = begin();
+      size_t lds = 0;
+      for (int l = 0; l < TG_MAXLEV; ++l) b->vb_need[t][l] = false;
+      for (int p : active) {
+        const tg_grid* g = b->grids[p];
+        const int lb = vbottom_level(g, ts, lim);
+        for (int l = 0; l < std::min(lb, g->nlev); ++l) b->vb_need[t][l] = true;
+        if (lb < g->nlev) {
+          H.push_back(make_int2(p, 0));
+          lds = std::max(lds, vbottom_lds_bytes(g, lb, ts));
+        }
+      }
+      finish(b->vb[t], o);
+      b->vb_lds[t] = lds;
+    }
   }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");
   if (!H.empty())

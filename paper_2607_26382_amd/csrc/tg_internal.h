@@ -43,6 +43,15 @@ __device__ __forceinline__ T TG_GLOBAL* gp(T* p) {
   return (T TG_GLOBAL*)p;
 }
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup i runs on XCD
+// i mod 8) and each XCD has its own L2.  Giving every XCD a contiguous range
+// of the work list keeps neighbouring tiles, which share halo nodes and
+// partly used cache lines, in one L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
@@ -97,6 +106,9 @@ struct ProbDesc {
   // longer TG_RUNNING, so several steps run between host reads of the
   // status.  Null elsewhere.
   const double* gate;
+  // first level of the V-cycle run by the one-launch bottom kernel for FP32
+  // and FP64 vectors (TG_MAXLEV: none)
+  int vb_lb32, vb_lb64;
   LevelDesc lv[TG_MAXLEV];
 };
 // Workgroup-uniform early exit of a step kernel for a problem that stopped.
@@ -211,6 +223,12 @@ struct Batch {
   DevList fine;                   // level-0 z-march tiles, all problems
   DevList zm_s[TG_MAXLEV];        // level-l z-march tiles, problems where l is not the coarsest
   DevList zm_r[TG_MAXLEV];        // level-l residual-restriction tiles (same problems)
+  // one-launch V-cycle bottom, per vector type (0: FP32, 1: FP64): the problems
+  // it serves, its dynamic LDS, and per level whether any problem still needs
+  // the level-by-level launches there
+  DevList vb[2];
+  size_t vb_lds[2] = {0, 0};
+  bool vb_need[2][TG_MAXLEV] = {};
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
   int zc[TG_MAXLEV] = {};         // z-tile height per level for this batch
@@ -276,6 +294,16 @@ int level_restrict64(Batch* b, int l, const double* x, const double* bb, int slo
 int level_prolong64(Batch* b, int l, const double* ec, double* xf, hipStream_t s);
 int level_coarse64(Batch* b, int l, const double* bb, double* y, hipStream_t s);
 
+// policy pieces shared by the fixed-cycle and the adaptive-stack policies
+// (tg_solver.hip, tg_mlp.hip): probe features from a history, Eq. trigger,
+// the network's first rung, the six density statistics
+void probe_feats(const double* hist, int kstop, double* r50, double* r100);
+int rule_fires(const tg_policy* pol, double r50, double r100);
+int mlp_select(const tg_mlp* m, const std::vector<std::array<float, 8>>& feats, std::vector<int>& k0,
+               hipStream_t s);
+int density_features(Batch* b, const std::vector<int>& which, const double* const* rho_d, double p,
+                     double rho0, std::vector<std::array<float, 8>>& out, hipStream_t s);
+
 // kernel-class timer (tg_timer.hip)
 bool timer_on();
 void timer_suspend(bool on);
@@ -295,7 +323,15 @@ template <class T>
 // right-hand-side slot; sy2 >= 0 also writes that level's first Jacobi sweep
 // from zero into slot sy2
 int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const void* ex, int sb,
-                const void* eb, int sy, void* ey, double omega, hipStream_t s, int sy2 = -1);
+                const void* eb, int sy, void* ey, double omega, hipStream_t s, int sy2 = -1, int vbskip = 0);
+// the bottom of the V-cycle in one launch per problem (levels vb_lb.. in LDS)
+int vbottom_level(const tg_grid* g, size_t tsize, size_t lds);
+size_t vbottom_lds_limit();
+size_t vbottom_lds_bytes(const tg_grid* g, int lb, size_t tsize);
+double vbottom_bytes(const Batch* b, int tv);
+template <class T>
+int launch_vbottom(const Batch* b, const DevList& dl, size_t lds_bytes, int sfin, double omega, int nu_pre,
+                   int nu_post, hipStream_t s);
 int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, int sy, double omega,
                              hipStream_t s);
 int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,

@@ -447,10 +447,11 @@ __global__ __launch_bounds__(256) void k_jacobi_first(const ProbDesc* __restrict
 template <class T>
 __global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ probs,
                                                  const int2* __restrict__ work, int l, int sx,
-                                                 int se, const void* ee, void* ex) {
+                                                 int se, const void* ee, void* ex, int vbskip) {
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   TG_GATE(P);
+  if (vbskip && l >= (sizeof(T) == 8 ? P.vb_lb64 : P.vb_lb32)) return;   // run by k_vbottom
   const LevelDesc& Lf = P.lv[l];
   const LevelDesc& Lc = P.lv[l + 1];
   const int n = wi.y * TG_NODE_TILE + threadIdx.x;
@@ -482,11 +483,12 @@ __global__ __launch_bounds__(256) void k_prolong(const ProbDesc* __restrict__ pr
 template <class TB, class T, class TY>
 __global__ __launch_bounds__(256) void k_coarse_solve(const ProbDesc* __restrict__ probs,
                                                       const int2* __restrict__ work, int l, int sb,
-                                                      const void* eb_, int sy, void* ey_) {
+                                                      const void* eb_, int sy, void* ey_, int vbskip) {
   __shared__ T sb_[TG_MAX_COARSE];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   TG_GATE(P);
+  if (vbskip && l >= (sizeof(TY) == 8 ? P.vb_lb64 : P.vb_lb32)) return;   // run by k_vbottom
   const LevelDesc& L = P.lv[l];
   const int n = P.ncoarse;
   const auto* b = vslot<TB>(L, sb, eb_);
@@ -1493,7 +1495,8 @@ int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s) {
 template <class T, int OP>
 // (y: slot of level l, or for OP_RESTRICT the right-hand-side slot of level
 // l + 1, with y2 that level's first-sweep slot)
-static void vc_op(Batch* b, int l, int x, int bs, int y, T om, hipStream_t s, int mf = 0, int y2 = -1) {
+static void vc_op(Batch* b, int l, int x, int bs, int y, T om, hipStream_t s, int mf = 0, int y2 = -1,
+                  int vbs = 0) {
   const DevList& dl = (OP == OP_RESTRICT) ? b->zm_r[l] : b->zm_s[l];
   if (l == 0 && mf)
     TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP)),
@@ -1503,7 +1506,7 @@ static void vc_op(Batch* b, int l, int x, int bs, int y, T om, hipStream_t s, in
              launch_fine<T>(b, dl, 0, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s, y2));
   else
     TG_TIMED(TG_KT_VCYCLE_COARSE, (op_bytes<T>(b, l, 1, OP)),
-             launch_fine<T>(b, dl, l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s, y2));
+             launch_fine<T>(b, dl, l, OP, x, nullptr, bs, nullptr, y, nullptr, (double)om, s, y2, vbs));
 }
 
 // One fixed V-cycle.  Level-0 input b (slot sb of the FP64 pool or external
@@ -1530,8 +1533,16 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   for (int p : b->active) all_multi = all_multi && b->grids[p]->nlev > 1;
   const bool fast_in = !f64 && !in_is_f32 && sb >= 0 && all_multi;
   const bool fast_out = !f64 && !out_is_f32 && sy >= 0 && all_multi;
+  // The bottom of the cycle (each problem's levels from its vb_lb down) runs
+  // as one launch between the two passes; the level-by-level launches skip
+  // those levels (vbs) and whole levels no problem needs.
+  const int tv = f64 ? 1 : 0;
+  const bool use_vb = b->vb[tv].n > 0;
+  const int vbs = use_vb ? 1 : 0;
+  auto level_needed = [&](int l) { return !use_vb || b->vb_need[tv][l]; };
   // ---- descend
   for (int l = 0; l < L; ++l) {
+    if (!level_needed(l)) continue;
     const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB;
     const DevList& sm = b->smooth[l];
     const DevList& co = b->coarse[l];
@@ -1549,7 +1560,8 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
       const int fin = l == 0 ? FIN0 : FIN;
       level_sums(b, l, 2, nodes, elems, c2);
       TG_TIMED(TG_KT_TRANSFER, c2 * sT + 6.0 * nodes * sT,
-               k_coarse_solve<T, T, T><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, Bs, nullptr, fin, nullptr));
+               k_coarse_solve<T, T, T><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, Bs, nullptr, fin, nullptr,
+                                                                vbs));
     }
     if (!sm.n) continue;
     level_sums(b, l, 1, nodes, elems, c2);
@@ -1563,24 +1575,27 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     // (levels >= 1: the restriction above already wrote the first sweep)
     int c = XA, o = XB;
     for (int it = 1; it < mg.nu_pre; ++it) {
-      vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf);
+      vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf, -1, vbs);
       std::swap(c, o);
     }
     // residual, restricted straight into the next level's right-hand side,
     // and that level's first Jacobi sweep from zero
-    vc_op<T, OP_RESTRICT>(b, l, c, Bs, C_B, om, s, mf, C_XA);
+    vc_op<T, OP_RESTRICT>(b, l, c, Bs, C_B, om, s, mf, C_XA, vbs);
     cur[l] = c;
   }
+  if (use_vb)
+    TG_TIMED(TG_KT_VCYCLE_COARSE, vbottom_bytes(b, tv),
+             launch_vbottom<T>(b, b->vb[tv], b->vb_lds[tv], FIN, mg.omega, mg.nu_pre, mg.nu_post, s));
   // ---- ascend
   for (int l = L - 1; l >= 0; --l) {
     const DevList& sm = b->smooth[l];
-    if (!sm.n) continue;
+    if (!sm.n || !level_needed(l)) continue;
     const int Bs = l == 0 ? B0 : C_B, XA = l == 0 ? XA0 : C_XA, XB = l == 0 ? XB0 : C_XB;
     int c = cur[l];
     int o = (c == XA) ? XB : XA;
     level_sums(b, l, 1, nodes, elems, c2);
     TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 3.0 * nodes / 8 * sT,
-             k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN, nullptr, nullptr));
+             k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN, nullptr, nullptr, vbs));
     for (int it = 0; it < mg.nu_post; ++it) {
       if (l == 0 && fast_out && it == mg.nu_post - 1) {
         if (mf)
@@ -1593,7 +1608,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
         c = -1;   // result is in the output slot
         break;
       }
-      vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf);
+      vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf, -1, vbs);
       std::swap(c, o);
     }
     cur[l] = c;
@@ -1640,7 +1655,7 @@ int level_prolong64(Batch* b, int l, const double* ec, double* xf, hipStream_t s
     double nodes, elems, c2;
     level_sums(b, l, 1, nodes, elems, c2);
     TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 16.0 + 3.0 * nodes / 8 * 8.0,
-             k_prolong<double><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, -1, -1, ec, xf));
+             k_prolong<double><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, -1, -1, ec, xf, 0));
   }
   return check_launch("level prolongation");
 }
@@ -1650,7 +1665,8 @@ int level_coarse64(Batch* b, int l, const double* bb, double* y, hipStream_t s) 
     double nodes, elems, c2;
     level_sums(b, l, 2, nodes, elems, c2);
     TG_TIMED(TG_KT_TRANSFER, c2 * 8.0 + 6.0 * nodes * 8.0,
-             k_coarse_solve<double, double, double><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, -1, bb, -1, y));
+             k_coarse_solve<double, double, double><<<nblk(co), 256, 0, s>>>(b->desc_d, co.ptr, l, -1, bb, -1, y,
+                                                                             0));
   }
   return check_launch("coarsest solve");
 }

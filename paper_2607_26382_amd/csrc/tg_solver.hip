@@ -366,19 +366,14 @@ static void fill_result(const ScalRead& r, tg_solve_result* res) {
 
 // ---------------------------------------------------------------------------
 // Probe features (Sec. 3.4) from a probe history.
-static void probe_feats(const double* hist, int kstop, double* r50, double* r100) {
+void probe_feats(const double* hist, int kstop, double* r50, double* r100) {
   *r50 = hist[std::min(50, kstop)];
   *r100 = hist[std::min(100, kstop)];
 }
 
-static int rule_fires(const tg_policy* pol, double r50, double r100) {
+int rule_fires(const tg_policy* pol, double r50, double r100) {
   return (r50 >= pol->t_high) || (r100 >= pol->t_plateau && r100 / r50 >= pol->t_ratio);
 }
-
-int mlp_select(const tg_mlp* m, const std::vector<std::array<float, 8>>& feats, std::vector<int>& k0,
-               hipStream_t s);
-int density_features(Batch* b, const std::vector<int>& which, const double* const* rho_d, double p,
-                     double rho0, std::vector<std::array<float, 8>>& out, hipStream_t s);
 
 // Alg. floor_policy for every problem of the batch.
 int select_floor_batch(Batch* b, const double* const* rho_d, const double* const* f_d,

@@ -286,6 +286,18 @@ class Grid:
         return (u, result_dict(res), hist[:res.iterations + 1].copy(), [stack_log_dict(logs[i]) for i in range(n)],
                 [lams[i] for i in range(nl)])
 
+    def stack_select_floor(self, rho, f, pol, so=None):
+        """(u, policy dict): Alg. floor_policy with the full adaptive stack
+        preconditioning the probe and every rung's solve."""
+        so = so or stack_opts()
+        ws, wptr, nb = self._stack_ws(max(pol.probe_restart, pol.solve.restart), so)
+        u = torch.empty_like(f)
+        out = L.PolicyResult()
+        check(lib().tg_stack_select_floor(self.handle, _ptr(rho), _ptr(f), C.byref(pol), C.byref(so), wptr, nb,
+                                          _ptr(u), C.byref(out), _stream()))
+        del ws
+        return u, policy_dict(out)
+
     def density_features(self, rho, p=3.0, rho0=1e-9):
         """Six density statistics of rho (device FP64) at probe floor rho0."""
         out = (C.c_double * 6)()

@@ -5,7 +5,10 @@ a read after every step would (solutions, iteration counts, outcomes,
 histories), for both Gram-Schmidt forms, with and without graph replay, for
 one grid and for an uneven batch whose problems stop at different steps.
 The autotuner's per-grid-size tile heights are valid and change nothing
-but the work decomposition."""
+but the work decomposition.  The bottom of the V-cycle (one launch from a
+level that fits one workgroup's LDS) starts at each problem's own level, so
+a batch of grids with different bottom levels solves each problem bit for
+bit as it is solved alone."""
 import numpy as np
 import pytest
 import torch
@@ -90,3 +93,26 @@ def test_per_size_tile_heights():
     u1, r1 = batch.solve(fs, tg.solver_opts(prec=tg.F32))
     for i in range(len(dims_list)):
         assert r1[i]["iterations"] == r0[i]["iterations"] and torch.equal(u1[i], u0[i])
+
+
+@pytest.mark.parametrize("prec", [tg.F32, tg.F64])
+def test_bottom_levels_per_problem(prec):
+    """32x16x16 and 48x24x24 start the one-launch bottom at level 2 in FP32,
+    96x48x48 at level 3 (level 2 does not fit); in FP64 the levels differ
+    again.  Every problem of the batch equals its own single-grid solve."""
+    cases = [((32, 16, 16), 1e-4), ((96, 48, 48), 1e-3), ((48, 24, 24), 1e-6)]
+    rhos = [torch.tensor(synth.blobs(*d, 4100 + i), device=DEV) for i, (d, _) in enumerate(cases)]
+    opts = tg.solver_opts(prec=prec, max_iters=40)
+    grids = [tg.Grid(*d, max_restart=30, device=DEV) for d, _ in cases]
+    batch = tg.Batch(grids)
+    batch.set_density(rhos, 3.0, [fl for _, fl in cases])
+    fs = [torch.tensor(g.edge_load(), device=DEV) for g in grids]
+    us, res = batch.solve(fs, opts)
+    for i, (d, fl) in enumerate(cases):
+        g = tg.Grid(*d, max_restart=30, device=DEV)
+        g.set_density(rhos[i], 3.0, fl)
+        u1, r1, _ = g.fgmres_solve(fs[i], opts)
+        print(f"bottom levels {d} prec={prec}: batch {res[i]['iterations']} its, alone {r1['iterations']}",
+              flush=True)
+        assert r1["iterations"] == res[i]["iterations"] and torch.equal(u1, us[i])
+        assert res[i]["iterations"] > 5

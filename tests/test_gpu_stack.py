@@ -5,7 +5,10 @@ residual ratio and accept decision, the fine correction's decision, the
 output element by element), the cases the stack reduces to (level 1
 coarsest, no coarse Krylov steps, every correction rejected), the flexible
 GMRES around it (histories, iteration counts, per-application decisions,
-the solution) and the error paths."""
+the solution), Alg. floor_policy with the stack preconditioning every solve
+(probe features, first rung, the attempts and their guard decisions, the
+oracle's recheck of the accepted solution, the paper's false stop at
+rho_0 = 1e-12 caught by the guard) and the error paths."""
 import ctypes as C
 
 import numpy as np
@@ -18,6 +21,7 @@ from oracle import ke as oke
 from oracle import mesh
 from oracle import multigrid as omg
 from oracle import operator as op
+from oracle import policy as opol
 from paper_2607_26382_amd import synth
 from paper_2607_26382_amd import topoguard as tg
 from paper_2607_26382_amd._lib import TopoguardError, lib
@@ -214,3 +218,114 @@ def test_errors():
     # zero right-hand side: nothing to do, zero solution
     u, res, hist, logs, lams = g.stack_solve(torch.zeros_like(v), tg.solver_opts())
     assert res["iterations"] == 0 and list(hist) == [0.0] and not torch.any(u)
+
+
+def _oracle_stack_select(dims, rho, rungs, p, restart, cap, probe_restart=100, probe_iters=100, k0=None):
+    """Alg. floor_policy in the oracle with the oracle's adaptive stack
+    preconditioning the probe and every rung's solve."""
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    f = og.edge_load()[free]
+    cache = {}
+
+    def hier(fl):
+        if fl not in cache:
+            cache[fl] = omg.build_hierarchy(og, op.young(rho, p, fl), KE)
+        return cache[fl]
+
+    def probe(fl):
+        H = hier(fl)
+        r = ofg.fgmres(lambda v: H[0].K @ v, oad.adaptive_stack(H), f, probe_restart, probe_iters, 1e-6)
+        return r.hist, r.iters
+
+    def solve(fl):
+        H = hier(fl)
+        r = ofg.fgmres(lambda v: H[0].K @ v, oad.adaptive_stack(H), f, restart, cap, 1e-6)
+        return r.x, r.iters, r.outcome, r.proj_eta
+
+    def eta(fl, u):
+        return op.relative_residual(hier(fl)[0].K, f, u)
+
+    sel = None if k0 is None else (lambda r50, r100: k0)
+    return opol.select_floor(rungs, probe, solve, eta, selector=sel), hier, og, free, f
+
+
+# (grid, field, seed, p, rungs, restart = cap, fixed first rung or None).  The
+# second case is the paper's failure in small: under p = 4.5 and rho_0 = 1e-12
+# the projected estimate stops the rho_0 solve at 9.5e-7 while the recomputed
+# residual is 1.8e-4; the guard rejects it and the ladder accepts 1e-3.
+STACK_POLICY_CASES = [((16, 8, 8), "blob2", 11, 3.0, [1e-9, 1e-6, 1e-3], 30, 200, None),
+                      ((16, 8, 8), "blob", 12, 4.5, [1e-12, 1e-3, 1e-2], 300, 300, None),
+                      ((24, 12, 8), "blob2", 13, 4.5, [1e-12, 1e-3, 1e-2], 300, 300, None),
+                      ((16, 8, 8), "blob2", 11, 3.0, [1e-9, 1e-6, 1e-3], 30, 200, 1)]
+
+
+@pytest.mark.parametrize("dims,kind,seed,p,rungs,restart,cap,fixed", STACK_POLICY_CASES)
+def test_stack_select_floor_matches_oracle(dims, kind, seed, p, rungs, restart, cap, fixed):
+    rho = _field(kind, dims, seed)
+    (ref, hier, og, free, f_free) = _oracle_stack_select(dims, rho, rungs, p, restart, cap, k0=fixed)
+    print(f"stack policy {dims} seed={seed} p={p} rungs={rungs}: oracle k0={ref['k0']} rung={ref['rung']} "
+          f"attempts={[(a.rung, a.iters, a.accepted) for a in ref['attempts']]}", flush=True)
+    g = tg.Grid(*dims, max_restart=30, device=DEV)   # the stack binds its own Krylov workspace
+    f = torch.tensor(g.edge_load(), device=DEV)
+    rho_d = torch.tensor(rho, device=DEV)
+    sel = dict(selector=tg.L.TG_SELECT_FIXED, fixed_rung=fixed) if fixed is not None else {}
+    pol = tg.policy(rungs=rungs, p=p, solve=tg.solver_opts(restart=restart, max_iters=cap), **sel)
+    u, out = g.stack_select_floor(rho_d, f, pol)
+    print(f"  gpu k0={out['k0']} rung={out['rung']} r50={out['r50']:.4e} r100={out['r100']:.4e} attempts="
+          f"{[(a['rung'], a['iterations'], a['proj_eta'], a['true_eta'], a['accepted']) for a in out['attempts']]}",
+          flush=True)
+    # Under p = 4.5 at rho_0 = 1e-12 the probe can stop on an estimate below
+    # the operator's attainable FP64 accuracy (the case the guard exists
+    # for): there its digits past the fourth are rounding, and two correct
+    # FP64 runs in different summation orders agree to about 1e-4.
+    rtol = 1e-6 if p == 3.0 else 1e-3
+    assert out["r50"] == pytest.approx(ref["r50"], rel=rtol)
+    assert out["r100"] == pytest.approx(ref["r100"], rel=rtol)
+    assert out["probe_iters"] == ref["k_stop"] and out["iters_probe"] == ref["k_stop"]
+    assert out["k0"] == ref["k0"]
+    assert out["rung"] == ref["rung"]
+    assert [a["rung"] for a in out["attempts"]] == [a.rung for a in ref["attempts"]]
+    for a, b in zip(out["attempts"], ref["attempts"]):
+        assert abs(a["iterations"] - b.iters) <= 1
+        assert a["accepted"] == b.accepted
+        assert a["floor"] == rungs[a["rung"]]
+        assert a["accepted"] == (a["true_eta"] <= 1e-6)
+    assert out["iters_rejected"] == sum(a["iterations"] for a in out["attempts"] if not a["accepted"])
+    if out["rung"] >= 0:
+        # the oracle recomputes eta of the GPU's accepted solution at its floor
+        uf = u.cpu().numpy()
+        assert np.all(uf[~free] == 0.0)
+        K = hier(rungs[out["rung"]])[0].K
+        eta_o = op.relative_residual(K, f_free, uf[free])
+        assert eta_o <= 1e-6 + 2 * op.residual_bound(K, f_free, uf[free])
+        assert out["iters_selected"] == out["attempts"][-1]["iterations"]
+    else:
+        assert not torch.any(u)
+
+
+def test_stack_select_floor_reports_the_false_stop():
+    """The case above in detail: the rho_0 attempt stops on a projected
+    estimate inside the tolerance whose recomputed residual is far outside it
+    (on the GPU as in the oracle), and no accepted attempt has eta > tau."""
+    dims, rungs = (16, 8, 8), [1e-12, 1e-3, 1e-2]
+    rho = _field("blob", dims, 12)
+    g = tg.Grid(*dims, max_restart=30, device=DEV)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    pol = tg.policy(rungs=rungs, p=4.5, solve=tg.solver_opts(restart=300, max_iters=300))
+    u, out = g.stack_select_floor(torch.tensor(rho, device=DEV), f, pol)
+    a0 = out["attempts"][0]
+    assert a0["rung"] == 0 and a0["outcome"] == "PROJ_CONVERGED"
+    assert a0["proj_eta"] <= 1e-6 and a0["true_eta"] > 100 * 1e-6 and not a0["accepted"]
+    assert out["rung"] == 1 and g.true_residual(f, u) <= 1e-6
+
+
+def test_stack_select_floor_errors():
+    dims = (8, 4, 4)
+    g = tg.Grid(*dims, device=DEV)
+    rho_d = torch.tensor(synth.uniform(*dims, 0), device=DEV)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    with pytest.raises(TopoguardError):
+        g.stack_select_floor(rho_d, f, tg.policy(rungs=[1e-9, 2.0]))
+    with pytest.raises(TopoguardError):       # restart beyond the bound workspace's range
+        g.stack_select_floor(rho_d, f, tg.policy(rungs=[1e-3], solve=tg.solver_opts(restart=600)))
