@@ -121,7 +121,7 @@ def parse():
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive-preconditioner leg (fine-level correction)")
     ap.add_argument("--adaptive-only", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--stack-states", type=int, default=24,
+    ap.add_argument("--stack-states", type=int, default=16,
                     help="states of the full-adaptive-stack policy leg (paper setting, one at a time)")
     ap.add_argument("--no-stack", action="store_true", help="skip the full-adaptive-stack policy leg")
     ap.add_argument("--stack-only", action="store_true", help=argparse.SUPPRESS)
@@ -275,12 +275,14 @@ def compact(result, full_path=None):
                                          _get(ad, "plain_vcycle", "seconds_per_solve")]}
     sp = r.get("stack_policy")
     if sp:
-        c["stack_policy_paper_setting"] = {
-            "states": sp.get("states"), "certified": sp.get("certified"),
-            "false_stops_caught": sp.get("false_stops_caught"),
-            "accepted_above_tolerance": sp.get("accepted_above_tolerance"),
-            "oracle_false_acceptances": _get(sp, "oracle_recheck", "false_acceptances_oracle"),
-            "s_per_state": sp.get("seconds_per_state")}
+        c["stack_policy_paper_setting"] = {"states": sp.get("states")}
+        for name in ("rule", "always_rho0_then_ladder"):
+            v = sp.get(name) or {}
+            c["stack_policy_paper_setting"][name] = {
+                "certified": v.get("certified"), "false_stops_caught": v.get("false_stops_caught"),
+                "accepted_above_tolerance": v.get("accepted_above_tolerance"),
+                "oracle_false_acceptances": _get(v, "oracle_recheck", "false_acceptances_oracle"),
+                "s_per_state": v.get("seconds_per_state")}
     if full_path:
         c["full_record"] = full_path
     return _r(c)
@@ -764,54 +766,61 @@ def stack_policy_leg(tg, torch, dev, rhos, fs, n_states, recheck=True, tau=1e-6)
     steps, fine-level correction) preconditioning the probe and every rung,
     under the paper's settings (Tab. solver-config: p = 4.5, rho_0 = 1e-12,
     ladder {1e-3, 1e-2}, 100-iteration probe, FGMRES(300) with cap 300, FP64
-    throughout), one state at a time through tg_stack_select_floor.  Reports
-    certified states, the attempts whose projected estimate converged while the
-    recomputed residual is above tau (false stops the guard rejects), first
-    and selected rungs, stage iterations, seconds per state and the oracle's
-    recheck of every accepted solution."""
+    throughout), one state at a time through tg_stack_select_floor, with the
+    two-feature rule (the paper's policy) and with the original floor always
+    tried first (the paper's exhaust-the-original-floor baseline).  Per
+    variant: certified states, the attempts whose projected estimate
+    converged while the recomputed residual is above tau (false stops the
+    guard rejects), first and selected rungs, stage iterations, seconds per
+    state, and the oracle's recheck of every accepted solution."""
     n = min(n_states, len(rhos))
     g = tg.Grid(*GRID, max_restart=30, device=dev)
-    pol = tg.policy(rungs=PAPER_RUNGS, p=4.5, solve=tg.solver_opts(restart=300, max_iters=300, prec=tg.F64))
-    outs, us, secs = [], [], []
-    for i in range(n):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u, o = g.stack_select_floor(rhos[i], fs[i], pol)
-        torch.cuda.synchronize()
-        secs.append(time.perf_counter() - t0)
-        outs.append(o)
-        us.append(u.cpu().numpy() if o["rung"] >= 0 else None)
-        log(f"stack policy state {SEED0 + i}: k0={o['k0']} rung={o['rung']} r50={o['r50']:.3g} "
-            f"r100={o['r100']:.3g} attempts={[(a['rung'], a['iterations'], a['outcome'], a['true_eta']) for a in o['attempts']]} "
-            f"{secs[-1]:.2f}s")
-    false_stops = [[SEED0 + i, a["rung"], a["iterations"], a["proj_eta"], a["true_eta"]]
-                   for i, o in enumerate(outs) for a in o["attempts"]
-                   if a["outcome"] == "PROJ_CONVERGED" and not a["true_eta"] <= tau]
-    acc = [o for o in outs if o["rung"] >= 0]
-    res = {"states": n, "p": 4.5, "rungs": list(PAPER_RUNGS), "probe": "100 its, restart 100",
-           "solve": "FGMRES(300), cap 300, adaptive stack, FP64 throughout",
-           "certified": len(acc),
-           "first_rung": {str(r): sum(1 for o in outs if o["k0"] == r) for r in range(len(PAPER_RUNGS))},
-           "selected_rungs": {str(r): sum(1 for o in outs if o["rung"] == r) for r in range(-1, len(PAPER_RUNGS))},
-           "false_stops_caught": len(false_stops), "false_stop_rows": false_stops,
-           "accepted_above_tolerance": sum(1 for o in outs for a in o["attempts"]
-                                           if a["accepted"] and not a["true_eta"] <= tau),
-           "max_accepted_true_eta": max((o["attempts"][-1]["true_eta"] for o in acc), default=None),
-           "mean_attempts": float(np.mean([len(o["attempts"]) for o in outs])) if outs else None,
-           "mean_iters": {k: float(np.mean([o[k] for o in outs])) if outs else None
-                          for k in ("iters_probe", "iters_selected", "iters_rejected")},
-           "seconds_per_state": float(np.mean(secs)) if secs else None}
-    if recheck and acc:
-        f_np = fs[0].cpu().numpy()
-        items = [(GRID, rhos[i].cpu().numpy(), 4.5, PAPER_RUNGS[o["rung"]], f_np, us[i])
-                 for i, o in enumerate(outs) if o["rung"] >= 0]
-        res["oracle_recheck"] = oracle_recheck(items, [o["attempts"][-1]["true_eta"] for o in acc])
-    log(f"stack policy leg: certified {res['certified']}/{n}, false stops caught {res['false_stops_caught']}, "
-        f"{res['seconds_per_state']:.2f} s/state")
+    solve = tg.solver_opts(restart=300, max_iters=300, prec=tg.F64)
+    out = {"states": n, "p": 4.5, "rungs": list(PAPER_RUNGS), "probe": "100 its, restart 100",
+           "solve": "FGMRES(300), cap 300, adaptive stack, FP64 throughout"}
+    for name, sel in (("rule", {}), ("always_rho0_then_ladder", dict(selector=tg.SELECT_FIXED, fixed_rung=0))):
+        pol = tg.policy(rungs=PAPER_RUNGS, p=4.5, solve=solve, **sel)
+        outs, us, secs = [], [], []
+        for i in range(n):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, o = g.stack_select_floor(rhos[i], fs[i], pol)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            outs.append(o)
+            us.append(u.cpu().numpy() if o["rung"] >= 0 else None)
+            log(f"stack policy ({name}) state {SEED0 + i}: k0={o['k0']} rung={o['rung']} r50={o['r50']:.3g} "
+                f"r100={o['r100']:.3g} attempts="
+                f"{[(a['rung'], a['iterations'], a['outcome'], a['true_eta']) for a in o['attempts']]} "
+                f"{secs[-1]:.2f}s")
+        false_stops = [[SEED0 + i, a["rung"], a["iterations"], a["proj_eta"], a["true_eta"]]
+                       for i, o in enumerate(outs) for a in o["attempts"]
+                       if a["outcome"] == "PROJ_CONVERGED" and not a["true_eta"] <= tau]
+        acc = [o for o in outs if o["rung"] >= 0]
+        res = {"certified": len(acc),
+               "first_rung": {str(r): sum(1 for o in outs if o["k0"] == r) for r in range(len(PAPER_RUNGS))},
+               "selected_rungs": {str(r): sum(1 for o in outs if o["rung"] == r)
+                                  for r in range(-1, len(PAPER_RUNGS))},
+               "false_stops_caught": len(false_stops), "false_stop_rows": false_stops,
+               "accepted_above_tolerance": sum(1 for o in outs for a in o["attempts"]
+                                               if a["accepted"] and not a["true_eta"] <= tau),
+               "max_accepted_true_eta": max((o["attempts"][-1]["true_eta"] for o in acc), default=None),
+               "mean_attempts": float(np.mean([len(o["attempts"]) for o in outs])) if outs else None,
+               "mean_iters": {k: float(np.mean([o[k] for o in outs])) if outs else None
+                              for k in ("iters_probe", "iters_selected", "iters_rejected")},
+               "seconds_per_state": float(np.mean(secs)) if secs else None}
+        if recheck and acc:
+            f_np = fs[0].cpu().numpy()
+            items = [(GRID, rhos[i].cpu().numpy(), 4.5, PAPER_RUNGS[o["rung"]], f_np, us[i])
+                     for i, o in enumerate(outs) if o["rung"] >= 0]
+            res["oracle_recheck"] = oracle_recheck(items, [o["attempts"][-1]["true_eta"] for o in acc])
+        log(f"stack policy leg ({name}): certified {res['certified']}/{n}, false stops caught "
+            f"{res['false_stops_caught']}, {res['seconds_per_state']:.2f} s/state")
+        out[name] = res
+        del us
     del g
     torch.cuda.empty_cache()
-    return res
-
+    return out
 
 B4_GRIDS = ((32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48))
 

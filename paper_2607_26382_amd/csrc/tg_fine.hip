@@ -30,7 +30,12 @@ namespace tg {
 __host__ __device__ __forceinline__ float mad_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __host__ __device__ __forceinline__ double mad_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-enum { FOP_APPLY = 0, FOP_RESID = 1, FOP_SMOOTH = 2, FOP_RESTRICT = 3 };
+enum { FOP_APPLY = 0, FOP_RESID = 1, FOP_SMOOTH = 2, FOP_RESTRICT = 3, FOP_SMOOTH1 = 4 };
+// FOP_SMOOTH1 (level 0): the first two sweeps from x = 0 in one pass.  The
+// right-hand side is read from an FP64 slot (sb), times the per-problem scale
+// small[sx] when sx >= 0; every staged node gets x = w D^-1 b on the fly (the
+// first sweep), the output is the second sweep x + w D^-1 (b - K x), and the
+// FP32 copy of b that later sweeps read goes to slot sy2.
 
 // Tiling of the residual sweep fused with the restriction (OP = FOP_RESTRICT):
 // a tile owns 7 x 7 coarse node columns and m coarse node layers, and computes
@@ -137,17 +142,17 @@ __device__ __forceinline__ void mode_contract_e(T* ux, T* uy, T* uz, const ModeC
 // modes out).  Restricting the level-1 moment matrices to a child keeps their
 // joint pattern, so every deeper Galerkin element matrix lives on the same 279
 // symmetric positions; it is held as its 150 entries with row <= col
-// (kGMPairs), padded to TG_GM_STRIDE, element e at Km[e * TG_GM_STRIDE].  The
-// entries are read in 16-byte pieces, a few pieces ahead of their use, so that
-// few registers hold them at a time.  279 multiply-adds per element.
-template <class T>
+// (kGMPairs), padded to TG_GM_STRIDE, in the 64-element blocks of gm_index.
+// The entries are read in 16-byte pieces, a few pieces ahead of their use, so
+// that few registers hold them at a time.  279 multiply-adds per element.
+template <class T, int G = 4>   // G: pieces per group of loads in flight
 __device__ __forceinline__ void elem_mode_stored(T* ux, T* uy, T* uz, const T* __restrict__ Km, int e) {
   constexpr int W = 16 / sizeof(T);                  // entries per piece
   constexpr int NP = TG_GM_STRIDE / W;               // pieces per element
-  constexpr int G = 4;                               // pieces per group
   constexpr int NG = (NP + G - 1) / G;
   typedef T vecT __attribute__((ext_vector_type(W)));
-  const vecT* kp = (const vecT*)gp(Km + (long long)e * TG_GM_STRIDE);
+  // piece p of element e at kp[64 p]
+  const vecT* kp = (const vecT*)gp(Km) + (((long long)(e >> 6) * NP) << 6) + (e & 63);
   T a[24], y[24];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -159,13 +164,13 @@ __device__ __forceinline__ void elem_mode_stored(T* ux, T* uy, T* uz, const T* _
   for (int r = 0; r < 24; ++r) y[r] = T(-0.0);
   vecT buf[2][G];
 #pragma unroll
-  for (int i = 0; i < G; ++i) buf[0][i] = kp[i];
+  for (int i = 0; i < G; ++i) buf[0][i] = kp[64 * i];
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + 1 < NG) {
 #pragma unroll
       for (int i = 0; i < G; ++i)
-        if ((g + 1) * G + i < NP) buf[(g + 1) & 1][i] = kp[(g + 1) * G + i];
+        if ((g + 1) * G + i < NP) buf[(g + 1) & 1][i] = kp[64 * ((g + 1) * G + i)];
     }
 #pragma unroll
     for (int i = 0; i < G; ++i)
@@ -423,10 +428,40 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   // returned by value so they stay in registers
   struct Pre {
     T a0, a1, a2, e0, e1, e2;
+    T b0, b1, b2;              // FOP_SMOOTH1: b at the own node
+  };
+  constexpr bool S1 = (OP == FOP_SMOOTH1);
+  const double in_scale = (S1 && sx >= 0) ? P.small[sx] : 1.0;
+  // FOP_SMOOTH1: b at node (column base, layer k) from the FP64 slot, scaled,
+  // and the first sweep x = w D^-1 b there
+  auto first_sweep = [&](long long base, int k, T& x0, T& x1, T& x2, T& c0, T& c1, T& c2) {
+    const double TG_GLOBAL* bp = gp(P.lv[0].vec64 + (long long)sb * L.stride) + base + lstride * k;
+    c0 = T(bp[0] * in_scale);
+    c1 = T(bp[1] * in_scale);
+    c2 = T(bp[2] * in_scale);
+    const T TG_GLOBAL* Dp = gp(fD<T>(L)) + 9 * (base / 3 + (lstride / 3) * k);
+    x0 = omega * mad_(Dp[2], c2, mad_(Dp[1], c1, Dp[0] * c0));
+    x1 = omega * mad_(Dp[5], c2, mad_(Dp[4], c1, Dp[3] * c0));
+    x2 = omega * mad_(Dp[8], c2, mad_(Dp[7], c1, Dp[6] * c0));
   };
   auto fetch = [&](int k) -> Pre {
     Pre r;
+    r.b0 = r.b1 = r.b2 = T(0);
     const bool kin = (k >= 0 && k < NZ);
+    if (S1) {
+      T c0, c1, c2;
+      if (own_col && kin) {
+        first_sweep(own_base, k, r.a0, r.a1, r.a2, r.b0, r.b1, r.b2);
+      } else {
+        r.a0 = r.a1 = r.a2 = T(0);
+      }
+      if (ext_col && kin) {
+        first_sweep(ext_base, k, r.e0, r.e1, r.e2, c0, c1, c2);
+      } else {
+        r.e0 = r.e1 = r.e2 = T(0);
+      }
+      return r;
+    }
     if (own_col && kin) {
       const auto* p = u + own_base + lstride * k;
       r.a0 = p[0];
@@ -471,6 +506,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     T bx[4], by[4], bz[4];     // bottom face, corner c = di + 2 dj
     T tpx[4], tpy[4], tpz[4];  // top-face outputs of the previous element layer
     T own[3];
+    T bo[3];                   // FOP_SMOOTH1: b at node (ni, nj, k)
     T E;
     T cr[16];                  // matrix-core forms: the same outputs in the D layout
   };
@@ -481,6 +517,9 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   for (int q = 0; q < 16; ++q) s0.cr[q] = T(0);
   Pre pre = fetch(z0 - 1);
   stage(pre, z0 - 1);
+  s0.bo[0] = pre.b0;
+  s0.bo[1] = pre.b1;
+  s0.bo[2] = pre.b2;
   if constexpr (MF) {
     // node (ni, nj, z0 - 1) of this thread; the face stays in LDS
     s0.own[0] = pre.a0;
@@ -522,6 +561,13 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       B.own[1] = pre.a1;
       B.own[2] = pre.a2;
     }
+    // (A and B may be one object: read A's b before B's is written)
+    const T bo0 = A.bo[0], bo1 = A.bo[1], bo2 = A.bo[2];   // b at node (ni, nj, k)
+    if constexpr (S1) {
+      B.bo[0] = pre.b0;      // b at node (ni, nj, k + 1)
+      B.bo[1] = pre.b1;
+      B.bo[2] = pre.b2;
+    }
     stage(pre, k + 1);       // node layer k + 1 (fetched one step ahead)
     pre = fetch(k + 2);      // next layer in flight during this step
     const T Ecur = A.E;      // modulus of element layer k (0 outside the grid)
@@ -532,11 +578,13 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
     T D[9];
     const bool out_now = owner && own_col && k >= z0 && k >= 0;
     const long long n = ni + (long long)NX * (nj + (long long)NY * k);
-    if (OP != FOP_APPLY && out_now) {
+    if (S1) {
+      rb0 = bo0; rb1 = bo1; rb2 = bo2;
+    } else if (OP != FOP_APPLY && out_now) {
       const auto* bb = gp(fvec<T>(L, sb, eb_)) + 3 * n;
       rb0 = bb[0]; rb1 = bb[1]; rb2 = bb[2];
     }
-    if (OP == FOP_SMOOTH && out_now) {
+    if ((OP == FOP_SMOOTH || S1) && out_now) {
       const auto* Dp = gp(fD<T>(L)) + 9 * n;
 #pragma unroll
       for (int q = 0; q < 9; ++q) D[q] = Dp[q];
@@ -654,6 +702,13 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
         for (int q = 0; q < 3; ++q) rl[q][ty][tx] = out_now ? (q == 0 ? rb0 : q == 1 ? rb1 : rb2) - a[q] : T(0);
       } else {
       auto* y = gp((sy < 0 ? (TY*)ey_ : fpool<TY>(L) + (long long)sy * L.stride)) + 3 * n;
+      if constexpr (S1) {
+        // the FP32 copy of b for the later sweeps (zero at clamped nodes)
+        auto* bt = gp(fpool<T>(L) + (long long)sy2 * L.stride) + 3 * n;
+        bt[0] = rb0;
+        bt[1] = rb1;
+        bt[2] = rb2;
+      }
       if (ni == 0) {
         y[0] = y[1] = y[2] = TY(0);
       } else if (OP == FOP_APPLY) {
@@ -945,9 +1000,12 @@ int launch_fine(const Batch* b, const DevList& dl, int l, int op, int sx, const 
       k_fine_zm<T, FOP_RESID, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip);    \
     else if (op == FOP_SMOOTH)                                                                            \
       k_fine_zm<T, FOP_SMOOTH, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip);   \
+    else if (op == FOP_SMOOTH1)                                                                           \
+      k_fine_zm<T, FOP_SMOOTH1, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip);  \
     else                                                                                                  \
       k_fine_zm<T, FOP_RESTRICT, KV><<<dl.n, 256, 0, s>>>(desc, dl.ptr, l, sx, ex, sb, eb, sy, ey, sy2, om, mc, vbskip); \
   } while (0)
+  if (op == FOP_SMOOTH1 && l != 0) return fail(TG_EINVAL, "the fused first sweeps are a level-0 operation");
   if (l == 0)
     TG_ZM(0);
   else if (l <= TG_MF_LEVELS)
@@ -977,6 +1035,8 @@ int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int 
     if (split) TG_MF(FOP_RESID, 3, float); else TG_MF(FOP_RESID, 2, float);
   } else if (op == FOP_SMOOTH) {
     if (split) TG_MF(FOP_SMOOTH, 3, float); else TG_MF(FOP_SMOOTH, 2, float);
+  } else if (op == FOP_SMOOTH1) {
+    if (split) TG_MF(FOP_SMOOTH1, 3, float); else TG_MF(FOP_SMOOTH1, 2, float);
   } else {
     if (split) TG_MF(FOP_RESTRICT, 3, float); else TG_MF(FOP_RESTRICT, 2, float);
   }
@@ -1011,6 +1071,9 @@ template int launch_fine<float>(const Batch*, const DevList&, int, int, int, con
 // the restriction from level lb - 1; b only when lb is the coarsest level);
 // exit: the level-lb result in slot sfin.
 // threads per workgroup: FP32 fits 128 registers (16 waves), FP64 takes 256
+#ifndef VB_GROUP
+#define VB_GROUP 8
+#endif
 template <class T>
 struct VbThreads {
   static constexpr int N = sizeof(T) == 8 ? 512 : 1024;
@@ -1096,7 +1159,7 @@ __device__ __forceinline__ void vb_elements(const LevelDesc& L, const VbLev<T>& 
     wht_fwd(ux);
     wht_fwd(uy);
     wht_fwd(uz);
-    elem_mode_stored<T>(ux, uy, uz, (const T*)Km, e);
+    elem_mode_stored<T, VB_GROUP>(ux, uy, uz, (const T*)Km, e);
     wht_inv(ux);
     wht_inv(uy);
     wht_inv(uz);

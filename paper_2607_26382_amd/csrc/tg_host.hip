@@ -189,8 +189,8 @@ static void grid_layout(tg_grid* g, Bump& bp, int mmax) {
       L.Kel64 = bp.take<double>((size_t)H.n_elem * 576);
     }
     if (l > TG_MF_LEVELS) {
-      L.Km64 = bp.take<double>((size_t)H.n_elem * TG_GM_STRIDE);
-      L.Km32 = bp.take<float>((size_t)H.n_elem * TG_GM_STRIDE);
+      L.Km64 = bp.take<double>((size_t)gm_elems(H.n_elem) * TG_GM_STRIDE);
+      L.Km32 = bp.take<float>((size_t)gm_elems(H.n_elem) * TG_GM_STRIDE);
     }
     L.Dinv64 = bp.take<double>((size_t)9 * H.n_nodes);
     L.Dinv32 = bp.take<float>((size_t)9 * H.n_nodes);
@@ -253,6 +253,10 @@ int batch_bind(Batch* b, void* ws, size_t bytes) {
   return TG_OK;
 }
 
+// The height a launch uses: the chosen one, capped while only a few problems
+// run (zc_cap, see batch_set_active).
+int batch_zc_run(const Batch* b, int p, int l) { return std::min(batch_zc(b, p, l), b->zc_cap[l]); }
+
 int batch_zc(const Batch* b, int p, int l) {
   const tg_grid* g = b->grids[p];
   if (!b->zc_size.empty()) {
@@ -271,6 +275,7 @@ unsigned long long batch_zc_hash(const Batch* b) {
     }
   };
   for (int l = 0; l < TG_MAXLEV; ++l) mix(b->zc[l]);
+  for (int l = 0; l < TG_MAXLEV; ++l) mix(b->zc_cap[l]);
   for (const auto& kv : b->zc_size) {
     for (int d : kv.first) mix(d);
     for (int z : kv.second) mix(z);
@@ -286,13 +291,53 @@ int batch_upload_desc(Batch* b, hipStream_t s) {
     b->host_desc[p].vb_lb32 = vbottom_level(b->grids[p], sizeof(float), lim);
     b->host_desc[p].vb_lb64 = vbottom_level(b->grids[p], sizeof(double), lim);
     for (int l = 0; l < b->grids[p]->nlev; ++l)
-      b->host_desc[p].lv[l].zc = zm_height(b->grids[p]->lv[l].ez + 1, batch_zc(b, p, l));
+      b->host_desc[p].lv[l].zc = zm_height(b->grids[p]->lv[l].ez + 1, batch_zc_run(b, p, l));
   }
   TG_HIP(hipMemcpyAsync(b->desc_d, b->host_desc.data(), sizeof(ProbDesc) * b->n, hipMemcpyHostToDevice, s));
   return TG_OK;
 }
 
+// z-tile caps for a subset of the batch: while few problems run (the tail of a
+// ladder), a level whose z-march launch would have fewer than 1024
+// workgroups at the chosen heights gets the tallest height in {16, 12, 8, 6,
+// 4, 3} that restores 1024, else 2.  Shorter tiles redo one element layer
+// more often but shorten each workgroup's serial march, and the device is
+// mostly idle then.  Results do not depend on the heights.
+static void batch_tile_caps(const Batch* b, const std::vector<int>& active, int* cap) {
+  for (int l = 0; l < TG_MAXLEV; ++l) cap[l] = 1 << 30;
+  if ((int)active.size() >= b->n) return;
+  for (int l = 0; l < TG_MAXLEV; ++l) {
+    auto tiles = [&](int c) {
+      long long t = 0;
+      for (int p : active) {
+        const tg_grid* g = b->grids[p];
+        if (l < g->nlev - 1) t += zm_tiles(g, l, std::min(batch_zc(b, p, l), c));
+      }
+      return t;
+    };
+    const long long t0 = tiles(1 << 30);
+    if (t0 == 0 || t0 >= 1024) continue;
+    int pick = 2;
+    for (int c : {16, 12, 8, 6, 4, 3})
+      if (tiles(c) >= 1024) {
+        pick = c;
+        break;
+      }
+    cap[l] = pick;
+  }
+}
+
 int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bool with_elem) {
+  {
+    int cap[TG_MAXLEV];
+    batch_tile_caps(b, active, cap);
+    if (!std::equal(cap, cap + TG_MAXLEV, b->zc_cap)) {
+      // the descriptors carry the tile heights the kernels use
+      std::copy(cap, cap + TG_MAXLEV, b->zc_cap);
+      const int rc = batch_upload_desc(b, s);
+      if (rc) return rc;
+    }
+  }
   const unsigned long long zh = batch_zc_hash(b);
   if (b->lists_valid && b->lists_active == active && (b->lists_elem || !with_elem) && b->lists_zc_hash == zh) {
     b->active = active;
@@ -354,18 +399,18 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
   finish(b->prob, o);
   o = begin();
   for (int p : active)
-    for (int t = 0, nt = zm_tiles(b->grids[p], 0, batch_zc(b, p, 0)); t < nt; ++t) H.push_back(make_int2(p, t));
+    for (int t = 0, nt = zm_tiles(b->grids[p], 0, batch_zc_run(b, p, 0)); t < nt; ++t) H.push_back(make_int2(p, t));
   finish(b->fine, o);
   for (int l = 0; l < TG_MAXLEV; ++l) {
     o = begin();
     for (int p : active)
       if (l < b->grids[p]->nlev - 1)
-        for (int t = 0, nt = zm_tiles(b->grids[p], l, batch_zc(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
+        for (int t = 0, nt = zm_tiles(b->grids[p], l, batch_zc_run(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_s[l], o);
     o = begin();
     for (int p : active)
       if (l < b->grids[p]->nlev - 1)
-        for (int t = 0, nt = rz_tiles(b->grids[p], l, batch_zc(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
+        for (int t = 0, nt = rz_tiles(b->grids[p], l, batch_zc_run(b, p, l)); t < nt; ++t) H.push_back(make_int2(p, t));
     finish(b->zm_r[l], o);
   }
   // the one-launch V-cycle bottom (per vector type): its problems, its LDS,

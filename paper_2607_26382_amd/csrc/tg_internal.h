@@ -26,6 +26,17 @@
 #define TG_MAX_COARSE 512    // max free DOFs of the coarsest level
 #define TG_HIST_CAP 4096     // residual-history capacity per problem
 #define TG_GM_STRIDE 152    // stored entries per mode-basis element matrix (TG_GM_NU = 150, padded)
+// The stored mode-basis element matrices of a level are laid out in blocks of
+// 64 elements: entry v of element e belongs to 16-byte piece v / W (W = 16 /
+// sizeof entry), and piece p of element e sits at piece index
+// ((e / 64) * (TG_GM_STRIDE / W) + p) * 64 + e % 64.  The 64 lanes of a wave
+// reading piece p of 64 consecutive elements thus read 1 KB of consecutive
+// memory.  Arrays hold ceil(n_elem / 64) * 64 elements.
+__host__ __device__ inline long long gm_index(long long e, int v, int W) {
+  const long long np = TG_GM_STRIDE / W;
+  return ((((e >> 6) * np + v / W) << 6) + (e & 63)) * W + v % W;
+}
+__host__ __device__ inline long long gm_elems(long long n_elem) { return (n_elem + 63) & ~63LL; }
 #define TG_MF_LEVELS 1       // levels 1..TG_MF_LEVELS apply the Galerkin operator matrix-free
 
 namespace tg {
@@ -232,6 +243,8 @@ struct Batch {
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
   int zc[TG_MAXLEV] = {};         // z-tile height per level for this batch
+  // caps on the heights while only part of the batch runs (batch_set_active)
+  int zc_cap[TG_MAXLEV] = {1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30};
   // z-tile heights per grid size (nx, ny, nz) and level where the autotuner
   // chose one for that size (0: zc[l])
   std::map<std::array<int, 3>, std::array<int, TG_MAXLEV>> zc_size;
@@ -255,6 +268,7 @@ int batch_upload_desc(Batch* b, hipStream_t s);
 int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bool with_elem = false);
 int batch_read_status(Batch* b, hipStream_t s);   // fills sc_h from small[SC_STATUS]
 int batch_zc(const Batch* b, int p, int l);       // z-tile height of problem p at level l
+int batch_zc_run(const Batch* b, int p, int l);   // the same, capped for a small running set
 unsigned long long batch_zc_hash(const Batch* b); // of zc and every per-size choice
 
 // launch wrappers (tg_kernels.hip)

@@ -201,8 +201,8 @@ __global__ __launch_bounds__(256) void k_mode_pack(const ProbDesc* __restrict__ 
   __syncthreads();
   for (int v = threadIdx.x; v < TG_GM_STRIDE; v += 256) {
     if (v >= TG_GM_NU) {
-      L.Km64[e * TG_GM_STRIDE + v] = 0.0;
-      L.Km32[e * TG_GM_STRIDE + v] = 0.f;
+      L.Km64[gm_index(e, v, 2)] = 0.0;
+      L.Km32[gm_index(e, v, 4)] = 0.f;
       continue;
     }
     const int r = kGMPairs[v][0], c = kGMPairs[v][1];
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(256) void k_mode_pack(const ProbDesc* __restrict__ 
       t2 += sX[c * 24 + 3 * b + i] * H(m, b);
     }
     const double k = 0.5 * (t1 + t2) / 64.0;
-    L.Km64[e * TG_GM_STRIDE + v] = k;
-    L.Km32[e * TG_GM_STRIDE + v] = (float)k;
+    L.Km64[gm_index(e, v, 2)] = k;
+    L.Km32[gm_index(e, v, 4)] = (float)k;
   }
 }
 
@@ -410,7 +410,9 @@ __global__ __launch_bounds__(CF_THREADS) void k_coarse_factor_lds(const ProbDesc
 //   OP_RESID : y = b - K x
 //   OP_SMOOTH: y = x + w D^-1 (b - K x)      (damped node-block Jacobi)
 //   OP_RESTRICT: b_{l+1} = P^T (b - K x)     (residual fused with the restriction)
-enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_RESTRICT = 3 };
+//   OP_SMOOTH1: level 0, the first two sweeps from x = 0 with b read from an
+//               FP64 slot (x = scale offset, y2 = slot of b's FP32 copy)
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_RESTRICT = 3, OP_SMOOTH1 = 4 };
 
 // First pre-sweep from x = 0: x = w D^-1 b; optionally keep b in type T.
 template <class TB, class T>
@@ -1468,6 +1470,8 @@ static double op_bytes(const Batch* b, int l, int lmode, int op) {
   const int nvec = op == OP_APPLY ? 2 : 3;
   // the fused restriction reads x and b and writes the coarse right-hand side
   if (op == OP_RESTRICT) return 2 * vec + mat + vec / 8.0;
+  // the fused first sweeps read b in FP64 and the node blocks, write x and b's copy
+  if (op == OP_SMOOTH1) return 3.0 * nodes * 8.0 + 9.0 * nodes * sizeof(T) + mat + 2 * vec;
   return nvec * vec + mat + dinv;
 }
 
@@ -1565,7 +1569,14 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
     }
     if (!sm.n) continue;
     level_sums(b, l, 1, nodes, elems, c2);
-    if (l == 0 && fast_in)
+    int c = XA, o = XB;
+    int it0 = 1;
+    if (l == 0 && fast_in && mg.nu_pre >= 2) {
+      // first sweep from zero computed while staging, second sweep in the same pass
+      vc_op<T, OP_SMOOTH1>(b, 0, in_scale, sb, o, om, s, mf, Bs, vbs);
+      std::swap(c, o);
+      it0 = 2;
+    } else if (l == 0 && fast_in)
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * (8.0 + 2 * sT) + 9.0 * nodes * sT,
                k_jacobi_first<double, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, 0, sb, nullptr, Bs, XA, om,
                                                                     in_scale));
@@ -1573,8 +1584,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
       TG_TIMED(TG_KT_TRANSFER, 3.0 * nodes * 2 * sT + 9.0 * nodes * sT,
                k_jacobi_first<T, T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, Bs, nullptr, INT_MIN, XA, om, -1));
     // (levels >= 1: the restriction above already wrote the first sweep)
-    int c = XA, o = XB;
-    for (int it = 1; it < mg.nu_pre; ++it) {
+    for (int it = it0; it < mg.nu_pre; ++it) {
       vc_op<T, OP_SMOOTH>(b, l, c, Bs, o, om, s, mf, -1, vbs);
       std::swap(c, o);
     }

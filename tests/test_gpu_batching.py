@@ -116,3 +116,27 @@ def test_bottom_levels_per_problem(prec):
               flush=True)
         assert r1["iterations"] == res[i]["iterations"] and torch.equal(u1, us[i])
         assert res[i]["iterations"] > 5
+
+
+def test_batch_policy_equals_single_grid_policy():
+    """While only part of a batch runs (the ladder's later rungs) the z-tile
+    heights are capped for parallelism; heights change only the work
+    decomposition, so every problem's policy result in the batch equals its
+    single-grid policy bit for bit (attempts, iterations, guard values,
+    solution)."""
+    dims = (32, 16, 16)
+    n = 8
+    rhos = [torch.tensor(synth.blobs(*dims, 1000 + i), device=DEV) for i in range(n)]
+    grids = [tg.Grid(*dims, max_restart=100, device=DEV) for _ in range(n)]
+    batch = tg.Batch(grids)
+    fs = [torch.tensor(g.edge_load(), device=DEV) for g in grids]
+    pol = tg.policy(rungs=[1e-9, 1e-6, 1e-4, 1e-3],
+                    solve=tg.solver_opts(restart=30, max_iters=200, prec=tg.BF16X3MFMA))
+    us, outs = batch.select_floor(rhos, fs, pol)
+    # (every stop inside a batched solve shrinks the running set, which caps
+    # the heights on this batch: 8 problems give fewer than 1024 tiles)
+    print("batch policy attempts", [len(o["attempts"]) for o in outs], flush=True)
+    for i in range(n):
+        u1, o1 = grids[i].select_floor(rhos[i], fs[i], pol)
+        assert o1["rung"] == outs[i]["rung"] and o1["attempts"] == outs[i]["attempts"], i
+        assert torch.equal(u1, us[i]), i
