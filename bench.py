@@ -26,6 +26,7 @@ import os
 import multiprocessing
 import subprocess
 import sys
+import threading
 import time
 from concurrent.futures import ProcessPoolExecutor
 
@@ -121,6 +122,8 @@ def parse():
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive-preconditioner leg (fine-level correction)")
     ap.add_argument("--adaptive-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--streams", type=int, default=1,
+                    help="split the states into this many batches, each on its own stream and host thread")
     ap.add_argument("--stack-states", type=int, default=16,
                     help="states of the full-adaptive-stack policy leg (paper setting, one at a time)")
     ap.add_argument("--no-stack", action="store_true", help="skip the full-adaptive-stack policy leg")
@@ -191,7 +194,7 @@ def compact(result, full_path=None):
                                "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
     cfg = r.get("config") or {}
     c["config"] = {k: cfg.get(k) for k in ("workload", "states", "grid", "rungs", "p", "probe", "solve",
-                                            "preconditioner")}
+                                            "preconditioner", "streams")}
     c["config"]["mixed_form"] = r.get("mixed_form")
     c["config"]["selector"] = r.get("selector")
     rf = r.get("roofline")
@@ -745,6 +748,11 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
         log(f"adaptive leg, checkpoints on state {SEED0 + i}: stop at {res['iterations']}, "
             f"first checkpoint with true > 2 x projected at {first}")
     ps["adaptive_cgs1_checkpoints"] = drift
+    # the states whose estimate drifted furthest from the recomputed residual
+    # under the fine-level correction with CGS2 (largest recomputed /
+    # projected at the stop), for the full-stack policy leg
+    rows = ps["adaptive"]["per_state"]
+    ps["drift_order"] = sorted(range(len(rows)), key=lambda i: -(rows[i][3] / rows[i][2] if rows[i][2] > 0 else 0.0))
     # per-state rows only where the estimate converged but the guard rejects
     for name in ("adaptive", "plain_vcycle", "adaptive_cgs1", "plain_vcycle_cgs1"):
         rows = ps[name].pop("per_state")
@@ -760,7 +768,7 @@ def adaptive_leg(tg, torch, dev, rhos, fs, prec, n_states=102, floor=1e-9, n_pap
 PAPER_RUNGS = (1e-12, 1e-3, 1e-2)
 
 
-def stack_policy_leg(tg, torch, dev, rhos, fs, n_states, recheck=True, tau=1e-6):
+def stack_policy_leg(tg, torch, dev, rhos, fs, n_states, recheck=True, tau=1e-6, order=None):
     """Alg. floor_policy with the full adaptive stack (Chebyshev smoothing,
     line-searched and rejectable coarse correction with 10 level-1 GMRES
     steps, fine-level correction) preconditioning the probe and every rung,
@@ -772,12 +780,19 @@ def stack_policy_leg(tg, torch, dev, rhos, fs, n_states, recheck=True, tau=1e-6)
     variant: certified states, the attempts whose projected estimate
     converged while the recomputed residual is above tau (false stops the
     guard rejects), first and selected rungs, stage iterations, seconds per
-    state, and the oracle's recheck of every accepted solution."""
+    state, and the oracle's recheck of every accepted solution.  `order`
+    (state indices) picks the states, by default the first n_states."""
     n = min(n_states, len(rhos))
+    pick = list(order[:n]) if order is not None else list(range(n))
+    rhos = [rhos[i] for i in pick]
+    fs = [fs[i] for i in pick]
+    seeds = [SEED0 + i for i in pick]
     g = tg.Grid(*GRID, max_restart=30, device=dev)
     solve = tg.solver_opts(restart=300, max_iters=300, prec=tg.F64)
-    out = {"states": n, "p": 4.5, "rungs": list(PAPER_RUNGS), "probe": "100 its, restart 100",
-           "solve": "FGMRES(300), cap 300, adaptive stack, FP64 throughout"}
+    out = {"states": n, "seeds": seeds, "p": 4.5, "rungs": list(PAPER_RUNGS), "probe": "100 its, restart 100",
+           "solve": "FGMRES(300), cap 300, adaptive stack, FP64 throughout",
+           "selection": "first states" if order is None else
+           "largest recomputed / projected residual at the stop of the fine-correction paper-setting solve"}
     for name, sel in (("rule", {}), ("always_rho0_then_ladder", dict(selector=tg.SELECT_FIXED, fixed_rung=0))):
         pol = tg.policy(rungs=PAPER_RUNGS, p=4.5, solve=solve, **sel)
         outs, us, secs = [], [], []
@@ -789,11 +804,11 @@ def stack_policy_leg(tg, torch, dev, rhos, fs, n_states, recheck=True, tau=1e-6)
             secs.append(time.perf_counter() - t0)
             outs.append(o)
             us.append(u.cpu().numpy() if o["rung"] >= 0 else None)
-            log(f"stack policy ({name}) state {SEED0 + i}: k0={o['k0']} rung={o['rung']} r50={o['r50']:.3g} "
+            log(f"stack policy ({name}) state {seeds[i]}: k0={o['k0']} rung={o['rung']} r50={o['r50']:.3g} "
                 f"r100={o['r100']:.3g} attempts="
                 f"{[(a['rung'], a['iterations'], a['outcome'], a['true_eta']) for a in o['attempts']]} "
                 f"{secs[-1]:.2f}s")
-        false_stops = [[SEED0 + i, a["rung"], a["iterations"], a["proj_eta"], a["true_eta"]]
+        false_stops = [[seeds[i], a["rung"], a["iterations"], a["proj_eta"], a["true_eta"]]
                        for i, o in enumerate(outs) for a in o["attempts"]
                        if a["outcome"] == "PROJ_CONVERGED" and not a["true_eta"] <= tau]
         acc = [o for o in outs if o["rung"] >= 0]
@@ -1070,27 +1085,61 @@ def main():
     torch.cuda.synchronize()
     log(f"{n} grids bound ({sum(g.ws_bytes for g in grids) / 2**30:.1f} GiB workspace)")
 
-    mlp = None
+    # The states are independent: split them into `streams` contiguous parts,
+    # each a batch of its own driven by its own host thread on its own stream
+    # (default priority), so one part's bandwidth-bound Krylov sweeps overlap
+    # another part's latency- and ALU-bound multigrid kernels.  Every
+    # problem's result is the same bits in any batch.
+    n_parts = max(1, min(args.streams, n))
+    bounds = [(k * n // n_parts, (k + 1) * n // n_parts) for k in range(n_parts)]
+    parts = [(tg.Batch(grids[lo:hi]), lo, hi, torch.cuda.Stream(device=dev)) for lo, hi in bounds]
+    mlps = [None] * n_parts
     if args.selector == "mlp":
         from paper_2607_26382_amd import selector as sel
-        mlp, model = sel.load_model(device=dev)
+        for k in range(n_parts):   # one network per part: its staging buffers are per handle
+            mlps[k], model = sel.load_model(device=dev)
         log("stored first-floor selector loaded ({} training states)".format(model["meta"]["train_states"]))
+    mlp = mlps[0]
 
-    def policy(prec, use_mlp):
+    def policy(prec, use_mlp, k=0):
         solve = tg.solver_opts(restart=30, max_iters=200, prec=prec, cgs_passes=args.cgs_passes)
         if use_mlp:
-            return tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_MLP, mlp=mlp)
+            return tg.policy(rungs=RUNGS, p=3.0, solve=solve, selector=tg.SELECT_MLP, mlp=mlps[k])
         return tg.policy(rungs=RUNGS, p=3.0, solve=solve)
+
+    def select_all(pols):
+        """The policy over every state: one part per thread and stream."""
+        if n_parts == 1:
+            return batch.select_floor(rhos, fs, pols[0])
+        res, err = [None] * n_parts, []
+
+        def work(k):
+            b, lo, hi, st = parts[k]
+            try:
+                with torch.cuda.stream(st):
+                    res[k] = b.select_floor(rhos[lo:hi], fs[lo:hi], pols[k])
+                st.synchronize()
+            except Exception as e:   # re-raised on the calling thread
+                err.append(e)
+        th = [threading.Thread(target=work, args=(k,)) for k in range(n_parts)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if err:
+            raise err[0]
+        return [u for r in res for u in r[0]], [o for r in res for o in r[1]]
 
     step_times = []   # wall seconds of every timed step of the last run (select_floor syncs)
     last_us = []      # solutions of the last timed step
 
     def run(prec, steps, warmup, timer_mask, use_mlp, pol=None):
-        pol = pol if pol is not None else policy(prec, use_mlp)
+        # (a given policy carries no network, so the parts may share it)
+        pols = [pol] * n_parts if pol is not None else [policy(prec, use_mlp, k) for k in range(n_parts)]
         step_times.clear()
         for w in range(warmup):
             t = time.perf_counter()
-            batch.select_floor(rhos, fs, pol)
+            select_all(pols)
             log(f"warmup {w} prec={prec} {time.perf_counter() - t:.2f}s")
         tg.kernel_timer_enable(timer_mask)
         tg.kernel_timer_reset()
@@ -1100,7 +1149,7 @@ def main():
         us = None
         for st in range(steps):
             t = time.perf_counter()
-            us, outs = batch.select_floor(rhos, fs, pol)
+            us, outs = select_all(pols)
             step_times.append(time.perf_counter() - t)
             log(f"step {st} prec={prec} {time.perf_counter() - t:.2f}s "
                 f"certified={sum(1 for o in outs if o['rung'] >= 0)}")
@@ -1117,6 +1166,10 @@ def main():
     batch.set_density(rhos, 3.0, [RUNGS[0]] * n)
     zc_mixed, _ = batch.autotune(mixed_prec)
     log(f"autotuned z-tile heights (levels 0, 1): {zc_mixed[:2]}")
+    if n_parts > 1:
+        for b, lo, hi, _ in parts:
+            b.set_density(rhos[lo:hi], 3.0, [RUNGS[0]] * (hi - lo))
+            b.autotune(mixed_prec)
     # one untimed pass with every kernel class timed picks the dominant class;
     # the timed steps then carry events around that class only
     use_mlp = args.selector == "mlp"
@@ -1144,7 +1197,8 @@ def main():
         "config": {"workload": "102 severe random states, 64x32x32 cantilever, guarded floor ladder",
                    "states": n, "grid": list(GRID), "rungs": list(RUNGS), "p": 3.0,
                    "probe": "100 its, restart 100", "solve": "FGMRES(30), cap 200, tol 1e-6",
-                   "preconditioner": "5-level GMG V-cycle, node-block Jacobi w=0.6 2/2, FP32 vectors"},
+                   "preconditioner": "5-level GMG V-cycle, node-block Jacobi w=0.6 2/2, FP32 vectors",
+                   "streams": n_parts},
     }
     acc = [o for o in outs if o["rung"] >= 0]
     result["policy"] = {
@@ -1220,8 +1274,9 @@ def main():
         result["adaptive_preconditioner"] = adaptive_leg(tg, torch, dev, rhos, fs, mixed_prec, n_states=n,
                                                          n_paper=args.paper_states)
     if not args.no_stack and args.stack_states > 0:
+        order = _get(result, "adaptive_preconditioner", "paper_setting", "drift_order")
         result["stack_policy"] = stack_policy_leg(tg, torch, dev, rhos, fs, args.stack_states,
-                                                  recheck=not args.no_recheck)
+                                                  recheck=not args.no_recheck, order=order)
     if use_mlp and not args.no_rule_leg:
         d, o, _ = run(mixed_prec, args.steps, 0, 0, False)
         result["mixed_rule"] = brief(o, d, args.steps)

@@ -14,6 +14,7 @@
 // K u at node layer k, fused with the residual or the damped node-block Jacobi
 // update.  Output nodes: 15 x 15 columns per workgroup, ZC node layers.
 #include <cmath>
+#include <mutex>
 #include <cstring>
 #include <vector>
 
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
   const ProbDesc& P = probs[wi.x];
   TG_GATE(P);
   // inside a V-cycle, levels from the problem's bottom level down belong to k_vbottom
-  if (KIND == 4 && vbskip && l >= (sizeof(T) == 8 ? P.vb_lb64 : P.vb_lb32)) return;
+  if ((KIND == 1 || KIND == 4) && vbskip && l >= (sizeof(T) == 8 ? P.vb_lb64 : P.vb_lb32)) return;
   const LevelDesc& L = P.lv[l];
   const int NX = L.NX, NY = L.NY, NZ = L.NZ, nx = L.ex, ny = L.ey, nz = L.ez;
   const int nx0 = P.lv[0].ex, ny0 = P.lv[0].ey;
@@ -1071,12 +1072,13 @@ template int launch_fine<float>(const Batch*, const DevList&, int, int, int, con
 // the restriction from level lb - 1; b only when lb is the coarsest level);
 // exit: the level-lb result in slot sfin.
 // threads per workgroup: FP32 fits 128 registers (16 waves), FP64 takes 256
-#ifndef VB_GROUP
-#define VB_GROUP 8
-#endif
-template <class T>
+// threads per workgroup (FP32 fits 128 registers with 16 waves, FP64 takes
+// 256 with 8) and pieces of a stored element matrix in flight per group of
+// loads (measured: all 38 FP32 pieces at once with 512 threads is no faster)
+template <class T, bool L1>
 struct VbThreads {
   static constexpr int N = sizeof(T) == 8 ? 512 : 1024;
+  static constexpr int G = 8;
 };
 
 // LDS words (of type T) the bottom needs from level lb of grid g down
@@ -1104,7 +1106,9 @@ double vbottom_bytes(const Batch* b, int tv) {
     if (lb >= g->nlev) continue;
     const int Lc = g->nlev - 1;
     for (int l = lb; l < Lc; ++l) {
-      bytes += (mg.nu_pre + mg.nu_post) * (double)TG_GM_STRIDE * ts * g->lv[l].n_elem;
+      // level 1 reads its children's eight moduli, deeper levels their stored elements
+      const double per_elem = l <= TG_MF_LEVELS ? 8.0 : (double)TG_GM_STRIDE;
+      bytes += (mg.nu_pre + mg.nu_post) * per_elem * ts * g->lv[l].n_elem;
       bytes += (mg.nu_pre - 1 + mg.nu_post) * 9.0 * ts * g->lv[l].n_nodes;
       if (l + 1 < Lc) bytes += 9.0 * ts * g->lv[l + 1].n_nodes;
     }
@@ -1115,11 +1119,11 @@ double vbottom_bytes(const Batch* b, int tv) {
 }
 
 // First level from which the bottom kernel runs the cycle of g (TG_MAXLEV if
-// none): the smallest lb >= 2 whose levels fit `lds` bytes with elements of
+// none): the smallest lb >= 1 whose levels fit `lds` bytes with elements of
 // `tsize` bytes and a direct coarsest solve.
 int vbottom_level(const tg_grid* g, size_t tsize, size_t lds) {
-  if (g->ncoarse <= 0 || g->nlev < 3) return TG_MAXLEV;
-  for (int lb = 2; lb < g->nlev; ++lb)
+  if (g->ncoarse <= 0 || g->nlev < 2) return TG_MAXLEV;
+  for (int lb = 1; lb < g->nlev; ++lb)
     if (vb_words(g, lb) * tsize <= lds) return lb;
   return TG_MAXLEV;
 }
@@ -1141,11 +1145,14 @@ __device__ __forceinline__ VbLev<T> vb_lev(const LevelDesc& L, T* x, T* b) {
 }
 
 // eb[(3 a + c) * ne + e] = (K_e x_e)[3 a + c] for every element e of level l
-template <class T>
-__device__ __forceinline__ void vb_elements(const LevelDesc& L, const VbLev<T>& V, T* eb) {
+// (level 1: the matrix-free moment form from the fine moduli; deeper levels:
+// the stored mode-basis elements)
+template <class T, bool L1>
+__device__ __forceinline__ void vb_elements(const ProbDesc& P, int l, const LevelDesc& L, const VbLev<T>& V,
+                                            T* eb) {
   const T TG_GLOBAL* Km = gp(fKm<T>(L));
   const int NXY = V.NX * V.NY;
-  for (int e = threadIdx.x; e < V.ne; e += VbThreads<T>::N) {
+  for (int e = threadIdx.x; e < V.ne; e += (int)blockDim.x) {
     const int i = e % V.ex, t = e / V.ex, j = t % V.ey, k = t / V.ey;
     const int n0 = i + V.NX * j + NXY * k;
     T ux[8], uy[8], uz[8];
@@ -1159,7 +1166,11 @@ __device__ __forceinline__ void vb_elements(const LevelDesc& L, const VbLev<T>& 
     wht_fwd(ux);
     wht_fwd(uy);
     wht_fwd(uz);
-    elem_mode_stored<T, VB_GROUP>(ux, uy, uz, (const T*)Km, e);
+    if (L1 && l <= TG_MF_LEVELS)
+      elem_galerkin1<T>(ux, uy, uz, gp(fE<T>(P)), P.lv[0].ex, P.lv[0].ey, i, j, k,
+                        (const T __attribute__((address_space(4)))*)G1V<T>(P));
+    else
+      elem_mode_stored<T, VbThreads<T, L1>::G>(ux, uy, uz, (const T*)Km, e);
     wht_inv(ux);
     wht_inv(uy);
     wht_inv(uz);
@@ -1196,11 +1207,12 @@ __device__ __forceinline__ void vb_gather(const VbLev<T>& V, const T* eb, int i,
 // false; after the element pass a node's update reads only its own x, so x
 // is updated in place), or r = b - K x into rbuf (RESID = true); clamped
 // nodes 0.
-template <class T, bool RESID>
-__device__ void vb_sweep(const LevelDesc& L, const VbLev<T>& V, T* eb, T* rbuf, T omega) {
-  vb_elements<T>(L, V, eb);
+template <class T, bool RESID, bool L1>
+__device__ void vb_sweep(const ProbDesc& P, int l, const VbLev<T>& V, T* eb, T* rbuf, T omega) {
+  const LevelDesc& L = P.lv[l];
+  vb_elements<T, L1>(P, l, L, V, eb);
   __syncthreads();
-  for (int n = threadIdx.x; n < V.nn; n += VbThreads<T>::N) {
+  for (int n = threadIdx.x; n < V.nn; n += (int)blockDim.x) {
     const int i = n % V.NX, t = n / V.NX, j = t % V.NY, k = t / V.NY;
     T* dst = RESID ? rbuf : V.x;
     if (i == 0) {
@@ -1232,7 +1244,7 @@ __device__ void vb_sweep(const LevelDesc& L, const VbLev<T>& V, T* eb, T* rbuf, 
 template <class T>
 __device__ void vb_restrict(const VbLev<T>& F, const T* r, const LevelDesc& Lc, const VbLev<T>& C, T omega,
                             bool first_sweep) {
-  for (int n = threadIdx.x; n < C.nn; n += VbThreads<T>::N) {
+  for (int n = threadIdx.x; n < C.nn; n += (int)blockDim.x) {
     const int I = n % C.NX, t = n / C.NX, J = t % C.NY, K = t / C.NY;
     T s[3] = {T(0), T(0), T(0)};
     if (I > 0) {
@@ -1268,7 +1280,7 @@ __device__ void vb_restrict(const VbLev<T>& F, const T* r, const LevelDesc& Lc, 
 // x_f += P x_c (trilinear; clamped fine nodes untouched)
 template <class T>
 __device__ void vb_prolong(const VbLev<T>& F, const VbLev<T>& C) {
-  for (int n = threadIdx.x; n < F.nn; n += VbThreads<T>::N) {
+  for (int n = threadIdx.x; n < F.nn; n += (int)blockDim.x) {
     const int i = n % F.NX, t = n / F.NX, j = t % F.NY, k = t / F.NY;
     if (i == 0) continue;
     const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
@@ -1301,10 +1313,11 @@ __device__ void vb_coarse(const ProbDesc& P, const VbLev<T>& C) {
   const T TG_GLOBAL* Ci = gp(vb_cinv<T>(P));
   const int part = threadIdx.x & 7, row0 = threadIdx.x >> 3;
   const int NXm = C.NX - 1;
-  for (int q0 = 0; q0 < n; q0 += VbThreads<T>::N / 8) {
+  for (int q0 = 0; q0 < n; q0 += (int)blockDim.x / 8) {
     const int q = q0 + row0;
     T s = T(0);
     if (q < n)
+#pragma unroll 8
       for (int c = part; c < n; c += 8) {
         const int fn = c / 3, node = fn % NXm + 1 + C.NX * (fn / NXm);
         s = mad_(Ci[(long long)q * n + c], C.b[3 * node + c % 3], s);
@@ -1320,8 +1333,10 @@ __device__ void vb_coarse(const ProbDesc& P, const VbLev<T>& C) {
   __syncthreads();
 }
 
-template <class T>
-__global__ __launch_bounds__(VbThreads<T>::N) void k_vbottom(const ProbDesc* __restrict__ probs,
+// L1: some problem of the launch starts at level 1 (the moment-form
+// operator is compiled in only then: it costs registers)
+template <class T, bool L1>
+__global__ __launch_bounds__((VbThreads<T, L1>::N)) void k_vbottom(const ProbDesc* __restrict__ probs,
                                                         const int2* __restrict__ work, int sfin, T omega,
                                                         int nu_pre, int nu_post) {
   extern __shared__ __align__(16) unsigned char vb_smem[];
@@ -1346,21 +1361,21 @@ __global__ __launch_bounds__(VbThreads<T>::N) void k_vbottom(const ProbDesc* __r
     const T TG_GLOBAL* xg = gp(fpool<T>(L) + (long long)C_XA * L.stride);
     const bool first = lb < Lc;
     const VbLev<T> Vb = V(lb);
-    for (int q = threadIdx.x; q < 3 * Vb.nn; q += VbThreads<T>::N) {
+    for (int q = threadIdx.x; q < 3 * Vb.nn; q += (int)blockDim.x) {
       Vb.b[q] = bg[q];
       Vb.x[q] = first ? xg[q] : T(0);
     }
     for (int l = lb + 1; l <= Lc; ++l) {
       const VbLev<T> Vl = V(l);
-      for (int q = threadIdx.x; q < 3 * Vl.nn; q += VbThreads<T>::N) Vl.x[q] = T(0);
+      for (int q = threadIdx.x; q < 3 * Vl.nn; q += (int)blockDim.x) Vl.x[q] = T(0);
     }
   }
   __syncthreads();
   // descend
   for (int l = lb; l < Lc; ++l) {
     const VbLev<T> Vl = V(l);
-    for (int it = 1; it < nu_pre; ++it) vb_sweep<T, false>(P.lv[l], Vl, eb, rbuf, omega);
-    vb_sweep<T, true>(P.lv[l], Vl, eb, rbuf, omega);
+    for (int it = 1; it < nu_pre; ++it) vb_sweep<T, false, L1>(P, l, Vl, eb, rbuf, omega);
+    vb_sweep<T, true, L1>(P, l, Vl, eb, rbuf, omega);
     vb_restrict<T>(Vl, rbuf, P.lv[l + 1], V(l + 1), omega, l + 1 < Lc);
   }
   vb_coarse<T>(P, V(Lc));
@@ -1368,12 +1383,12 @@ __global__ __launch_bounds__(VbThreads<T>::N) void k_vbottom(const ProbDesc* __r
   for (int l = Lc - 1; l >= lb; --l) {
     const VbLev<T> Vl = V(l);
     vb_prolong<T>(Vl, V(l + 1));
-    for (int it = 0; it < nu_post; ++it) vb_sweep<T, false>(P.lv[l], Vl, eb, rbuf, omega);
+    for (int it = 0; it < nu_post; ++it) vb_sweep<T, false, L1>(P, l, Vl, eb, rbuf, omega);
   }
   const LevelDesc& L = P.lv[lb];
   const VbLev<T> Vb = V(lb);
   T TG_GLOBAL* yg = gp(fpool<T>(L) + (long long)sfin * L.stride);
-  for (int q = threadIdx.x; q < 3 * Vb.nn; q += VbThreads<T>::N) yg[q] = Vb.x[q];
+  for (int q = threadIdx.x; q < 3 * Vb.nn; q += (int)blockDim.x) yg[q] = Vb.x[q];
 }
 
 // Dynamic LDS the bottom kernel may take on the current device (the
@@ -1382,6 +1397,8 @@ __global__ __launch_bounds__(VbThreads<T>::N) void k_vbottom(const ProbDesc* __r
 size_t vbottom_lds_limit() {
   static size_t lim[64] = {};
   static bool done[64] = {};
+  static std::mutex mu;   // batches on several host threads
+  std::lock_guard<std::mutex> lk(mu);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
     (void)hipGetLastError();
@@ -1394,10 +1411,12 @@ size_t vbottom_lds_limit() {
       v = 0;
     }
     size_t l = v > 1024 ? (size_t)v - 1024 : 0;
-    if (l && (hipFuncSetAttribute((const void*)k_vbottom<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)l) != hipSuccess ||
-              hipFuncSetAttribute((const void*)k_vbottom<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)l) != hipSuccess)) {
+    const void* kf[4] = {(const void*)k_vbottom<float, false>, (const void*)k_vbottom<float, true>,
+                         (const void*)k_vbottom<double, false>, (const void*)k_vbottom<double, true>};
+    bool ok = true;
+    for (const void* k : kf)
+      ok = ok && l && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l) == hipSuccess;
+    if (l && !ok) {
       (void)hipGetLastError();
       l = std::min<size_t>(l, 65536 - 1024);
     }
@@ -1409,12 +1428,15 @@ size_t vbottom_lds_limit() {
 
 template <class T>
 int launch_vbottom(const Batch* b, const DevList& dl, size_t lds_bytes, int sfin, double omega, int nu_pre,
-                   int nu_post, hipStream_t s) {
+                   int nu_post, bool l1, hipStream_t s) {
   if (!dl.n) return TG_OK;
-  k_vbottom<T><<<dl.n, VbThreads<T>::N, lds_bytes, s>>>(b->desc_d, dl.ptr, sfin, T(omega), nu_pre, nu_post);
+  if (l1)
+    k_vbottom<T, true><<<dl.n, VbThreads<T, true>::N, lds_bytes, s>>>(b->desc_d, dl.ptr, sfin, T(omega), nu_pre, nu_post);
+  else
+    k_vbottom<T, false><<<dl.n, VbThreads<T, false>::N, lds_bytes, s>>>(b->desc_d, dl.ptr, sfin, T(omega), nu_pre, nu_post);
   return TG_OK;
 }
-template int launch_vbottom<float>(const Batch*, const DevList&, size_t, int, double, int, int, hipStream_t);
-template int launch_vbottom<double>(const Batch*, const DevList&, size_t, int, double, int, int, hipStream_t);
+template int launch_vbottom<float>(const Batch*, const DevList&, size_t, int, double, int, int, bool, hipStream_t);
+template int launch_vbottom<double>(const Batch*, const DevList&, size_t, int, double, int, int, bool, hipStream_t);
 
 }  // namespace tg

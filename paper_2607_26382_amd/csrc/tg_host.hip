@@ -421,6 +421,7 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
       const size_t ts = t ? sizeof(double) : sizeof(float);
       o = begin();
       size_t lds = 0;
+      bool l1 = false;
       for (int l = 0; l < TG_MAXLEV; ++l) b->vb_need[t][l] = false;
       for (int p : active) {
         const tg_grid* g = b->grids[p];
@@ -429,10 +430,12 @@ int batch_set_active(Batch* b, const std::vector<int>& active, hipStream_t s, bo
         if (lb < g->nlev) {
           H.push_back(make_int2(p, 0));
           lds = std::max(lds, vbottom_lds_bytes(g, lb, ts));
+          l1 = l1 || lb <= TG_MF_LEVELS;
         }
       }
       finish(b->vb[t], o);
       b->vb_lds[t] = lds;
+      b->vb_l1[t] = l1;
     }
   }
   if (H.size() > b->list_cap) return fail(TG_EWORKSPACE, "work-list capacity exceeded");

@@ -239,6 +239,7 @@ struct Batch {
   // the level-by-level launches there
   DevList vb[2];
   size_t vb_lds[2] = {0, 0};
+  bool vb_l1[2] = {false, false};   // some problem's bottom starts at level 1
   bool vb_need[2][TG_MAXLEV] = {};
   std::vector<int2> host_lists;   // kept alive until the next synchronization
   std::vector<ProbDesc> host_desc;
@@ -345,7 +346,7 @@ size_t vbottom_lds_bytes(const tg_grid* g, int lb, size_t tsize);
 double vbottom_bytes(const Batch* b, int tv);
 template <class T>
 int launch_vbottom(const Batch* b, const DevList& dl, size_t lds_bytes, int sfin, double omega, int nu_pre,
-                   int nu_post, hipStream_t s);
+                   int nu_post, bool l1, hipStream_t s);
 int launch_fine_smooth_out64(const Batch* b, const DevList& dl, int sx, int sb, int sy, double omega,
                              hipStream_t s);
 int launch_fine_mfma(const Batch* b, const DevList& dl, int op, bool split, int sx, const void* ex, int sb,

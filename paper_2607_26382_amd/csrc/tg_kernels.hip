@@ -4,6 +4,7 @@
 // serves problem work[b].x, tile work[b].y.  Vectors are full length
 // (3 * nodes, AoS) and hold zeros on the clamped x = 0 nodes.
 #include <climits>
+#include <mutex>
 
 #include "tg_internal.h"
 
@@ -1405,6 +1406,8 @@ static int coarse_lds_n() {
 static size_t coarse_lds_limit() {
   static size_t lim[64] = {};
   static bool done[64] = {};
+  static std::mutex mu;   // batches on several host threads
+  std::lock_guard<std::mutex> lk(mu);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
   if (!done[dev]) {
@@ -1530,13 +1533,13 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   const int L = b->maxlev;
   double nodes, elems, c2;
   const double sT = sizeof(T), sIn = in_is_f32 ? 4.0 : 8.0, sOut = out_is_f32 ? 4.0 : 8.0;
-  // Fast level-0 boundary: FGMRES calls with an FP64 slot in, an FP64 slot out,
-  // FP32 working precision and every problem multilevel.  The first sweep
-  // reads the FP64 vector directly and the last sweep writes the FP64 output.
+  // Fast level-0 boundary: FGMRES calls with an FP64 slot in, an FP64 slot out
+  // and every problem multilevel.  The first sweep reads the FP64 vector
+  // directly and the last sweep writes the FP64 output.
   bool all_multi = true;
   for (int p : b->active) all_multi = all_multi && b->grids[p]->nlev > 1;
-  const bool fast_in = !f64 && !in_is_f32 && sb >= 0 && all_multi;
-  const bool fast_out = !f64 && !out_is_f32 && sy >= 0 && all_multi;
+  const bool fast_in = !in_is_f32 && sb >= 0 && all_multi;
+  const bool fast_out = !out_is_f32 && sy >= 0 && all_multi;
   // The bottom of the cycle (each problem's levels from its vb_lb down) runs
   // as one launch between the two passes; the level-by-level launches skip
   // those levels (vbs) and whole levels no problem needs.
@@ -1595,7 +1598,7 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
   }
   if (use_vb)
     TG_TIMED(TG_KT_VCYCLE_COARSE, vbottom_bytes(b, tv),
-             launch_vbottom<T>(b, b->vb[tv], b->vb_lds[tv], FIN, mg.omega, mg.nu_pre, mg.nu_post, s));
+             launch_vbottom<T>(b, b->vb[tv], b->vb_lds[tv], FIN, mg.omega, mg.nu_pre, mg.nu_post, b->vb_l1[tv], s));
   // ---- ascend
   for (int l = L - 1; l >= 0; --l) {
     const DevList& sm = b->smooth[l];
@@ -1608,7 +1611,9 @@ static int vcycle_t(Batch* b, int in_is_f32, int sb, const void* eb, int out_is_
              k_prolong<T><<<nblk(sm), 256, 0, s>>>(b->desc_d, sm.ptr, l, c, FIN, nullptr, nullptr, vbs));
     for (int it = 0; it < mg.nu_post; ++it) {
       if (l == 0 && fast_out && it == mg.nu_post - 1) {
-        if (mf)
+        if (f64)
+          vc_op<T, OP_SMOOTH>(b, 0, c, Bs, sy, om, s, 0, -1, vbs);   // straight into the FP64 output slot
+        else if (mf)
           TG_TIMED(TG_KT_VCYCLE_FINE, (op_bytes<T>(b, 0, 1, OP_SMOOTH) + 3.0 * nodes * (8.0 - sT)),
                    launch_fine_mfma(b, b->zm_s[0], OP_SMOOTH, mf == 2, c, nullptr, Bs, nullptr, sy, nullptr,
                                     (double)om, true, s));
