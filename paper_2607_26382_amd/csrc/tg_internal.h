@@ -277,9 +277,8 @@ int k_set_density(Batch* b, hipStream_t s);
 int k_apply(Batch* b, int prec, int sx, const void* ex, int sy, void* ey, hipStream_t s);
 int k_residual64(Batch* b, int sb, int sx, int sy, hipStream_t s);
 int k_dots2(Batch* b, int sbase, int nv, int sq, int sw, hipStream_t s);
-int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, hipStream_t s);
-int k_dcgs_a(Batch* b, int j, hipStream_t s);
-int k_dcgs_b(Batch* b, int j, int cap, double tol, double brk, hipStream_t s);
+int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, int cap, double tol, double brk,
+              hipStream_t s);
 int k_vcycle(Batch* b, int prec, int in_is_f32, int sb, const void* eb, int out_is_f32, int sy,
              void* ey, hipStream_t s, int in_scale_sc = -1);   // input scaled by small[scal + in_scale_sc]
 int k_copy_ext(Batch* b, int dir, int slot, hipStream_t s);  // dir 0: ext0 -> slot; 1: slot -> ext1

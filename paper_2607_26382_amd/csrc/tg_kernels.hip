@@ -833,6 +833,14 @@ __global__ __launch_bounds__(256) void k_update_dots_reg_(const ProbDesc* __rest
   }
 }
 
+struct SmallOffs {
+  int mmax, H, g, cs, sn, y, h, tmp, scal, hist;
+};
+// the scalar parts of a delayed-CGS2 step, run by one wave (defined below)
+__device__ void dcgs_a_wave(const ProbDesc& P, int p, const SmallOffs& o, int j, double* status_out);
+__device__ void dcgs_b_wave(const ProbDesc& P, int p, const SmallOffs& o, int j, int cap, double tol, double brk,
+                            double* status_out);
+
 // CGS2 with delayed reorthogonalization, sweep A.  For k < nv the chunk
 // partials of V_k . q and V_k . w, then q . q, q . w, w . w: 2 nv + 3 entries
 // in the order [V.q (nv) | V.w (nv) | q.q, q.w, w.w].  One read of V, q, w.
@@ -980,10 +988,6 @@ __global__ __launch_bounds__(256) void k_scale_(const ProbDesc* __restrict__ pro
 
 // ---------------------------------------------------------------------------
 // FGMRES scalar kernels: one thread per problem (work list {p, 0}).
-struct SmallOffs {
-  int mmax, H, g, cs, sn, y, h, tmp, scal, hist;
-};
-
 __global__ void k_init_small_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
                               int total) {
   const ProbDesc& P = probs[work[blockIdx.x].x];
@@ -1096,16 +1100,22 @@ __global__ void k_arnoldi_(const ProbDesc* __restrict__ probs, const int2* __res
 // coefficients), replacing the tentative column and rotation of step j-1.
 // The first-pass coefficients of column j are h1 = [Q^T w ; q_j . w]; the
 // coefficients of sweep B go to tmp (see k_update2_).
-__global__ __launch_bounds__(64) void k_dcgs_a_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
-                                                SmallOffs o, int j, double* status_out) {
-  // one wave per problem: the column and the rotations are read in parallel
-  // and rotated in LDS by lane 0 (a chain of register operations rather than
-  // of round trips through memory)
+// LDS ordering between the lanes of the one wave that runs a scalar part
+// (the wave is in lockstep; the fence keeps the compiler and the LDS queue
+// from moving a lane's reads above another lane's writes)
+#define TG_WAVE_SYNC()                                       \
+  do {                                                       \
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   \
+    __builtin_amdgcn_wave_barrier();                         \
+  } while (0)
+
+__device__ void dcgs_a_wave(const ProbDesc& P, int p, const SmallOffs& o, int j, double* status_out) {
+  // one wave: the column and the rotations are read in parallel and rotated
+  // in LDS by lane 0 (a chain of register operations rather than of round
+  // trips through memory)
   __shared__ double sH[TG_MAX_RESTART + 2], sC[TG_MAX_RESTART + 1], sS[TG_MAX_RESTART + 1];
   __shared__ int bad;
-  const int2 wi = work[blockIdx.x];
-  const ProbDesc& P = probs[wi.x];
-  TG_GATE(P);
+  const int2 wi = make_int2(p, 0);
   const int lane = threadIdx.x;
   double* S = P.small;
   double* sc = S + o.scal;
@@ -1143,7 +1153,7 @@ __global__ __launch_bounds__(64) void k_dcgs_a_(const ProbDesc* __restrict__ pro
       sC[i] = S[o.cs + i];
       sS[i] = S[o.sn + i];
     }
-    __syncthreads();
+    TG_WAVE_SYNC();
     if (lane == 0) {
       sH[j] = rho * nu;
       double carry = sH[0];
@@ -1169,7 +1179,7 @@ __global__ __launch_bounds__(64) void k_dcgs_a_(const ProbDesc* __restrict__ pro
         S[o.g + j] = -sn * gj;
       }
     }
-    __syncthreads();
+    TG_WAVE_SYNC();
     for (int i = lane; i <= j; i += 64) Hc[i] = sH[i];
     if (bad) return;
   }
@@ -1191,14 +1201,11 @@ __global__ __launch_bounds__(64) void k_dcgs_a_(const ProbDesc* __restrict__ pro
 // tentatively as [h1 ; rho'] (its reorthogonalization correction is known
 // only after the next sweep A): rotations, projected residual estimate,
 // history and stop tests as in the immediate form.
-__global__ __launch_bounds__(64) void k_dcgs_b_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
-                                                SmallOffs o, int j, int cap, double tol, double brk,
-                                                double* status_out) {
+__device__ void dcgs_b_wave(const ProbDesc& P, int p, const SmallOffs& o, int j, int cap, double tol, double brk,
+                            double* status_out) {
   __shared__ double sH[TG_MAX_RESTART + 2], sC[TG_MAX_RESTART + 1], sS[TG_MAX_RESTART + 1];
   __shared__ int bad;
-  const int2 wi = work[blockIdx.x];
-  const ProbDesc& P = probs[wi.x];
-  TG_GATE(P);
+  const int2 wi = make_int2(p, 0);
   const int lane = threadIdx.x;
   double* S = P.small;
   double* sc = S + o.scal;
@@ -1226,7 +1233,7 @@ __global__ __launch_bounds__(64) void k_dcgs_b_(const ProbDesc* __restrict__ pro
     }
     return;
   }
-  __syncthreads();
+  TG_WAVE_SYNC();
   if (lane == 0) {
     sH[j + 1] = rn;
     double carry = sH[0];
@@ -1268,8 +1275,45 @@ __global__ __launch_bounds__(64) void k_dcgs_b_(const ProbDesc* __restrict__ pro
       status_out[wi.x] = st;
     }
   }
-  __syncthreads();
+  TG_WAVE_SYNC();
   for (int i = lane; i <= j + 1; i += 64) Hc[i] = sH[i];
+}
+
+// The scalar ends of the two sweeps of a delayed-CGS2 step, one workgroup per
+// problem: the chunk partials summed in a fixed order into small+tmp, then the
+// step's scalar part on one wave.  A: rows [V.q | V.w | q.q, q.w, w.w], each
+// summed over the chunks in chunk order; B: ||q_next||^2 over the chunks.
+__global__ __launch_bounds__(256) void k_fin_a_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                                                SmallOffs o, int j, double* status_out) {
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
+  const int nc = P.lv[0].n_chunks;
+  double* tmp = P.small + o.tmp;
+  for (int r = threadIdx.x; r < 2 * j + 3; r += 256) {
+    const double* pr = P.part + (long long)r * nc;
+    double a = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < nc; ++c) a += pr[c];
+    tmp[r] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) dcgs_a_wave(P, wi.x, o, j, status_out);
+}
+__global__ __launch_bounds__(256) void k_fin_b_(const ProbDesc* __restrict__ probs, const int2* __restrict__ work,
+                                                SmallOffs o, int j, int cap, double tol, double brk,
+                                                double* status_out) {
+  __shared__ double sh[4];
+  const int2 wi = work[blockIdx.x];
+  const ProbDesc& P = probs[wi.x];
+  TG_GATE(P);
+  const int nc = P.lv[0].n_chunks;
+  double a = 0.0;
+  for (int c = threadIdx.x; c < nc; c += 256) a += P.part[c];
+  a = block_sum256(a, sh);
+  if (threadIdx.x == 0) P.small[o.tmp] = a;
+  __syncthreads();
+  if (threadIdx.x < 64) dcgs_b_wave(P, wi.x, o, j, cap, tol, brk, status_out);
 }
 
 // Least squares: y = R^{-1} g over the jdone columns (back substitution).
@@ -1740,29 +1784,28 @@ int k_update_dots(Batch* b, int sbase, int nv, int sw, int coef_is_tmp, int ndot
   return check_launch("update_dots");
 }
 
+// Sweep A of the delayed CGS2 step j (nv = j basis vectors), then its
+// scalar end (chunk sums and the first scalar part) in one per-problem launch.
 int k_dots2(Batch* b, int sbase, int nv, int sq, int sw, hipStream_t s) {
   if (b->vec.n)
     TG_TIMED(TG_KT_MULTIDOT, 8.0 * (nv + 2) * dofs0(b),
              k_dots2_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sq, sw));
+  if (b->prob.n)
+    TG_TIMED(TG_KT_SCALAR, 0, k_fin_a_<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), nv, b->sc_d));
   return check_launch("dots2");
 }
-int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, hipStream_t s) {
+// Sweep B, then its scalar end (the norm sum, the Givens update, the history
+// entry and the stop tests) in one per-problem launch.
+int k_update2(Batch* b, int sbase, int nv, int sq, int sw, int snext, int cap, double tol, double brk,
+              hipStream_t s) {
   const SmallOffs o = offs(b);
   if (b->vec.n)
     TG_TIMED(TG_KT_UPDATE, 8.0 * (nv + 4) * dofs0(b),
              k_update2_<<<nblk(b->vec), 256, 0, s>>>(b->desc_d, b->vec.ptr, sbase, nv, sq, sw, snext, o.tmp));
-  return check_launch("update2");
-}
-int k_dcgs_a(Batch* b, int j, hipStream_t s) {
-  if (b->prob.n)
-    TG_TIMED(TG_KT_SCALAR, 0, k_dcgs_a_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, b->sc_d));
-  return check_launch("dcgs_a");
-}
-int k_dcgs_b(Batch* b, int j, int cap, double tol, double brk, hipStream_t s) {
   if (b->prob.n)
     TG_TIMED(TG_KT_SCALAR, 0,
-             k_dcgs_b_<<<nblk(b->prob), 64, 0, s>>>(b->desc_d, b->prob.ptr, offs(b), j, cap, tol, brk, b->sc_d));
-  return check_launch("dcgs_b");
+             k_fin_b_<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, o, nv, cap, tol, brk, b->sc_d));
+  return check_launch("update2");
 }
 int k_scale_to(Batch* b, int src, int dst, int sc_index, hipStream_t s) {
   const int sidx = offs(b).scal + sc_index;

@@ -245,12 +245,10 @@ static int fgmres_batch_impl(Batch* b, const std::vector<int>& which, const tg_s
           if ((r = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, st, SC_INV)))
             return r;
           if ((r = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, st))) return r;
+          // (each sweep is followed by one per-problem launch that sums its
+          // chunk partials and runs that part's scalar work)
           if ((r = k_dots2(b, slot_V(0), j, slot_V(j), S_W, st))) return r;
-          if ((r = k_reduce(b, 2 * j + 3, 2, 0, -1, st))) return r;
-          if ((r = k_dcgs_a(b, j, st))) return r;
-          if ((r = k_update2(b, slot_V(0), j, slot_V(j), S_W, slot_V(j + 1), st))) return r;
-          if ((r = k_reduce(b, 1, 2, 0, -1, st))) return r;
-          return k_dcgs_b(b, j, cap, tol, brk, st);
+          return k_update2(b, slot_V(0), j, slot_V(j), S_W, slot_V(j + 1), cap, tol, brk, st);
         }
         if ((r = k_vcycle(b, o->prec, 0, slot_V(j), nullptr, 0, slot_Z(mmax, j), nullptr, st))) return r;
         if ((r = k_apply(b, TG_F64, slot_Z(mmax, j), nullptr, S_W, nullptr, st))) return r;
