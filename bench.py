@@ -42,11 +42,13 @@ sys.path.insert(0, ROOT)
 # the listed kernel definitions within a file), else the traffic is reported
 # as null.
 MEASURED_TRAFFIC = {
-    "vcycle_fine_op": {"bytes_per_launch": 193.4e6, "sources": {"tg_fine.hip": "89396403ba2d182e"},
+    "vcycle_fine_op": {"bytes_per_launch": 225.0e6, "sources": {"tg_fine.hip:k_fine_zm": "35bf562ab09feec1"},
                        "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
-    "multidot": {"bytes_per_launch": 1818.4e6, "sources": {"tg_kernels.hip:k_dots2_": "413b15d1d0705f54"},
+    "multidot": {"bytes_per_launch": 1728.5e6, "sources": {"tg_kernels.hip:k_dots2_": "2a5a808e5c73d3e2",
+                                                           "tg_kernels.hip:k_multidot_": "2ecbcc0448c99c92"},
                  "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
-    "vector_update": {"bytes_per_launch": 1938.0e6, "sources": {"tg_kernels.hip:k_update2_": "e3884c42c4c540bf"},
+    "vector_update": {"bytes_per_launch": 1920.4e6, "sources": {"tg_kernels.hip:k_update2_": "eb211e836eb4dda9",
+                                                                "tg_kernels.hip:k_xupdate_": "0fc098785e738a14"},
                       "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
 }
 

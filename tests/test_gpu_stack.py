@@ -329,3 +329,31 @@ def test_stack_select_floor_errors():
         g.stack_select_floor(rho_d, f, tg.policy(rungs=[1e-9, 2.0]))
     with pytest.raises(TopoguardError):       # restart beyond the bound workspace's range
         g.stack_select_floor(rho_d, f, tg.policy(rungs=[1e-3], solve=tg.solver_opts(restart=600)))
+
+
+def test_stack_select_floor_with_network():
+    """The learned first-floor selector inside the stack policy: the first
+    attempted rung is the network's argmax (ties to the lower rung) on the
+    features the call reports, the ladder climbs from there, and the
+    oracle's recomputed residual of the accepted solution is within tau."""
+    from paper_2607_26382_amd import selector as sel
+    mlp, _ = sel.load_model(device=DEV)
+    dims, rungs = (16, 8, 8), [1e-9, 1e-6, 1e-4, 1e-3]
+    rho = _field("blob2", dims, 11)
+    g = tg.Grid(*dims, max_restart=30, device=DEV)
+    f = torch.tensor(g.edge_load(), device=DEV)
+    pol = tg.policy(rungs=rungs, p=3.0, selector=tg.SELECT_MLP, mlp=mlp,
+                    solve=tg.solver_opts(restart=30, max_iters=200))
+    u, out = g.stack_select_floor(torch.tensor(rho, device=DEV), f, pol)
+    k0 = int(sel.predict(mlp, [out["features"]])[0])
+    print(f"stack policy with the network: k0={out['k0']} (network {k0}) rung={out['rung']} "
+          f"attempts={[(a['rung'], a['iterations'], a['accepted']) for a in out['attempts']]}", flush=True)
+    assert out["k0"] == k0
+    assert [a["rung"] for a in out["attempts"]] == list(range(k0, k0 + len(out["attempts"])))
+    assert out["rung"] >= 0
+    og = mesh.Grid(*dims)
+    free = og.free_dofs()
+    K = op.free_block(op.assemble(og, op.young(rho, 3.0, rungs[out["rung"]]), KE), free)
+    uf = u.cpu().numpy()[free]
+    ff = og.edge_load()[free]
+    assert op.relative_residual(K, ff, uf) <= 1e-6 + 2 * op.residual_bound(K, ff, uf)
