@@ -347,6 +347,7 @@ __global__ __launch_bounds__(256) void k_coarse_factor(const ProbDesc* __restric
 // n^2 updates of a step in parallel; the explicit inverse is symmetrized as
 // in k_coarse_factor.  A non-positive pivot flags the problem.
 #define CF_THREADS 1024
+#define CF_REG 16   // register form: rows per thread (n <= 128)
 __global__ __launch_bounds__(CF_THREADS) void k_coarse_factor_lds(const ProbDesc* __restrict__ probs,
                                                                   const int2* __restrict__ work, int* bad,
                                                                   int nmax) {
@@ -377,6 +378,69 @@ __global__ __launch_bounds__(CF_THREADS) void k_coarse_factor_lds(const ProbDesc
     }
     __syncthreads();
   }
+  // Register form: thread t holds column j = t mod n of the rows t / n +
+  // q rpp (rpp = rows per pass, q < cm).  Each step publishes the pivot
+  // column and row through one of two alternating LDS buffers (one barrier
+  // per step); the column is stored in slot order, row i at
+  // (i mod rpp) cm + i / rpp, so a thread's rows are contiguous.  Every
+  // register takes the generic update a -= c_i r_j / p (unused ones too, on
+  // values never stored), then the holders of row k and of column k write
+  // their special values: the same operations as the LDS form below.
+  const int rpp = CF_THREADS / n;
+  const int cm = (n + rpp - 1) / rpp;
+  if (n >= 2 && cm <= CF_REG) {
+    const int t = threadIdx.x, j = t % n, i0 = t / n;
+    const bool act = t < rpp * n;
+    const int cnt = act ? (n - i0 + rpp - 1) / rpp : 0;
+    const int csz = rpp * cm + CF_REG, bsz = csz + n;   // column part (padded), buffer
+    const int cb = (act ? i0 : 0) * cm;                 // this thread's first slot
+    double a[CF_REG];
+#pragma unroll
+    for (int q = 0; q < CF_REG; ++q) a[q] = q < cnt ? A[(i0 + q * rpp) * n + j] : 0.0;
+    __syncthreads();   // A's storage now holds the pivot buffers
+    for (int k = 0; k < n; ++k) {
+      double* ck = smem + (k & 1) * bsz;
+      double* rk = ck + csz;
+      const bool rowk = act && k % rpp == i0, colk = act && j == k;
+      const int qk = k / rpp;
+      if (colk) {
+#pragma unroll
+        for (int q = 0; q < CF_REG; ++q)
+          if (q < cnt) ck[cb + q] = a[q];
+      }
+      if (rowk) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < CF_REG; ++q) v = q == qk ? a[q] : v;
+        rk[j] = v;
+      }
+      __syncthreads();
+      const double p = ck[(k % rpp) * cm + qk];
+      if (t == 0 && !(p > 0.0)) atomicOr(bad + wi.x, 2);
+      const double ip = 1.0 / p;
+      const double rj = rk[j] * ip;
+      double ci[CF_REG];
+#pragma unroll
+      for (int q = 0; q < CF_REG; ++q) ci[q] = ck[cb + q];
+#pragma unroll
+      for (int q = 0; q < CF_REG; ++q) a[q] -= ci[q] * rj;
+      if (rowk) {
+        const double v = colk ? ip : rj;
+#pragma unroll
+        for (int q = 0; q < CF_REG; ++q) a[q] = q == qk ? v : a[q];
+      }
+      if (colk) {
+#pragma unroll
+        for (int q = 0; q < CF_REG; ++q)
+          if (q < cnt && i0 + q * rpp != k) a[q] = -ci[q] * ip;
+      }
+    }
+    __syncthreads();   // every read of the last pivot buffers is done
+#pragma unroll
+    for (int q = 0; q < CF_REG; ++q)
+      if (q < cnt) A[(i0 + q * rpp) * n + j] = a[q];
+    __syncthreads();
+  } else {
   for (int k = 0; k < n; ++k) {
     const double p = A[k * n + k];
     if (threadIdx.x == 0 && !(p > 0.0)) atomicOr(bad + wi.x, 2);
@@ -396,6 +460,7 @@ __global__ __launch_bounds__(CF_THREADS) void k_coarse_factor_lds(const ProbDesc
         A[q] -= colk[i] * rowk[j];
     }
     __syncthreads();
+  }
   }
   for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
     const int r = q / n, c = q % n;
@@ -1441,6 +1506,15 @@ static double dofs0(const Batch* b) {
 // device's per-workgroup limit less the kernel's static LDS), with the
 // kernel's limit raised to it once per device.
 static size_t coarse_lds_limit();
+// LDS doubles k_coarse_factor_lds needs for a coarsest level of n free
+// DOFs: the assembled matrix and two pivot rows (LDS form), or the two pivot
+// buffers of the register form when it applies.
+static size_t coarse_lds_words(int n) {
+  size_t w = (size_t)n * (n + 2);
+  const int rpp = CF_THREADS / n, cm = (n + rpp - 1) / rpp;
+  if (n >= 2 && cm <= CF_REG) w = std::max(w, (size_t)2 * (rpp * cm + CF_REG + n));
+  return w;
+}
 static int coarse_lds_n() {
   const size_t lim = coarse_lds_limit();
   int n = 0;
@@ -1494,9 +1568,13 @@ int k_set_density(Batch* b, hipStream_t s) {
         if (n > 0) nmax = std::max(nmax, n), nmin = std::min(nmin, n);
       }
       if (nmin <= nlds) {
-        const int nl = std::min(nmax, nlds);
-        k_coarse_factor_lds<<<nblk(b->prob), CF_THREADS, sizeof(double) * (size_t)nl * (nl + 2), s>>>(
-            b->desc_d, b->prob.ptr, bad, nlds);
+        size_t words = 0;
+        for (int p : b->active) {
+          const int n = b->grids[p]->ncoarse;
+          if (n > 0 && n <= nlds) words = std::max(words, coarse_lds_words(n));
+        }
+        k_coarse_factor_lds<<<nblk(b->prob), CF_THREADS, sizeof(double) * words, s>>>(b->desc_d, b->prob.ptr,
+                                                                                        bad, nlds);
       }
       if (nmax > nlds) k_coarse_factor<<<nblk(b->prob), 256, 0, s>>>(b->desc_d, b->prob.ptr, bad, nlds + 1);
     }
