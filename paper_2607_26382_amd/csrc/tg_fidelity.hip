@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ 
                                                      double* __restrict__ dc,
                                                      double* __restrict__ part) {
   constexpr int NT = EN_T + 1;            // nodes per tile edge
-  __shared__ double su[3][NT][NT];
+  __shared__ double su[2][3][NT][NT];   // node layers, alternating
   __shared__ double red[4];
   const int tx = threadIdx.x & (EN_T - 1), ty = threadIdx.x / EN_T;
   const int ntx = (nx + EN_T - 1) / EN_T;
@@ -141,43 +141,46 @@ __global__ __launch_bounds__(256) void k_energy_sens(const double* __restrict__ 
       }
     }
   };
-  auto stage = [&](bool count) {
+  auto stage = [&](int buf, bool count) {
 #pragma unroll
     for (int sI = 0; sI < 2; ++sI) {
       const int q = threadIdx.x + 256 * sI;
       if (q < NT * NT) {
 #pragma unroll
-        for (int cI = 0; cI < 3; ++cI) su[cI][q / NT][q % NT] = pv[sI][cI];
+        for (int cI = 0; cI < 3; ++cI) su[buf][cI][q / NT][q % NT] = pv[sI][cI];
         if (count) fu += pf[sI][0] * pv[sI][0] + pf[sI][1] * pv[sI][1] + pf[sI][2] * pv[sI][2];
       }
     }
   };
-  auto read_face = [&](double* X, double* Y, double* Z) {
+  auto read_face = [&](int buf, double* X, double* Y, double* Z) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      X[q] = su[0][ty + (q >> 1)][tx + (q & 1)];
-      Y[q] = su[1][ty + (q >> 1)][tx + (q & 1)];
-      Z[q] = su[2][ty + (q >> 1)][tx + (q & 1)];
+      X[q] = su[buf][0][ty + (q >> 1)][tx + (q & 1)];
+      Y[q] = su[buf][1][ty + (q >> 1)][tx + (q & 1)];
+      Z[q] = su[buf][2][ty + (q >> 1)][tx + (q & 1)];
     }
     face_walsh(X);
     face_walsh(Y);
     face_walsh(Z);
   };
   double bx[4], by[4], bz[4];
+  // node layer k lives in su[(k - z0) & 1]: the layer staged in step k goes
+  // to the buffer last read two steps earlier, so the barrier of the step
+  // between separates them and one barrier per layer suffices
   fetch(z0);
-  stage(z0 == 0);
+  stage(0, z0 == 0);
   fetch(z0 + 1);
   __syncthreads();
-  read_face(bx, by, bz);
+  read_face(0, bx, by, bz);
   for (int k = z0; k < z1; ++k) {
     const long long ek = ex + (long long)nx * (ey + (long long)ny * k);
     const double rk = (act && dc) ? (ipm1 >= 0 ? rho[ek] : dc[ek]) : 0.0;
-    __syncthreads();            // every read of the previous layer is done
-    stage(true);                // node layer k + 1
+    const int nb1 = (k + 1 - z0) & 1;
+    stage(nb1, true);           // node layer k + 1
     if (k + 1 < z1) fetch(k + 2);
     __syncthreads();
     double tx4[4], ty4[4], tz4[4];
-    read_face(tx4, ty4, tz4);
+    read_face(nb1, tx4, ty4, tz4);
     if (act) {
       double X[8], Y[8], Z[8];
 #pragma unroll
