@@ -133,6 +133,7 @@ def parse():
     ap.add_argument("--paper-states", type=int, default=102,
                     help="states of the adaptive leg's paper-setting part (p = 4.5, rho_0 = 1e-12, FGMRES(300))")
     ap.add_argument("--trajectory-only", action="store_true", help="run only the optimization-loop leg")
+    ap.add_argument("--small-only", action="store_true", help="run only the 16x8x8 plain-method leg")
     ap.add_argument("--no-fixed-legs", action="store_true",
                     help="skip the fixed-first-rung baselines (original floor first; always the top rung)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -1056,6 +1057,9 @@ def main():
         print(json.dumps({"trajectory": trajectory_leg(tg, torch, dev, {"f32": tg.F32, "bf16": tg.BF16MFMA,
                                                                           "bf16x3": tg.BF16X3MFMA}[args.mixed])}),
               flush=True)
+        return
+    if args.small_only:
+        print(json.dumps({"small_plain": small_leg(tg, torch, dev)}), flush=True)
         return
     if args.adaptive_only:
         n_ad = args.states
