@@ -111,10 +111,13 @@ def test_true_residual_parity(dims, kind, rmin):
 
 
 # (32x16x16 and 48x24x24: the one-launch bottom runs levels 2.. in FP32 and
-# FP64; 16x8x8 and 24x12x12: only the coarsest level)
+# FP64; 16x8x8 and 24x12x12: only the coarsest level.  Coarsest inverses:
+# 16x8x8 and 1x1x1 (108 and 12 free DOFs) take the register form of the
+# LDS kernel, 20x8x8 (coarsest 5x2x2, 135) its LDS-resident form, 24x12x12
+# (288) the global-memory kernel)
 @pytest.mark.parametrize("dims,kind,rmin", [((16, 8, 8), "uniform", 1e-3), ((24, 12, 12), "blob", 1e-3),
                                             ((1, 1, 1), "uniform", 0.5), ((32, 16, 16), "blob", 1e-6),
-                                            ((48, 24, 24), "blob", 1e-4)])
+                                            ((48, 24, 24), "blob", 1e-4), ((20, 8, 8), "blob", 1e-3)])
 def test_vcycle_f64_f32(dims, kind, rmin):
     rho = _field(kind, dims, 3)
     g = _gpu_grid(dims, rho, 3.0, rmin)
