@@ -912,7 +912,11 @@ __device__ void dcgs_b_wave(const ProbDesc& P, int p, const SmallOffs& o, int j,
 __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ probs,
                                                 const int2* __restrict__ work, int sbase, int nv, int sq,
                                                 int sw) {
-  __shared__ double sh[16][4];
+  // per group of eight basis vectors: the 16 wave sums of each wave (every
+  // group has its own slots, so the waves only meet once, at the end)
+  constexpr int NGRP = (TG_MAX_RESTART + 8) / 8;
+  __shared__ double sh[NGRP][16][4];
+  __shared__ double sh3[3][4];
   const int2 wi = work[blockIdx.x];
   const ProbDesc& P = probs[wi.x];
   TG_GATE(P);
@@ -934,6 +938,7 @@ __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ pro
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k0 = 0; k0 < nv; k0 += 8) {
+    const int gi = k0 >> 3;
     double a[8], c[8];
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
@@ -956,13 +961,7 @@ __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ pro
       v16[8 + g] = c[g];
     }
     const double r = wave_sum16(v16, lane);
-    if (lane < 16) sh[rev4(lane)][wave] = r;
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      const int t = threadIdx.x, k = k0 + (t & 7), which = t >> 3;
-      if (k < nv) P.part[((long long)which * nv + k) * nc + wi.y] = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
-    }
-    __syncthreads();
+    if (lane < 16) sh[gi][rev4(lane)][wave] = r;
   }
   double qq = 0.0, qw = 0.0, ww = 0.0;
 #pragma unroll
@@ -975,14 +974,19 @@ __global__ __launch_bounds__(256) void k_dots2_(const ProbDesc* __restrict__ pro
   qw = wave_sum(qw);
   ww = wave_sum(ww);
   if (lane == 0) {
-    sh[0][wave] = qq;
-    sh[1][wave] = qw;
-    sh[2][wave] = ww;
+    sh3[0][wave] = qq;
+    sh3[1][wave] = qw;
+    sh3[2][wave] = ww;
   }
   __syncthreads();
+  // rows [V.q | V.w]: row which * nv + k from slot (k & 7) + 8 which of group k / 8
+  for (int t = threadIdx.x; t < 2 * nv; t += 256) {
+    const int which = t / nv, k = t - which * nv, gi = k >> 3, sl = (k & 7) + 8 * which;
+    P.part[(long long)t * nc + wi.y] = (sh[gi][sl][0] + sh[gi][sl][1]) + (sh[gi][sl][2] + sh[gi][sl][3]);
+  }
   if (threadIdx.x < 3) {
     const int t = threadIdx.x;
-    P.part[(2LL * nv + t) * nc + wi.y] = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
+    P.part[(2LL * nv + t) * nc + wi.y] = (sh3[t][0] + sh3[t][1]) + (sh3[t][2] + sh3[t][3]);
   }
 }
 
