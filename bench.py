@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 # the listed kernel definitions within a file), else the traffic is reported
 # as null.
 MEASURED_TRAFFIC = {
-    "vcycle_fine_op": {"bytes_per_launch": 220.0e6, "sources": {"tg_fine.hip:k_fine_zm": "35bf562ab09feec1"},
+    "vcycle_fine_op": {"bytes_per_launch": 220.0e6, "sources": {"tg_fine.hip:k_fine_zm": "19467845af83fd66"},
                        "profile": "profiles/policy_severe102_64x32x32_hbm_counters.md"},
     "multidot": {"bytes_per_launch": 1728.5e6, "sources": {"tg_kernels.hip:k_dots2_": "4a3f94abdb36d47c",
                                                            "tg_kernels.hip:k_multidot_": "2ecbcc0448c99c92"},

@@ -785,8 +785,8 @@ __global__ __launch_bounds__(256) void k_fine_zm(const ProbDesc* __restrict__ pr
       }
     }
   };
-  if constexpr (MF || KIND == 4) {
-    // register-bound forms: one state, updated in place
+  if constexpr (MF || KIND == 4 || sizeof(T) == 8) {
+    // register-bound forms (and FP64): one state, updated in place
     for (int k = z0 - 1; k < zend; ++k) step(k, s0, s0);
   } else {
     int k = z0 - 1;
