@@ -17,7 +17,7 @@ beside it.  Inputs are resident in HBM before the timed region.
 The last line on stdout is one compact JSON object (under 4 KB) with the
 headline, the roofline of the dominant kernel, the CPU oracle baseline and
 the oracle's recheck of the accepted solutions; every leg's full record goes
-to --full-out (default gpurun_out/bench_full.json).
+to --full-out (default bench_full.json in the working directory).
 """
 import argparse
 import json
@@ -140,7 +140,7 @@ def parse():
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--no-recheck", action="store_true",
                     help="skip the oracle's recomputation of the accepted solutions' residuals")
-    ap.add_argument("--full-out", default=os.path.join("gpurun_out", "bench_full.json"),
+    ap.add_argument("--full-out", default="bench_full.json",
                     help="file for the full record of every leg (the stdout line is the compact summary)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-seed", type=int, default=1000, help=argparse.SUPPRESS)

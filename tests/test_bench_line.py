@@ -69,7 +69,7 @@ def _full_result():
 def test_summary_line_is_short_and_complete():
     full = _full_result()
     assert len(json.dumps(full)) > 8000           # the full record is far longer than the line
-    c = bench.compact(full, "gpurun_out/bench_full.json")
+    c = bench.compact(full, "bench_full.json")
     line = json.dumps(c)
     assert "\n" not in line and len(line) <= 4096
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
