@@ -110,8 +110,9 @@ def test_true_residual_parity(dims, kind, rmin):
         assert abs(eta - op.relative_residual(K, ff, uf)) <= 2 * op.residual_bound(K, ff, uf)
 
 
-# (32x16x16 and 48x24x24: the one-launch bottom runs levels 2.. in FP32 and
-# FP64; 16x8x8 and 24x12x12: only the coarsest level.  Coarsest inverses:
+# (the one-launch bottom starts at level 1 on 16x8x8, 20x8x8 and 24x12x12,
+# at level 1 in FP32 and 2 in FP64 on 32x16x16, at level 2 on 48x24x24; the
+# bench grid's level 3 in FP64 is covered at 64x32x32.  Coarsest inverses:
 # 16x8x8 and 1x1x1 (108 and 12 free DOFs) take the register form of the
 # LDS kernel, 20x8x8 (coarsest 5x2x2, 135) its LDS-resident form, 24x12x12
 # (288) the global-memory kernel)
